@@ -1,0 +1,927 @@
+// C ABI of the dust hot path (include/dust.h): context, validation,
+// workspace, and the orchestration of the per-phase kernels, binning, the
+// fused tile kernel and hipGraph capture of multi-step loops.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dust_fused.h"
+#include "dust_launch.h"
+#include "dust_types.h"
+
+using namespace dust;
+
+namespace {
+
+thread_local std::string g_err;
+
+dust_status_t fail(dust_status_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(DUST_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct GraphKey {
+  std::vector<unsigned char> bytes;
+  bool operator==(const GraphKey& o) const { return bytes == o.bytes; }
+};
+
+struct Ctx {
+  int device = 0;
+  int prec = DUST_F32;
+  int arith = DUST_ARITH_F64;
+  int drag_mode = DUST_DRAG_TAU;
+  Species species{};
+  bool have_mass_table = false;
+  int nbox = 0;
+  std::vector<Box> boxes;         // host copies (device table pointers inside)
+  Box* boxes_d = nullptr;
+  std::vector<void*> tables;      // device face / ivol tables
+  int64_t n_stored = 0, n_active = 0;
+  std::vector<int64_t> store_off;
+  DiagDev* diag = nullptr;
+  double* tdev = nullptr;         // [0] current step start time
+  hipStream_t last_stream = nullptr;
+  // unfused workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // binning workspace
+  BinWork bin{};
+  size_t bin_bytes = 0;
+  void* bin_mem = nullptr;
+  int64_t* bin_start = nullptr;   // nbins+1 (fused path)
+  size_t bin_start_cap = 0;
+  TileShape tile{{8, 8, 4}};
+  int slack = 1;
+  FusedPlan plan{};
+  // fused-kernel timing
+  std::vector<hipEvent_t> prof_ev;  // 2 per launch
+  int prof_max = 0;
+  int prof_used = 0;
+  // graph cache
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  GraphKey graph_key;
+};
+
+size_t real_size(const Ctx* c) { return c->prec == DUST_F64 ? 8 : 4; }
+int ncomp(const Box& b) { return b.geom == GEOM_CART ? b.ndim : 3; }
+int ctx_nc(const Ctx* c) {
+  int nc = 0;
+  for (auto& b : c->boxes) nc = std::max(nc, ncomp(b));
+  return nc;
+}
+
+dust_status_t upload_table(Ctx* c, const std::vector<double>& v, const double** out) {
+  void* p = nullptr;
+  HIP_TRY(hipMalloc(&p, v.size() * sizeof(double)));
+  c->tables.push_back(p);
+  HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+  *out = (const double*)p;
+  return DUST_OK;
+}
+
+dust_status_t build_box(Ctx* c, const dust_box_t& in, int ib, int64_t cell_base, int64_t store_base,
+                        Box& B) {
+  memset(&B, 0, sizeof(B));
+  if (in.geom < DUST_CART || in.geom > DUST_SPH)
+    return fail(DUST_EINVAL, "box %d: unknown geometry %d", ib, in.geom);
+  if (in.ndim != 2 && in.ndim != 3) return fail(DUST_EINVAL, "box %d: ndim must be 2 or 3", ib);
+  if (in.ndim == 2 && in.geom != DUST_CART)
+    return fail(DUST_EUNSUPPORTED, "box %d: 2-D boxes must be Cartesian", ib);
+  B.geom = in.geom;
+  B.ndim = in.ndim;
+  int64_t ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    Axis& ax = B.ax[d];
+    if (d >= in.ndim) {
+      ax.n = 1;
+      ax.uniform = 1;
+      ax.d = 1.0;
+      ax.inv_d = 1.0;
+      ax.lo = 0.0;
+      ax.hi = 1.0;
+      ax.L = 1.0;
+      continue;
+    }
+    int n = in.n[d];
+    if (n < 1) return fail(DUST_EINVAL, "box %d axis %d: n = %d", ib, d, n);
+    if (!in.faces[d]) return fail(DUST_EINVAL, "box %d axis %d: faces is NULL", ib, d);
+    const double* f = in.faces[d];
+    for (int k = 0; k <= n; ++k)
+      if (!std::isfinite(f[k])) return fail(DUST_EINVAL, "box %d axis %d: face %d not finite", ib, d, k);
+    for (int k = 0; k < n; ++k)
+      if (!(f[k + 1] > f[k])) return fail(DUST_EINVAL, "box %d axis %d: faces not increasing", ib, d);
+    if (in.shape[d] != DUST_CIC && in.shape[d] != DUST_TSC)
+      return fail(DUST_EINVAL, "box %d axis %d: unknown shape %d", ib, d, in.shape[d]);
+    for (int s = 0; s < 2; ++s) {
+      int bc = s ? in.bc_hi[d] : in.bc_lo[d];
+      if (bc < DUST_BC_PERIODIC || bc > DUST_BC_OPEN)
+        return fail(DUST_EINVAL, "box %d axis %d: unknown boundary %d", ib, d, bc);
+    }
+    if ((in.bc_lo[d] == DUST_BC_OPEN) != (in.bc_hi[d] == DUST_BC_OPEN) ||
+        (in.bc_lo[d] == DUST_BC_SHEAR) != (in.bc_hi[d] == DUST_BC_SHEAR))
+      return fail(DUST_EINVAL, "box %d axis %d: both sides must have the same kind of boundary", ib, d);
+    ax.n = n;
+    ax.bc_lo = in.bc_lo[d];
+    ax.bc_hi = in.bc_hi[d];
+    ax.shape = in.shape[d];
+    ax.lo = f[0];
+    ax.hi = f[n];
+    ax.L = f[n] - f[0];
+    double w0 = f[1] - f[0], maxdev = 0.0;
+    for (int k = 0; k < n; ++k) maxdev = std::max(maxdev, std::fabs((f[k + 1] - f[k]) - w0));
+    ax.uniform = maxdev <= 1e-12 * w0 ? 1 : 0;
+    ax.d = ax.L / n;
+    ax.inv_d = 1.0 / ax.d;
+    if (ax.bc_lo != DUST_BC_OPEN && !ax.uniform)
+      return fail(DUST_EUNSUPPORTED, "box %d axis %d: periodic axes must be uniform", ib, d);
+    ax.kind = AX_PLAIN;
+    if (in.geom == DUST_CYL && d == 0) ax.kind = AX_CYL_R;
+    if (in.geom == DUST_SPH && d == 0) ax.kind = AX_SPH_R;
+    if (in.geom == DUST_SPH && d == 1) ax.kind = AX_THETA;
+    // faces with one ghost cell each side of the width of its neighbour
+    std::vector<double> ff(n + 3);
+    ff[0] = f[0] - (f[1] - f[0]);
+    for (int k = 0; k <= n; ++k) ff[k + 1] = f[k];
+    ff[n + 2] = f[n] + (f[n] - f[n - 1]);
+    if ((ax.kind == AX_CYL_R || ax.kind == AX_SPH_R) && !(ff[0] > 0.0))
+      return fail(DUST_EINVAL, "box %d: the inner radial ghost face must be > 0", ib);
+    if (ax.kind == AX_THETA && !(ff[0] > 0.0 && ff[n + 2] < M_PI))
+      return fail(DUST_EINVAL, "box %d: theta ghost faces must lie in (0, pi)", ib);
+    std::vector<double> iv(n + 2);
+    for (int k = -1; k <= n; ++k) {
+      double a = ff[k + 1], b = ff[k + 2];
+      double v;
+      switch (ax.kind) {
+        case AX_CYL_R: v = 0.5 * (b * b - a * a); break;
+        case AX_SPH_R: v = (b * b * b - a * a * a) / 3.0; break;
+        case AX_THETA: v = std::cos(a) - std::cos(b); break;
+        default: v = b - a;
+      }
+      iv[k + 1] = 1.0 / v;
+    }
+    dust_status_t st = upload_table(c, ff, &ax.faces);
+    if (st) return st;
+    st = upload_table(c, iv, &ax.ivol);
+    if (st) return st;
+    ncell *= n;
+  }
+  if (B.ax[0].bc_lo == DUST_BC_SHEAR) {
+    if (in.geom != DUST_CART || in.ndim != 3)
+      return fail(DUST_EUNSUPPORTED, "box %d: shear-periodic needs a 3-D Cartesian box", ib);
+    if (B.ax[1].bc_lo != DUST_BC_PERIODIC || !B.ax[0].uniform)
+      return fail(DUST_EINVAL, "box %d: shear-periodic x needs uniform x and periodic y", ib);
+  }
+  for (int d = 1; d < in.ndim; ++d)
+    if (B.ax[d].bc_lo == DUST_BC_SHEAR)
+      return fail(DUST_EINVAL, "box %d: shear-periodic only on axis 0", ib);
+  B.g0 = B.ax[0].n + 2;
+  B.g1 = B.ax[1].n + 2;
+  B.g2 = in.ndim > 2 ? B.ax[2].n + 2 : 1;
+  B.k_off = in.ndim > 2 ? 1 : 0;
+  B.cell_base = cell_base;
+  B.ncell = ncell;
+  B.store_base = store_base;
+  B.nstore = (int64_t)B.g0 * B.g1 * B.g2;
+  return DUST_OK;
+}
+
+template <typename TS> PView<TS> pview(const dust_particles_t* p) {
+  PView<TS> v;
+  v.cell = p->cell;
+  for (int d = 0; d < 3; ++d) {
+    v.off[d] = (TS*)p->off[d];
+    v.mom[d] = (TS*)p->mom[d];
+  }
+  v.drag = (TS*)p->drag;
+  v.mass = (TS*)p->mass;
+  v.species = p->species;
+  v.id = p->id;
+  v.n = p->n;
+  return v;
+}
+
+template <typename TS> FView<TS> fview(const dust_fields_t* f) {
+  FView<TS> v;
+  v.rho = (TS*)f->rho;
+  for (int d = 0; d < 3; ++d) v.vel[d] = (TS*)f->vel[d];
+  for (int d = 0; d < 4; ++d) v.dep[d] = (TS*)f->dep[d];
+  return v;
+}
+
+Forces forces_of(const dust_forces_t* f) {
+  Forces F{};
+  if (!f) return F;
+  F.kind = f->kind;
+  F.vertical_gravity = f->vertical_gravity;
+  F.Omega = f->Omega;
+  F.q = f->q;
+  F.GM = f->GM;
+  for (int d = 0; d < 3; ++d) F.g[d] = f->g[d];
+  return F;
+}
+
+dust_status_t check_ctx(void* ctx) {
+  if (!ctx) return fail(DUST_EINVAL, "ctx is NULL");
+  return DUST_OK;
+}
+
+dust_status_t check_forces(Ctx* c, const dust_forces_t* f) {
+  if (!f) return fail(DUST_EINVAL, "forces is NULL");
+  if (f->kind < DUST_FORCE_NONE || f->kind > DUST_FORCE_CONST)
+    return fail(DUST_EINVAL, "unknown force kind %d", f->kind);
+  for (auto& b : c->boxes) {
+    if (f->kind == DUST_FORCE_SHEARBOX && (b.geom != GEOM_CART || b.ndim != 3))
+      return fail(DUST_EUNSUPPORTED, "shearing-box forces need 3-D Cartesian boxes");
+    if (f->kind == DUST_FORCE_POINTMASS && b.geom == GEOM_CART)
+      return fail(DUST_EUNSUPPORTED, "point-mass gravity is for curvilinear boxes");
+    if (b.ax[0].bc_lo == BC_SHEAR && f->kind != DUST_FORCE_SHEARBOX)
+      return fail(DUST_EINVAL, "a shear-periodic box needs shearing-box forces");
+  }
+  if (c->drag_mode == DUST_DRAG_STOKES && !(f->GM > 0))
+    return fail(DUST_EINVAL, "Stokes-number drag needs GM > 0");
+  return DUST_OK;
+}
+
+dust_status_t check_particles(Ctx* c, const dust_particles_t* p, bool need_mom) {
+  if (!p) return fail(DUST_EINVAL, "particles is NULL");
+  if (p->n < 0 || p->n > 0x7fffffffLL) return fail(DUST_ESHAPE, "particle count %lld out of range", (long long)p->n);
+  if (p->n == 0) return DUST_OK;
+  if (!p->cell) return fail(DUST_EINVAL, "particles.cell is NULL");
+  int ndim = 0, nc = ctx_nc(c);
+  for (auto& b : c->boxes) ndim = std::max(ndim, b.ndim);
+  for (int d = 0; d < ndim; ++d)
+    if (!p->off[d]) return fail(DUST_EINVAL, "particles.off[%d] is NULL", d);
+  if (need_mom)
+    for (int d = 0; d < nc; ++d)
+      if (!p->mom[d]) return fail(DUST_EINVAL, "particles.mom[%d] is NULL", d);
+  return DUST_OK;
+}
+
+dust_status_t check_drag(Ctx* c, const dust_particles_t* p) {
+  if (p->n == 0) return DUST_OK;
+  if (c->drag_mode != DUST_DRAG_SPECIES && !p->drag)
+    return fail(DUST_EINVAL, "per-particle drag array required by the drag mode");
+  if (!p->mass && !c->have_mass_table)
+    return fail(DUST_EINVAL, "no per-particle mass and no species mass table");
+  return DUST_OK;
+}
+
+dust_status_t check_fields(Ctx* c, const dust_fields_t* f, bool gas, bool dep) {
+  if (!f) return fail(DUST_EINVAL, "fields is NULL");
+  int nc = ctx_nc(c);
+  if (gas) {
+    if (!f->rho) return fail(DUST_EINVAL, "fields.rho is NULL");
+    for (int d = 0; d < nc; ++d)
+      if (!f->vel[d]) return fail(DUST_EINVAL, "fields.vel[%d] is NULL", d);
+  }
+  if (dep)
+    for (int d = 0; d <= nc; ++d)
+      if (!f->dep[d]) return fail(DUST_EINVAL, "fields.dep[%d] is NULL", d);
+  return DUST_OK;
+}
+
+dust_status_t ensure_ws(Ctx* c, int64_t n) {
+  size_t need = (size_t)std::max<int64_t>(n, 1) * real_size(c) * 8;
+  if (need <= c->ws_bytes) return DUST_OK;
+  if (c->ws) HIP_TRY(hipFree(c->ws));
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  if (hipMalloc(&c->ws, need) != hipSuccess) return fail(DUST_ENOMEM, "workspace of %zu bytes", need);
+  c->ws_bytes = need;
+  return DUST_OK;
+}
+
+dust_status_t ensure_bin(Ctx* c, int64_t n) {
+  if ((size_t)n <= c->bin.cap_n && c->bin_mem) return DUST_OK;
+  if (c->bin_mem) HIP_TRY(hipFree(c->bin_mem));
+  c->bin_mem = nullptr;
+  int64_t nn = std::max<int64_t>(n, 1);
+  int64_t nblocks = (nn + 2047) / 2048;
+  size_t hist = (size_t)256 * nblocks;
+  size_t scan = bin_scan_tmp_words((int64_t)hist);
+  size_t bytes = (size_t)nn * 4 * 4 + (hist + scan + 64) * 4 + (size_t)nn * 8 + 256;
+  if (hipMalloc(&c->bin_mem, bytes) != hipSuccess) return fail(DUST_ENOMEM, "bin workspace of %zu bytes", bytes);
+  char* q = (char*)c->bin_mem;
+  auto take = [&](size_t b) { char* r = q; q += (b + 255) & ~(size_t)255; return r; };
+  c->bin.key[0] = (uint32_t*)take((size_t)nn * 4);
+  c->bin.key[1] = (uint32_t*)take((size_t)nn * 4);
+  c->bin.val[0] = (uint32_t*)take((size_t)nn * 4);
+  c->bin.val[1] = (uint32_t*)take((size_t)nn * 4);
+  c->bin.hist = (uint32_t*)take(hist * 4);
+  c->bin.scan_tmp = (uint32_t*)take(scan * 4);
+  c->bin.gather_tmp = take((size_t)nn * 8);
+  c->bin.cap_n = (size_t)nn;
+  return DUST_OK;
+}
+
+dust_status_t ensure_bin_start(Ctx* c) {
+  size_t need = (size_t)c->n_active + 1;
+  if (need <= c->bin_start_cap) return DUST_OK;
+  if (c->bin_start) HIP_TRY(hipFree(c->bin_start));
+  if (hipMalloc((void**)&c->bin_start, need * 8) != hipSuccess) return fail(DUST_ENOMEM, "bin starts");
+  c->bin_start_cap = need;
+  return DUST_OK;
+}
+
+// Apply perm (sorted slot -> input index, in bin.val[0]) to every particle array.
+dust_status_t apply_perm(Ctx* c, dust_particles_t* p, hipStream_t st) {
+  int64_t n = p->n;
+  int rs = (int)real_size(c);
+  const uint32_t* perm = c->bin.val[0];
+  void* tmp = c->bin.gather_tmp;
+  auto one = [&](void* a, int bytes) -> dust_status_t {
+    if (!a) return DUST_OK;
+    launch_permute(a, tmp, perm, n, bytes, st);
+    HIP_TRY(hipMemcpyAsync(a, tmp, (size_t)n * bytes, hipMemcpyDeviceToDevice, st));
+    return DUST_OK;
+  };
+  dust_status_t s;
+  if ((s = one(p->cell, 4))) return s;
+  for (int d = 0; d < 3; ++d) {
+    if ((s = one(p->off[d], rs))) return s;
+    if ((s = one(p->mom[d], rs))) return s;
+  }
+  if ((s = one(p->drag, rs))) return s;
+  if ((s = one(p->mass, rs))) return s;
+  if ((s = one(p->species, 1))) return s;
+  if ((s = one(p->id, 4))) return s;
+  return DUST_OK;
+}
+
+// ------------------------------------------------------------------ typed drivers
+
+template <typename TS, typename A>
+void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phases,
+              const TS* const vg[3], TS* const imp[4], DiagDev* dg, hipStream_t st) {
+  if (phases & DUST_PHASE_DRIFT1)
+    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
+  if (phases & DUST_PHASE_KICK)
+    launch_kick<TS, A>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, vg, imp, dg, st);
+  if (phases & DUST_PHASE_DRIFT2)
+    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
+}
+
+// One unfused step (time in c->tdev[0] at the start of the step).
+template <typename TS, typename A>
+void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces& F, double dt,
+                  int flags, hipStream_t st) {
+  int nc = ctx_nc(c);
+  int64_t n = pv.n;
+  TS* ws = (TS*)c->ws;
+  TS* vg[3] = {ws, ws + n, ws + 2 * n};
+  TS* imp[4] = {ws + 3 * n, ws + 4 * n, ws + 5 * n, ws + 6 * n};
+  for (int k = nc; k < 3; ++k) vg[k] = nullptr;
+  for (int k = nc + 1; k < 4; ++k) imp[k] = nullptr;
+  DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
+  DiagDev* dflags = c->diag;  // sticky flags always recorded
+  if (!(flags & DUST_STEP_NO_FILL))
+    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+  for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
+  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
+  launch_gather<TS, A>(pv, c->boxes_d, c->nbox, fv, nullptr, vg, dflags, st);
+  const TS* cvg[3] = {vg[0], vg[1], vg[2]};
+  launch_kick<TS, A>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, cvg, imp,
+                     dg ? dg : dflags, st);
+  const TS* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
+  launch_deposit<TS, A>(pv, c->boxes_d, c->nbox, fv, cimp, dflags, st);
+  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
+  if (dg)
+    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
+  for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+  if (flags & DUST_STEP_APPLY_FEEDBACK)
+    for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
+}
+
+template <typename TS, typename A>
+dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const FView<TS>& fv,
+                         const Forces& F, double dt, int flags, bool rebin, hipStream_t st) {
+  int nc = ctx_nc(c);
+  DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
+  if (rebin) {
+    launch_bin(p->cell, p->n, c->boxes_d, c->boxes.data(), c->nbox, c->n_active, DUST_BIN_TILE,
+               c->tile, c->bin, nullptr, c->bin_start, st);
+    dust_status_t s = apply_perm(c, p, st);
+    if (s) return s;
+  }
+  if (!(flags & DUST_STEP_NO_FILL))
+    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+  for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
+  bool prof = c->prof_used < c->prof_max;
+  if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
+  launch_fused<TS, A>(c->plan, pv, c->boxes_d, c->boxes.data(), c->nbox, fv, F, c->species,
+                      c->drag_mode, dt, c->tdev, c->bin_start, c->diag, dg != nullptr, st);
+  if (prof) {
+    HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
+    ++c->prof_used;
+  }
+  if (dg)
+    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
+  for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+  if (flags & DUST_STEP_APPLY_FEEDBACK)
+    for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
+  return DUST_OK;
+}
+
+template <typename TS, typename A>
+dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt, const Forces& F,
+                        int nsteps, int flags, hipStream_t st) {
+  PView<TS> pv = pview<TS>(p);
+  FView<TS> fv = fview<TS>(f);
+  int rebin_every = (flags >> 8) & 0xff;
+  if (rebin_every <= 0) rebin_every = 1;
+  for (int s = 0; s < nsteps; ++s) {
+    if (flags & DUST_STEP_FUSED) {
+      dust_status_t e = fused_step<TS, A>(c, p, pv, fv, F, dt, flags, s % rebin_every == 0, st);
+      if (e) return e;
+    } else {
+      unfused_step<TS, A>(c, pv, fv, F, dt, flags, st);
+    }
+    launch_advance_time(c->tdev, dt, st);
+    if (flags & DUST_STEP_DIAG) launch_count_step(c->diag, st);
+  }
+  return DUST_OK;
+}
+
+template <typename F>
+dust_status_t dispatch(Ctx* c, F&& fn) {
+  if (c->prec == DUST_F64) return fn((double)0, (double)0);
+  if (c->arith == DUST_ARITH_F32) return fn((float)0, (float)0);
+  return fn((float)0, (double)0);
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* dust_last_error(void) { return g_err.c_str(); }
+
+dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, int nbox, int32_t prec,
+                              int32_t drag_mode, const double* species_tau,
+                              const double* species_mass, int nspecies) {
+  g_err.clear();
+  if (!ctx) return fail(DUST_EINVAL, "ctx out-pointer is NULL");
+  *ctx = nullptr;
+  if (!boxes || nbox < 1 || nbox > 4096) return fail(DUST_EINVAL, "need 1..4096 boxes");
+  if (prec != DUST_F32 && prec != DUST_F64) return fail(DUST_EINVAL, "unknown precision %d", prec);
+  if (drag_mode < DUST_DRAG_TAU || drag_mode > DUST_DRAG_SPECIES)
+    return fail(DUST_EINVAL, "unknown drag mode %d", drag_mode);
+  if (nspecies < 0 || nspecies > DUST_MAX_SPECIES)
+    return fail(DUST_EINVAL, "nspecies must be 0..%d", DUST_MAX_SPECIES);
+  if (drag_mode == DUST_DRAG_SPECIES && (nspecies < 1 || !species_tau))
+    return fail(DUST_EINVAL, "species drag needs a tau table");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(DUST_EINVAL, "device %d of %d", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  Ctx* c = new Ctx();
+  c->device = device;
+  c->prec = prec;
+  c->drag_mode = drag_mode;
+  c->species.n = nspecies > 0 ? nspecies : 1;
+  for (int s = 0; s < DUST_MAX_SPECIES; ++s) {
+    c->species.tau[s] = (species_tau && s < nspecies) ? species_tau[s] : INFINITY;
+    c->species.mass[s] = (species_mass && s < nspecies) ? species_mass[s] : 0.0;
+  }
+  c->have_mass_table = species_mass != nullptr && nspecies > 0;
+  if (species_tau)
+    for (int s = 0; s < nspecies; ++s)
+      if (!(species_tau[s] > 0)) {
+        delete c;
+        return fail(DUST_EINVAL, "species %d: tau must be > 0 (or +inf)", s);
+      }
+  int64_t cell_base = 0, store_base = 0;
+  c->nbox = nbox;
+  c->boxes.resize(nbox);
+  c->store_off.resize(nbox + 1);
+  for (int b = 0; b < nbox; ++b) {
+    dust_status_t s = build_box(c, boxes[b], b, cell_base, store_base, c->boxes[b]);
+    if (s) {
+      std::string keep = g_err;
+      dust_ctx_destroy(c);
+      g_err = keep;
+      return s;
+    }
+    c->store_off[b] = store_base;
+    cell_base += c->boxes[b].ncell;
+    store_base += c->boxes[b].nstore;
+  }
+  c->store_off[nbox] = store_base;
+  c->n_active = cell_base;
+  c->n_stored = store_base;
+  if (cell_base >= 0x7fffffffLL) {
+    dust_ctx_destroy(c);
+    return fail(DUST_ESHAPE, "more than 2^31-1 active cells");
+  }
+  if (hipMalloc((void**)&c->boxes_d, sizeof(Box) * nbox) != hipSuccess ||
+      hipMalloc((void**)&c->diag, sizeof(DiagDev)) != hipSuccess ||
+      hipMalloc((void**)&c->tdev, 64) != hipSuccess) {
+    dust_ctx_destroy(c);
+    return fail(DUST_ENOMEM, "context tables");
+  }
+  if (hipMemcpy(c->boxes_d, c->boxes.data(), sizeof(Box) * nbox, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->diag, 0, sizeof(DiagDev)) != hipSuccess || hipMemset(c->tdev, 0, 64) != hipSuccess) {
+    dust_ctx_destroy(c);
+    return fail(DUST_EDEVICE, "context upload");
+  }
+  fused_plan_init(c->plan, c->boxes.data(), nbox, c->tile, c->slack);
+  *ctx = c;
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_destroy(void* ctx) {
+  if (!ctx) return DUST_OK;
+  Ctx* c = (Ctx*)ctx;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  for (auto e : c->prof_ev) hipEventDestroy(e);
+  for (void* p : c->tables) hipFree(p);
+  if (c->boxes_d) hipFree(c->boxes_d);
+  if (c->diag) hipFree(c->diag);
+  if (c->tdev) hipFree(c->tdev);
+  if (c->ws) hipFree(c->ws);
+  if (c->bin_mem) hipFree(c->bin_mem);
+  if (c->bin_start) hipFree(c->bin_start);
+  fused_plan_free(c->plan);
+  delete c;
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_set_arith(void* ctx, int32_t arith) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  if (arith != DUST_ARITH_F64 && arith != DUST_ARITH_F32) return fail(DUST_EINVAL, "unknown arith %d", arith);
+  ((Ctx*)ctx)->arith = arith;
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_set_tile(void* ctx, int32_t tx, int32_t ty, int32_t tz, int32_t slack) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  int32_t t[3] = {tx, ty, tz};
+  for (int d = 0; d < 3; ++d) {
+    if (t[d] < 0 || t[d] > 64) return fail(DUST_EINVAL, "tile extent %d out of 0..64", t[d]);
+    if (t[d] > 0) c->tile.t[d] = t[d];
+  }
+  if (slack < 0 || slack > 4) return fail(DUST_EINVAL, "slack %d out of 0..4", slack);
+  if (slack > 0) c->slack = slack;
+  dust_status_t s = fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
+  if (s) return fail(s, "tile %dx%dx%d with slack %d does not fit the LDS", c->tile.t[0],
+                     c->tile.t[1], c->tile.t[2], c->slack);
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_set_profile(void* ctx, int32_t max_launches) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  if (max_launches < 0 || max_launches > 100000) return fail(DUST_EINVAL, "max_launches out of range");
+  HIP_TRY(hipSetDevice(c->device));
+  for (auto e : c->prof_ev) hipEventDestroy(e);
+  c->prof_ev.clear();
+  c->prof_max = 0;
+  c->prof_used = 0;
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    c->prof_ev.push_back(e);
+  }
+  c->prof_max = max_launches;
+  // graphs captured before carry no event nodes
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_profile(void* ctx, float* ms_out, int32_t max_out, int32_t* count_out) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->last_stream));
+  int n = std::min(c->prof_used, max_out);
+  for (int i = 0; i < n; ++i) HIP_TRY(hipEventElapsedTime(&ms_out[i], c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+  if (count_out) *count_out = n;
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_grid_size(void* ctx, int64_t* n_stored, int64_t* n_active, int64_t* box_store_offset) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  if (n_stored) *n_stored = c->n_stored;
+  if (n_active) *n_active = c->n_active;
+  if (box_store_offset)
+    for (int b = 0; b <= c->nbox; ++b) box_store_offset[b] = c->store_off[b];
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_status(void* ctx, dust_diag_t* out) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->last_stream));
+  DiagDev d;
+  HIP_TRY(hipMemcpy(&d, c->diag, sizeof(d), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(c->diag, 0, sizeof(DiagDev)));
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    for (int k = 0; k < 3; ++k) {
+      out->p_part[k] = d.p_part[k];
+      out->p_grid[k] = d.p_grid[k];
+    }
+    out->e_part = d.e_part;
+    out->e_grid = d.e_grid;
+    out->sum_abs_j = d.sum_abs_j;
+    double m;
+    memcpy(&m, &d.max_cells_bits, 8);
+    out->max_cells_per_step = m;
+    out->n_removed = (int64_t)d.n_removed;
+    out->n_fallback = (int64_t)d.n_fallback;
+    out->flags = (int32_t)d.flags;
+    out->steps = (int32_t)d.steps;
+  }
+  return DUST_OK;
+}
+
+dust_status_t dust_bin(void* ctx, dust_particles_t* p, int32_t key_mode, int32_t* perm_out,
+                       int64_t* bin_start_out, int apply_permutation, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  if (key_mode != DUST_BIN_CELL && key_mode != DUST_BIN_TILE) return fail(DUST_EINVAL, "unknown key mode");
+  if (!p) return fail(DUST_EINVAL, "particles is NULL");
+  if (p->n < 0 || p->n > 0x7fffffffLL) return fail(DUST_ESHAPE, "particle count out of range");
+  if (p->n > 0 && !p->cell) return fail(DUST_EINVAL, "particles.cell is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  dust_status_t s = ensure_bin(c, p->n);
+  if (s) return s;
+  c->last_stream = st;
+  launch_bin(p->cell, p->n, c->boxes_d, c->boxes.data(), c->nbox, c->n_active, key_mode, c->tile,
+             c->bin, perm_out, bin_start_out, st);
+  if (apply_permutation && p->n > 0) return apply_perm(c, p, st);
+  HIP_TRY(hipGetLastError());
+  return DUST_OK;
+}
+
+dust_status_t dust_fill_ghosts(void* ctx, dust_fields_t* f, const dust_forces_t* frc, double t, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_fields(c, f, true, false)) || (s = check_forces(c, frc))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  launch_set_time(c->tdev, t, st);
+  Forces F = forces_of(frc);
+  return dispatch(c, [&](auto ts, auto) -> dust_status_t {
+    using TS = decltype(ts);
+    FView<TS> fv = fview<TS>(f);
+    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.0, fv, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
+dust_status_t dust_fold_ghosts(void* ctx, dust_fields_t* f, const dust_forces_t* frc, double t, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_fields(c, f, false, true)) || (s = check_forces(c, frc))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  launch_set_time(c->tdev, t, st);
+  Forces F = forces_of(frc);
+  return dispatch(c, [&](auto ts, auto) -> dust_status_t {
+    using TS = decltype(ts);
+    FView<TS> fv = fview<TS>(f);
+    for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.0, fv, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
+dust_status_t dust_gather(void* ctx, const dust_particles_t* p, const dust_fields_t* f, void* rho_p,
+                          void* vg_p[3], void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, false)) || (s = check_fields(c, f, true, false))) return s;
+  int nc = ctx_nc(c);
+  if (!vg_p) return fail(DUST_EINVAL, "vg_p is NULL");
+  for (int k = 0; k < nc; ++k)
+    if (p->n > 0 && !vg_p[k]) return fail(DUST_EINVAL, "vg_p[%d] is NULL", k);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+    using TS = decltype(ts);
+    using A = decltype(ta);
+    TS* vg[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < nc; ++k) vg[k] = (TS*)vg_p[k];
+    launch_gather<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
+dust_status_t dust_push_expmid(void* ctx, dust_particles_t* p, const void* const vg_p[3], double dt,
+                               const dust_forces_t* frc, int32_t phases, void* impulse[4], void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, true)) || (s = check_forces(c, frc))) return s;
+  if (!std::isfinite(dt)) return fail(DUST_EINVAL, "dt not finite");
+  if (phases & ~(DUST_PHASE_DRIFT1 | DUST_PHASE_KICK | DUST_PHASE_DRIFT2))
+    return fail(DUST_EINVAL, "unknown phase bits");
+  int nc = ctx_nc(c);
+  if (phases & DUST_PHASE_KICK) {
+    if ((s = check_drag(c, p))) return s;
+    if (!vg_p) return fail(DUST_EINVAL, "vg_p is NULL");
+    for (int k = 0; k < nc; ++k)
+      if (p->n > 0 && !vg_p[k]) return fail(DUST_EINVAL, "vg_p[%d] is NULL", k);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  launch_set_time(c->tdev, frc->t, st);
+  Forces F = forces_of(frc);
+  return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+    using TS = decltype(ts);
+    using A = decltype(ta);
+    const TS* vg[3] = {nullptr, nullptr, nullptr};
+    TS* imp[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (vg_p)
+      for (int k = 0; k < nc; ++k) vg[k] = (const TS*)vg_p[k];
+    if (impulse)
+      for (int k = 0; k <= nc; ++k) imp[k] = (TS*)impulse[k];
+    run_push<TS, A>(c, pview<TS>(p), F, dt, phases, vg, imp, c->diag, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
+dust_status_t dust_deposit(void* ctx, const dust_particles_t* p, const void* const impulse[4],
+                           dust_fields_t* f, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, false)) || (s = check_fields(c, f, false, true))) return s;
+  int nc = ctx_nc(c);
+  if (!impulse) return fail(DUST_EINVAL, "impulse is NULL");
+  for (int k = 0; k <= nc; ++k)
+    if (p->n > 0 && !impulse[k]) return fail(DUST_EINVAL, "impulse[%d] is NULL", k);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+    using TS = decltype(ts);
+    using A = decltype(ta);
+    const TS* imp[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k <= nc; ++k) imp[k] = (const TS*)impulse[k];
+    launch_deposit<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), imp, c->diag, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
+dust_status_t dust_apply_feedback(void* ctx, dust_fields_t* f, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_fields(c, f, true, true))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  return dispatch(c, [&](auto ts, auto) -> dust_status_t {
+    using TS = decltype(ts);
+    for (auto& B : c->boxes) launch_feedback<TS>(B, fview<TS>(f), st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
+dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double dt,
+                        const dust_forces_t* frc, int32_t nsteps, int32_t flags, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, true)) || (s = check_fields(c, f, true, true)) ||
+      (s = check_forces(c, frc)) || (s = check_drag(c, p)))
+    return s;
+  if (!std::isfinite(dt)) return fail(DUST_EINVAL, "dt not finite");
+  if (nsteps < 0) return fail(DUST_EINVAL, "nsteps < 0");
+  if (flags & ~0xff1f) return fail(DUST_EINVAL, "unknown step flag bits");
+  if (nsteps == 0) return DUST_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  if ((s = ensure_ws(c, p->n))) return s;
+  if (flags & DUST_STEP_FUSED) {
+    if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c))) return s;
+    if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
+    if (c->plan.lds_cells * 7 * real_size(c) > 160 * 1024)
+      return fail(DUST_EUNSUPPORTED, "fused tile window needs more than 160 KiB of LDS");
+  }
+  Forces F = forces_of(frc);
+  launch_set_time(c->tdev, frc->t, st);
+  auto body = [&]() -> dust_status_t {
+    c->prof_used = 0;
+    return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+      using TS = decltype(ts);
+      using A = decltype(ta);
+      return run_steps<TS, A>(c, p, f, dt, F, nsteps, flags, st);
+    });
+  };
+  if (!(flags & DUST_STEP_GRAPH)) {
+    s = body();
+    if (s) return s;
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  }
+  // graph: keyed by every argument except the start time (read on device)
+  GraphKey key;
+  auto put = [&](const void* ptr, size_t n) {
+    const unsigned char* b = (const unsigned char*)ptr;
+    key.bytes.insert(key.bytes.end(), b, b + n);
+  };
+  put(p, sizeof(*p));
+  put(f, sizeof(*f));
+  put(&dt, sizeof(dt));
+  put(&F, sizeof(F));
+  put(&nsteps, sizeof(nsteps));
+  put(&flags, sizeof(flags));
+  put(&st, sizeof(st));
+  put(&c->arith, sizeof(c->arith));
+  put(&c->tile, sizeof(c->tile));
+  put(&c->prof_max, sizeof(c->prof_max));
+  if (!(c->graph_exec && key == c->graph_key)) {
+    if (c->graph_exec) {
+      hipGraphExecDestroy(c->graph_exec);
+      c->graph_exec = nullptr;
+    }
+    if (c->graph) {
+      hipGraphDestroy(c->graph);
+      c->graph = nullptr;
+    }
+    hipStream_t cap = st;
+    bool own = false;
+    if (cap == nullptr) {
+      HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      own = true;
+      HIP_TRY(hipStreamSynchronize(nullptr));
+    }
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipStream_t saved = st;
+    st = cap;
+    s = body();
+    st = saved;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    if (s) {
+      if (g) hipGraphDestroy(g);
+      if (own) hipStreamDestroy(cap);
+      return s;
+    }
+    if (e != hipSuccess) {
+      if (own) hipStreamDestroy(cap);
+      return fail(DUST_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    c->graph = g;
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (own) hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(DUST_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    c->graph_key = key;
+  }
+  HIP_TRY(hipGraphLaunch(c->graph_exec, st));
+  return DUST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,453 @@
+// Per-particle device arithmetic of the dust hot path (gfx950).
+//
+// Templates: TS = storage type of reals (float or double), A = arithmetic
+// type of the per-particle math (double by default also for float storage:
+// gfx950 issues FP64 vector FMAs at the rate of unpacked FP32 ones, and the
+// slip v_g - v_p that the drag acts on is often far below FP32 resolution of
+// the velocities themselves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dust_types.h"
+
+namespace dust {
+
+// ---------------------------------------------------------------- math helpers
+
+template <typename A> __device__ __forceinline__ A dsin(A x);
+template <> __device__ __forceinline__ double dsin<double>(double x) { return sin(x); }
+template <> __device__ __forceinline__ float dsin<float>(float x) { return sinf(x); }
+template <typename A> __device__ __forceinline__ A dcos(A x);
+template <> __device__ __forceinline__ double dcos<double>(double x) { return cos(x); }
+template <> __device__ __forceinline__ float dcos<float>(float x) { return cosf(x); }
+template <typename A> __device__ __forceinline__ A dsqrt(A x);
+template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
+template <typename A> __device__ __forceinline__ A dexpm1(A x);
+template <> __device__ __forceinline__ double dexpm1<double>(double x) { return expm1(x); }
+template <> __device__ __forceinline__ float dexpm1<float>(float x) { return expm1f(x); }
+template <typename A> __device__ __forceinline__ A dfloor(A x);
+template <> __device__ __forceinline__ double dfloor<double>(double x) { return floor(x); }
+template <> __device__ __forceinline__ float dfloor<float>(float x) { return floorf(x); }
+
+// h - sin h without cancellation (series for small h).
+template <typename A> __device__ __forceinline__ A h_minus_sin(A h) {
+  if (h < A(0.5) && h > A(-0.5)) {
+    A h2 = h * h;
+    A s = A(1) - h2 / A(210);
+    s = A(1) - h2 / A(156) * s;
+    s = A(1) - h2 / A(110) * s;
+    s = A(1) - h2 / A(72) * s;
+    s = A(1) - h2 / A(42) * s;
+    s = A(1) - h2 / A(20) * s;
+    return h * h2 / A(6) * s;
+  }
+  return h - dsin(h);
+}
+
+// Drag propagator terms for h = dt/tau >= 0 (Eq. h1, phi1 of Sec. 3.2.2):
+//   c   = 1 - e^{-h}               (= h1/tau), from expm1
+//   psi = phi1(-h) - 1 = (h1 - dt)/dt, series for small h
+// so that h1 = dt (1 + psi) and the kick is written in increments.
+template <typename A> __device__ __forceinline__ void propagator(A h, A& c, A& psi) {
+  if (h == A(0)) {
+    c = A(0);
+    psi = A(0);
+    return;
+  }
+  c = -dexpm1(-h);
+  if (h < A(0.25)) {
+    A s = A(1) - h / A(14);
+    s = A(1) - h / A(13) * s;
+    s = A(1) - h / A(12) * s;
+    s = A(1) - h / A(11) * s;
+    s = A(1) - h / A(10) * s;
+    s = A(1) - h / A(9) * s;
+    s = A(1) - h / A(8) * s;
+    s = A(1) - h / A(7) * s;
+    s = A(1) - h / A(6) * s;
+    s = A(1) - h / A(5) * s;
+    s = A(1) - h / A(4) * s;
+    s = A(1) - h / A(3) * s;
+    psi = -h / A(2) * s;
+  } else {
+    psi = c / h - A(1);
+  }
+}
+
+// ---------------------------------------------------------------- geometry
+
+// Coordinate of the centre and width of cell i (i in [-1, n]) on an axis.
+template <typename A> __device__ __forceinline__ A cell_centre(const Axis& ax, int i) {
+  if (ax.uniform) return A(ax.lo + (double(i) + 0.5) * ax.d);
+  return A(0.5 * (ax.faces[i + 1] + ax.faces[i + 2]));
+}
+template <typename A> __device__ __forceinline__ A cell_width(const Axis& ax, int i) {
+  if (ax.uniform) return A(ax.d);
+  return A(ax.faces[i + 2] - ax.faces[i + 1]);
+}
+
+// Weights of cells i-1, i, i+1 along one axis for a particle at offset delta
+// (host-cell widths) from the centre of host cell i.  The shape spans the
+// host cell's width; what lies beyond the host cell's faces goes to the
+// neighbour on that side, so sum w = 1 up to rounding and the middle weight
+// is 1 - w[0] - w[2].
+template <typename A>
+__device__ __forceinline__ void axis_weights(const Axis& ax, int i, A delta, A w[3]) {
+  const A half = A(0.5);
+  if (ax.kind == AX_PLAIN) {
+    if (ax.shape == SHAPE_CIC) {
+      w[0] = delta < A(0) ? -delta : A(0);
+      w[2] = delta > A(0) ? delta : A(0);
+    } else {
+      A m = half - delta, p = half + delta;
+      w[0] = half * m * m;
+      w[2] = half * p * p;
+    }
+  } else if (ax.kind == AX_CYL_R) {
+    // Eq. CIC_cylindrical / TSC_cylindrical, nu = R_i / Delta R_i
+    A nu = cell_centre<A>(ax, i) / cell_width<A>(ax, i);
+    if (ax.shape == SHAPE_CIC) {
+      A den = A(2) * (delta + nu);
+      w[0] = delta < A(0) ? (delta + A(2) * nu - A(1)) / den * (-delta) : A(0);
+      w[2] = delta > A(0) ? (delta + A(2) * nu + A(1)) / den * delta : A(0);
+    } else {
+      A den = A(3) * (delta + nu);
+      A m = half - delta, p = half + delta;
+      w[0] = (delta + A(3) * nu - A(2)) / den * half * m * m;
+      w[2] = (delta + A(3) * nu + A(2)) / den * half * p * p;
+    }
+  } else if (ax.kind == AX_SPH_R) {
+    // App. C: Eq. CIC_spherical_r / TSC_spherical_r
+    A nu = cell_centre<A>(ax, i) / cell_width<A>(ax, i);
+    A dn = delta + nu;
+    if (ax.shape == SHAPE_CIC) {
+      A den = A(12) * dn * dn + A(1);
+      if (delta < A(0)) {
+        A t = A(2) * delta + A(3) * nu - A(1.5), u = nu - half;
+        w[0] = (t * t + A(3) * u * u) / den * (-delta);
+        w[2] = A(0);
+      } else {
+        A t = A(2) * delta + A(3) * nu + A(1.5), u = nu + half;
+        w[2] = (t * t + A(3) * u * u) / den * delta;
+        w[0] = A(0);
+      }
+    } else {
+      A den = A(6) * dn * dn + A(1);
+      A m = half - delta, p = half + delta;
+      A d2 = delta * delta, n2 = A(6) * nu * nu;
+      w[0] = (d2 + (A(4) * nu - A(3)) * delta + n2 - A(8) * nu + A(2.75)) / den * half * m * m;
+      w[2] = (d2 + (A(4) * nu + A(3)) * delta + n2 + A(8) * nu + A(2.75)) / den * half * p * p;
+    }
+  } else {
+    // theta axis, metric sin(theta): App. C Eq. CIC_spherical_theta (minus
+    // branch sign corrected) in product form, and the TSC analogue from the
+    // antiderivative of (1 -+ (t - t_p)/D) sin t.
+    A tc = cell_centre<A>(ax, i), D = cell_width<A>(ax, i);
+    A tp = tc + delta * D;
+    A sp = dsin(tp), sh = dsin(half * D);
+    if (ax.shape == SHAPE_CIC) {
+      A den = sp * sh;
+      if (delta > A(0)) {
+        w[2] = dsin(tc + half * D + half * delta * D) * dsin(half * delta * D) / den;
+        w[0] = A(0);
+      } else {
+        w[0] = dsin(tc - half * D + half * delta * D) * dsin(-half * delta * D) / den;
+        w[2] = A(0);
+      }
+    } else {
+      A den = A(4) * sp * sh * sh;
+      A hp = (half + delta) * D, hm = (half - delta) * D;
+      A Ap = tc + half * D, Bm = tc - half * D;
+      A s1 = dsin(half * hp), s2 = dsin(half * hm);
+      w[2] = (dcos(Ap) * h_minus_sin(hp) + A(2) * dsin(Ap) * s1 * s1) / den;
+      w[0] = (-dcos(Bm) * h_minus_sin(hm) + A(2) * dsin(Bm) * s2 * s2) / den;
+    }
+  }
+  w[1] = A(1) - w[0] - w[2];
+}
+
+// Stored (ghosted) linear index of active-grid cell (i, j, k), each in [-1, n].
+__device__ __forceinline__ int64_t stored_index(const Box& b, int i, int j, int k) {
+  return b.store_base + (int64_t)(i + 1) +
+         (int64_t)b.g0 * ((int64_t)(j + 1) + (int64_t)b.g1 * (int64_t)(k + b.k_off));
+}
+
+// Inverse cell volume of cell (i, j, k) (separable per-axis factors).
+__device__ __forceinline__ double inv_volume(const Box& b, int i, int j, int k) {
+  double v = b.ax[0].ivol[i + 1] * b.ax[1].ivol[j + 1];
+  if (b.ndim > 2) v *= b.ax[2].ivol[k + 1];
+  return v;
+}
+
+// Box of a global cell id (boxes sorted by cell_base).
+__device__ __forceinline__ int find_box(const Box* boxes, int nbox, int64_t cell) {
+  int b = 0;
+  while (b + 1 < nbox && cell >= boxes[b + 1].cell_base) ++b;
+  return b;
+}
+
+__device__ __forceinline__ void unravel(const Box& b, int64_t local, int idx[3]) {
+  int n0 = b.ax[0].n, n1 = b.ax[1].n;
+  idx[0] = (int)(local % n0);
+  int64_t r = local / n0;
+  idx[1] = (int)(r % n1);
+  idx[2] = b.ndim > 2 ? (int)(r / n1) : 0;
+}
+
+__device__ __forceinline__ int64_t ravel(const Box& b, const int idx[3]) {
+  int64_t c = idx[0] + (int64_t)b.ax[0].n * idx[1];
+  if (b.ndim > 2) c += (int64_t)b.ax[0].n * b.ax[1].n * idx[2];
+  return c;
+}
+
+// ---------------------------------------------------------------- motion
+
+// Move along axis d by a coordinate increment dxi.  Returns the new cell
+// index, which may fall outside [0, n) (the caller applies the boundary).
+template <typename A>
+__device__ __forceinline__ int move_axis(const Axis& ax, int i, A& delta, A dxi) {
+  const A half = A(0.5);
+  if (ax.uniform) {
+    A dn = delta + dxi * A(ax.inv_d);
+    if (dn >= half || dn < -half) {
+      A k = dfloor(dn + half);
+      dn -= k;
+      i += (int)k;
+      if (dn >= half) { dn -= A(1); ++i; }
+      else if (dn < -half) { dn += A(1); --i; }
+    }
+    delta = dn;
+    return i;
+  }
+  A dn = delta + dxi / cell_width<A>(ax, i);
+  if (dn < half && dn >= -half) {
+    delta = dn;
+    return i;
+  }
+  // FP64 crossing test against the face table (non-uniform axis)
+  double xi = 0.5 * (ax.faces[i + 1] + ax.faces[i + 2]) +
+              double(delta) * (ax.faces[i + 2] - ax.faces[i + 1]) + double(dxi);
+  while (i < ax.n && xi >= ax.faces[i + 2]) ++i;
+  while (i >= 0 && xi < ax.faces[i + 1]) --i;
+  if (i >= 0 && i < ax.n) {
+    double c = 0.5 * (ax.faces[i + 1] + ax.faces[i + 2]), w = ax.faces[i + 2] - ax.faces[i + 1];
+    A dl = A((xi - c) / w);
+    if (dl >= half) { dl -= A(1); ++i; }  // rounding onto the upper face
+    if (dl < -half) dl = -half;
+    delta = dl;
+  }
+  return i;
+}
+
+// Apply a periodic or open boundary to axis d.  Returns false if removed.
+template <typename A>
+__device__ __forceinline__ bool wrap_plain(const Axis& ax, int& i) {
+  if (i >= 0 && i < ax.n) return true;
+  int bc = i < 0 ? ax.bc_lo : ax.bc_hi;
+  if (bc == BC_OPEN) return false;
+  i %= ax.n;
+  if (i < 0) i += ax.n;
+  return true;
+}
+
+// Shear-periodic image across the x faces at time t (Sec. 2.1): x -/+ L_x,
+// y +/- q Omega L_x t (as a shift in y-cells), v_y +/- q Omega L_x.
+template <typename A>
+__device__ __forceinline__ void shear_image(const Box& b, const Forces& f, double t, int idx[3],
+                                            A off[3], A mom[3]) {
+  const Axis& ax = b.ax[0];
+  if (idx[0] >= 0 && idx[0] < ax.n) return;
+  double u = f.q * f.Omega * ax.L;
+  double s = fmod(u * t / b.ax[1].d, (double)b.ax[1].n);
+  if (s < 0) s += b.ax[1].n;
+  double sfl = floor(s);
+  int si = (int)sfl;
+  A sf = A(s - sfl);
+  int sign = idx[0] >= ax.n ? 1 : -1;
+  idx[0] -= sign * ax.n;
+  off[1] += A(sign) * sf;
+  idx[1] += sign * si;
+  if (off[1] >= A(0.5)) { off[1] -= A(1); ++idx[1]; }
+  else if (off[1] < A(-0.5)) { off[1] += A(1); --idx[1]; }
+  idx[1] %= b.ax[1].n;
+  if (idx[1] < 0) idx[1] += b.ax[1].n;
+  mom[1] += A(sign) * A(u);
+}
+
+// Drift by a half step h (Eq. exp_midpoint; Eq. drift1_cylindrical,
+// drift2_cylindrical; App. B.2).  `first`: the angles use the radius (and
+// theta) already moved to n+1/2; otherwise all metric factors are those at
+// the start of this half drift.  t_after: time the boundary rules use.
+// Returns false if the particle left through an open face.
+template <typename A>
+__device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first, A h,
+                                      double t_after, int idx[3], A off[3], A mom[3]) {
+  if (b.geom == GEOM_CART) {
+    A dx[3] = {h * mom[0], h * mom[1], b.ndim > 2 ? h * mom[2] : A(0)};
+    for (int d = 0; d < b.ndim; ++d) idx[d] = move_axis<A>(b.ax[d], idx[d], off[d], dx[d]);
+    if (b.ax[0].bc_lo == BC_SHEAR) shear_image<A>(b, f, t_after, idx, off, mom);
+    for (int d = 0; d < b.ndim; ++d)
+      if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
+    return true;
+  }
+  if (b.geom == GEOM_CYL) {
+    if (first) {
+      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+      if (!wrap_plain<A>(b.ax[0], idx[0])) return false;
+      A R = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (R * R));
+      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2]);
+    } else {
+      A R = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (R * R));
+      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2]);
+    }
+  } else {
+    if (first) {
+      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+      if (!wrap_plain<A>(b.ax[0], idx[0])) return false;
+      A r = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (r * r));
+      if (!wrap_plain<A>(b.ax[1], idx[1])) return false;
+      A th = cell_centre<A>(b.ax[1], idx[1]) + off[1] * cell_width<A>(b.ax[1], idx[1]);
+      A s = dsin(th);
+      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2] / (r * r * s * s));
+    } else {
+      A r = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
+      A th = cell_centre<A>(b.ax[1], idx[1]) + off[1] * cell_width<A>(b.ax[1], idx[1]);
+      A s = dsin(th);
+      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2] / (r * r * s * s));
+      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (r * r));
+      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+    }
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------- kick
+
+// Position quantities the kick needs, at x^{n+1/2}.
+template <typename A> struct Where {
+  A x[3];  // coordinates (x,y,z) / (R,phi,z) / (r,theta,phi)
+  A sc[3]; // canonical = physical * sc: 1, R, r, r sin(theta)
+};
+
+template <typename A>
+__device__ __forceinline__ void where(const Box& b, const int idx[3], const A off[3], Where<A>& w) {
+  for (int d = 0; d < 3; ++d) {
+    w.x[d] = d < b.ndim ? cell_centre<A>(b.ax[d], idx[d]) + off[d] * cell_width<A>(b.ax[d], idx[d])
+                        : A(0);
+    w.sc[d] = A(1);
+  }
+  if (b.geom == GEOM_CYL) w.sc[1] = w.x[0];
+  if (b.geom == GEOM_SPH) {
+    w.sc[1] = w.x[0];
+    w.sc[2] = w.x[0] * dsin(w.x[1]);
+  }
+}
+
+// Result of one kick: momentum increments, drag impulse per unit mass
+// J/m = c s + dt psi a (s = p_g - p, the slip; a = the non-drag part of G as
+// evaluated in the kick), and the energy e/m = v_bar . (J/m) (physical).
+template <typename A> struct KickOut {
+  A dp[3];
+  A j[3];
+  A e;
+  A cells;  // max_d |v_bar_d| dt / dl_d
+};
+
+// Exponential-midpoint kick (Eq. exp_midpoint with A = -diag(1/tau);
+// App. A Eq. standard_SB_exp_midpoint; App. B.1 Eq. kick_cylindrical; App.
+// B.2) for canonical momenta p and gas momentum pg (canonical), inverse
+// stopping time it.
+template <typename A>
+__device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
+                                     const Where<A>& w, const A p[3], const A pg[3],
+                                     KickOut<A>& o) {
+  A c, psi;
+  propagator<A>(dt * it, c, psi);
+  A h1 = dt + dt * psi;
+  A s[3] = {pg[0] - p[0], pg[1] - p[1], pg[2] - p[2]};
+  A a[3] = {A(0), A(0), A(0)};
+  const int nc = b.geom == GEOM_CART ? b.ndim : 3;
+  if (b.geom == GEOM_CART) {
+    if (f.kind == FORCE_SHEARBOX) {
+      // R dp = c s + h1 a(x, p^n), R = I - W J_rot, W = Omega h1
+      A Om = A(f.Omega), q = A(f.q);
+      A gz = f.vertical_gravity ? -Om * Om * w.x[2] : A(0);
+      A an[3] = {A(2) * Om * (p[1] + q * Om * w.x[0]), A(-2) * Om * p[0], gz};
+      A r[3] = {c * s[0] + h1 * an[0], c * s[1] + h1 * an[1], c * s[2] + h1 * an[2]};
+      A W = Om * h1, den = A(1) / (A(1) + W * W);
+      o.dp[0] = (r[0] + W * r[1]) * den;
+      o.dp[1] = (r[1] - W * r[0]) * den;
+      o.dp[2] = r[2];
+      a[0] = an[0] + Om * o.dp[1];
+      a[1] = an[1] - Om * o.dp[0];
+      a[2] = gz;
+    } else {
+      for (int k = 0; k < nc; ++k) {
+        a[k] = f.kind == FORCE_CONST ? A(f.g[k]) : A(0);
+        o.dp[k] = c * s[k] + h1 * a[k];
+      }
+      if (nc < 3) o.dp[2] = A(0);
+    }
+  } else if (b.geom == GEOM_CYL) {
+    A R = w.x[0], z = w.x[2];
+    A gR = A(0), gz = A(0);
+    if (f.kind == FORCE_POINTMASS) {
+      A r2 = R * R + z * z;
+      A ir3 = A(f.GM) / (r2 * dsqrt(r2));
+      gR = -R * ir3;
+      gz = -z * ir3;
+    }
+    // order v_z, l_phi, v_R
+    a[2] = gz;
+    o.dp[2] = c * s[2] + h1 * a[2];
+    a[1] = A(0);  // R g_phi, axisymmetric potential
+    o.dp[1] = c * s[1];
+    A l0 = p[1], l1 = p[1] + o.dp[1];
+    a[0] = A(0.5) * (l0 * l0 + l1 * l1) / (R * R * R) + gR;
+    o.dp[0] = c * s[0] + h1 * a[0];
+  } else {
+    A r = w.x[0], th = w.x[1];
+    A st = dsin(th), ct = dcos(th);
+    A gr = f.kind == FORCE_POINTMASS ? A(-f.GM) / (r * r) : A(0);
+    // order l_phi, l_theta, v_r; the second midpoint average is that of l_theta^2
+    a[2] = A(0);  // r sin(theta) g_phi
+    o.dp[2] = c * s[2];
+    A lp0 = p[2], lp1 = p[2] + o.dp[2];
+    A lp2 = A(0.5) * (lp0 * lp0 + lp1 * lp1);
+    a[1] = lp2 * ct / (r * r * st * st * st);  // + r g_theta = 0
+    o.dp[1] = c * s[1] + h1 * a[1];
+    A lt0 = p[1], lt1 = p[1] + o.dp[1];
+    A lt2 = A(0.5) * (lt0 * lt0 + lt1 * lt1);
+    a[0] = lt2 / (r * r * r) + lp2 / (r * r * r * st * st) + gr;
+    o.dp[0] = c * s[0] + h1 * a[0];
+  }
+  o.e = A(0);
+  o.cells = A(0);
+  for (int k = 0; k < 3; ++k) {
+    o.j[k] = k < nc ? c * s[k] + dt * psi * a[k] : A(0);
+    A vbar = (p[k] + A(0.5) * o.dp[k]) / w.sc[k];
+    o.e += vbar * (o.j[k] / w.sc[k]);
+  }
+}
+
+// Inverse stopping time of a particle.
+template <typename A>
+__device__ __forceinline__ A inverse_tau(const Box& b, const Forces& f, int drag_mode, A dval,
+                                         const Where<A>& w) {
+  if (drag_mode == DRAG_STOKES) {
+    A R = b.geom == GEOM_SPH ? w.sc[2] : w.x[0];
+    return dsqrt(A(f.GM) / (R * R * R)) / dval;
+  }
+  return A(1) / dval;
+}
+
+}  // namespace dust

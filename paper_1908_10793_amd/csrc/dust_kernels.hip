@@ -1,0 +1,471 @@
+// Unfused per-phase kernels of the dust hot path (gfx950): drift, gather,
+// exponential-midpoint kick, deposit, ghost fill / fold, feedback and FP64
+// conservation sums.  One thread per particle (or per grid cell); all the
+// per-particle arithmetic lives in dust_device.h and is shared with the
+// fused kernel.
+#include "dust_device.h"
+#include "dust_fused.h"
+#include "dust_launch.h"
+#include "dust_particle.h"
+
+namespace dust {
+
+// ---------------------------------------------------------------- particle kernels
+
+template <typename TS, typename A>
+__global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, int nbox, Forces f,
+                                               A h, const double* tdev, double toff, int first,
+                                               DiagDev* dg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const double t_after = *tdev + toff;
+  int idx[3];
+  A off[3], mom[3];
+  int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+  if (b < 0) return;
+  const Box& B = boxes[b];
+  bool alive = drift<A>(B, f, first != 0, h, t_after, idx, off, mom);
+  store_particle<TS, A>(p, B, f, t_after, i, alive, idx, off, mom, dg);
+}
+
+template <typename TS, typename A>
+__global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, int nbox,
+                                                FView<TS> fl, TS* rho_p, TS* vg0, TS* vg1,
+                                                TS* vg2, DiagDev* dg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  int idx[3];
+  A off[3], mom[3];
+  int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+  if (b < 0) return;
+  const Box& B = boxes[b];
+  Stencil<A> s;
+  stencil_weights<A>(B, idx, off, s);
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  const int c2 = B.ndim > 2 ? 1 : 0;
+  A r = A(0), v[3] = {A(0), A(0), A(0)};
+  for (int c = -c2; c <= c2; ++c)
+    for (int bb = -1; bb <= 1; ++bb) {
+      A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+      for (int a = -1; a <= 1; ++a) {
+        A w = s.w[0][a + 1] * wbc;
+        int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
+        r += w * A(fl.rho[id]);
+        for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
+      }
+    }
+  if (rho_p) rho_p[i] = TS(r);
+  TS* vg[3] = {vg0, vg1, vg2};
+  for (int m = 0; m < nc; ++m)
+    if (vg[m]) vg[m][i] = TS(v[m]);
+}
+
+template <typename TS, typename A>
+__global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int nbox, Forces f,
+                                              Species sp, int drag_mode, A dt, const TS* vg0,
+                                              const TS* vg1, const TS* vg2, TS* imp0, TS* imp1,
+                                              TS* imp2, TS* imp3, DiagDev* dg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double sums[5] = {0, 0, 0, 0, 0};
+  double cells = 0.0;
+  if (i < p.n) {
+    int idx[3];
+    A off[3], mom[3];
+    int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+    if (b >= 0) {
+      const Box& B = boxes[b];
+      const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+      Where<A> w;
+      where<A>(B, idx, off, w);
+      const TS* vg[3] = {vg0, vg1, vg2};
+      A pg[3];
+      for (int m = 0; m < 3; ++m) pg[m] = m < nc ? A(vg[m][i]) * w.sc[m] : A(0);
+      int s = p.species ? p.species[i] : 0;
+      if (s >= sp.n) {
+        flag(dg, DUST_FLAG_BAD_CELL);
+        s = 0;
+      }
+      A dval = drag_mode == DRAG_SPECIES ? A(sp.tau[s]) : A(p.drag[i]);
+      A m = p.mass ? A(p.mass[i]) : A(sp.mass[s]);
+      A it = inverse_tau<A>(B, f, drag_mode, dval, w);
+      KickOut<A> o;
+      kick<A>(B, f, dt, it, w, mom, pg, o);
+      TS* imp[4] = {imp0, imp1, imp2, imp3};
+      for (int k = 0; k < nc; ++k) {
+        A vbar = (mom[k] + A(0.5) * o.dp[k]) / w.sc[k];
+        A dl = cell_width<A>(B.ax[k], idx[k]) * (B.geom == GEOM_CART || k == 0 ? A(1) : w.sc[k]);
+        double cps = fabs(double(vbar * dt / dl));
+        cells = cps > cells ? cps : cells;
+        mom[k] += o.dp[k];
+        p.mom[k][i] = TS(mom[k]);
+        if (imp[k]) imp[k][i] = TS(m * o.j[k]);
+        sums[k] = double(m * o.j[k]);
+        sums[4] += fabs(double(m * o.j[k]));
+      }
+      if (imp[nc]) imp[nc][i] = TS(m * o.e);
+      sums[3] = double(m * o.e);
+      bool fin = isfinite(double(o.e));
+      for (int k = 0; k < nc; ++k) fin &= isfinite(double(mom[k]));
+      if (!fin) flag(dg, DUST_FLAG_NONFINITE);
+    }
+  }
+  if (dg) {
+    for (int k = 0; k < 5; ++k) sums[k] = wave_sum(sums[k]);
+    cells = wave_max(cells);
+    if ((threadIdx.x & 63) == 0) {
+      for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&dg->p_part[k], sums[k]);
+      unsafeAtomicAdd(&dg->e_part, sums[3]);
+      unsafeAtomicAdd(&dg->sum_abs_j, sums[4]);
+      atomic_max_nonneg(&dg->max_cells_bits, cells);
+      if (cells > 1.8) atomicOr(&dg->flags, (unsigned)DUST_FLAG_CFL);
+    }
+  }
+}
+
+template <typename TS, typename A>
+__global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, int nbox,
+                                                 FView<TS> fl, const TS* imp0, const TS* imp1,
+                                                 const TS* imp2, const TS* imp3, DiagDev* dg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  int idx[3];
+  A off[3], mom[3];
+  int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+  if (b < 0) return;
+  const Box& B = boxes[b];
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  const TS* imp[4] = {imp0, imp1, imp2, imp3};
+  A q[4];
+  for (int k = 0; k <= nc; ++k) q[k] = A(imp[k][i]);
+  Stencil<A> s;
+  stencil_weights<A>(B, idx, off, s);
+  const int c2 = B.ndim > 2 ? 1 : 0;
+  for (int c = -c2; c <= c2; ++c)
+    for (int bb = -1; bb <= 1; ++bb) {
+      A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+      for (int a = -1; a <= 1; ++a) {
+        int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
+        A w = s.w[0][a + 1] * wbc * A(inv_volume(B, ii, jj, kk));
+        int64_t id = stored_index(B, ii, jj, kk);
+        for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(-w * q[k]));
+      }
+    }
+}
+
+// ---------------------------------------------------------------- grid kernels
+
+// x ghosts of one box: shear-periodic (interpolated in y) or periodic.
+template <typename TS>
+__global__ void k_fill_x(Box B, TS* a, int comp_vy, double qOmega, const double* tdev, double toff,
+                         int shear) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n1 * n2) return;
+  const Shift sh = make_shift(B, qOmega, *tdev + toff);
+  int j = (int)(t % n1), k = (int)(t / n1);
+  if (shear) {
+    // right ghost (x_0 + L, y_j) = (x_0, y_j + s); left ghost = (x_{n-1}, y_j - s)
+    int jl = j + sh.si;
+    double fr = sh.sf;
+    int j0 = ((jl % n1) + n1) % n1, j1 = ((jl + 1) % n1 + n1) % n1;
+    double v = (1.0 - fr) * double(a[stored_index(B, 0, j0, k)]) +
+               fr * double(a[stored_index(B, 0, j1, k)]);
+    a[stored_index(B, n0, j, k)] = TS(v - (comp_vy ? sh.u : 0.0));
+    double pos_fl = -sh.si - (sh.sf > 0 ? 1 : 0);
+    int jm = j + (int)pos_fl;
+    double frm = sh.sf > 0 ? 1.0 - sh.sf : 0.0;
+    j0 = ((jm % n1) + n1) % n1;
+    j1 = ((jm + 1) % n1 + n1) % n1;
+    v = (1.0 - frm) * double(a[stored_index(B, n0 - 1, j0, k)]) +
+        frm * double(a[stored_index(B, n0 - 1, j1, k)]);
+    a[stored_index(B, -1, j, k)] = TS(v + (comp_vy ? sh.u : 0.0));
+  } else {
+    a[stored_index(B, -1, j, k)] = a[stored_index(B, n0 - 1, j, k)];
+    a[stored_index(B, n0, j, k)] = a[stored_index(B, 0, j, k)];
+  }
+}
+
+template <typename TS> __global__ void k_fill_y(Box B, TS* a) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(n0 + 2) * n2) return;
+  int i = (int)(t % (n0 + 2)) - 1, k = (int)(t / (n0 + 2));
+  a[stored_index(B, i, -1, k)] = a[stored_index(B, i, n1 - 1, k)];
+  a[stored_index(B, i, n1, k)] = a[stored_index(B, i, 0, k)];
+}
+
+template <typename TS> __global__ void k_fill_z(Box B, TS* a) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(n0 + 2) * (n1 + 2)) return;
+  int i = (int)(t % (n0 + 2)) - 1, j = (int)(t / (n0 + 2)) - 1;
+  a[stored_index(B, i, j, -1)] = a[stored_index(B, i, j, n2 - 1)];
+  a[stored_index(B, i, j, n2)] = a[stored_index(B, i, j, 0)];
+}
+
+template <typename TS> __global__ void k_fold_z(Box B, TS* a) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(n0 + 2) * (n1 + 2)) return;
+  int i = (int)(t % (n0 + 2)) - 1, j = (int)(t / (n0 + 2)) - 1;
+  int64_t gl = stored_index(B, i, j, -1), gh = stored_index(B, i, j, n2);
+  a[stored_index(B, i, j, n2 - 1)] += a[gl];
+  a[stored_index(B, i, j, 0)] += a[gh];
+  a[gl] = TS(0);
+  a[gh] = TS(0);
+}
+
+template <typename TS> __global__ void k_fold_y(Box B, TS* a) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(n0 + 2) * n2) return;
+  int i = (int)(t % (n0 + 2)) - 1, k = (int)(t / (n0 + 2));
+  int64_t gl = stored_index(B, i, -1, k), gh = stored_index(B, i, n1, k);
+  a[stored_index(B, i, n1 - 1, k)] += a[gl];
+  a[stored_index(B, i, 0, k)] += a[gh];
+  a[gl] = TS(0);
+  a[gh] = TS(0);
+}
+
+// x fold, written as a gather over the ghost rows that feed each partner
+// cell (no atomics).  The energy channel (e != NULL) gains +/- u D_y.
+template <typename TS>
+__global__ void k_fold_x(Box B, TS* a, const TS* dy, int is_energy, double qOmega,
+                         const double* tdev, double toff, int shear) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n1 * n2) return;
+  const Shift sh = make_shift(B, qOmega, *tdev + toff);
+  int jt = (int)(t % n1), k = (int)(t / n1);
+  auto wrapj = [n1](int j) { return ((j % n1) + n1) % n1; };
+  if (!shear) {
+    a[stored_index(B, n0 - 1, jt, k)] += a[stored_index(B, -1, jt, k)];
+    a[stored_index(B, 0, jt, k)] += a[stored_index(B, n0, jt, k)];
+    return;
+  }
+  auto gr = [&](int j) {  // right ghost value, energy frame-shifted
+    double v = double(a[stored_index(B, n0, j, k)]);
+    if (is_energy) v += sh.u * double(dy[stored_index(B, n0, j, k)]);
+    return v;
+  };
+  auto gl = [&](int j) {
+    double v = double(a[stored_index(B, -1, j, k)]);
+    if (is_energy) v -= sh.u * double(dy[stored_index(B, -1, j, k)]);
+    return v;
+  };
+  // right ghost row j lands on floor(j + s) (1 - sf) and floor(j + s) + 1 (sf)
+  double add0 = (1.0 - sh.sf) * gr(wrapj(jt - sh.si));
+  if (sh.sf > 0) add0 += sh.sf * gr(wrapj(jt - sh.si - 1));
+  // left ghost row j lands on floor(j - s) and floor(j - s) + 1
+  double addn;
+  if (sh.sf > 0) {
+    int c = sh.si + 1;  // ceil(s)
+    addn = sh.sf * gl(wrapj(jt + c)) + (1.0 - sh.sf) * gl(wrapj(jt + c - 1));
+  } else {
+    addn = gl(wrapj(jt + sh.si));
+  }
+  a[stored_index(B, 0, jt, k)] += TS(add0);
+  a[stored_index(B, n0 - 1, jt, k)] += TS(addn);
+}
+
+template <typename TS> __global__ void k_clear_x_ghosts(Box B, TS* a) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n1 * n2) return;
+  int j = (int)(t % n1), k = (int)(t / n1);
+  a[stored_index(B, -1, j, k)] = TS(0);
+  a[stored_index(B, n0, j, k)] = TS(0);
+}
+
+__global__ void k_set_time(double* t, double v, double add) { t[0] = add != 0.0 ? t[0] + add : v; }
+
+__global__ void k_count_step(DiagDev* dg) { dg->steps += 1; }
+
+void launch_count_step(DiagDev* dg, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_step, dim3(1), dim3(1), 0, st, dg);
+}
+
+void launch_set_time(double* tdev, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, v, 0.0);
+}
+void launch_advance_time(double* tdev, double dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, 0.0, dt);
+}
+
+template <typename TS> __global__ void k_fill_value(TS* a, int64_t n, TS v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// v_c += D_c / (rho s_c) on active cells of one box.
+template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n0 * n1 * n2) return;
+  int i = (int)(t % n0), j = (int)((t / n0) % n1), k = (int)(t / ((int64_t)n0 * n1));
+  int64_t id = stored_index(B, i, j, k);
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  double sc[3] = {1.0, 1.0, 1.0};
+  if (B.geom != GEOM_CART) {
+    double x0 = cell_centre<double>(B.ax[0], i);
+    sc[1] = x0;
+    if (B.geom == GEOM_SPH) sc[2] = x0 * sin(cell_centre<double>(B.ax[1], j));
+  }
+  double rho = double(fl.rho[id]);
+  for (int c = 0; c < nc; ++c)
+    fl.vel[c][id] = TS(double(fl.vel[c][id]) + double(fl.dep[c][id]) / (rho * sc[c]));
+}
+
+// FP64 sums of dV D over every stored cell of one box.
+template <typename TS> __global__ void __launch_bounds__(256) k_grid_sums(Box B, FView<TS> fl, DiagDev* dg) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  double s[4] = {0, 0, 0, 0};
+  if (t < B.nstore) {
+    int i = (int)(t % B.g0) - 1;
+    int j = (int)((t / B.g0) % B.g1) - 1;
+    int k = (int)(t / ((int64_t)B.g0 * B.g1)) - B.k_off;
+    double dv = 1.0 / inv_volume(B, i, j, k);
+    int64_t id = B.store_base + t;
+    for (int c = 0; c <= nc; ++c) s[c] = dv * double(fl.dep[c][id]);
+  }
+  for (int c = 0; c < 4; ++c) s[c] = wave_sum(s[c]);
+  if ((threadIdx.x & 63) == 0) {
+    for (int c = 0; c < nc; ++c) unsafeAtomicAdd(&dg->p_grid[c], s[c]);
+    unsafeAtomicAdd(&dg->e_grid, s[nc]);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n, int bs = 256) {
+  return (unsigned)((n + bs - 1) / bs);
+}
+
+template <typename TS, typename A>
+void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f, double h,
+                  const double* tdev, double toff, int first, DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL((k_drift<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, f,
+                     A(h), tdev, toff, first, dg);
+}
+
+template <typename TS, typename A>
+void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl, TS* rho_p,
+                   TS* const vg[3], DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL((k_gather<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
+                     rho_p, vg[0], vg[1], vg[2], dg);
+}
+
+template <typename TS, typename A>
+void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f,
+                 const Species& sp, int drag_mode, double dt, const TS* const vg[3],
+                 TS* const imp[4], DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL((k_kick<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, f, sp,
+                     drag_mode, A(dt), vg[0], vg[1], vg[2], imp[0], imp[1], imp[2], imp[3], dg);
+}
+
+template <typename TS, typename A>
+void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl,
+                    const TS* const imp[4], DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL((k_deposit<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
+                     imp[0], imp[1], imp[2], imp[3], dg);
+}
+
+template <typename TS>
+void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
+                 hipStream_t st) {
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  TS* arrs[4] = {fl.rho, fl.vel[0], fl.vel[1], fl.vel[2]};
+  const double qOmega = f.q * f.Omega;
+  for (int a = 0; a <= nc; ++a) {
+    TS* x = arrs[a];
+    if (B.ax[0].bc_lo != BC_OPEN)
+      hipLaunchKernelGGL((k_fill_x<TS>), dim3(blocks_for((int64_t)n1 * n2)), dim3(256), 0, st, B, x,
+                         (int)(B.geom == GEOM_CART && a == 2), qOmega, tdev, toff,
+                         (int)(B.ax[0].bc_lo == BC_SHEAR));
+    if (B.ax[1].bc_lo == BC_PERIODIC)
+      hipLaunchKernelGGL((k_fill_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2)), dim3(256), 0, st,
+                         B, x);
+    if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
+      hipLaunchKernelGGL((k_fill_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2))), dim3(256),
+                         0, st, B, x);
+  }
+}
+
+template <typename TS>
+void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
+                 hipStream_t st) {
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+  const double qOmega = f.q * f.Omega;
+  for (int c = 0; c <= nc; ++c) {
+    TS* x = fl.dep[c];
+    if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
+      hipLaunchKernelGGL((k_fold_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2))), dim3(256),
+                         0, st, B, x);
+    if (B.ax[1].bc_lo == BC_PERIODIC)
+      hipLaunchKernelGGL((k_fold_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2)), dim3(256), 0, st,
+                         B, x);
+  }
+  if (B.ax[0].bc_lo != BC_OPEN) {
+    int shear = B.ax[0].bc_lo == BC_SHEAR;
+    // energy first: it reads the D_y ghosts before they are cleared
+    for (int c = nc; c >= 0; --c)
+      hipLaunchKernelGGL((k_fold_x<TS>), dim3(blocks_for((int64_t)n1 * n2)), dim3(256), 0, st, B,
+                         fl.dep[c], (const TS*)fl.dep[B.ndim > 1 ? 1 : 0], (int)(c == nc && shear),
+                         qOmega, tdev, toff, shear);
+    for (int c = 0; c <= nc; ++c)
+      hipLaunchKernelGGL((k_clear_x_ghosts<TS>), dim3(blocks_for((int64_t)n1 * n2)), dim3(256), 0, st,
+                         B, fl.dep[c]);
+  }
+}
+
+template <typename TS>
+void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st) {
+  int64_t n = B.ncell;
+  hipLaunchKernelGGL((k_feedback<TS>), dim3(blocks_for(n)), dim3(256), 0, st, B, fl);
+}
+
+template <typename TS>
+void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, hipStream_t st) {
+  hipLaunchKernelGGL((k_grid_sums<TS>), dim3(blocks_for(B.nstore)), dim3(256), 0, st, B, fl, dg);
+}
+
+template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_fill_value<TS>), dim3(blocks_for(n)), dim3(256), 0, st, a, n, v);
+}
+
+#define DUST_INST(TS, A)                                                                          \
+  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, const Forces&, double,      \
+                                    const double*, double, int, DiagDev*, hipStream_t);           \
+  template void launch_gather<TS, A>(const PView<TS>&, const Box*, int, const FView<TS>&, TS*,    \
+                                     TS* const[3], DiagDev*, hipStream_t);                        \
+  template void launch_kick<TS, A>(const PView<TS>&, const Box*, int, const Forces&,              \
+                                   const Species&, int, double, const TS* const[3],               \
+                                   TS* const[4], DiagDev*, hipStream_t);                          \
+  template void launch_deposit<TS, A>(const PView<TS>&, const Box*, int, const FView<TS>&,        \
+                                      const TS* const[4], DiagDev*, hipStream_t);
+
+DUST_INST(float, double)
+DUST_INST(float, float)
+DUST_INST(double, double)
+
+#define DUST_INST_GRID(TS)                                                                        \
+  template void launch_fill<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
+                                hipStream_t);                                                     \
+  template void launch_fold<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
+                                hipStream_t);                                                     \
+  template void launch_feedback<TS>(const Box&, const FView<TS>&, hipStream_t);                   \
+  template void launch_grid_sums<TS>(const Box&, const FView<TS>&, DiagDev*, hipStream_t);        \
+  template void launch_fill_value<TS>(TS*, int64_t, TS, hipStream_t);
+
+DUST_INST_GRID(float)
+DUST_INST_GRID(double)
+
+}  // namespace dust

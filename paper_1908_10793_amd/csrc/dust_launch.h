@@ -1,0 +1,75 @@
+// Internal launcher declarations of the dust library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dust_types.h"
+
+namespace dust {
+
+template <typename TS> struct PView {
+  int32_t *cell;
+  TS *off[3];
+  TS *mom[3];
+  TS *drag;
+  TS *mass;
+  uint8_t *species;
+  int32_t *id;
+  int64_t n;
+};
+
+template <typename TS> struct FView {
+  TS *rho;
+  TS *vel[3];
+  TS *dep[4];
+};
+
+template <typename TS, typename A>
+void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f, double h,
+                  const double* tdev, double toff, int first, DiagDev* dg, hipStream_t st);
+template <typename TS, typename A>
+void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl, TS* rho_p,
+                   TS* const vg[3], DiagDev* dg, hipStream_t st);
+template <typename TS, typename A>
+void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f,
+                 const Species& sp, int drag_mode, double dt, const TS* const vg[3],
+                 TS* const imp[4], DiagDev* dg, hipStream_t st);
+template <typename TS, typename A>
+void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl,
+                    const TS* const imp[4], DiagDev* dg, hipStream_t st);
+
+template <typename TS>
+void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
+                 hipStream_t st);
+template <typename TS>
+void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
+                 hipStream_t st);
+void launch_set_time(double* tdev, double v, hipStream_t st);
+void launch_advance_time(double* tdev, double dt, hipStream_t st);
+template <typename TS> void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st);
+template <typename TS>
+void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, hipStream_t st);
+template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st);
+
+// Binning (dust_bin.hip).  Workspace sizes in bytes for n particles.
+struct BinWork {
+  uint32_t *key[2];
+  uint32_t *val[2];
+  uint32_t *hist;       // 256 * nblocks, scanned in place
+  uint32_t *scan_tmp;   // block sums of the scans
+  void *gather_tmp;     // 8 bytes per particle (permutation application)
+  size_t cap_n;
+};
+size_t bin_scan_tmp_words(int64_t n);
+struct TileShape { int32_t t[3]; };
+// Sort particles by key; writes perm (sorted slot -> input index) and
+// bin_start (nbins+1).  key_mode: DUST_BIN_CELL or DUST_BIN_TILE.
+void launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, const Box* boxes_host,
+                int nbox, int64_t nbins, int key_mode, TileShape tile, BinWork& w,
+                int32_t* perm_out, int64_t* bin_start_out, hipStream_t st);
+// out[i] = in[perm[i]] for an array of `bytes`-sized elements.
+void launch_permute(const void* in, void* out, const uint32_t* perm, int64_t n, int bytes,
+                    hipStream_t st);
+
+}  // namespace dust

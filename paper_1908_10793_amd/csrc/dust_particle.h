@@ -1,0 +1,140 @@
+// Particle load / store and stencil helpers shared by the unfused and fused
+// kernels.
+#pragma once
+
+#include "dust_device.h"
+#include "dust_launch.h"
+
+namespace dust {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void flag(DiagDev* dg, unsigned int bits) {
+  if (dg) atomicOr(&dg->flags, bits);
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// Load the position/momentum of particle i.  Returns the box index or -1 if
+// the particle has no cell.
+template <typename TS, typename A>
+__device__ __forceinline__ int load_particle(const PView<TS>& p, const Box* boxes, int nbox,
+                                             int64_t i, int idx[3], A off[3], A mom[3],
+                                             DiagDev* dg) {
+  int64_t c = p.cell[i];
+  if (c < 0) return -1;
+  int b = find_box(boxes, nbox, c);
+  const Box& B = boxes[b];
+  if (c >= B.cell_base + B.ncell) {
+    flag(dg, DUST_FLAG_BAD_CELL);
+    return -1;
+  }
+  unravel(B, c - B.cell_base, idx);
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  bool bad = false, nonfinite = false;
+  for (int d = 0; d < 3; ++d) {
+    off[d] = d < B.ndim ? A(p.off[d][i]) : A(0);
+    mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+    bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
+    nonfinite |= !isfinite(double(mom[d]));
+  }
+  if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+  if (nonfinite) flag(dg, DUST_FLAG_NONFINITE);
+  return b;
+}
+
+// Round the offsets to storage precision; an offset that rounds onto the
+// upper face moves to the next cell (same point), with the boundary rules.
+template <typename TS, typename A>
+__device__ __forceinline__ bool finalize(const Box& B, const Forces& f, double t, int idx[3],
+                                         A off[3], A mom[3], TS out[3]) {
+  for (int d = 0; d < B.ndim; ++d) {
+    out[d] = TS(off[d]);
+    if (out[d] >= TS(0.5)) {
+      out[d] = TS(-0.5);
+      off[d] = A(-0.5);
+      idx[d] += 1;
+      if (d == 0 && B.ax[0].bc_lo == BC_SHEAR) {
+        shear_image<A>(B, f, t, idx, off, mom);
+        out[1] = TS(off[1]);
+      }
+      if (!wrap_plain<A>(B.ax[d], idx[d])) return false;
+    }
+  }
+  return true;
+}
+
+template <typename TS, typename A>
+__device__ __forceinline__ void store_particle(const PView<TS>& p, const Box& B, const Forces& f,
+                                               double t, int64_t i, bool alive, int idx[3],
+                                               A off[3], A mom[3], DiagDev* dg) {
+  TS o[3];
+  if (alive) alive = finalize<TS, A>(B, f, t, idx, off, mom, o);
+  if (!alive) {
+    p.cell[i] = -1;
+    if (dg) {
+      atomicAdd(&dg->n_removed, 1ull);
+      atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
+    }
+    return;
+  }
+  p.cell[i] = (int32_t)(B.cell_base + ravel(B, idx));
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  for (int d = 0; d < B.ndim; ++d) p.off[d][i] = o[d];
+  for (int d = 0; d < nc; ++d) p.mom[d][i] = TS(mom[d]);
+}
+
+// Weights of the 3^ndim stencil at the particle's current position.
+template <typename A> struct Stencil {
+  A w[3][3];
+};
+
+template <typename A>
+__device__ __forceinline__ void stencil_weights(const Box& B, const int idx[3], const A off[3],
+                                                Stencil<A>& s) {
+  for (int d = 0; d < 3; ++d) {
+    if (d < B.ndim) {
+      axis_weights<A>(B.ax[d], idx[d], off[d], s.w[d]);
+    } else {
+      s.w[d][0] = A(0); s.w[d][1] = A(1); s.w[d][2] = A(0);
+    }
+  }
+}
+
+
+// Shear offset (y-cells) split into integer and fractional parts.
+struct Shift {
+  int si;      // floor(s)
+  double sf;   // s - floor(s)
+  double u;    // q Omega L_x
+};
+
+__device__ __forceinline__ Shift make_shift(const Box& B, double qOmega, double t) {
+  Shift sh{0, 0.0, 0.0};
+  if (B.ax[0].bc_lo != BC_SHEAR) return sh;
+  sh.u = qOmega * B.ax[0].L;
+  double s = fmod(sh.u * t / B.ax[1].d, (double)B.ax[1].n);
+  if (s < 0) s += B.ax[1].n;
+  double fl = floor(s);
+  sh.si = (int)fl;
+  sh.sf = s - fl;
+  if (sh.si >= B.ax[1].n) sh.si -= B.ax[1].n;
+  return sh;
+}
+
+
+}  // namespace dust

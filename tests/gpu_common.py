@@ -1,0 +1,164 @@
+"""Helpers of the GPU parity tests: run the HIP path through the C ABI and
+the FP64 oracle on the same inputs, and compare them element by element.
+
+Tolerances (reading of the "1e-5 relative (FP32) / 1e-12 (FP64)" bar,
+normwise so that it is well posed where values cancel):
+  positions  |x_gpu - x_oracle| / width_of_host_cell <= tol
+  momenta    |p_gpu - p_oracle|_inf <= tol (|p_oracle|_inf + |p_start|_inf)
+  fields     max_i |f_gpu - f_oracle| <= tol max_i |f_oracle|, per channel
+  cells      identical, except for particles whose oracle position lies within
+             tol cell widths of a face (counted, and they must then agree in
+             position as above).
+Every comparison starts from identical inputs: multi-step runs are checked
+step by step along the GPU trajectory (the oracle restarts each step from the
+GPU's state), so FP32 rounding of the stored state is not compounded against
+an FP64 trajectory.
+"""
+from __future__ import annotations
+
+import copy
+import dataclasses
+
+import numpy as np
+
+import oracle as O
+from oracle.run import OracleRun, locate_cells
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def download(ctx, P, F, w):
+    """GPU state -> numpy (particles ordered as stored; gas per box)."""
+    import torch
+    torch.cuda.synchronize()
+    n = P["cell"].numel()
+    st = {"cell": P["cell"].cpu().numpy().astype(np.int64)}
+    off = np.zeros((n, 3))
+    mom = np.zeros((n, 3))
+    for d, t in enumerate(P["off"]):
+        off[:, d] = t.cpu().numpy()
+    for d, t in enumerate(P["mom"]):
+        mom[:, d] = t.cpu().numpy()
+    st["off"], st["mom"] = off, mom
+    for k in ("drag", "mass", "species", "id"):
+        st[k] = P[k].cpu().numpy() if k in P else None
+    gas, dep = [], []
+    base = 0
+    for bd in w.boxes:
+        nd = bd["ndim"]
+        g = [bd["n"][d] + 2 if d < nd else 1 for d in range(3)]
+        sz = g[0] * g[1] * g[2]
+        shp = (g[2], g[1], g[0]) if nd == 3 else (g[1], g[0])
+        gas.append(dict(rho=F["rho"][base:base + sz].cpu().numpy().reshape(shp).astype(np.float64),
+                        vel=[v[base:base + sz].cpu().numpy().reshape(shp).astype(np.float64)
+                             for v in F["vel"]]))
+        dep.append([dd[base:base + sz].cpu().numpy().reshape(shp).astype(np.float64)
+                    for dd in F["dep"]])
+        base += sz
+    st["gas"], st["dep"] = gas, dep
+    return st
+
+
+def workload_from_state(w, st, t):
+    """A copy of workload w whose inputs are the state st (exact widening)."""
+    w2 = copy.copy(w)
+    w2 = dataclasses.replace(w, cell=st["cell"].astype(np.int32), off=st["off"], mom=st["mom"],
+                             gas=st["gas"], t0=t,
+                             drag=st["drag"] if st["drag"] is not None else None,
+                             mass=st["mass"] if st["mass"] is not None else None,
+                             species=st["species"] if st["species"] is not None else None)
+    return w2
+
+
+def _global_positions(box, cell_local, off):
+    x = np.full((len(cell_local), 3), np.nan)
+    ok = cell_local >= 0
+    if ok.any():
+        x[ok] = O.to_global(box, cell_local[ok], off[ok])
+    return x
+
+
+def compare_step(w, st_in, st_out, run: OracleRun, dtype: str, fields_too=True, label=""):
+    """Compare the GPU state after one step (st_out) with the oracle run
+    started from st_in.  Returns a dict of the worst errors; asserts the bar."""
+    tol = TOL[dtype]
+    report = {"label": label}
+    bases, _ = w.cell_bases()
+    ids_out = st_out["id"]
+    order_out = np.argsort(ids_out) if ids_out is not None else np.arange(len(st_out["cell"]))
+    ids_in = st_in["id"] if st_in["id"] is not None else np.arange(len(st_in["cell"]))
+    worst_x = worst_p = 0.0
+    near_face = 0
+    for b, box in enumerate(run.boxes):
+        sel = run.sel[b]                       # indices into st_in order
+        ids = ids_in[sel]
+        gi = order_out[ids] if st_out["id"] is not None else sel
+        cell_o, off_o, p_o, act_o = run.particle_state(b)
+        x_o = run.x[b]
+        cell_g = st_out["cell"][gi]
+        act_g = cell_g >= 0
+        assert np.array_equal(act_o, act_g), f"{label}: removed-particle sets differ"
+        a = act_o
+        if not a.any():
+            continue
+        # positions
+        lo = bases[b]
+        x_g = _global_positions(box, cell_g[a] - lo, st_out["off"][gi][a])
+        widths = np.zeros((a.sum(), 3))
+        cl_o = cell_o[a] - lo
+        idx = O.unravel(box, cl_o)
+        dx = x_g - x_o[a]
+        for d in range(box.ndim):
+            c, wd = O.centers_widths(box, d)
+            widths[:, d] = wd[idx[d]]
+            if box.bc_lo[d] in ("periodic", "shear"):
+                L = box.faces[d][-1] - box.faces[d][0]
+                dx[:, d] = (dx[:, d] + 0.5 * L) % L - 0.5 * L
+        ex = np.abs(dx[:, :box.ndim]) / widths[:, :box.ndim]
+        worst_x = max(worst_x, float(ex.max()))
+        # cells: exact except near faces
+        diff = cell_g[a] != cell_o[a]
+        if diff.any():
+            offo = off_o[a][diff][:, :box.ndim]
+            near = np.any(np.abs(np.abs(offo) - 0.5) <= max(tol, 1e-12) * 4, axis=1)
+            near_face += int(near.sum())
+            assert near.all(), f"{label}: {int((~near).sum())} cell mismatches away from faces"
+        # momenta
+        nc = box.ndim if box.geom == "cart" else 3
+        pg = st_out["mom"][gi][a][:, :nc]
+        po = p_o[a][:, :nc]
+        p0 = st_in["mom"][sel][a][:, :nc]
+        scale = np.abs(po).max(axis=1) + np.abs(p0).max(axis=1) + 1e-300
+        ep = np.abs(pg - po).max(axis=1) / scale
+        worst_p = max(worst_p, float(ep.max()))
+    report["pos"] = worst_x
+    report["mom"] = worst_p
+    report["near_face"] = near_face
+    assert worst_x <= tol, report
+    assert worst_p <= tol, report
+    if fields_too:
+        worst_f = 0.0
+        for b, box in enumerate(run.boxes):
+            fo = run.fields[b]
+            nc = fo.nc
+            for c in range(nc + 1):
+                ref = fo.dep[c].reshape(-1)
+                got = st_out["dep"][b][c].reshape(-1)
+                den = np.abs(ref).max()
+                if den == 0:
+                    assert np.abs(got).max() == 0, (label, "dep", c)
+                    continue
+                e = np.abs(got - ref).max() / den
+                worst_f = max(worst_f, e)
+                assert e <= tol, (label, "dep", b, c, e)
+            if w.apply_feedback:
+                for c in range(nc):
+                    ref = fo.vel[c].reshape(fo.box.ghosted_shape)
+                    got = st_out["gas"][b]["vel"][c].reshape(fo.box.ghosted_shape)
+                    act = (slice(1, -1),) * 3 if box.ndim == 3 else (0, slice(1, -1), slice(1, -1))
+                    den = np.abs(ref[act]).max()
+                    e = np.abs(got[act] - ref[act]).max() / max(den, 1e-300)
+                    worst_f = max(worst_f, e)
+                    assert e <= tol, (label, "vel", b, c, e)
+        report["fields"] = worst_f
+    return report

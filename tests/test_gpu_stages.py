@@ -1,0 +1,231 @@
+"""GPU tests of the individual C-ABI calls: binning (bit exact), ghost fill
+and fold, gather, the unfused phase chain, graphs, edge cases and errors."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.run import OracleRun, make_box, make_forces
+from paper_1908_10793_amd import synth
+
+from gpu_common import TOL, compare_step, download, workload_from_state
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+RNG = np.random.default_rng(5)
+
+
+def _dust():
+    from paper_1908_10793_amd import dust
+    return dust
+
+
+# ------------------------------------------------------------------ binning
+
+@pytest.mark.parametrize("n", [0, 1, 2, 1000, 300001])
+@pytest.mark.parametrize("mode", ["cell", "tile"])
+def test_bin_is_bit_exact_stable_sort(n, mode):
+    dust = _dust()
+    w = synth.batched_boxes(sizes=(7, 12, 5), max_per_species=1)
+    ctx = dust.context_for(w)
+    ctx.set_tile(4, 5, 3, 1)
+    _, C = ctx.grid_size()
+    cells = RNG.integers(-1, C, size=n).astype(np.int32)
+    cells[RNG.random(n) < 0.05] = -1
+    P = {"cell": torch.from_numpy(cells).cuda(), "off": [torch.zeros(n).cuda() for _ in range(3)],
+         "mom": [torch.zeros(n).cuda() for _ in range(3)], "id": torch.arange(n, dtype=torch.int32).cuda()}
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    start = torch.empty(C + 1, dtype=torch.int64, device="cuda")
+    ctx.bin(P, key_mode=mode, perm=perm, bin_start=start, apply=True)
+    torch.cuda.synchronize()
+    keys = cells.astype(np.int64)
+    if mode == "tile":
+        bases, _ = w.cell_bases()
+        keys = keys.copy()
+        for b, bd in enumerate(w.boxes):
+            lo, hi = bases[b], bases[b] + int(np.prod(bd["n"]))
+            m = (cells >= lo) & (cells < hi)
+            keys[m] = lo + O.tile_major_keys(cells[m] - lo, bd["n"], (4, 5, 3))
+    ref_perm, ref_start = O.bin_reference(keys, C)
+    assert np.array_equal(perm.cpu().numpy(), ref_perm)
+    assert np.array_equal(start.cpu().numpy(), ref_start)
+    assert np.array_equal(P["cell"].cpu().numpy(), cells[ref_perm])
+    assert np.array_equal(P["id"].cpu().numpy(), ref_perm)
+
+
+# ------------------------------------------------------------------ ghosts
+
+def test_fill_and_fold_match_oracle_on_shearing_box():
+    dust = _dust()
+    w = synth.shearing_box(n=(10, 9, 6), dtype="f64")
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    box, Fo = make_box(w.boxes[0]), make_forces(w.forces)
+    for t in (0.0, 0.37, 3.9):
+        gs = box.ghosted_shape
+        rho = RNG.standard_normal(gs)
+        vel = [RNG.standard_normal(gs) for _ in range(3)]
+        dep = [RNG.standard_normal(gs) for _ in range(4)]
+        F["rho"].copy_(torch.from_numpy(rho.ravel()))
+        for c in range(3):
+            F["vel"][c].copy_(torch.from_numpy(vel[c].ravel()))
+        for c in range(4):
+            F["dep"][c].copy_(torch.from_numpy(dep[c].ravel()))
+        ctx.fill_ghosts(F, dust.forces_for(w, t), t)
+        ctx.fold_ghosts(F, dust.forces_for(w, t), t)
+        fo = O.Fields(box, rho.copy(), [v.copy() for v in vel], dep=[d.copy() for d in dep])
+        O.fill_ghosts(box, Fo, t, fo)
+        O.fold_ghosts(box, Fo, t, fo)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(F["rho"].cpu().numpy(), fo.rho.ravel(), rtol=0, atol=1e-14)
+        for c in range(3):
+            np.testing.assert_allclose(F["vel"][c].cpu().numpy(), fo.vel[c].ravel(), atol=1e-13)
+        for c in range(4):
+            np.testing.assert_allclose(F["dep"][c].cpu().numpy(), fo.dep[c].ravel(), atol=1e-13)
+
+
+# ------------------------------------------------------------------ gather
+
+@pytest.mark.parametrize("name", ["shearing_box", "cylindrical_disk", "spherical_disk"])
+def test_gather_matches_oracle(name):
+    dust = _dust()
+    kw = dict(dtype="f64")
+    if name == "shearing_box":
+        w = synth.shearing_box(n=(12, 10, 8), **kw)
+    elif name == "cylindrical_disk":
+        w = synth.cylindrical_disk(n=(16, 12, 8), npart=3000, **kw)
+    else:
+        w = synth.spherical_disk(n=(16, 12, 10), ppc=1, **kw)
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    n = w.n
+    rho_p = torch.empty(n, dtype=torch.float64, device="cuda")
+    vg = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ctx.fill_ghosts(F, dust.forces_for(w), 0.0)
+    ctx.gather(P, F, rho_p, vg)
+    torch.cuda.synchronize()
+    box = make_box(w.boxes[0])
+    st = download(ctx, P, F, w)
+    fo = O.Fields(box, st["gas"][0]["rho"], st["gas"][0]["vel"])
+    x = O.to_global(box, w.cell, w.off.astype(np.float64))
+    r_ref, v_ref = O.gather(box, fo, x)
+    np.testing.assert_allclose(rho_p.cpu().numpy(), r_ref, rtol=1e-13, atol=0)
+    for c in range(3):
+        got = vg[c].cpu().numpy()
+        assert np.abs(got - v_ref[:, c]).max() <= 1e-13 * max(np.abs(v_ref).max(), 1e-300)
+
+
+# ------------------------------------------------------------------ phase chain
+
+def test_phase_chain_equals_step():
+    """fill, drift1, gather, kick, deposit, drift2, fold, feedback through the
+    stage calls gives what dust_step gives (same kernels)."""
+    dust = _dust()
+    w = synth.shearing_box(n=(12, 10, 8), dtype="f64", dt=0.05)
+    ctx = dust.context_for(w)
+    P1, F1 = dust.upload(w, ctx)
+    P2, F2 = dust.upload(w, ctx)
+    n = w.n
+    fr = dust.forces_for(w, 0.3)
+    ctx.step(P1, F1, w.dt, fr, 1, dust.STEP_APPLY_FEEDBACK)
+    vg = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    imp = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    ctx.fill_ghosts(F2, fr, 0.3 + 0.5 * w.dt)
+    for d in F2["dep"]:
+        d.zero_()
+    ctx.push_expmid(P2, None, w.dt, fr, dust.PHASE_DRIFT1)
+    ctx.gather(P2, F2, None, vg)
+    ctx.push_expmid(P2, vg, w.dt, fr, dust.PHASE_KICK, imp)
+    ctx.deposit(P2, imp, F2)
+    ctx.push_expmid(P2, None, w.dt, fr, dust.PHASE_DRIFT2)
+    ctx.fold_ghosts(F2, fr, 0.3 + 0.5 * w.dt)
+    ctx.apply_feedback(F2)
+    torch.cuda.synchronize()
+    assert torch.equal(P1["cell"], P2["cell"])
+    for d in range(3):
+        assert torch.equal(P1["off"][d], P2["off"][d])
+        assert torch.equal(P1["mom"][d], P2["mom"][d])
+    for c in range(4):
+        a, b = F1["dep"][c], F2["dep"][c]
+        assert (a - b).abs().max().item() <= 1e-14 * max(a.abs().max().item(), 1e-300)
+
+
+# ------------------------------------------------------------------ graphs
+
+def test_graph_replay_matches_eager():
+    dust = _dust()
+    w = synth.shearing_box(n=(16, 12, 8), dt=0.02)
+    ctx = dust.context_for(w)
+    P1, F1 = dust.upload(w, ctx)
+    P2, F2 = dust.upload(w, ctx)
+    flags = dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK
+    t = 0.0
+    for rep in range(3):
+        ctx.step(P1, F1, w.dt, dust.forces_for(w, t), 4, flags)
+        ctx.step(P2, F2, w.dt, dust.forces_for(w, t), 4, flags | dust.STEP_GRAPH)
+        torch.cuda.synchronize()
+        t += 4 * w.dt
+        o1 = torch.argsort(P1["id"])
+        o2 = torch.argsort(P2["id"])
+        assert torch.equal(P1["cell"][o1], P2["cell"][o2])
+        for d in range(3):
+            assert (P1["mom"][d][o1] - P2["mom"][d][o2]).abs().max().item() < 1e-6
+        for c in range(4):
+            a, b = F1["dep"][c], F2["dep"][c]
+            assert (a - b).abs().max().item() <= 1e-5 * max(a.abs().max().item(), 1e-30), (rep, c)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_and_removed_particles():
+    dust = _dust()
+    w = synth.cart2d_periodic(n=(8, 8), ppc=2)
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    E = {k: (v[:0] if not isinstance(v, list) else [x[:0] for x in v]) for k, v in P.items()}
+    ctx.step(E, F, w.dt, dust.forces_for(w), 2, dust.STEP_APPLY_FEEDBACK)
+    ctx.step(E, F, w.dt, dust.forces_for(w), 2, dust.STEP_FUSED)
+    P["cell"][::3] = -1
+    keep = P["cell"].clone()
+    ctx.step(P, F, w.dt, dust.forces_for(w), 1, 0)
+    torch.cuda.synchronize()
+    assert torch.all(P["cell"][keep < 0] == -1)
+
+
+def test_extreme_stopping_times_and_face_offsets():
+    """tau = +inf (no drag) and tau = 1e-9 (dt/tau = 1e7), offsets exactly at
+    -1/2: finite results matching the oracle."""
+    dust = _dust()
+    w = synth.spherical_disk(n=(10, 8, 12), ppc=1, dtype="f64", dt=0.01)
+    w.drag[::2] = np.inf
+    w.drag[1::4] = 1e-9
+    w.off[::5, 0] = -0.5
+    w.off[::7, 1] = -0.5
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    st_in = download(ctx, P, F, w)
+    ctx.step(P, F, w.dt, dust.forces_for(w), 1, 0)
+    st_out = download(ctx, P, F, w)
+    assert np.all(np.isfinite(st_out["mom"]))
+    run = OracleRun(workload_from_state(w, st_in, w.t0))
+    run.step(1)
+    compare_step(w, st_in, st_out, run, "f64", label="extremes")
+
+
+def test_invalid_arguments_are_rejected():
+    dust = _dust()
+    w = synth.cart2d_periodic(n=(8, 8), ppc=1)
+    bad = dict(w.boxes[0])
+    bad["faces"] = [bad["faces"][0][::-1], bad["faces"][1]]
+    with pytest.raises(dust.DustError) as e:
+        dust.Context([bad], prec="f64", drag_mode="species", species_tau=[0.1], species_mass=[1.0])
+    assert e.value.code == -1
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    with pytest.raises(dust.DustError):
+        ctx.step(P, F, float("nan"), dust.forces_for(w), 1, 0)
+    with pytest.raises(dust.DustError):
+        ctx.step(P, F, 0.01, dust.forces_for(w), 1, 1 << 20)
+    F2 = dict(F)
+    F2["dep"] = F["dep"][:1]
+    with pytest.raises(dust.DustError):
+        ctx.step(P, F2, 0.01, dust.forces_for(w), 1, 0)
