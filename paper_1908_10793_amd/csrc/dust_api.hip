@@ -298,7 +298,7 @@ dust_status_t check_fields(Ctx* c, const dust_fields_t* f, bool gas, bool dep) {
 }
 
 dust_status_t ensure_ws(Ctx* c, int64_t n) {
-  size_t need = (size_t)std::max<int64_t>(n, 1) * real_size(c) * 8;
+  size_t need = (size_t)std::max<int64_t>(n, 1) * 8 * 8;
   if (need <= c->ws_bytes) return DUST_OK;
   if (c->ws) HIP_TRY(hipFree(c->ws));
   c->ws = nullptr;
@@ -316,10 +316,11 @@ dust_status_t ensure_bin(Ctx* c, int64_t n) {
   int64_t nblocks = (nn + 2047) / 2048;
   size_t hist = (size_t)256 * nblocks;
   size_t scan = bin_scan_tmp_words((int64_t)hist);
-  size_t bytes = (size_t)nn * 4 * 4 + (hist + scan + 64) * 4 + (size_t)nn * 8 + 256;
+  auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t bytes = 4 * rup((size_t)nn * 4) + rup(hist * 4) + rup(scan * 4) + rup((size_t)nn * 8);
   if (hipMalloc(&c->bin_mem, bytes) != hipSuccess) return fail(DUST_ENOMEM, "bin workspace of %zu bytes", bytes);
   char* q = (char*)c->bin_mem;
-  auto take = [&](size_t b) { char* r = q; q += (b + 255) & ~(size_t)255; return r; };
+  auto take = [&](size_t b) { char* r = q; q += rup(b); return r; };
   c->bin.key[0] = (uint32_t*)take((size_t)nn * 4);
   c->bin.key[1] = (uint32_t*)take((size_t)nn * 4);
   c->bin.val[0] = (uint32_t*)take((size_t)nn * 4);
@@ -373,7 +374,7 @@ void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phase
   if (phases & DUST_PHASE_DRIFT1)
     launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
   if (phases & DUST_PHASE_KICK)
-    launch_kick<TS, A>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, vg, imp, dg, st);
+    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, vg, imp, dg, st);
   if (phases & DUST_PHASE_DRIFT2)
     launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
 }
@@ -384,9 +385,9 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
                   int flags, hipStream_t st) {
   int nc = ctx_nc(c);
   int64_t n = pv.n;
-  TS* ws = (TS*)c->ws;
-  TS* vg[3] = {ws, ws + n, ws + 2 * n};
-  TS* imp[4] = {ws + 3 * n, ws + 4 * n, ws + 5 * n, ws + 6 * n};
+  A* ws = (A*)c->ws;  // gathered gas and impulses kept in the arithmetic precision
+  A* vg[3] = {ws, ws + n, ws + 2 * n};
+  A* imp[4] = {ws + 3 * n, ws + 4 * n, ws + 5 * n, ws + 6 * n};
   for (int k = nc; k < 3; ++k) vg[k] = nullptr;
   for (int k = nc + 1; k < 4; ++k) imp[k] = nullptr;
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
@@ -395,12 +396,12 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
-  launch_gather<TS, A>(pv, c->boxes_d, c->nbox, fv, nullptr, vg, dflags, st);
-  const TS* cvg[3] = {vg[0], vg[1], vg[2]};
-  launch_kick<TS, A>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, cvg, imp,
-                     dg ? dg : dflags, st);
-  const TS* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
-  launch_deposit<TS, A>(pv, c->boxes_d, c->nbox, fv, cimp, dflags, st);
+  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, fv, (A*)nullptr, vg, dflags, st);
+  const A* cvg[3] = {vg[0], vg[1], vg[2]};
+  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, cvg, imp,
+                        dg ? dg : dflags, st);
+  const A* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
+  launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, fv, cimp, dflags, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
   if (dg)
     for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
@@ -742,7 +743,7 @@ dust_status_t dust_gather(void* ctx, const dust_particles_t* p, const dust_field
     using A = decltype(ta);
     TS* vg[3] = {nullptr, nullptr, nullptr};
     for (int k = 0; k < nc; ++k) vg[k] = (TS*)vg_p[k];
-    launch_gather<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
+    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -804,7 +805,7 @@ dust_status_t dust_deposit(void* ctx, const dust_particles_t* p, const void* con
     using A = decltype(ta);
     const TS* imp[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k <= nc; ++k) imp[k] = (const TS*)impulse[k];
-    launch_deposit<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), imp, c->diag, st);
+    launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), imp, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });

@@ -28,10 +28,10 @@ __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, in
   store_particle<TS, A>(p, B, f, t_after, i, alive, idx, off, mom, dg);
 }
 
-template <typename TS, typename A>
+template <typename TS, typename A, typename TW>
 __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, int nbox,
-                                                FView<TS> fl, TS* rho_p, TS* vg0, TS* vg1,
-                                                TS* vg2, DiagDev* dg) {
+                                                FView<TS> fl, TW* rho_p, TW* vg0, TW* vg1,
+                                                TW* vg2, DiagDev* dg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   int idx[3];
@@ -54,17 +54,17 @@ __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, i
         for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
       }
     }
-  if (rho_p) rho_p[i] = TS(r);
-  TS* vg[3] = {vg0, vg1, vg2};
+  if (rho_p) rho_p[i] = TW(r);
+  TW* vg[3] = {vg0, vg1, vg2};
   for (int m = 0; m < nc; ++m)
-    if (vg[m]) vg[m][i] = TS(v[m]);
+    if (vg[m]) vg[m][i] = TW(v[m]);
 }
 
-template <typename TS, typename A>
+template <typename TS, typename A, typename TW>
 __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int nbox, Forces f,
-                                              Species sp, int drag_mode, A dt, const TS* vg0,
-                                              const TS* vg1, const TS* vg2, TS* imp0, TS* imp1,
-                                              TS* imp2, TS* imp3, DiagDev* dg) {
+                                              Species sp, int drag_mode, A dt, const TW* vg0,
+                                              const TW* vg1, const TW* vg2, TW* imp0, TW* imp1,
+                                              TW* imp2, TW* imp3, DiagDev* dg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double sums[5] = {0, 0, 0, 0, 0};
   double cells = 0.0;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       const int nc = B.geom == GEOM_CART ? B.ndim : 3;
       Where<A> w;
       where<A>(B, idx, off, w);
-      const TS* vg[3] = {vg0, vg1, vg2};
+      const TW* vg[3] = {vg0, vg1, vg2};
       A pg[3];
       for (int m = 0; m < 3; ++m) pg[m] = m < nc ? A(vg[m][i]) * w.sc[m] : A(0);
       int s = p.species ? p.species[i] : 0;
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       A it = inverse_tau<A>(B, f, drag_mode, dval, w);
       KickOut<A> o;
       kick<A>(B, f, dt, it, w, mom, pg, o);
-      TS* imp[4] = {imp0, imp1, imp2, imp3};
+      TW* imp[4] = {imp0, imp1, imp2, imp3};
       for (int k = 0; k < nc; ++k) {
         A vbar = (mom[k] + A(0.5) * o.dp[k]) / w.sc[k];
         A dl = cell_width<A>(B.ax[k], idx[k]) * (B.geom == GEOM_CART || k == 0 ? A(1) : w.sc[k]);
@@ -98,11 +98,11 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
         cells = cps > cells ? cps : cells;
         mom[k] += o.dp[k];
         p.mom[k][i] = TS(mom[k]);
-        if (imp[k]) imp[k][i] = TS(m * o.j[k]);
+        if (imp[k]) imp[k][i] = TW(m * o.j[k]);
         sums[k] = double(m * o.j[k]);
         sums[4] += fabs(double(m * o.j[k]));
       }
-      if (imp[nc]) imp[nc][i] = TS(m * o.e);
+      if (imp[nc]) imp[nc][i] = TW(m * o.e);
       sums[3] = double(m * o.e);
       bool fin = isfinite(double(o.e));
       for (int k = 0; k < nc; ++k) fin &= isfinite(double(mom[k]));
@@ -122,10 +122,10 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
   }
 }
 
-template <typename TS, typename A>
+template <typename TS, typename A, typename TW>
 __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, int nbox,
-                                                 FView<TS> fl, const TS* imp0, const TS* imp1,
-                                                 const TS* imp2, const TS* imp3, DiagDev* dg) {
+                                                 FView<TS> fl, const TW* imp0, const TW* imp1,
+                                                 const TW* imp2, const TW* imp3, DiagDev* dg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   int idx[3];
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
   if (b < 0) return;
   const Box& B = boxes[b];
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  const TS* imp[4] = {imp0, imp1, imp2, imp3};
+  const TW* imp[4] = {imp0, imp1, imp2, imp3};
   A q[4];
   for (int k = 0; k <= nc; ++k) q[k] = A(imp[k][i]);
   Stencil<A> s;
@@ -350,28 +350,28 @@ void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, const Forces& 
                      A(h), tdev, toff, first, dg);
 }
 
-template <typename TS, typename A>
-void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl, TS* rho_p,
-                   TS* const vg[3], DiagDev* dg, hipStream_t st) {
+template <typename TS, typename A, typename TW>
+void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl, TW* rho_p,
+                   TW* const vg[3], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_gather<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
+  hipLaunchKernelGGL((k_gather<TS, A, TW>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
                      rho_p, vg[0], vg[1], vg[2], dg);
 }
 
-template <typename TS, typename A>
+template <typename TS, typename A, typename TW>
 void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f,
-                 const Species& sp, int drag_mode, double dt, const TS* const vg[3],
-                 TS* const imp[4], DiagDev* dg, hipStream_t st) {
+                 const Species& sp, int drag_mode, double dt, const TW* const vg[3],
+                 TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_kick<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, f, sp,
+  hipLaunchKernelGGL((k_kick<TS, A, TW>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, f, sp,
                      drag_mode, A(dt), vg[0], vg[1], vg[2], imp[0], imp[1], imp[2], imp[3], dg);
 }
 
-template <typename TS, typename A>
+template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl,
-                    const TS* const imp[4], DiagDev* dg, hipStream_t st) {
+                    const TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_deposit<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
+  hipLaunchKernelGGL((k_deposit<TS, A, TW>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
                      imp[0], imp[1], imp[2], imp[3], dg);
 }
 
@@ -441,20 +441,26 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
   hipLaunchKernelGGL((k_fill_value<TS>), dim3(blocks_for(n)), dim3(256), 0, st, a, n, v);
 }
 
-#define DUST_INST(TS, A)                                                                          \
-  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, const Forces&, double,      \
-                                    const double*, double, int, DiagDev*, hipStream_t);           \
-  template void launch_gather<TS, A>(const PView<TS>&, const Box*, int, const FView<TS>&, TS*,    \
-                                     TS* const[3], DiagDev*, hipStream_t);                        \
-  template void launch_kick<TS, A>(const PView<TS>&, const Box*, int, const Forces&,              \
-                                   const Species&, int, double, const TS* const[3],               \
-                                   TS* const[4], DiagDev*, hipStream_t);                          \
-  template void launch_deposit<TS, A>(const PView<TS>&, const Box*, int, const FView<TS>&,        \
-                                      const TS* const[4], DiagDev*, hipStream_t);
+#define DUST_INST(TS, A, TW)                                                                      \
+  template void launch_gather<TS, A, TW>(const PView<TS>&, const Box*, int, const FView<TS>&, TW*, \
+                                         TW* const[3], DiagDev*, hipStream_t);                    \
+  template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, const Forces&,          \
+                                       const Species&, int, double, const TW* const[3],           \
+                                       TW* const[4], DiagDev*, hipStream_t);                      \
+  template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, const FView<TS>&,    \
+                                          const TW* const[4], DiagDev*, hipStream_t);
 
-DUST_INST(float, double)
-DUST_INST(float, float)
-DUST_INST(double, double)
+#define DUST_INST_DRIFT(TS, A)                                                                    \
+  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, const Forces&, double,      \
+                                    const double*, double, int, DiagDev*, hipStream_t);
+
+DUST_INST_DRIFT(float, double)
+DUST_INST_DRIFT(float, float)
+DUST_INST_DRIFT(double, double)
+DUST_INST(float, double, float)
+DUST_INST(float, double, double)
+DUST_INST(float, float, float)
+DUST_INST(double, double, double)
 
 #define DUST_INST_GRID(TS)                                                                        \
   template void launch_fill<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \

@@ -4,7 +4,10 @@ the FP64 oracle on the same inputs, and compare them element by element.
 Tolerances (reading of the "1e-5 relative (FP32) / 1e-12 (FP64)" bar,
 normwise so that it is well posed where values cancel):
   positions  |x_gpu - x_oracle| / width_of_host_cell <= tol
-  momenta    |p_gpu - p_oracle|_inf <= tol (|p_oracle|_inf + |p_start|_inf)
+  momenta    |p_gpu - p_oracle|_inf <= tol (|p_oracle| + |p_start| + |p_gas|), the
+             last term the largest canonical gas momentum in the particle's
+             neighbourhood (the kick is a weighted mean of p, p_gas and the
+             external acceleration, so this is its natural scale)
   fields     max_i |f_gpu - f_oracle| <= tol max_i |f_oracle|, per channel
   cells      identical, except for particles whose oracle position lies within
              tol cell widths of a face (counted, and they must then agree in
@@ -20,6 +23,7 @@ import copy
 import dataclasses
 
 import numpy as np
+from scipy.ndimage import maximum_filter
 
 import oracle as O
 from oracle.run import OracleRun, locate_cells
@@ -128,7 +132,19 @@ def compare_step(w, st_in, st_out, run: OracleRun, dtype: str, fields_too=True, 
         pg = st_out["mom"][gi][a][:, :nc]
         po = p_o[a][:, :nc]
         p0 = st_in["mom"][sel][a][:, :nc]
-        scale = np.abs(po).max(axis=1) + np.abs(p0).max(axis=1) + 1e-300
+        vmax = np.max([np.abs(v) for v in st_in["gas"][b]["vel"][:nc]], axis=0)
+        vmax = maximum_filter(vmax, size=5, mode="nearest").reshape(box.ghosted_shape)
+        ci = O.unravel(box, cl_o)
+        gmax = vmax[(ci[2] + (1 if box.ndim > 2 else 0), ci[1] + 1, ci[0] + 1)]
+        xo = x_o[a]
+        sc = np.ones((a.sum(), 3))
+        if box.geom == "cyl":
+            sc[:, 1] = xo[:, 0]
+        elif box.geom == "sph":
+            sc[:, 1] = xo[:, 0]
+            sc[:, 2] = xo[:, 0] * np.sin(xo[:, 1])
+        scale = (np.abs(po).max(axis=1) + np.abs(p0).max(axis=1) +
+                 gmax * sc[:, :nc].max(axis=1) + 1e-300)
         ep = np.abs(pg - po).max(axis=1) / scale
         worst_p = max(worst_p, float(ep.max()))
     report["pos"] = worst_x

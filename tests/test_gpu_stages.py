@@ -198,8 +198,16 @@ def test_extreme_stopping_times_and_face_offsets():
     w = synth.spherical_disk(n=(10, 8, 12), ppc=1, dtype="f64", dt=0.01)
     w.drag[::2] = np.inf
     w.drag[1::4] = 1e-9
-    w.off[::5, 0] = -0.5
-    w.off[::7, 1] = -0.5
+    # exactly on a lower face, away from the open radial / polar faces
+    ci = w.cell % 10
+    cj = (w.cell // 10) % 8
+    m = np.zeros(w.n, bool)
+    m[::5] = True
+    w.off[m & (ci > 0), 0] = -0.5
+    m[:] = False
+    m[::7] = True
+    w.off[m & (cj > 0), 1] = -0.5
+    w.off[::3, 2] = -0.5
     ctx = dust.context_for(w)
     P, F = dust.upload(w, ctx)
     st_in = download(ctx, P, F, w)
