@@ -47,7 +47,9 @@ struct Ctx {
   int arith = DUST_ARITH_F64;
   int drag_mode = DUST_DRAG_TAU;
   Species species{};
+  Species* species_d = nullptr;
   bool have_mass_table = false;
+  int geom = 0, ndim = 3;         // shared by every box
   int nbox = 0;
   std::vector<Box> boxes;         // host copies (device table pointers inside)
   Box* boxes_d = nullptr;
@@ -372,11 +374,11 @@ template <typename TS, typename A>
 void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phases,
               const TS* const vg[3], TS* const imp[4], DiagDev* dg, hipStream_t st) {
   if (phases & DUST_PHASE_DRIFT1)
-    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
+    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
   if (phases & DUST_PHASE_KICK)
-    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, vg, imp, dg, st);
+    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, c->species_d, c->drag_mode, dt, vg, imp, dg, st);
   if (phases & DUST_PHASE_DRIFT2)
-    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
+    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
 }
 
 // One unfused step (time in c->tdev[0] at the start of the step).
@@ -395,14 +397,14 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
-  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
-  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, fv, (A*)nullptr, vg, dflags, st);
+  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
+  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, fv, (A*)nullptr, vg, dflags, st);
   const A* cvg[3] = {vg[0], vg[1], vg[2]};
-  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, F, c->species, c->drag_mode, dt, cvg, imp,
+  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, c->species_d, c->drag_mode, dt, cvg, imp,
                         dg ? dg : dflags, st);
   const A* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
-  launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, fv, cimp, dflags, st);
-  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
+  launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, fv, cimp, dflags, st);
+  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
   if (dg)
     for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
   for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
@@ -426,7 +428,7 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
   bool prof = c->prof_used < c->prof_max;
   if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
-  launch_fused<TS, A>(c->plan, pv, c->boxes_d, c->boxes.data(), c->nbox, fv, F, c->species,
+  launch_fused<TS, A>(c->plan, pv, c->boxes_d, c->nbox, c->geom, c->ndim, fv, F, c->species_d,
                       c->drag_mode, dt, c->tdev, c->bin_start, c->diag, dg != nullptr, st);
   if (prof) {
     HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
@@ -526,13 +528,22 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
     store_base += c->boxes[b].nstore;
   }
   c->store_off[nbox] = store_base;
+  c->geom = c->boxes[0].geom;
+  c->ndim = c->boxes[0].ndim;
+  for (int b = 1; b < nbox; ++b)
+    if (c->boxes[b].geom != c->geom || c->boxes[b].ndim != c->ndim) {
+      dust_ctx_destroy(c);
+      return fail(DUST_EUNSUPPORTED, "all boxes of a context must share geometry and ndim");
+    }
   c->n_active = cell_base;
   c->n_stored = store_base;
   if (cell_base >= 0x7fffffffLL) {
     dust_ctx_destroy(c);
     return fail(DUST_ESHAPE, "more than 2^31-1 active cells");
   }
-  if (hipMalloc((void**)&c->boxes_d, sizeof(Box) * nbox) != hipSuccess ||
+  if (hipMalloc((void**)&c->species_d, sizeof(Species)) != hipSuccess ||
+      hipMemcpy(c->species_d, &c->species, sizeof(Species), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc((void**)&c->boxes_d, sizeof(Box) * nbox) != hipSuccess ||
       hipMalloc((void**)&c->diag, sizeof(DiagDev)) != hipSuccess ||
       hipMalloc((void**)&c->tdev, 64) != hipSuccess) {
     dust_ctx_destroy(c);
@@ -558,6 +569,7 @@ dust_status_t dust_ctx_destroy(void* ctx) {
   for (auto e : c->prof_ev) hipEventDestroy(e);
   for (void* p : c->tables) hipFree(p);
   if (c->boxes_d) hipFree(c->boxes_d);
+  if (c->species_d) hipFree(c->species_d);
   if (c->diag) hipFree(c->diag);
   if (c->tdev) hipFree(c->tdev);
   if (c->ws) hipFree(c->ws);
@@ -743,7 +755,7 @@ dust_status_t dust_gather(void* ctx, const dust_particles_t* p, const dust_field
     using A = decltype(ta);
     TS* vg[3] = {nullptr, nullptr, nullptr};
     for (int k = 0; k < nc; ++k) vg[k] = (TS*)vg_p[k];
-    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
+    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -805,7 +817,7 @@ dust_status_t dust_deposit(void* ctx, const dust_particles_t* p, const void* con
     using A = decltype(ta);
     const TS* imp[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k <= nc; ++k) imp[k] = (const TS*)impulse[k];
-    launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, fview<TS>(f), imp, c->diag, st);
+    launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, fview<TS>(f), imp, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });

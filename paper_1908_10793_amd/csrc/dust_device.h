@@ -282,18 +282,20 @@ __device__ __forceinline__ void shear_image(const Box& b, const Forces& f, doubl
 // theta) already moved to n+1/2; otherwise all metric factors are those at
 // the start of this half drift.  t_after: time the boundary rules use.
 // Returns false if the particle left through an open face.
-template <typename A>
+template <typename A, int GEOM, int NDIM>
 __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first, A h,
                                       double t_after, int idx[3], A off[3], A mom[3]) {
-  if (b.geom == GEOM_CART) {
-    A dx[3] = {h * mom[0], h * mom[1], b.ndim > 2 ? h * mom[2] : A(0)};
-    for (int d = 0; d < b.ndim; ++d) idx[d] = move_axis<A>(b.ax[d], idx[d], off[d], dx[d]);
-    if (b.ax[0].bc_lo == BC_SHEAR) shear_image<A>(b, f, t_after, idx, off, mom);
-    for (int d = 0; d < b.ndim; ++d)
+  if constexpr (GEOM == GEOM_CART) {
+    A dx[3] = {h * mom[0], h * mom[1], NDIM > 2 ? h * mom[2] : A(0)};
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) idx[d] = move_axis<A>(b.ax[d], idx[d], off[d], dx[d]);
+    if (NDIM == 3 && b.ax[0].bc_lo == BC_SHEAR) shear_image<A>(b, f, t_after, idx, off, mom);
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d)
       if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
     return true;
   }
-  if (b.geom == GEOM_CYL) {
+  if constexpr (GEOM == GEOM_CYL) {
     if (first) {
       idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
       if (!wrap_plain<A>(b.ax[0], idx[0])) return false;
@@ -325,6 +327,7 @@ __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first,
       idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
     }
   }
+#pragma unroll
   for (int d = 0; d < 3; ++d)
     if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
   return true;
@@ -338,15 +341,16 @@ template <typename A> struct Where {
   A sc[3]; // canonical = physical * sc: 1, R, r, r sin(theta)
 };
 
-template <typename A>
+template <typename A, int GEOM, int NDIM>
 __device__ __forceinline__ void where(const Box& b, const int idx[3], const A off[3], Where<A>& w) {
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    w.x[d] = d < b.ndim ? cell_centre<A>(b.ax[d], idx[d]) + off[d] * cell_width<A>(b.ax[d], idx[d])
-                        : A(0);
+    w.x[d] = d < NDIM ? cell_centre<A>(b.ax[d], idx[d]) + off[d] * cell_width<A>(b.ax[d], idx[d])
+                      : A(0);
     w.sc[d] = A(1);
   }
-  if (b.geom == GEOM_CYL) w.sc[1] = w.x[0];
-  if (b.geom == GEOM_SPH) {
+  if constexpr (GEOM == GEOM_CYL) w.sc[1] = w.x[0];
+  if constexpr (GEOM == GEOM_SPH) {
     w.sc[1] = w.x[0];
     w.sc[2] = w.x[0] * dsin(w.x[1]);
   }
@@ -366,7 +370,7 @@ template <typename A> struct KickOut {
 // App. A Eq. standard_SB_exp_midpoint; App. B.1 Eq. kick_cylindrical; App.
 // B.2) for canonical momenta p and gas momentum pg (canonical), inverse
 // stopping time it.
-template <typename A>
+template <typename A, int GEOM, int NDIM>
 __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
                                      const Where<A>& w, const A p[3], const A pg[3],
                                      KickOut<A>& o) {
@@ -375,9 +379,9 @@ __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
   A h1 = dt + dt * psi;
   A s[3] = {pg[0] - p[0], pg[1] - p[1], pg[2] - p[2]};
   A a[3] = {A(0), A(0), A(0)};
-  const int nc = b.geom == GEOM_CART ? b.ndim : 3;
-  if (b.geom == GEOM_CART) {
-    if (f.kind == FORCE_SHEARBOX) {
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  if constexpr (GEOM == GEOM_CART) {
+    if (NDIM == 3 && f.kind == FORCE_SHEARBOX) {
       // R dp = c s + h1 a(x, p^n), R = I - W J_rot, W = Omega h1
       A Om = A(f.Omega), q = A(f.q);
       A gz = f.vertical_gravity ? -Om * Om * w.x[2] : A(0);
@@ -391,13 +395,14 @@ __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
       a[1] = an[1] - Om * o.dp[0];
       a[2] = gz;
     } else {
+#pragma unroll
       for (int k = 0; k < nc; ++k) {
         a[k] = f.kind == FORCE_CONST ? A(f.g[k]) : A(0);
         o.dp[k] = c * s[k] + h1 * a[k];
       }
       if (nc < 3) o.dp[2] = A(0);
     }
-  } else if (b.geom == GEOM_CYL) {
+  } else if constexpr (GEOM == GEOM_CYL) {
     A R = w.x[0], z = w.x[2];
     A gR = A(0), gz = A(0);
     if (f.kind == FORCE_POINTMASS) {
@@ -432,6 +437,7 @@ __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
   }
   o.e = A(0);
   o.cells = A(0);
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     o.j[k] = k < nc ? c * s[k] + dt * psi * a[k] : A(0);
     A vbar = (p[k] + A(0.5) * o.dp[k]) / w.sc[k];
@@ -440,11 +446,11 @@ __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
 }
 
 // Inverse stopping time of a particle.
-template <typename A>
-__device__ __forceinline__ A inverse_tau(const Box& b, const Forces& f, int drag_mode, A dval,
+template <typename A, int GEOM>
+__device__ __forceinline__ A inverse_tau(const Forces& f, int drag_mode, A dval,
                                          const Where<A>& w) {
   if (drag_mode == DRAG_STOKES) {
-    A R = b.geom == GEOM_SPH ? w.sc[2] : w.x[0];
+    A R = GEOM == GEOM_SPH ? w.sc[2] : w.x[0];
     return dsqrt(A(f.GM) / (R * R * R)) / dval;
   }
   return A(1) / dval;

@@ -31,8 +31,8 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
 void fused_plan_free(FusedPlan& plan);
 
 template <typename TS, typename A>
-void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, const Box* boxes_h,
-                  int nbox, const FView<TS>& fl, const Forces& f, const Species& sp, int drag_mode,
+void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, int nbox, int geom,
+                  int ndim, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                   double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg, bool sums,
                   hipStream_t st);
 

@@ -11,8 +11,10 @@
 namespace dust {
 
 // ---------------------------------------------------------------- particle kernels
+// Templated on the geometry and dimension of the context's boxes so that the
+// stencil and component loops unroll into registers.
 
-template <typename TS, typename A>
+template <typename TS, typename A, int GEOM, int NDIM>
 __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, int nbox, Forces f,
                                                A h, const double* tdev, double toff, int first,
                                                DiagDev* dg) {
@@ -21,14 +23,14 @@ __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, in
   const double t_after = *tdev + toff;
   int idx[3];
   A off[3], mom[3];
-  int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+  int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
   if (b < 0) return;
   const Box& B = boxes[b];
-  bool alive = drift<A>(B, f, first != 0, h, t_after, idx, off, mom);
-  store_particle<TS, A>(p, B, f, t_after, i, alive, idx, off, mom, dg);
+  bool alive = drift<A, GEOM, NDIM>(B, f, first != 0, h, t_after, idx, off, mom);
+  store_particle<TS, A, GEOM, NDIM>(p, B, f, t_after, i, alive, idx, off, mom, dg);
 }
 
-template <typename TS, typename A, typename TW>
+template <typename TS, typename A, typename TW, int GEOM, int NDIM>
 __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, int nbox,
                                                 FView<TS> fl, TW* rho_p, TW* vg0, TW* vg1,
                                                 TW* vg2, DiagDev* dg) {
@@ -36,67 +38,72 @@ __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, i
   if (i >= p.n) return;
   int idx[3];
   A off[3], mom[3];
-  int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+  int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
   if (b < 0) return;
   const Box& B = boxes[b];
   Stencil<A> s;
-  stencil_weights<A>(B, idx, off, s);
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  const int c2 = B.ndim > 2 ? 1 : 0;
+  stencil_weights<A, NDIM>(B, idx, off, s);
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
   A r = A(0), v[3] = {A(0), A(0), A(0)};
+#pragma unroll
   for (int c = -c2; c <= c2; ++c)
+#pragma unroll
     for (int bb = -1; bb <= 1; ++bb) {
       A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
       for (int a = -1; a <= 1; ++a) {
         A w = s.w[0][a + 1] * wbc;
         int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
-        r += w * A(fl.rho[id]);
+        if (rho_p) r += w * A(fl.rho[id]);
+#pragma unroll
         for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
       }
     }
   if (rho_p) rho_p[i] = TW(r);
-  TW* vg[3] = {vg0, vg1, vg2};
-  for (int m = 0; m < nc; ++m)
-    if (vg[m]) vg[m][i] = TW(v[m]);
+  if (vg0) vg0[i] = TW(v[0]);
+  if (vg1) vg1[i] = TW(v[1]);
+  if (nc > 2 && vg2) vg2[i] = TW(v[2]);
 }
 
-template <typename TS, typename A, typename TW>
+template <typename TS, typename A, typename TW, int GEOM, int NDIM>
 __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int nbox, Forces f,
-                                              Species sp, int drag_mode, A dt, const TW* vg0,
+                                              const Species* sp, int drag_mode, A dt, const TW* vg0,
                                               const TW* vg1, const TW* vg2, TW* imp0, TW* imp1,
                                               TW* imp2, TW* imp3, DiagDev* dg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   double sums[5] = {0, 0, 0, 0, 0};
   double cells = 0.0;
   if (i < p.n) {
     int idx[3];
     A off[3], mom[3];
-    int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+    int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
     if (b >= 0) {
       const Box& B = boxes[b];
-      const int nc = B.geom == GEOM_CART ? B.ndim : 3;
       Where<A> w;
-      where<A>(B, idx, off, w);
-      const TW* vg[3] = {vg0, vg1, vg2};
-      A pg[3];
-      for (int m = 0; m < 3; ++m) pg[m] = m < nc ? A(vg[m][i]) * w.sc[m] : A(0);
+      where<A, GEOM, NDIM>(B, idx, off, w);
+      A pg[3] = {A(vg0[i]) * w.sc[0], A(vg1[i]) * w.sc[1], nc > 2 ? A(vg2[i]) * w.sc[2] : A(0)};
       int s = p.species ? p.species[i] : 0;
-      if (s >= sp.n) {
+      if (s >= sp->n) {
         flag(dg, DUST_FLAG_BAD_CELL);
         s = 0;
       }
-      A dval = drag_mode == DRAG_SPECIES ? A(sp.tau[s]) : A(p.drag[i]);
-      A m = p.mass ? A(p.mass[i]) : A(sp.mass[s]);
-      A it = inverse_tau<A>(B, f, drag_mode, dval, w);
+      A dval = drag_mode == DRAG_SPECIES ? A(sp->tau[s]) : A(p.drag[i]);
+      A m = p.mass ? A(p.mass[i]) : A(sp->mass[s]);
+      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, w);
       KickOut<A> o;
-      kick<A>(B, f, dt, it, w, mom, pg, o);
+      kick<A, GEOM, NDIM>(B, f, dt, it, w, mom, pg, o);
       TW* imp[4] = {imp0, imp1, imp2, imp3};
+      bool fin = isfinite(double(o.e));
+#pragma unroll
       for (int k = 0; k < nc; ++k) {
         A vbar = (mom[k] + A(0.5) * o.dp[k]) / w.sc[k];
-        A dl = cell_width<A>(B.ax[k], idx[k]) * (B.geom == GEOM_CART || k == 0 ? A(1) : w.sc[k]);
+        A dl = cell_width<A>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : w.sc[k]);
         double cps = fabs(double(vbar * dt / dl));
         cells = cps > cells ? cps : cells;
         mom[k] += o.dp[k];
+        fin &= isfinite(double(mom[k]));
         p.mom[k][i] = TS(mom[k]);
         if (imp[k]) imp[k][i] = TW(m * o.j[k]);
         sums[k] = double(m * o.j[k]);
@@ -104,12 +111,11 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       }
       if (imp[nc]) imp[nc][i] = TW(m * o.e);
       sums[3] = double(m * o.e);
-      bool fin = isfinite(double(o.e));
-      for (int k = 0; k < nc; ++k) fin &= isfinite(double(mom[k]));
       if (!fin) flag(dg, DUST_FLAG_NONFINITE);
     }
   }
   if (dg) {
+#pragma unroll
     for (int k = 0; k < 5; ++k) sums[k] = wave_sum(sums[k]);
     cells = wave_max(cells);
     if ((threadIdx.x & 63) == 0) {
@@ -122,7 +128,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
   }
 }
 
-template <typename TS, typename A, typename TW>
+template <typename TS, typename A, typename TW, int GEOM, int NDIM>
 __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, int nbox,
                                                  FView<TS> fl, const TW* imp0, const TW* imp1,
                                                  const TW* imp2, const TW* imp3, DiagDev* dg) {
@@ -130,27 +136,48 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
   if (i >= p.n) return;
   int idx[3];
   A off[3], mom[3];
-  int b = load_particle<TS, A>(p, boxes, nbox, i, idx, off, mom, dg);
+  int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
   if (b < 0) return;
   const Box& B = boxes[b];
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  const TW* imp[4] = {imp0, imp1, imp2, imp3};
-  A q[4];
-  for (int k = 0; k <= nc; ++k) q[k] = A(imp[k][i]);
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  A q[4] = {A(imp0[i]), A(imp1[i]), A(imp2[i]), A(0)};
+  if (nc > 2) q[3] = A(imp3[i]);
   Stencil<A> s;
-  stencil_weights<A>(B, idx, off, s);
-  const int c2 = B.ndim > 2 ? 1 : 0;
+  stencil_weights<A, NDIM>(B, idx, off, s);
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
+#pragma unroll
   for (int c = -c2; c <= c2; ++c)
+#pragma unroll
     for (int bb = -1; bb <= 1; ++bb) {
       A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
       for (int a = -1; a <= 1; ++a) {
         int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
         A w = s.w[0][a + 1] * wbc * A(inv_volume(B, ii, jj, kk));
         int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
         for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(-w * q[k]));
       }
     }
 }
+
+// Dispatch on the (geometry, dimension) shared by the context's boxes.
+#define DUST_GEOM_SWITCH(geom, ndim, CALL)                            \
+  do {                                                                \
+    if ((geom) == GEOM_CART && (ndim) == 2) {                         \
+      constexpr int G_ = GEOM_CART, D_ = 2;                           \
+      CALL;                                                           \
+    } else if ((geom) == GEOM_CART) {                                 \
+      constexpr int G_ = GEOM_CART, D_ = 3;                           \
+      CALL;                                                           \
+    } else if ((geom) == GEOM_CYL) {                                  \
+      constexpr int G_ = GEOM_CYL, D_ = 3;                            \
+      CALL;                                                           \
+    } else {                                                          \
+      constexpr int G_ = GEOM_SPH, D_ = 3;                            \
+      CALL;                                                           \
+    }                                                                 \
+  } while (0)
 
 // ---------------------------------------------------------------- grid kernels
 
@@ -343,36 +370,42 @@ static inline unsigned blocks_for(int64_t n, int bs = 256) {
 }
 
 template <typename TS, typename A>
-void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f, double h,
-                  const double* tdev, double toff, int first, DiagDev* dg, hipStream_t st) {
+void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+                  const Forces& f, double h, const double* tdev, double toff, int first,
+                  DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_drift<TS, A>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, f,
-                     A(h), tdev, toff, first, dg);
+  DUST_GEOM_SWITCH(geom, ndim,
+                   hipLaunchKernelGGL((k_drift<TS, A, G_, D_>), dim3(blocks_for(p.n)), dim3(256), 0,
+                                      st, p, boxes, nbox, f, A(h), tdev, toff, first, dg));
 }
 
 template <typename TS, typename A, typename TW>
-void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl, TW* rho_p,
-                   TW* const vg[3], DiagDev* dg, hipStream_t st) {
+void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+                   const FView<TS>& fl, TW* rho_p, TW* const vg[3], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_gather<TS, A, TW>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
-                     rho_p, vg[0], vg[1], vg[2], dg);
+  DUST_GEOM_SWITCH(geom, ndim,
+                   hipLaunchKernelGGL((k_gather<TS, A, TW, G_, D_>), dim3(blocks_for(p.n)), dim3(256),
+                                      0, st, p, boxes, nbox, fl, rho_p, vg[0], vg[1], vg[2], dg));
 }
 
 template <typename TS, typename A, typename TW>
-void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, const Forces& f,
-                 const Species& sp, int drag_mode, double dt, const TW* const vg[3],
-                 TW* const imp[4], DiagDev* dg, hipStream_t st) {
+void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+                 const Forces& f, const Species* sp, int drag_mode, double dt,
+                 const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_kick<TS, A, TW>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, f, sp,
-                     drag_mode, A(dt), vg[0], vg[1], vg[2], imp[0], imp[1], imp[2], imp[3], dg);
+  DUST_GEOM_SWITCH(geom, ndim,
+                   hipLaunchKernelGGL((k_kick<TS, A, TW, G_, D_>), dim3(blocks_for(p.n)), dim3(256),
+                                      0, st, p, boxes, nbox, f, sp, drag_mode, A(dt), vg[0], vg[1],
+                                      vg[2], imp[0], imp[1], imp[2], imp[3], dg));
 }
 
 template <typename TS, typename A, typename TW>
-void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl,
-                    const TW* const imp[4], DiagDev* dg, hipStream_t st) {
+void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+                    const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL((k_deposit<TS, A, TW>), dim3(blocks_for(p.n)), dim3(256), 0, st, p, boxes, nbox, fl,
-                     imp[0], imp[1], imp[2], imp[3], dg);
+  DUST_GEOM_SWITCH(geom, ndim,
+                   hipLaunchKernelGGL((k_deposit<TS, A, TW, G_, D_>), dim3(blocks_for(p.n)), dim3(256),
+                                      0, st, p, boxes, nbox, fl, imp[0], imp[1], imp[2], imp[3], dg));
 }
 
 template <typename TS>
@@ -442,17 +475,19 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
 }
 
 #define DUST_INST(TS, A, TW)                                                                      \
-  template void launch_gather<TS, A, TW>(const PView<TS>&, const Box*, int, const FView<TS>&, TW*, \
-                                         TW* const[3], DiagDev*, hipStream_t);                    \
-  template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, const Forces&,          \
-                                       const Species&, int, double, const TW* const[3],           \
+  template void launch_gather<TS, A, TW>(const PView<TS>&, const Box*, int, int, int,             \
+                                         const FView<TS>&, TW*, TW* const[3], DiagDev*,           \
+                                         hipStream_t);                                            \
+  template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, const Forces&, \
+                                       const Species*, int, double, const TW* const[3],           \
                                        TW* const[4], DiagDev*, hipStream_t);                      \
-  template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, const FView<TS>&,    \
-                                          const TW* const[4], DiagDev*, hipStream_t);
+  template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, int, int,            \
+                                          const FView<TS>&, const TW* const[4], DiagDev*,         \
+                                          hipStream_t);
 
 #define DUST_INST_DRIFT(TS, A)                                                                    \
-  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, const Forces&, double,      \
-                                    const double*, double, int, DiagDev*, hipStream_t);
+  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, int, int, const Forces&,   \
+                                    double, const double*, double, int, DiagDev*, hipStream_t);
 
 DUST_INST_DRIFT(float, double)
 DUST_INST_DRIFT(float, float)

@@ -31,7 +31,7 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* a, double 
 
 // Load the position/momentum of particle i.  Returns the box index or -1 if
 // the particle has no cell.
-template <typename TS, typename A>
+template <typename TS, typename A, int GEOM, int NDIM>
 __device__ __forceinline__ int load_particle(const PView<TS>& p, const Box* boxes, int nbox,
                                              int64_t i, int idx[3], A off[3], A mom[3],
                                              DiagDev* dg) {
@@ -44,10 +44,11 @@ __device__ __forceinline__ int load_particle(const PView<TS>& p, const Box* boxe
     return -1;
   }
   unravel(B, c - B.cell_base, idx);
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   bool bad = false, nonfinite = false;
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    off[d] = d < B.ndim ? A(p.off[d][i]) : A(0);
+    off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
     mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
     bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
     nonfinite |= !isfinite(double(mom[d]));
@@ -59,16 +60,17 @@ __device__ __forceinline__ int load_particle(const PView<TS>& p, const Box* boxe
 
 // Round the offsets to storage precision; an offset that rounds onto the
 // upper face moves to the next cell (same point), with the boundary rules.
-template <typename TS, typename A>
+template <typename TS, typename A, int GEOM, int NDIM>
 __device__ __forceinline__ bool finalize(const Box& B, const Forces& f, double t, int idx[3],
                                          A off[3], A mom[3], TS out[3]) {
-  for (int d = 0; d < B.ndim; ++d) {
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
     out[d] = TS(off[d]);
     if (out[d] >= TS(0.5)) {
       out[d] = TS(-0.5);
       off[d] = A(-0.5);
       idx[d] += 1;
-      if (d == 0 && B.ax[0].bc_lo == BC_SHEAR) {
+      if (GEOM == GEOM_CART && NDIM == 3 && d == 0 && B.ax[0].bc_lo == BC_SHEAR) {
         shear_image<A>(B, f, t, idx, off, mom);
         out[1] = TS(off[1]);
       }
@@ -78,12 +80,12 @@ __device__ __forceinline__ bool finalize(const Box& B, const Forces& f, double t
   return true;
 }
 
-template <typename TS, typename A>
+template <typename TS, typename A, int GEOM, int NDIM>
 __device__ __forceinline__ void store_particle(const PView<TS>& p, const Box& B, const Forces& f,
                                                double t, int64_t i, bool alive, int idx[3],
                                                A off[3], A mom[3], DiagDev* dg) {
   TS o[3];
-  if (alive) alive = finalize<TS, A>(B, f, t, idx, off, mom, o);
+  if (alive) alive = finalize<TS, A, GEOM, NDIM>(B, f, t, idx, off, mom, o);
   if (!alive) {
     p.cell[i] = -1;
     if (dg) {
@@ -93,8 +95,10 @@ __device__ __forceinline__ void store_particle(const PView<TS>& p, const Box& B,
     return;
   }
   p.cell[i] = (int32_t)(B.cell_base + ravel(B, idx));
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  for (int d = 0; d < B.ndim; ++d) p.off[d][i] = o[d];
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) p.off[d][i] = o[d];
+#pragma unroll
   for (int d = 0; d < nc; ++d) p.mom[d][i] = TS(mom[d]);
 }
 
@@ -103,11 +107,12 @@ template <typename A> struct Stencil {
   A w[3][3];
 };
 
-template <typename A>
+template <typename A, int NDIM>
 __device__ __forceinline__ void stencil_weights(const Box& B, const int idx[3], const A off[3],
                                                 Stencil<A>& s) {
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (d < B.ndim) {
+    if (d < NDIM) {
       axis_weights<A>(B.ax[d], idx[d], off[d], s.w[d]);
     } else {
       s.w[d][0] = A(0); s.w[d][1] = A(1); s.w[d][2] = A(0);
