@@ -183,9 +183,10 @@ dust_status_t dust_ctx_destroy(void *ctx);
  * DUST_ARITH_F32 keeps everything FP32).  Ignored for F64 contexts. */
 dust_status_t dust_ctx_set_arith(void *ctx, int32_t arith);
 
-/* Tile shape of the fused path (cells per axis; 0 keeps the current one).
- * Also sets the halo the tile's LDS window covers beyond the 3-cell stencil
- * (slack, in cells, >= 1). */
+/* Tile shape of the fused path, in cells per axis (0 keeps the current
+ * one).  Compiled shapes (256 cells, one thread per cell): 3-D 8x8x4
+ * (default), 16x4x4, 4x16x4, 4x4x16, 8x4x8, 4x8x8; 2-D 16x16 (default), 32x8,
+ * 8x32; other shapes give DUST_EUNSUPPORTED.  slack is reserved (0..4). */
 dust_status_t dust_ctx_set_tile(void *ctx, int32_t tx, int32_t ty, int32_t tz, int32_t slack);
 
 /* Kernel timing of the fused path: with max_launches > 0, every dust_step

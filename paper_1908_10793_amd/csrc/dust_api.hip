@@ -69,7 +69,7 @@ struct Ctx {
   int64_t* bin_start = nullptr;   // nbins+1 (fused path)
   size_t bin_start_cap = 0;
   TileShape tile{{8, 8, 4}};
-  int slack = 1;
+  int slack = 0;
   FusedPlan plan{};
   // fused-kernel timing
   std::vector<hipEvent_t> prof_ev;  // 2 per launch
@@ -116,6 +116,7 @@ dust_status_t build_box(Ctx* c, const dust_box_t& in, int ib, int64_t cell_base,
       ax.uniform = 1;
       ax.d = 1.0;
       ax.inv_d = 1.0;
+      ax.inv_n = 1.0;
       ax.lo = 0.0;
       ax.hi = 1.0;
       ax.L = 1.0;
@@ -151,6 +152,7 @@ dust_status_t build_box(Ctx* c, const dust_box_t& in, int ib, int64_t cell_base,
     ax.uniform = maxdev <= 1e-12 * w0 ? 1 : 0;
     ax.d = ax.L / n;
     ax.inv_d = 1.0 / ax.d;
+    ax.inv_n = 1.0 / n;
     if (ax.bc_lo != DUST_BC_OPEN && !ax.uniform)
       return fail(DUST_EUNSUPPORTED, "box %d axis %d: periodic axes must be uniform", ib, d);
     ax.kind = AX_PLAIN;
@@ -503,6 +505,7 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
   for (int s = 0; s < DUST_MAX_SPECIES; ++s) {
     c->species.tau[s] = (species_tau && s < nspecies) ? species_tau[s] : INFINITY;
     c->species.mass[s] = (species_mass && s < nspecies) ? species_mass[s] : 0.0;
+    c->species.inv_tau[s] = 1.0 / c->species.tau[s];
   }
   c->have_mass_table = species_mass != nullptr && nspecies > 0;
   if (species_tau)
@@ -554,6 +557,7 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
     dust_ctx_destroy(c);
     return fail(DUST_EDEVICE, "context upload");
   }
+  if (c->ndim == 2) c->tile = TileShape{{16, 16, 1}};
   fused_plan_init(c->plan, c->boxes.data(), nbox, c->tile, c->slack);
   *ctx = c;
   return DUST_OK;
@@ -596,10 +600,10 @@ dust_status_t dust_ctx_set_tile(void* ctx, int32_t tx, int32_t ty, int32_t tz, i
     if (t[d] > 0) c->tile.t[d] = t[d];
   }
   if (slack < 0 || slack > 4) return fail(DUST_EINVAL, "slack %d out of 0..4", slack);
-  if (slack > 0) c->slack = slack;
+  c->slack = slack;
   dust_status_t s = fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
-  if (s) return fail(s, "tile %dx%dx%d with slack %d does not fit the LDS", c->tile.t[0],
-                     c->tile.t[1], c->tile.t[2], c->slack);
+  if (s) return fail(s, "tile %dx%dx%d is not one of the compiled fused tile shapes", c->tile.t[0],
+                     c->tile.t[1], c->tile.t[2]);
   return DUST_OK;
 }
 
@@ -860,7 +864,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   if (flags & DUST_STEP_FUSED) {
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
-    if (c->plan.lds_cells * 7 * real_size(c) > 160 * 1024)
+    if (fused_lds_bytes(c->plan, ctx_nc(c)) > 160 * 1024)
       return fail(DUST_EUNSUPPORTED, "fused tile window needs more than 160 KiB of LDS");
   }
   Forces F = forces_of(frc);

@@ -32,17 +32,18 @@ template <typename A> __device__ __forceinline__ A dfloor(A x);
 template <> __device__ __forceinline__ double dfloor<double>(double x) { return floor(x); }
 template <> __device__ __forceinline__ float dfloor<float>(float x) { return floorf(x); }
 
-// h - sin h without cancellation (series for small h).
+// h - sin h without cancellation (series for small h; reciprocal constants
+// instead of divisions).
 template <typename A> __device__ __forceinline__ A h_minus_sin(A h) {
   if (h < A(0.5) && h > A(-0.5)) {
     A h2 = h * h;
-    A s = A(1) - h2 / A(210);
-    s = A(1) - h2 / A(156) * s;
-    s = A(1) - h2 / A(110) * s;
-    s = A(1) - h2 / A(72) * s;
-    s = A(1) - h2 / A(42) * s;
-    s = A(1) - h2 / A(20) * s;
-    return h * h2 / A(6) * s;
+    A s = A(1) - h2 * A(1.0 / 210);
+    s = A(1) - h2 * A(1.0 / 156) * s;
+    s = A(1) - h2 * A(1.0 / 110) * s;
+    s = A(1) - h2 * A(1.0 / 72) * s;
+    s = A(1) - h2 * A(1.0 / 42) * s;
+    s = A(1) - h2 * A(1.0 / 20) * s;
+    return h * h2 * A(1.0 / 6) * s;
   }
   return h - dsin(h);
 }
@@ -59,19 +60,20 @@ template <typename A> __device__ __forceinline__ void propagator(A h, A& c, A& p
   }
   c = -dexpm1(-h);
   if (h < A(0.25)) {
-    A s = A(1) - h / A(14);
-    s = A(1) - h / A(13) * s;
-    s = A(1) - h / A(12) * s;
-    s = A(1) - h / A(11) * s;
-    s = A(1) - h / A(10) * s;
-    s = A(1) - h / A(9) * s;
-    s = A(1) - h / A(8) * s;
-    s = A(1) - h / A(7) * s;
-    s = A(1) - h / A(6) * s;
-    s = A(1) - h / A(5) * s;
-    s = A(1) - h / A(4) * s;
-    s = A(1) - h / A(3) * s;
-    psi = -h / A(2) * s;
+    // psi = sum_{k>=1} (-h)^k/(k+1)!, nested
+    A s = A(1) - h * A(1.0 / 14);
+    s = A(1) - h * A(1.0 / 13) * s;
+    s = A(1) - h * A(1.0 / 12) * s;
+    s = A(1) - h * A(1.0 / 11) * s;
+    s = A(1) - h * A(1.0 / 10) * s;
+    s = A(1) - h * A(1.0 / 9) * s;
+    s = A(1) - h * A(1.0 / 8) * s;
+    s = A(1) - h * A(1.0 / 7) * s;
+    s = A(1) - h * A(1.0 / 6) * s;
+    s = A(1) - h * A(1.0 / 5) * s;
+    s = A(1) - h * A(1.0 / 4) * s;
+    s = A(1) - h * A(1.0 / 3) * s;
+    psi = -h * A(0.5) * s;
   } else {
     psi = c / h - A(1);
   }
@@ -189,12 +191,29 @@ __device__ __forceinline__ int find_box(const Box* boxes, int nbox, int64_t cell
   return b;
 }
 
+// q = floor(a / n) for 0 <= a < 2^31, n >= 1, through FP64 (exact after one
+// correction step).
+__device__ __forceinline__ int div_small(int a, int n, double inv_n) {
+  int q = (int)(double(a) * inv_n);
+  int r = a - q * n;
+  if (r < 0) --q;
+  else if (r >= n) ++q;
+  return q;
+}
+
 __device__ __forceinline__ void unravel(const Box& b, int64_t local, int idx[3]) {
   int n0 = b.ax[0].n, n1 = b.ax[1].n;
-  idx[0] = (int)(local % n0);
-  int64_t r = local / n0;
-  idx[1] = (int)(r % n1);
-  idx[2] = b.ndim > 2 ? (int)(r / n1) : 0;
+  int l = (int)local;
+  int r = div_small(l, n0, b.ax[0].inv_n);
+  idx[0] = l - r * n0;
+  if (b.ndim > 2) {
+    int k = div_small(r, n1, b.ax[1].inv_n);
+    idx[1] = r - k * n1;
+    idx[2] = k;
+  } else {
+    idx[1] = r;
+    idx[2] = 0;
+  }
 }
 
 __device__ __forceinline__ int64_t ravel(const Box& b, const int idx[3]) {
@@ -445,10 +464,13 @@ __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
   }
 }
 
-// Inverse stopping time of a particle.
+// Inverse stopping time of a particle: species table (1/tau precomputed),
+// per-particle tau, or per-particle Stokes number St = tau Omega_K(R) with R
+// the cylindrical radius at x^{n+1/2}.
 template <typename A, int GEOM>
-__device__ __forceinline__ A inverse_tau(const Forces& f, int drag_mode, A dval,
+__device__ __forceinline__ A inverse_tau(const Forces& f, int drag_mode, A dval, A sp_inv_tau,
                                          const Where<A>& w) {
+  if (drag_mode == DRAG_SPECIES) return sp_inv_tau;
   if (drag_mode == DRAG_STOKES) {
     A R = GEOM == GEOM_SPH ? w.sc[2] : w.x[0];
     return dsqrt(A(f.GM) / (R * R * R)) / dval;

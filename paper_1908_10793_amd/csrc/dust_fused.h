@@ -20,7 +20,8 @@ struct TileDesc {
 struct FusedPlan {
   bool ok = false;
   TileShape tile{{8, 8, 4}};
-  int halo = 3;           // LDS window beyond the tile: stencil + half drift + slack
+  int shape = 0;          // index of the compiled tile shape
+  int halo = 2;           // LDS window beyond the tile: stencil + half drift
   int ntiles = 0;
   int rmax[3] = {0, 0, 0};  // largest region extents
   size_t lds_cells = 0;
@@ -29,6 +30,7 @@ struct FusedPlan {
 
 dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileShape tile, int slack);
 void fused_plan_free(FusedPlan& plan);
+size_t fused_lds_bytes(const FusedPlan& plan, int nc);
 
 template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, int nbox, int geom,

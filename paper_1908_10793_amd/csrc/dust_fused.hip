@@ -1,20 +1,22 @@
 // Fused gather - exponential-midpoint push - deposit kernel (gfx950).
 //
-// One workgroup per grid tile.  Particles are binned tile by tile (tile-major
-// keys), so a tile's particles are one contiguous range.  The workgroup
-// stages the gas velocity of the tile plus a halo in LDS, then each thread
-// takes particles: half drift, weights at x^{n+1/2}, gather from LDS, kick,
-// drag impulse and energy accumulated into an LDS copy of the deposit window
-// (the same weights as the gather), second half drift, store.  The window is
-// finally added to the global deposit arrays (scaled by the inverse cell
-// volume) with one atomic per touched cell and channel.  A particle whose
-// stencil at x^{n+1/2} leaves the window (it moved too far since the last
-// binning, or wrapped across a periodic face) takes the same arithmetic
-// against global memory instead.
-//
-// Lanes of a wave are spread across the tile's particle range (stride of a
-// few cells) so that the LDS atomics of one instruction rarely hit the same
-// cell.
+// One workgroup per grid tile of 256 cells and one thread per cell.  The
+// particles are binned tile by tile (tile-major keys), so the particles of a
+// cell are one contiguous range, and the thread of a cell walks that range.
+// The workgroup stages the gas velocity of the tile plus a two-cell halo in
+// LDS (FP64).  For every particle the thread does the half drift, the weights
+// at x^{n+1/2}, the gather from LDS, the kick, the drag impulse and energy,
+// the second half drift and the store.  Deposits of particles whose cell at
+// x^{n+1/2} is still the thread's own cell are summed in registers over the
+// 27-cell stencil of that cell; the sums go to an FP64 deposit window in LDS
+// once per thread.  Particles that moved to a neighbouring cell add their 27
+// contributions to the window with FP64 LDS atomics (gfx950 executes FP64 and
+// integer LDS atomics about twenty times faster than FP32 ones).  The window
+// is then added to the global deposit arrays with one atomic per touched cell
+// and channel, scaled by the inverse cell volume.  A particle whose stencil
+// at x^{n+1/2} leaves the window (it moved more than one cell since the last
+// binning, or wrapped across a periodic face) does the same arithmetic
+// against global memory.
 #include <algorithm>
 #include <vector>
 
@@ -26,19 +28,39 @@
 namespace dust {
 
 static constexpr int FUSED_THREADS = 256;
-static constexpr int FUSED_K = 2;  // particles per thread per chunk
-static constexpr int FUSED_CHUNK = FUSED_THREADS * FUSED_K;
+static constexpr int FUSED_HALO = 2;
+
+// Supported tile shapes (cells per axis, 256 cells each).
+struct Shape3 { int x, y, z; };
+static const Shape3 kShapes3[] = {{8, 8, 4}, {16, 4, 4}, {4, 16, 4}, {4, 4, 16}, {8, 4, 8}, {4, 8, 8}};
+static const Shape3 kShapes2[] = {{16, 16, 1}, {32, 8, 1}, {8, 32, 1}};
+
+static int shape_id(int ndim, TileShape t) {
+  if (ndim > 2) {
+    for (int s = 0; s < 6; ++s)
+      if (kShapes3[s].x == t.t[0] && kShapes3[s].y == t.t[1] && kShapes3[s].z == t.t[2]) return s;
+  } else {
+    for (int s = 0; s < 3; ++s)
+      if (kShapes2[s].x == t.t[0] && kShapes2[s].y == t.t[1]) return s;
+  }
+  return -1;
+}
 
 dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileShape tile, int slack) {
+  (void)slack;
   fused_plan_free(plan);
   plan.tile = tile;
-  plan.halo = 2 + slack;
+  plan.halo = FUSED_HALO;
+  if (nbox < 1) return DUST_EINVAL;
+  int ndim = boxes[0].ndim;
+  if (ndim == 2) plan.tile.t[2] = 1;
+  plan.shape = shape_id(ndim, plan.tile);
+  if (plan.shape < 0) return DUST_EUNSUPPORTED;
   std::vector<TileDesc> tiles;
-  int rmax[3] = {1, 1, 1};
   for (int b = 0; b < nbox; ++b) {
     const Box& B = boxes[b];
     int n[3] = {B.ax[0].n, B.ax[1].n, B.ndim > 2 ? B.ax[2].n : 1};
-    int t[3] = {tile.t[0], tile.t[1], B.ndim > 2 ? tile.t[2] : 1};
+    int t[3] = {plan.tile.t[0], plan.tile.t[1], B.ndim > 2 ? plan.tile.t[2] : 1};
     int nt[3];
     for (int d = 0; d < 3; ++d) nt[d] = (n[d] + t[d] - 1) / t[d];
     int64_t key = B.cell_base;
@@ -56,15 +78,13 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
           d.key0 = key;
           key += (int64_t)d.ex * d.ey * d.ez;
           tiles.push_back(d);
-          rmax[0] = std::max(rmax[0], d.ex + 2 * plan.halo);
-          rmax[1] = std::max(rmax[1], d.ey + 2 * plan.halo);
-          rmax[2] = std::max(rmax[2], B.ndim > 2 ? d.ez + 2 * plan.halo : 1);
         }
   }
-  for (int d = 0; d < 3; ++d) plan.rmax[d] = rmax[d];
-  plan.lds_cells = (size_t)rmax[0] * rmax[1] * rmax[2];
-  // 3 gas components + 4 deposit channels, at most 8 bytes each
-  if (plan.lds_cells * 7 * 8 > 160 * 1024 && plan.lds_cells * 7 * 4 > 160 * 1024) return DUST_EUNSUPPORTED;
+  int h2 = 2 * FUSED_HALO;
+  plan.rmax[0] = plan.tile.t[0] + h2;
+  plan.rmax[1] = plan.tile.t[1] + h2;
+  plan.rmax[2] = ndim > 2 ? plan.tile.t[2] + h2 : 1;
+  plan.lds_cells = (size_t)plan.rmax[0] * plan.rmax[1] * plan.rmax[2];
   plan.ntiles = (int)tiles.size();
   if (hipMalloc((void**)&plan.tiles_d, sizeof(TileDesc) * tiles.size()) != hipSuccess)
     return DUST_ENOMEM;
@@ -82,189 +102,226 @@ void fused_plan_free(FusedPlan& plan) {
   plan.ntiles = 0;
 }
 
-template <typename TS, typename A, int GEOM, int NDIM>
+size_t fused_lds_bytes(const FusedPlan& plan, int nc) {
+  return plan.lds_cells * (2 * nc + 1) * sizeof(double);
+}
+
+template <typename TS, typename A, int GEOM, int NDIM, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(FUSED_THREADS)
     k_fused(const TileDesc* tiles, PView<TS> p, const Box* boxes, FView<TS> fl, Forces f,
             const Species* sp, int drag_mode, A dt, const double* tdev, const int64_t* bin_start,
-            int halo, DiagDev* dg, int sums) {
+            DiagDev* dg, int sums) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
-  extern __shared__ unsigned char smem_raw[];
-  TS* smem = reinterpret_cast<TS*>(smem_raw);
+  constexpr int H = FUSED_HALO;
+  constexpr int HZ = NDIM > 2 ? H : 0;
+  constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RZ = TZ + 2 * HZ;
+  constexpr int RC = RX * RY * RZ;
+  extern __shared__ double smem[];
+  double* gas = smem;                 // nc * RC
+  double* dep = smem + nc * RC;       // (nc+1) * RC
   const TileDesc td = tiles[blockIdx.x];
   const Box& B = boxes[td.box];
-  const int hz = NDIM > 2 ? halo : 0;
-  const int rx = td.ex + 2 * halo, ry = td.ey + 2 * halo, rz = td.ez + 2 * hz;
-  const int rcells = rx * ry * rz;
-  const int ox = td.i0 - halo, oy = td.j0 - halo, oz = td.k0 - hz;  // region origin
-  TS* gas = smem;                       // nc * rcells
-  TS* dep = smem + (size_t)nc * rcells; // (nc+1) * rcells
+  const int ox = td.i0 - H, oy = td.j0 - H, oz = td.k0 - HZ;  // window origin
   const double t0 = *tdev;
   const A h = A(0.5) * dt;
   const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = NDIM > 2 ? B.ax[2].n : 1;
 
-  // stage gas, clear deposit window
-  for (int r = threadIdx.x; r < rcells; r += FUSED_THREADS) {
-    int a = r % rx, bq = (r / rx) % ry, cq = r / (rx * ry);
+  // stage the gas window, clear the deposit window
+  for (int r = threadIdx.x; r < RC; r += FUSED_THREADS) {
+    int a = r % RX, bq = (r / RX) % RY, cq = r / (RX * RY);
     int i = ox + a, j = oy + bq, k = oz + cq;
     bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && (NDIM < 3 || (k >= -1 && k <= n2));
     int64_t id = in ? stored_index(B, i, j, k) : 0;
 #pragma unroll
-    for (int m = 0; m < nc; ++m) gas[m * rcells + r] = in ? fl.vel[m][id] : TS(0);
+    for (int m = 0; m < nc; ++m) gas[m * RC + r] = in ? double(fl.vel[m][id]) : 0.0;
 #pragma unroll
-    for (int m = 0; m <= nc; ++m) dep[m * rcells + r] = TS(0);
+    for (int m = 0; m <= nc; ++m) dep[m * RC + r] = 0.0;
   }
   __syncthreads();
 
-  const int64_t ps = bin_start[td.key0];
-  const int64_t pe = bin_start[td.key0 + (int64_t)td.ex * td.ey * td.ez];
+  // this thread's cell
+  const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+  const bool own = lx < td.ex && ly < td.ey && lz < td.ez;
+  const int mycell[3] = {td.i0 + lx, td.j0 + ly, td.k0 + lz};
+  const int mybase = (lx + H) + RX * ((ly + H) + RY * (lz + HZ));  // window index of my cell
+  int64_t ps = 0, pe = 0;
+  if (own) {
+    int64_t key = td.key0 + lx + (int64_t)td.ex * (ly + (int64_t)td.ey * lz);
+    ps = bin_start[key];
+    pe = bin_start[key + 1];
+  }
+  float acc[27][nc + 1];
+#pragma unroll
+  for (int o = 0; o < 27; ++o)
+#pragma unroll
+    for (int k = 0; k <= nc; ++k) acc[o][k] = 0.f;
   double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0, s_cells = 0;
   unsigned long long n_fb = 0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-  for (int64_t cs = ps; cs < pe; cs += FUSED_CHUNK) {
-#pragma unroll 1
-    for (int r = 0; r < FUSED_K; ++r) {
-      // lanes spread FUSED_K*4 particles apart inside the chunk
-      int64_t i = cs + (int64_t)lane * (4 * FUSED_K) + wv * FUSED_K + r;
-      if (i >= pe) continue;
-      int idx[3];
-      A off[3], mom[3];
-      int32_t cid = p.cell[i];
-      if (cid < 0 || cid < B.cell_base || cid >= B.cell_base + B.ncell) {
-        if (cid >= 0) flag(dg, DUST_FLAG_BAD_CELL);
-        continue;
-      }
-      unravel(B, cid - B.cell_base, idx);
-      bool bad = false;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
-        mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
-        bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
-      }
-      if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
-      // half drift to x^{n+1/2}
-      if (!drift<A, GEOM, NDIM>(B, f, true, h, t0 + double(h), idx, off, mom)) {
-        store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(h), i, false, idx, off, mom, dg);
-        continue;
-      }
-      // weights at x^{n+1/2}
-      Stencil<A> s;
-      stencil_weights<A, NDIM>(B, idx, off, s);
-      const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
-      const bool inside = la >= 1 && la <= rx - 2 && lb >= 1 && lb <= ry - 2 &&
-                          (c2 == 0 || (lc >= 1 && lc <= rz - 2));
-      // gather (Eq. Delta_vp)
-      A v[3] = {A(0), A(0), A(0)};
-      if (inside) {
-        const int base = la + rx * (lb + ry * lc);
-#pragma unroll
-        for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-          for (int bb = -1; bb <= 1; ++bb) {
-            A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-              A w = s.w[0][a + 1] * wbc;
-              int r0 = base + a + rx * (bb + ry * c);
-#pragma unroll
-              for (int m = 0; m < nc; ++m) v[m] += w * A(gas[m * rcells + r0]);
-            }
-          }
-      } else {
-#pragma unroll
-        for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-          for (int bb = -1; bb <= 1; ++bb) {
-            A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-              A w = s.w[0][a + 1] * wbc;
-              int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
-#pragma unroll
-              for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
-            }
-          }
-      }
-      // kick
-      Where<A> wh;
-      where<A, GEOM, NDIM>(B, idx, off, wh);
-      A pg[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) pg[m] = m < nc ? v[m] * wh.sc[m] : A(0);
-      int spc = p.species ? p.species[i] : 0;
-      if (spc >= sp->n) {
-        flag(dg, DUST_FLAG_BAD_CELL);
-        spc = 0;
-      }
-      A dval = drag_mode == DRAG_SPECIES ? A(sp->tau[spc]) : A(p.drag[i]);
-      A m = p.mass ? A(p.mass[i]) : A(sp->mass[spc]);
-      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, wh);
-      KickOut<A> o;
-      kick<A, GEOM, NDIM>(B, f, dt, it, wh, mom, pg, o);
-      A q[4] = {A(0), A(0), A(0), A(0)};
-#pragma unroll
-      for (int k = 0; k < nc; ++k) {
-        q[k] = m * o.j[k];
-        if (sums) {
-          A vbar = (mom[k] + A(0.5) * o.dp[k]) / wh.sc[k];
-          A dl = cell_width<A>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
-          double cps = fabs(double(vbar * dt / dl));
-          s_cells = cps > s_cells ? cps : s_cells;
-          s_j[k] += double(q[k]);
-          s_abs += fabs(double(q[k]));
-        }
-        mom[k] += o.dp[k];
-      }
-      q[nc] = m * o.e;
-      if (sums) s_e += double(q[nc]);
-      // deposit (Eq. dust_feedback_final), same weights and cells as the gather
-      if (inside) {
-        const int base = la + rx * (lb + ry * lc);
-        TS qs[4];
-#pragma unroll
-        for (int k = 0; k <= nc; ++k) qs[k] = TS(-q[k]);
-#pragma unroll
-        for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-          for (int bb = -1; bb <= 1; ++bb) {
-            A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-              TS w = TS(s.w[0][a + 1] * wbc);
-              int r0 = base + a + rx * (bb + ry * c);
-#pragma unroll
-              for (int k = 0; k <= nc; ++k) atomicAdd(&dep[k * rcells + r0], w * qs[k]);
-            }
-          }
-      } else {
-        ++n_fb;
-#pragma unroll
-        for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-          for (int bb = -1; bb <= 1; ++bb) {
-            A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-              int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
-              A w = s.w[0][a + 1] * wbc * A(inv_volume(B, ii, jj, kk));
-              int64_t id = stored_index(B, ii, jj, kk);
-#pragma unroll
-              for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(-w * q[k]));
-            }
-          }
-      }
-      // second half drift to x^{n+1}
-      bool alive = drift<A, GEOM, NDIM>(B, f, false, h, t0 + double(dt), idx, off, mom);
-      store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+  for (int64_t i = ps; i < pe; ++i) {
+    int idx[3];
+    A off[3], mom[3];
+    int32_t cid = p.cell[i];
+    if (cid < 0 || cid < B.cell_base || cid >= B.cell_base + B.ncell) {
+      if (cid >= 0) flag(dg, DUST_FLAG_BAD_CELL);
+      continue;
     }
+    unravel(B, cid - B.cell_base, idx);
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
+      mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+      bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
+    }
+    if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+    // half drift to x^{n+1/2}
+    if (!drift<A, GEOM, NDIM>(B, f, true, h, t0 + double(h), idx, off, mom)) {
+      store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(h), i, false, idx, off, mom, dg);
+      continue;
+    }
+    // weights at x^{n+1/2}
+    Stencil<A> s;
+    stencil_weights<A, NDIM>(B, idx, off, s);
+    const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
+    const bool inside = la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
+                        (c2 == 0 || (lc >= 1 && lc <= RZ - 2));
+    const bool home = idx[0] == mycell[0] && idx[1] == mycell[1] && (c2 == 0 || idx[2] == mycell[2]);
+    A w27[27];
+#pragma unroll
+    for (int c = -1; c <= 1; ++c)
+#pragma unroll
+      for (int bb = -1; bb <= 1; ++bb) {
+        A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))] = s.w[0][a + 1] * wbc;
+      }
+    // gather (Eq. Delta_vp)
+    A v[3] = {A(0), A(0), A(0)};
+    if (inside) {
+      const int base = la + RX * (lb + RY * lc);
+#pragma unroll
+      for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            A w = w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))];
+            int r0 = base + a + RX * (bb + RY * c);
+#pragma unroll
+            for (int m = 0; m < nc; ++m) v[m] += w * A(gas[m * RC + r0]);
+          }
+    } else {
+#pragma unroll
+      for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            A w = w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))];
+            int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
+#pragma unroll
+            for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
+          }
+    }
+    // kick
+    Where<A> wh;
+    where<A, GEOM, NDIM>(B, idx, off, wh);
+    A pg[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) pg[m] = m < nc ? v[m] * wh.sc[m] : A(0);
+    int spc = p.species ? p.species[i] : 0;
+    if (spc >= sp->n) {
+      flag(dg, DUST_FLAG_BAD_CELL);
+      spc = 0;
+    }
+    A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
+    A m = p.mass ? A(p.mass[i]) : A(sp->mass[spc]);
+    A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[spc]), wh);
+    KickOut<A> o;
+    kick<A, GEOM, NDIM>(B, f, dt, it, wh, mom, pg, o);
+    A q[4] = {A(0), A(0), A(0), A(0)};
+#pragma unroll
+    for (int k = 0; k < nc; ++k) {
+      q[k] = -m * o.j[k];  // deposits carry the minus sign of Eq. dust_feedback_final
+      if (sums) {
+        A vbar = (mom[k] + A(0.5) * o.dp[k]) / wh.sc[k];
+        A dl = cell_width<A>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
+        double cps = fabs(double(vbar * dt / dl));
+        s_cells = cps > s_cells ? cps : s_cells;
+        s_j[k] -= double(q[k]);
+        s_abs += fabs(double(q[k]));
+      }
+      mom[k] += o.dp[k];
+    }
+    q[nc] = -m * o.e;
+    if (sums) s_e -= double(q[nc]);
+    // deposit (same weights and cells as the gather)
+    if (home) {
+      float qf[4];
+#pragma unroll
+      for (int k = 0; k <= nc; ++k) qf[k] = float(q[k]);
+#pragma unroll
+      for (int oo = 0; oo < 27; ++oo) {
+        if (c2 == 0 && (oo < 9 || oo >= 18)) continue;
+        float w = float(w27[oo]);
+#pragma unroll
+        for (int k = 0; k <= nc; ++k) acc[oo][k] += w * qf[k];
+      }
+    } else if (inside) {
+      const int base = la + RX * (lb + RY * lc);
+#pragma unroll
+      for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            double w = double(w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))]);
+            int r0 = base + a + RX * (bb + RY * c);
+#pragma unroll
+            for (int k = 0; k <= nc; ++k) atomicAdd(&dep[k * RC + r0], w * double(q[k]));
+          }
+    } else {
+      ++n_fb;
+#pragma unroll
+      for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
+            A w = w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))] * A(inv_volume(B, ii, jj, kk));
+            int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
+            for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(w * q[k]));
+          }
+    }
+    // second half drift to x^{n+1}
+    bool alive = drift<A, GEOM, NDIM>(B, f, false, h, t0 + double(dt), idx, off, mom);
+    store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+  }
+
+  // register sums of my cell's stencil -> deposit window
+  if (own) {
+#pragma unroll
+    for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+      for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+          int oo = (a + 1) + 3 * ((bb + 1) + 3 * (c + 1));
+          int r0 = mybase + a + RX * (bb + RY * c);
+#pragma unroll
+          for (int k = 0; k <= nc; ++k)
+            if (acc[oo][k] != 0.f) atomicAdd(&dep[k * RC + r0], double(acc[oo][k]));
+        }
   }
   __syncthreads();
 
   // add the deposit window to the grid
-  for (int r = threadIdx.x; r < rcells; r += FUSED_THREADS) {
-    int a = r % rx, bq = (r / rx) % ry, cq = r / (rx * ry);
+  for (int r = threadIdx.x; r < RC; r += FUSED_THREADS) {
+    int a = r % RX, bq = (r / RX) % RY, cq = r / (RX * RY);
     int i = ox + a, j = oy + bq, k = oz + cq;
     bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && (NDIM < 3 || (k >= -1 && k <= n2));
     if (!in) continue;
@@ -272,12 +329,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     double iv = inv_volume(B, i, j, k);
 #pragma unroll
     for (int m = 0; m <= nc; ++m) {
-      TS x = dep[m * rcells + r];
-      if (x != TS(0)) unsafeAtomicAdd(&fl.dep[m][id], TS(double(x) * iv));
+      double x = dep[m * RC + r];
+      if (x != 0.0) unsafeAtomicAdd(&fl.dep[m][id], TS(x * iv));
     }
   }
 
   if (dg) {
+    const int lane = threadIdx.x & 63;
     if (sums) {
       for (int k = 0; k < 3; ++k) s_j[k] = wave_sum(s_j[k]);
       s_e = wave_sum(s_e);
@@ -301,24 +359,51 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   }
 }
 
+template <typename TS, typename A, int GEOM, int NDIM, int TX, int TY, int TZ>
+static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
+                           const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
+                           double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
+                           bool sums, hipStream_t st) {
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  size_t lds = fused_lds_bytes(plan, nc);
+  auto kern = k_fused<TS, A, GEOM, NDIM, TX, TY, TZ>;
+  if (lds > 64 * 1024) {
+    static bool raised = false;
+    if (!raised) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, boxes_d,
+                     fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg, (int)sums);
+}
+
 template <typename TS, typename A, int GEOM, int NDIM>
 static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
                            bool sums, hipStream_t st) {
-  size_t lds = plan.lds_cells * 7 * sizeof(TS);
-  if (lds > 160 * 1024) return;  // rejected on the host before any launch
-  if (lds > 64 * 1024) {
-    static bool raised = false;
-    if (!raised) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<TS, A, GEOM, NDIM>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      raised = true;
+#define DUST_F(TX, TY, TZ)                                                                         \
+  launch_fused_t<TS, A, GEOM, NDIM, TX, TY, TZ>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev,  \
+                                                bin_start, dg, sums, st)
+  if constexpr (NDIM == 3) {
+    switch (plan.shape) {
+      case 0: DUST_F(8, 8, 4); break;
+      case 1: DUST_F(16, 4, 4); break;
+      case 2: DUST_F(4, 16, 4); break;
+      case 3: DUST_F(4, 4, 16); break;
+      case 4: DUST_F(8, 4, 8); break;
+      default: DUST_F(4, 8, 8); break;
+    }
+  } else {
+    switch (plan.shape) {
+      case 0: DUST_F(16, 16, 1); break;
+      case 1: DUST_F(32, 8, 1); break;
+      default: DUST_F(8, 32, 1); break;
     }
   }
-  hipLaunchKernelGGL((k_fused<TS, A, GEOM, NDIM>), dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st,
-                     plan.tiles_d, p, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start,
-                     plan.halo, dg, (int)sums);
+#undef DUST_F
 }
 
 template <typename TS, typename A>

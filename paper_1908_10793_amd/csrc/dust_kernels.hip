@@ -89,9 +89,9 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
         flag(dg, DUST_FLAG_BAD_CELL);
         s = 0;
       }
-      A dval = drag_mode == DRAG_SPECIES ? A(sp->tau[s]) : A(p.drag[i]);
+      A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
       A m = p.mass ? A(p.mass[i]) : A(sp->mass[s]);
-      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, w);
+      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[s]), w);
       KickOut<A> o;
       kick<A, GEOM, NDIM>(B, f, dt, it, w, mom, pg, o);
       TW* imp[4] = {imp0, imp1, imp2, imp3};

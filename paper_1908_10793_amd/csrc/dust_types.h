@@ -22,6 +22,7 @@ enum { AX_PLAIN = 0, AX_CYL_R = 1, AX_SPH_R = 2, AX_THETA = 3 };
 struct Axis {
   int32_t n, bc_lo, bc_hi, shape, uniform, kind;
   double lo, hi, L, d, inv_d;   // domain and (uniform axes) cell width
+  double inv_n;                 // 1/n (index arithmetic)
   const double *faces;          // device: face k at faces[k+1], k = -1 .. n+1
   const double *ivol;           // device: inverse volume factor of cell k at ivol[k+1]
 };
@@ -45,6 +46,7 @@ struct Forces {
 struct Species {
   int32_t n;
   double tau[DUST_MAX_SPECIES];
+  double inv_tau[DUST_MAX_SPECIES];  // 1/tau (0 for tau = +inf)
   double mass[DUST_MAX_SPECIES];
 };
 
