@@ -151,11 +151,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     ps = bin_start[key];
     pe = bin_start[key + 1];
   }
-  float acc[27][nc + 1];
+  // register sums: FP32 for FP32 storage, FP64 for FP64 storage
+  using TAcc = TS;
+  TAcc acc[27][nc + 1];
 #pragma unroll
   for (int o = 0; o < 27; ++o)
 #pragma unroll
-    for (int k = 0; k <= nc; ++k) acc[o][k] = 0.f;
+    for (int k = 0; k <= nc; ++k) acc[o][k] = TAcc(0);
   double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0, s_cells = 0;
   unsigned long long n_fb = 0;
 
@@ -259,13 +261,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     if (sums) s_e -= double(q[nc]);
     // deposit (same weights and cells as the gather)
     if (home) {
-      float qf[4];
+      TAcc qf[4];
 #pragma unroll
-      for (int k = 0; k <= nc; ++k) qf[k] = float(q[k]);
+      for (int k = 0; k <= nc; ++k) qf[k] = TAcc(q[k]);
 #pragma unroll
       for (int oo = 0; oo < 27; ++oo) {
         if (c2 == 0 && (oo < 9 || oo >= 18)) continue;
-        float w = float(w27[oo]);
+        TAcc w = TAcc(w27[oo]);
 #pragma unroll
         for (int k = 0; k <= nc; ++k) acc[oo][k] += w * qf[k];
       }
@@ -314,7 +316,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
           int r0 = mybase + a + RX * (bb + RY * c);
 #pragma unroll
           for (int k = 0; k <= nc; ++k)
-            if (acc[oo][k] != 0.f) atomicAdd(&dep[k * RC + r0], double(acc[oo][k]));
+            if (acc[oo][k] != TAcc(0)) atomicAdd(&dep[k * RC + r0], double(acc[oo][k]));
         }
   }
   __syncthreads();
