@@ -86,8 +86,14 @@ def test_fused_step_matches_oracle(name):
 
 
 def test_fused_with_other_tile_shapes():
-    _run("shearing_box", fused=True, nsteps=2, tile=(4, 16, 2, 1))
-    _run("batched_boxes", fused=True, nsteps=2, tile=(5, 3, 7, 2))
+    _run("shearing_box", fused=True, nsteps=2, tile=(4, 16, 4, 0))
+    _run("batched_boxes", fused=True, nsteps=2, tile=(4, 4, 16, 0))
+    _run("spherical_disk", fused=True, nsteps=1, tile=(8, 4, 8, 0))
+    dust = _dust()
+    ctx = dust.context_for(small("shearing_box"))
+    with pytest.raises(dust.DustError) as e:
+        ctx.set_tile(5, 3, 7, 0)
+    assert e.value.code == -5
 
 
 def test_fp32_arithmetic_variant_runs():

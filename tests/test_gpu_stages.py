@@ -27,7 +27,7 @@ def test_bin_is_bit_exact_stable_sort(n, mode):
     dust = _dust()
     w = synth.batched_boxes(sizes=(7, 12, 5), max_per_species=1)
     ctx = dust.context_for(w)
-    ctx.set_tile(4, 5, 3, 1)
+    ctx.set_tile(4, 16, 4, 0)
     _, C = ctx.grid_size()
     cells = RNG.integers(-1, C, size=n).astype(np.int32)
     cells[RNG.random(n) < 0.05] = -1
@@ -44,7 +44,7 @@ def test_bin_is_bit_exact_stable_sort(n, mode):
         for b, bd in enumerate(w.boxes):
             lo, hi = bases[b], bases[b] + int(np.prod(bd["n"]))
             m = (cells >= lo) & (cells < hi)
-            keys[m] = lo + O.tile_major_keys(cells[m] - lo, bd["n"], (4, 5, 3))
+            keys[m] = lo + O.tile_major_keys(cells[m] - lo, bd["n"], (4, 16, 4))
     ref_perm, ref_start = O.bin_reference(keys, C)
     assert np.array_equal(perm.cpu().numpy(), ref_perm)
     assert np.array_equal(start.cpu().numpy(), ref_start)
