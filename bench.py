@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--unfused", action="store_true", help="time the unfused per-phase chain")
+    ap.add_argument("--arith", choices=("f64", "f32"), default="f32",
+                    help="per-particle arithmetic of the FP32-storage path")
     return ap.parse_args()
 
 
@@ -98,6 +100,7 @@ def main():
     ctx = dust.context_for(w)
     tx, ty, tz, slack = (int(v) for v in args.tile.split(","))
     ctx.set_tile(tx, ty, tz, slack)
+    ctx.set_arith(args.arith)
     P, F = dust.upload(w, ctx, with_id=False)
     flags = (dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG | dust.STEP_REBIN_EVERY(args.rebin_every))
     if not args.unfused:
@@ -155,13 +158,14 @@ def main():
         "metric": "particle-steps/s (gather+exp-midpoint push+deposit)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": args.arith, "data": "synthetic",
         "config": {"workload": f"shearing_box {n}^3 standard shearing box, {N} particles "
-                               f"(8/cell, seeded sub-lattice), TSC, FP32 storage, FP64 push "
+                               f"(8/cell, seeded sub-lattice), TSC, FP32 storage, {args.arith.upper()} push "
                                f"arithmetic, dt=0.005, feedback on",
                    "n_particles": N, "grid": [n, n, n], "tile": [tx, ty, tz], "slack": slack,
                    "rebin_every": args.rebin_every, "fused": not args.unfused, "graph": False,
-                   "storage": "f32", "push_arith": "f64", "deposit_accum": "f32"},
+                   "storage": "f32", "push_arith": args.arith,
+                   "deposit_accum": "f32 registers per cell, f64 LDS tile window, f32 HBM atomics"},
         "roofline": roof,
         "graph_value": graph_value,
         "diag": {"momentum_residual": res, "max_cells_per_step": diag["max_cells_per_step"],

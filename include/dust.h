@@ -178,9 +178,18 @@ dust_status_t dust_ctx_create(void **ctx, int device, const dust_box_t *boxes, i
 /* Free the context and its workspace (waits for its work to finish). */
 dust_status_t dust_ctx_destroy(void *ctx);
 
-/* Push-arithmetic precision of an F32 context (DUST_ARITH_F64 default: the
- * per-particle arithmetic runs in FP64 registers, storage stays FP32;
- * DUST_ARITH_F32 keeps everything FP32).  Ignored for F64 contexts. */
+/* Per-particle arithmetic of an F32 context in the fused step and in the
+ * stage calls (dust_gather, dust_push_expmid, dust_deposit).
+ * DUST_ARITH_F32 (default for Cartesian boxes): FP32 registers; the fused
+ * kernel forms the slip p_g - p as a weighted sum of differences, which keeps
+ * its relative accuracy where the velocities are much larger than the slip.
+ * DUST_ARITH_F64 (default for cylindrical and spherical boxes): FP64
+ * registers, the stored state staying FP32; needed where a particle close to
+ * co-rotation has a slip far below the FP32 resolution of its angular
+ * momentum.
+ * The unfused chain of dust_step always computes in FP64 (its gathered
+ * velocities and impulses pass through memory).  Ignored for F64 contexts.
+ * Returns DUST_EINVAL for another value. */
 dust_status_t dust_ctx_set_arith(void *ctx, int32_t arith);
 
 /* Tile shape of the fused path, in cells per axis (0 keeps the current

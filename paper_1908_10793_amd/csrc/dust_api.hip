@@ -44,12 +44,13 @@ struct GraphKey {
 struct Ctx {
   int device = 0;
   int prec = DUST_F32;
-  int arith = DUST_ARITH_F64;
+  int arith = DUST_ARITH_F32;
   int drag_mode = DUST_DRAG_TAU;
   Species species{};
   Species* species_d = nullptr;
   bool have_mass_table = false;
   int geom = 0, ndim = 3;         // shared by every box
+  int unif = 0;                   // Cartesian boxes whose axes are all uniform
   int nbox = 0;
   std::vector<Box> boxes;         // host copies (device table pointers inside)
   Box* boxes_d = nullptr;
@@ -376,11 +377,11 @@ template <typename TS, typename A>
 void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phases,
               const TS* const vg[3], TS* const imp[4], DiagDev* dg, hipStream_t st) {
   if (phases & DUST_PHASE_DRIFT1)
-    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
+    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
   if (phases & DUST_PHASE_KICK)
-    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, c->species_d, c->drag_mode, dt, vg, imp, dg, st);
+    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, vg, imp, dg, st);
   if (phases & DUST_PHASE_DRIFT2)
-    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
+    launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
 }
 
 // One unfused step (time in c->tdev[0] at the start of the step).
@@ -399,14 +400,14 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
-  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
-  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, fv, (A*)nullptr, vg, dflags, st);
+  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
+  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, (A*)nullptr, vg, dflags, st);
   const A* cvg[3] = {vg[0], vg[1], vg[2]};
-  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, c->species_d, c->drag_mode, dt, cvg, imp,
+  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, cvg, imp,
                         dg ? dg : dflags, st);
   const A* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
-  launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, fv, cimp, dflags, st);
-  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
+  launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, cimp, dflags, st);
+  launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
   if (dg)
     for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
   for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
@@ -430,7 +431,7 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
   bool prof = c->prof_used < c->prof_max;
   if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
-  launch_fused<TS, A>(c->plan, pv, c->boxes_d, c->nbox, c->geom, c->ndim, fv, F, c->species_d,
+  launch_fused<TS, A>(c->plan, pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, F, c->species_d,
                       c->drag_mode, dt, c->tdev, c->bin_start, c->diag, dg != nullptr, st);
   if (prof) {
     HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
@@ -456,7 +457,9 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
       dust_status_t e = fused_step<TS, A>(c, p, pv, fv, F, dt, flags, s % rebin_every == 0, st);
       if (e) return e;
     } else {
-      unfused_step<TS, A>(c, pv, fv, F, dt, flags, st);
+      // the unfused chain passes gathered velocities and impulses through
+      // memory, where FP32 would lose the slip: it computes in FP64
+      unfused_step<TS, double>(c, pv, fv, F, dt, flags, st);
     }
     launch_advance_time(c->tdev, dt, st);
     if (flags & DUST_STEP_DIAG) launch_count_step(c->diag, st);
@@ -538,6 +541,16 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
       dust_ctx_destroy(c);
       return fail(DUST_EUNSUPPORTED, "all boxes of a context must share geometry and ndim");
     }
+  // FP32 push arithmetic where the slip form keeps the slip accurate
+  // (Cartesian boxes, where large velocities come from a smooth background
+  // flow that the weights reproduce); FP64 in curvilinear boxes, where a
+  // particle close to co-rotation has a slip far below the FP32 resolution
+  // of its angular momentum
+  c->arith = c->geom == GEOM_CART ? DUST_ARITH_F32 : DUST_ARITH_F64;
+  c->unif = c->geom == GEOM_CART ? 1 : 0;
+  for (int b = 0; b < nbox; ++b)
+    for (int d = 0; d < c->ndim; ++d)
+      if (!c->boxes[b].ax[d].uniform) c->unif = 0;
   c->n_active = cell_base;
   c->n_stored = store_base;
   if (cell_base >= 0x7fffffffLL) {
@@ -759,7 +772,7 @@ dust_status_t dust_gather(void* ctx, const dust_particles_t* p, const dust_field
     using A = decltype(ta);
     TS* vg[3] = {nullptr, nullptr, nullptr};
     for (int k = 0; k < nc; ++k) vg[k] = (TS*)vg_p[k];
-    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
+    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -821,7 +834,7 @@ dust_status_t dust_deposit(void* ctx, const dust_particles_t* p, const void* con
     using A = decltype(ta);
     const TS* imp[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k <= nc; ++k) imp[k] = (const TS*)impulse[k];
-    launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, fview<TS>(f), imp, c->diag, st);
+    launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), imp, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });

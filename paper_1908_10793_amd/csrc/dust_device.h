@@ -81,13 +81,23 @@ template <typename A> __device__ __forceinline__ void propagator(A h, A& c, A& p
 
 // ---------------------------------------------------------------- geometry
 
+// Weight formula of axis d of a geometry (known at compile time, so that a
+// kernel carries only the formulas of its own geometry).
+constexpr int axis_kind(int geom, int d) {
+  return geom == GEOM_CYL ? (d == 0 ? AX_CYL_R : AX_PLAIN)
+       : geom == GEOM_SPH ? (d == 0 ? AX_SPH_R : (d == 1 ? AX_THETA : AX_PLAIN))
+       : AX_PLAIN;
+}
+
 // Coordinate of the centre and width of cell i (i in [-1, n]) on an axis.
-template <typename A> __device__ __forceinline__ A cell_centre(const Axis& ax, int i) {
-  if (ax.uniform) return A(ax.lo + (double(i) + 0.5) * ax.d);
+// U: every axis of the boxes is known to be uniform (no face table needed);
+// otherwise uniformity is read from the axis.
+template <typename A, bool U> __device__ __forceinline__ A cell_centre(const Axis& ax, int i) {
+  if (U || ax.uniform) return A(ax.lo + (double(i) + 0.5) * ax.d);
   return A(0.5 * (ax.faces[i + 1] + ax.faces[i + 2]));
 }
-template <typename A> __device__ __forceinline__ A cell_width(const Axis& ax, int i) {
-  if (ax.uniform) return A(ax.d);
+template <typename A, bool U> __device__ __forceinline__ A cell_width(const Axis& ax, int i) {
+  if (U || ax.uniform) return A(ax.d);
   return A(ax.faces[i + 2] - ax.faces[i + 1]);
 }
 
@@ -96,10 +106,10 @@ template <typename A> __device__ __forceinline__ A cell_width(const Axis& ax, in
 // host cell's width; what lies beyond the host cell's faces goes to the
 // neighbour on that side, so sum w = 1 up to rounding and the middle weight
 // is 1 - w[0] - w[2].
-template <typename A>
+template <typename A, int KIND, bool U>
 __device__ __forceinline__ void axis_weights(const Axis& ax, int i, A delta, A w[3]) {
   const A half = A(0.5);
-  if (ax.kind == AX_PLAIN) {
+  if constexpr (KIND == AX_PLAIN) {
     if (ax.shape == SHAPE_CIC) {
       w[0] = delta < A(0) ? -delta : A(0);
       w[2] = delta > A(0) ? delta : A(0);
@@ -108,9 +118,9 @@ __device__ __forceinline__ void axis_weights(const Axis& ax, int i, A delta, A w
       w[0] = half * m * m;
       w[2] = half * p * p;
     }
-  } else if (ax.kind == AX_CYL_R) {
+  } else if constexpr (KIND == AX_CYL_R) {
     // Eq. CIC_cylindrical / TSC_cylindrical, nu = R_i / Delta R_i
-    A nu = cell_centre<A>(ax, i) / cell_width<A>(ax, i);
+    A nu = cell_centre<A, U>(ax, i) / cell_width<A, U>(ax, i);
     if (ax.shape == SHAPE_CIC) {
       A den = A(2) * (delta + nu);
       w[0] = delta < A(0) ? (delta + A(2) * nu - A(1)) / den * (-delta) : A(0);
@@ -121,9 +131,9 @@ __device__ __forceinline__ void axis_weights(const Axis& ax, int i, A delta, A w
       w[0] = (delta + A(3) * nu - A(2)) / den * half * m * m;
       w[2] = (delta + A(3) * nu + A(2)) / den * half * p * p;
     }
-  } else if (ax.kind == AX_SPH_R) {
+  } else if constexpr (KIND == AX_SPH_R) {
     // App. C: Eq. CIC_spherical_r / TSC_spherical_r
-    A nu = cell_centre<A>(ax, i) / cell_width<A>(ax, i);
+    A nu = cell_centre<A, U>(ax, i) / cell_width<A, U>(ax, i);
     A dn = delta + nu;
     if (ax.shape == SHAPE_CIC) {
       A den = A(12) * dn * dn + A(1);
@@ -147,7 +157,7 @@ __device__ __forceinline__ void axis_weights(const Axis& ax, int i, A delta, A w
     // theta axis, metric sin(theta): App. C Eq. CIC_spherical_theta (minus
     // branch sign corrected) in product form, and the TSC analogue from the
     // antiderivative of (1 -+ (t - t_p)/D) sin t.
-    A tc = cell_centre<A>(ax, i), D = cell_width<A>(ax, i);
+    A tc = cell_centre<A, U>(ax, i), D = cell_width<A, U>(ax, i);
     A tp = tc + delta * D;
     A sp = dsin(tp), sh = dsin(half * D);
     if (ax.shape == SHAPE_CIC) {
@@ -226,10 +236,10 @@ __device__ __forceinline__ int64_t ravel(const Box& b, const int idx[3]) {
 
 // Move along axis d by a coordinate increment dxi.  Returns the new cell
 // index, which may fall outside [0, n) (the caller applies the boundary).
-template <typename A>
+template <typename A, bool U>
 __device__ __forceinline__ int move_axis(const Axis& ax, int i, A& delta, A dxi) {
   const A half = A(0.5);
-  if (ax.uniform) {
+  if (U || ax.uniform) {
     A dn = delta + dxi * A(ax.inv_d);
     if (dn >= half || dn < -half) {
       A k = dfloor(dn + half);
@@ -241,7 +251,7 @@ __device__ __forceinline__ int move_axis(const Axis& ax, int i, A& delta, A dxi)
     delta = dn;
     return i;
   }
-  A dn = delta + dxi / cell_width<A>(ax, i);
+  A dn = delta + dxi / cell_width<A, U>(ax, i);
   if (dn < half && dn >= -half) {
     delta = dn;
     return i;
@@ -301,13 +311,13 @@ __device__ __forceinline__ void shear_image(const Box& b, const Forces& f, doubl
 // theta) already moved to n+1/2; otherwise all metric factors are those at
 // the start of this half drift.  t_after: time the boundary rules use.
 // Returns false if the particle left through an open face.
-template <typename A, int GEOM, int NDIM>
+template <typename A, int GEOM, int NDIM, bool U>
 __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first, A h,
                                       double t_after, int idx[3], A off[3], A mom[3]) {
   if constexpr (GEOM == GEOM_CART) {
     A dx[3] = {h * mom[0], h * mom[1], NDIM > 2 ? h * mom[2] : A(0)};
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) idx[d] = move_axis<A>(b.ax[d], idx[d], off[d], dx[d]);
+    for (int d = 0; d < NDIM; ++d) idx[d] = move_axis<A, U>(b.ax[d], idx[d], off[d], dx[d]);
     if (NDIM == 3 && b.ax[0].bc_lo == BC_SHEAR) shear_image<A>(b, f, t_after, idx, off, mom);
 #pragma unroll
     for (int d = 0; d < NDIM; ++d)
@@ -316,34 +326,34 @@ __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first,
   }
   if constexpr (GEOM == GEOM_CYL) {
     if (first) {
-      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+      idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
       if (!wrap_plain<A>(b.ax[0], idx[0])) return false;
-      A R = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
-      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (R * R));
-      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2]);
+      A R = cell_centre<A, U>(b.ax[0], idx[0]) + off[0] * cell_width<A, U>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A, U>(b.ax[1], idx[1], off[1], h * mom[1] / (R * R));
+      idx[2] = move_axis<A, U>(b.ax[2], idx[2], off[2], h * mom[2]);
     } else {
-      A R = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
-      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (R * R));
-      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
-      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2]);
+      A R = cell_centre<A, U>(b.ax[0], idx[0]) + off[0] * cell_width<A, U>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A, U>(b.ax[1], idx[1], off[1], h * mom[1] / (R * R));
+      idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
+      idx[2] = move_axis<A, U>(b.ax[2], idx[2], off[2], h * mom[2]);
     }
   } else {
     if (first) {
-      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+      idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
       if (!wrap_plain<A>(b.ax[0], idx[0])) return false;
-      A r = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
-      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (r * r));
+      A r = cell_centre<A, U>(b.ax[0], idx[0]) + off[0] * cell_width<A, U>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A, U>(b.ax[1], idx[1], off[1], h * mom[1] / (r * r));
       if (!wrap_plain<A>(b.ax[1], idx[1])) return false;
-      A th = cell_centre<A>(b.ax[1], idx[1]) + off[1] * cell_width<A>(b.ax[1], idx[1]);
+      A th = cell_centre<A, U>(b.ax[1], idx[1]) + off[1] * cell_width<A, U>(b.ax[1], idx[1]);
       A s = dsin(th);
-      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2] / (r * r * s * s));
+      idx[2] = move_axis<A, U>(b.ax[2], idx[2], off[2], h * mom[2] / (r * r * s * s));
     } else {
-      A r = cell_centre<A>(b.ax[0], idx[0]) + off[0] * cell_width<A>(b.ax[0], idx[0]);
-      A th = cell_centre<A>(b.ax[1], idx[1]) + off[1] * cell_width<A>(b.ax[1], idx[1]);
+      A r = cell_centre<A, U>(b.ax[0], idx[0]) + off[0] * cell_width<A, U>(b.ax[0], idx[0]);
+      A th = cell_centre<A, U>(b.ax[1], idx[1]) + off[1] * cell_width<A, U>(b.ax[1], idx[1]);
       A s = dsin(th);
-      idx[2] = move_axis<A>(b.ax[2], idx[2], off[2], h * mom[2] / (r * r * s * s));
-      idx[1] = move_axis<A>(b.ax[1], idx[1], off[1], h * mom[1] / (r * r));
-      idx[0] = move_axis<A>(b.ax[0], idx[0], off[0], h * mom[0]);
+      idx[2] = move_axis<A, U>(b.ax[2], idx[2], off[2], h * mom[2] / (r * r * s * s));
+      idx[1] = move_axis<A, U>(b.ax[1], idx[1], off[1], h * mom[1] / (r * r));
+      idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
     }
   }
 #pragma unroll
@@ -360,11 +370,11 @@ template <typename A> struct Where {
   A sc[3]; // canonical = physical * sc: 1, R, r, r sin(theta)
 };
 
-template <typename A, int GEOM, int NDIM>
+template <typename A, int GEOM, int NDIM, bool U>
 __device__ __forceinline__ void where(const Box& b, const int idx[3], const A off[3], Where<A>& w) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    w.x[d] = d < NDIM ? cell_centre<A>(b.ax[d], idx[d]) + off[d] * cell_width<A>(b.ax[d], idx[d])
+    w.x[d] = d < NDIM ? cell_centre<A, U>(b.ax[d], idx[d]) + off[d] * cell_width<A, U>(b.ax[d], idx[d])
                       : A(0);
     w.sc[d] = A(1);
   }
@@ -387,16 +397,15 @@ template <typename A> struct KickOut {
 
 // Exponential-midpoint kick (Eq. exp_midpoint with A = -diag(1/tau);
 // App. A Eq. standard_SB_exp_midpoint; App. B.1 Eq. kick_cylindrical; App.
-// B.2) for canonical momenta p and gas momentum pg (canonical), inverse
-// stopping time it.
+// B.2) for canonical momenta p, slip s = p_g - p (canonical; the gas
+// momentum at the particle minus p) and inverse stopping time it.
 template <typename A, int GEOM, int NDIM>
 __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
-                                     const Where<A>& w, const A p[3], const A pg[3],
+                                     const Where<A>& w, const A p[3], const A s[3],
                                      KickOut<A>& o) {
   A c, psi;
   propagator<A>(dt * it, c, psi);
   A h1 = dt + dt * psi;
-  A s[3] = {pg[0] - p[0], pg[1] - p[1], pg[2] - p[2]};
   A a[3] = {A(0), A(0), A(0)};
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   if constexpr (GEOM == GEOM_CART) {

@@ -34,7 +34,7 @@ size_t fused_lds_bytes(const FusedPlan& plan, int nc);
 
 template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, int nbox, int geom,
-                  int ndim, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
+                  int ndim, int unif, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                   double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg, bool sums,
                   hipStream_t st);
 

@@ -106,7 +106,23 @@ size_t fused_lds_bytes(const FusedPlan& plan, int nc) {
   return plan.lds_cells * (2 * nc + 1) * sizeof(double);
 }
 
-template <typename TS, typename A, int GEOM, int NDIM, int TX, int TY, int TZ>
+// Raw stored state of one particle (prefetched one particle ahead).
+template <typename TS> struct Raw {
+  int32_t cell;
+  TS off[3], mom[3];
+};
+
+template <typename TS, int NDIM, int NC>
+__device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>& r) {
+  r.cell = p.cell[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    r.off[d] = d < NDIM ? p.off[d][i] : TS(0);
+    r.mom[d] = d < NC ? p.mom[d][i] : TS(0);
+  }
+}
+
+template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(FUSED_THREADS)
     k_fused(const TileDesc* tiles, PView<TS> p, const Box* boxes, FView<TS> fl, Forces f,
             const Species* sp, int drag_mode, A dt, const double* tdev, const int64_t* bin_start,
@@ -153,86 +169,110 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   }
   // register sums: FP32 for FP32 storage, FP64 for FP64 storage
   using TAcc = TS;
-  TAcc acc[27][nc + 1];
+  constexpr int NS = c2 ? 27 : 9;   // stencil cells
+  TAcc acc[NS][nc + 1];
 #pragma unroll
-  for (int o = 0; o < 27; ++o)
+  for (int o = 0; o < NS; ++o)
 #pragma unroll
     for (int k = 0; k <= nc; ++k) acc[o][k] = TAcc(0);
   double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0, s_cells = 0;
   unsigned long long n_fb = 0;
 
+  Raw<TS> nxt;
+  if (ps < pe) load_raw<TS, NDIM, nc>(p, ps, nxt);
   for (int64_t i = ps; i < pe; ++i) {
-    int idx[3];
-    A off[3], mom[3];
-    int32_t cid = p.cell[i];
-    if (cid < 0 || cid < B.cell_base || cid >= B.cell_base + B.ncell) {
-      if (cid >= 0) flag(dg, DUST_FLAG_BAD_CELL);
-      continue;
-    }
-    unravel(B, cid - B.cell_base, idx);
-    bool bad = false;
+    const Raw<TS> cur = nxt;
+    if (i + 1 < pe) load_raw<TS, NDIM, nc>(p, i + 1, nxt);   // prefetch the next particle
+    // Lanes of one wave walk different cells, so nothing below branches
+    // around the register sums: a particle without a cell, or one that left
+    // through an open face, continues as a dummy at the centre of this
+    // thread's cell with zero deposits (a divergent skip would keep two
+    // copies of every register sum live).
+    int idx[3] = {mycell[0], mycell[1], mycell[2]};
+    A off[3] = {A(0), A(0), A(0)}, mom[3] = {A(0), A(0), A(0)};
+    const int32_t cid = cur.cell;
+    bool live = cid >= 0 && cid >= B.cell_base && cid < B.cell_base + B.ncell;
+    if (cid >= 0 && !live) flag(dg, DUST_FLAG_BAD_CELL);
+    if (live) {
+      unravel(B, cid - B.cell_base, idx);
+      bool bad = false;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
-      mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
-      bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
+      for (int d = 0; d < 3; ++d) {
+        off[d] = A(cur.off[d]);
+        mom[d] = A(cur.mom[d]);
+        bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
+      }
+      if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+      // half drift to x^{n+1/2}
+      if (!drift<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom)) {
+        store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(h), i, false, idx, off, mom, dg);
+        live = false;
+      }
     }
-    if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
-    // half drift to x^{n+1/2}
-    if (!drift<A, GEOM, NDIM>(B, f, true, h, t0 + double(h), idx, off, mom)) {
-      store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(h), i, false, idx, off, mom, dg);
-      continue;
+    if (!live) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        idx[d] = mycell[d];
+        off[d] = A(0);
+        mom[d] = A(0);
+      }
     }
     // weights at x^{n+1/2}
     Stencil<A> s;
-    stencil_weights<A, NDIM>(B, idx, off, s);
+    stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
     const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
     const bool inside = la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
                         (c2 == 0 || (lc >= 1 && lc <= RZ - 2));
     const bool home = idx[0] == mycell[0] && idx[1] == mycell[1] && (c2 == 0 || idx[2] == mycell[2]);
-    A w27[27];
+    // Gather (Eq. Delta_vp) in slip form: the weights sum to one, so the
+    // slip p_g - p is sc * sum_i W_i (v_i - u) with u = p / sc the particle's
+    // physical velocity.  Each v_i - u is exact or nearly so when the gas
+    // and particle velocities are close (FP32 keeps the slip's relative
+    // accuracy where the velocities themselves are large, as in the
+    // shearing box's background shear).
+    Where<A> wh;
+    where<A, GEOM, NDIM, U>(B, idx, off, wh);
+    A up[3];
 #pragma unroll
-    for (int c = -1; c <= 1; ++c)
-#pragma unroll
-      for (int bb = -1; bb <= 1; ++bb) {
-        A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-        for (int a = -1; a <= 1; ++a) w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))] = s.w[0][a + 1] * wbc;
-      }
-    // gather (Eq. Delta_vp)
+    for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
     A v[3] = {A(0), A(0), A(0)};
     if (inside) {
       const int base = la + RX * (lb + RY * lc);
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
 #pragma unroll
-        for (int bb = -1; bb <= 1; ++bb)
+        for (int bb = -1; bb <= 1; ++bb) {
+          const int r0 = base + RX * (bb + RY * c);
+          A u[3] = {A(0), A(0), A(0)};
 #pragma unroll
-          for (int a = -1; a <= 1; ++a) {
-            A w = w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))];
-            int r0 = base + a + RX * (bb + RY * c);
+          for (int a = -1; a <= 1; ++a)
 #pragma unroll
-            for (int m = 0; m < nc; ++m) v[m] += w * A(gas[m * RC + r0]);
-          }
+            for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(gas[m * RC + r0 + a]) - up[m]);
+          const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
+          for (int m = 0; m < nc; ++m) v[m] += wbc * u[m];
+        }
     } else {
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
 #pragma unroll
-        for (int bb = -1; bb <= 1; ++bb)
+        for (int bb = -1; bb <= 1; ++bb) {
+          A u[3] = {A(0), A(0), A(0)};
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
-            A w = w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))];
             int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
 #pragma unroll
-            for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
+            for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(fl.vel[m][id]) - up[m]);
           }
+          const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
+          for (int m = 0; m < nc; ++m) v[m] += wbc * u[m];
+        }
     }
     // kick
-    Where<A> wh;
-    where<A, GEOM, NDIM>(B, idx, off, wh);
-    A pg[3];
+    A sl[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) pg[m] = m < nc ? v[m] * wh.sc[m] : A(0);
+    for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
     int spc = p.species ? p.species[i] : 0;
     if (spc >= sp->n) {
       flag(dg, DUST_FLAG_BAD_CELL);
@@ -242,14 +282,14 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     A m = p.mass ? A(p.mass[i]) : A(sp->mass[spc]);
     A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[spc]), wh);
     KickOut<A> o;
-    kick<A, GEOM, NDIM>(B, f, dt, it, wh, mom, pg, o);
+    kick<A, GEOM, NDIM>(B, f, dt, it, wh, mom, sl, o);
     A q[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
     for (int k = 0; k < nc; ++k) {
-      q[k] = -m * o.j[k];  // deposits carry the minus sign of Eq. dust_feedback_final
-      if (sums) {
+      q[k] = live ? -m * o.j[k] : A(0);  // deposits carry the minus sign of Eq. dust_feedback_final
+      if (sums && live) {
         A vbar = (mom[k] + A(0.5) * o.dp[k]) / wh.sc[k];
-        A dl = cell_width<A>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
+        A dl = cell_width<A, U>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
         double cps = fabs(double(vbar * dt / dl));
         s_cells = cps > s_cells ? cps : s_cells;
         s_j[k] -= double(q[k]);
@@ -257,34 +297,48 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       }
       mom[k] += o.dp[k];
     }
-    q[nc] = -m * o.e;
+    q[nc] = live ? -m * o.e : A(0);
     if (sums) s_e -= double(q[nc]);
-    // deposit (same weights and cells as the gather)
-    if (home) {
-      TAcc qf[4];
+    // deposit (same weights and cells as the gather): register sums for a
+    // particle still in this thread's cell (zero otherwise), unconditionally
+    {
+      TAcc qf[4], wa[3];
 #pragma unroll
-      for (int k = 0; k <= nc; ++k) qf[k] = TAcc(q[k]);
+      for (int k = 0; k <= nc; ++k) qf[k] = home ? TAcc(q[k]) : TAcc(0);
 #pragma unroll
-      for (int oo = 0; oo < 27; ++oo) {
-        if (c2 == 0 && (oo < 9 || oo >= 18)) continue;
-        TAcc w = TAcc(w27[oo]);
+      for (int a = 0; a < 3; ++a) wa[a] = TAcc(s.w[0][a]);
 #pragma unroll
-        for (int k = 0; k <= nc; ++k) acc[oo][k] += w * qf[k];
-      }
-    } else if (inside) {
+      for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb) {
+          TAcc wbc = TAcc(s.w[1][bb + 1] * s.w[2][c + 1]);
+          TAcc qb[4];
+#pragma unroll
+          for (int k = 0; k <= nc; ++k) qb[k] = wbc * qf[k];
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            const int oo = (a + 1) + 3 * ((bb + 1) + 3 * (c + c2));
+#pragma unroll
+            for (int k = 0; k <= nc; ++k) acc[oo][k] += wa[a + 1] * qb[k];
+          }
+        }
+    }
+    if (live && !home && inside) {
       const int base = la + RX * (lb + RY * lc);
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
 #pragma unroll
-        for (int bb = -1; bb <= 1; ++bb)
+        for (int bb = -1; bb <= 1; ++bb) {
+          const double wbc = double(s.w[1][bb + 1] * s.w[2][c + 1]);
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
-            double w = double(w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))]);
-            int r0 = base + a + RX * (bb + RY * c);
+            const double w = double(s.w[0][a + 1]) * wbc;
+            const int r0 = base + a + RX * (bb + RY * c);
 #pragma unroll
             for (int k = 0; k <= nc; ++k) atomicAdd(&dep[k * RC + r0], w * double(q[k]));
           }
-    } else {
+        }
+    } else if (live && !inside) {
       ++n_fb;
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
@@ -293,15 +347,17 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
             int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
-            A w = w27[(a + 1) + 3 * ((bb + 1) + 3 * (c + 1))] * A(inv_volume(B, ii, jj, kk));
+            A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1] * A(inv_volume(B, ii, jj, kk));
             int64_t id = stored_index(B, ii, jj, kk);
 #pragma unroll
             for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(w * q[k]));
           }
     }
     // second half drift to x^{n+1}
-    bool alive = drift<A, GEOM, NDIM>(B, f, false, h, t0 + double(dt), idx, off, mom);
-    store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+    if (live) {
+      bool alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
+      store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+    }
   }
 
   // register sums of my cell's stencil -> deposit window
@@ -312,8 +368,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       for (int bb = -1; bb <= 1; ++bb)
 #pragma unroll
         for (int a = -1; a <= 1; ++a) {
-          int oo = (a + 1) + 3 * ((bb + 1) + 3 * (c + 1));
-          int r0 = mybase + a + RX * (bb + RY * c);
+          const int oo = (a + 1) + 3 * ((bb + 1) + 3 * (c + c2));
+          const int r0 = mybase + a + RX * (bb + RY * c);
 #pragma unroll
           for (int k = 0; k <= nc; ++k)
             if (acc[oo][k] != TAcc(0)) atomicAdd(&dep[k * RC + r0], double(acc[oo][k]));
@@ -361,14 +417,14 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   }
 }
 
-template <typename TS, typename A, int GEOM, int NDIM, int TX, int TY, int TZ>
+template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
 static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
                            bool sums, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   size_t lds = fused_lds_bytes(plan, nc);
-  auto kern = k_fused<TS, A, GEOM, NDIM, TX, TY, TZ>;
+  auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
   if (lds > 64 * 1024) {
     static bool raised = false;
     if (!raised) {
@@ -381,13 +437,13 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const Box*
                      fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg, (int)sums);
 }
 
-template <typename TS, typename A, int GEOM, int NDIM>
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
 static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
                            bool sums, hipStream_t st) {
 #define DUST_F(TX, TY, TZ)                                                                         \
-  launch_fused_t<TS, A, GEOM, NDIM, TX, TY, TZ>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev,  \
+  launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev,  \
                                                 bin_start, dg, sums, st)
   if constexpr (NDIM == 3) {
     switch (plan.shape) {
@@ -410,27 +466,25 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const Box*
 
 template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, int nbox, int geom,
-                  int ndim, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
+                  int ndim, int unif, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                   double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg, bool sums,
                   hipStream_t st) {
   (void)nbox;
   if (plan.ntiles == 0) return;
-  if (geom == GEOM_CART && ndim == 2)
-    launch_fused_g<TS, A, GEOM_CART, 2>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start,
-                                        dg, sums, st);
-  else if (geom == GEOM_CART)
-    launch_fused_g<TS, A, GEOM_CART, 3>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start,
-                                        dg, sums, st);
-  else if (geom == GEOM_CYL)
-    launch_fused_g<TS, A, GEOM_CYL, 3>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start,
-                                       dg, sums, st);
-  else
-    launch_fused_g<TS, A, GEOM_SPH, 3>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start,
-                                       dg, sums, st);
+#define DUST_G(G, D, UU)                                                                          \
+  launch_fused_g<TS, A, G, D, UU>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start, dg,  \
+                                  sums, st)
+  if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
+  else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
+  else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
+  else if (geom == GEOM_CART) DUST_G(GEOM_CART, 3, false);
+  else if (geom == GEOM_CYL) DUST_G(GEOM_CYL, 3, false);
+  else DUST_G(GEOM_SPH, 3, false);
+#undef DUST_G
 }
 
 #define DUST_FUSED_INST(TS, A)                                                                    \
-  template void launch_fused<TS, A>(const FusedPlan&, const PView<TS>&, const Box*, int, int, int,  \
+  template void launch_fused<TS, A>(const FusedPlan&, const PView<TS>&, const Box*, int, int, int, int, \
                                     const FView<TS>&, const Forces&, const Species*, int, double,  \
                                     const double*, const int64_t*, DiagDev*, bool, hipStream_t);
 

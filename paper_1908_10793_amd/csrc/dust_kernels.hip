@@ -14,7 +14,7 @@ namespace dust {
 // Templated on the geometry and dimension of the context's boxes so that the
 // stencil and component loops unroll into registers.
 
-template <typename TS, typename A, int GEOM, int NDIM>
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, int nbox, Forces f,
                                                A h, const double* tdev, double toff, int first,
                                                DiagDev* dg) {
@@ -26,11 +26,11 @@ __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, in
   int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
   if (b < 0) return;
   const Box& B = boxes[b];
-  bool alive = drift<A, GEOM, NDIM>(B, f, first != 0, h, t_after, idx, off, mom);
+  bool alive = drift<A, GEOM, NDIM, U>(B, f, first != 0, h, t_after, idx, off, mom);
   store_particle<TS, A, GEOM, NDIM>(p, B, f, t_after, i, alive, idx, off, mom, dg);
 }
 
-template <typename TS, typename A, typename TW, int GEOM, int NDIM>
+template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, int nbox,
                                                 FView<TS> fl, TW* rho_p, TW* vg0, TW* vg1,
                                                 TW* vg2, DiagDev* dg) {
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, i
   if (b < 0) return;
   const Box& B = boxes[b];
   Stencil<A> s;
-  stencil_weights<A, NDIM>(B, idx, off, s);
+  stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   A r = A(0), v[3] = {A(0), A(0), A(0)};
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, i
   if (nc > 2 && vg2) vg2[i] = TW(v[2]);
 }
 
-template <typename TS, typename A, typename TW, int GEOM, int NDIM>
+template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int nbox, Forces f,
                                               const Species* sp, int drag_mode, A dt, const TW* vg0,
                                               const TW* vg1, const TW* vg2, TW* imp0, TW* imp1,
@@ -82,8 +82,10 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
     if (b >= 0) {
       const Box& B = boxes[b];
       Where<A> w;
-      where<A, GEOM, NDIM>(B, idx, off, w);
-      A pg[3] = {A(vg0[i]) * w.sc[0], A(vg1[i]) * w.sc[1], nc > 2 ? A(vg2[i]) * w.sc[2] : A(0)};
+      where<A, GEOM, NDIM, U>(B, idx, off, w);
+      // slip: canonical gas momentum at the particle minus p
+      A sl[3] = {A(vg0[i]) * w.sc[0] - mom[0], A(vg1[i]) * w.sc[1] - mom[1],
+                 nc > 2 ? A(vg2[i]) * w.sc[2] - mom[2] : A(0)};
       int s = p.species ? p.species[i] : 0;
       if (s >= sp->n) {
         flag(dg, DUST_FLAG_BAD_CELL);
@@ -93,13 +95,13 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       A m = p.mass ? A(p.mass[i]) : A(sp->mass[s]);
       A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[s]), w);
       KickOut<A> o;
-      kick<A, GEOM, NDIM>(B, f, dt, it, w, mom, pg, o);
+      kick<A, GEOM, NDIM>(B, f, dt, it, w, mom, sl, o);
       TW* imp[4] = {imp0, imp1, imp2, imp3};
       bool fin = isfinite(double(o.e));
 #pragma unroll
       for (int k = 0; k < nc; ++k) {
         A vbar = (mom[k] + A(0.5) * o.dp[k]) / w.sc[k];
-        A dl = cell_width<A>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : w.sc[k]);
+        A dl = cell_width<A, U>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : w.sc[k]);
         double cps = fabs(double(vbar * dt / dl));
         cells = cps > cells ? cps : cells;
         mom[k] += o.dp[k];
@@ -128,7 +130,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
   }
 }
 
-template <typename TS, typename A, typename TW, int GEOM, int NDIM>
+template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, int nbox,
                                                  FView<TS> fl, const TW* imp0, const TW* imp1,
                                                  const TW* imp2, const TW* imp3, DiagDev* dg) {
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
   A q[4] = {A(imp0[i]), A(imp1[i]), A(imp2[i]), A(0)};
   if (nc > 2) q[3] = A(imp3[i]);
   Stencil<A> s;
-  stencil_weights<A, NDIM>(B, idx, off, s);
+  stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
   constexpr int c2 = NDIM > 2 ? 1 : 0;
 #pragma unroll
   for (int c = -c2; c <= c2; ++c)
@@ -162,19 +164,31 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
 }
 
 // Dispatch on the (geometry, dimension) shared by the context's boxes.
-#define DUST_GEOM_SWITCH(geom, ndim, CALL)                            \
+#define DUST_GEOM_SWITCH(geom, ndim, unif, CALL)                      \
   do {                                                                \
-    if ((geom) == GEOM_CART && (ndim) == 2) {                         \
+    if ((geom) == GEOM_CART && (ndim) == 2 && (unif)) {               \
       constexpr int G_ = GEOM_CART, D_ = 2;                           \
+      constexpr bool U_ = true;                                       \
+      CALL;                                                           \
+    } else if ((geom) == GEOM_CART && (ndim) == 2) {                  \
+      constexpr int G_ = GEOM_CART, D_ = 2;                           \
+      constexpr bool U_ = false;                                      \
+      CALL;                                                           \
+    } else if ((geom) == GEOM_CART && (unif)) {                       \
+      constexpr int G_ = GEOM_CART, D_ = 3;                           \
+      constexpr bool U_ = true;                                       \
       CALL;                                                           \
     } else if ((geom) == GEOM_CART) {                                 \
       constexpr int G_ = GEOM_CART, D_ = 3;                           \
+      constexpr bool U_ = false;                                      \
       CALL;                                                           \
     } else if ((geom) == GEOM_CYL) {                                  \
       constexpr int G_ = GEOM_CYL, D_ = 3;                            \
+      constexpr bool U_ = false;                                      \
       CALL;                                                           \
     } else {                                                          \
       constexpr int G_ = GEOM_SPH, D_ = 3;                            \
+      constexpr bool U_ = false;                                      \
       CALL;                                                           \
     }                                                                 \
   } while (0)
@@ -334,30 +348,49 @@ template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   double sc[3] = {1.0, 1.0, 1.0};
   if (B.geom != GEOM_CART) {
-    double x0 = cell_centre<double>(B.ax[0], i);
+    double x0 = cell_centre<double, false>(B.ax[0], i);
     sc[1] = x0;
-    if (B.geom == GEOM_SPH) sc[2] = x0 * sin(cell_centre<double>(B.ax[1], j));
+    if (B.geom == GEOM_SPH) sc[2] = x0 * sin(cell_centre<double, false>(B.ax[1], j));
   }
   double rho = double(fl.rho[id]);
   for (int c = 0; c < nc; ++c)
     fl.vel[c][id] = TS(double(fl.vel[c][id]) + double(fl.dep[c][id]) / (rho * sc[c]));
 }
 
-// FP64 sums of dV D over every stored cell of one box.
+// FP64 sums of dV D over every stored cell of one box: a grid-stride loop,
+// a block reduction, and one atomic per block and channel.
+static constexpr int GRID_SUM_BLOCKS = 512;
+
 template <typename TS> __global__ void __launch_bounds__(256) k_grid_sums(Box B, FView<TS> fl, DiagDev* dg) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double red[4][4];
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  const double inv_g0 = 1.0 / B.g0, inv_g1 = 1.0 / B.g1;
   double s[4] = {0, 0, 0, 0};
-  if (t < B.nstore) {
-    int i = (int)(t % B.g0) - 1;
-    int j = (int)((t / B.g0) % B.g1) - 1;
-    int k = (int)(t / ((int64_t)B.g0 * B.g1)) - B.k_off;
-    double dv = 1.0 / inv_volume(B, i, j, k);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < B.nstore; t += stride) {
+    int i, j, k;
+    if (B.nstore < 0x7fffffffLL) {
+      int r = div_small((int)t, B.g0, inv_g0);
+      i = (int)t - r * B.g0;
+      int q = div_small(r, B.g1, inv_g1);
+      j = r - q * B.g1;
+      k = q;
+    } else {
+      i = (int)(t % B.g0);
+      j = (int)((t / B.g0) % B.g1);
+      k = (int)(t / ((int64_t)B.g0 * B.g1));
+    }
+    double dv = 1.0 / inv_volume(B, i - 1, j - 1, k - B.k_off);
     int64_t id = B.store_base + t;
-    for (int c = 0; c <= nc; ++c) s[c] = dv * double(fl.dep[c][id]);
+    for (int c = 0; c <= nc; ++c) s[c] += dv * double(fl.dep[c][id]);
   }
   for (int c = 0; c < 4; ++c) s[c] = wave_sum(s[c]);
-  if ((threadIdx.x & 63) == 0) {
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 4; ++c) red[wave][c] = s[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 4; ++c) s[c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
     for (int c = 0; c < nc; ++c) unsafeAtomicAdd(&dg->p_grid[c], s[c]);
     unsafeAtomicAdd(&dg->e_grid, s[nc]);
   }
@@ -370,41 +403,41 @@ static inline unsigned blocks_for(int64_t n, int bs = 256) {
 }
 
 template <typename TS, typename A>
-void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                   const Forces& f, double h, const double* tdev, double toff, int first,
                   DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  DUST_GEOM_SWITCH(geom, ndim,
-                   hipLaunchKernelGGL((k_drift<TS, A, G_, D_>), dim3(blocks_for(p.n)), dim3(256), 0,
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_drift<TS, A, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256), 0,
                                       st, p, boxes, nbox, f, A(h), tdev, toff, first, dg));
 }
 
 template <typename TS, typename A, typename TW>
-void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                    const FView<TS>& fl, TW* rho_p, TW* const vg[3], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  DUST_GEOM_SWITCH(geom, ndim,
-                   hipLaunchKernelGGL((k_gather<TS, A, TW, G_, D_>), dim3(blocks_for(p.n)), dim3(256),
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_gather<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
                                       0, st, p, boxes, nbox, fl, rho_p, vg[0], vg[1], vg[2], dg));
 }
 
 template <typename TS, typename A, typename TW>
-void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                  const Forces& f, const Species* sp, int drag_mode, double dt,
                  const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  DUST_GEOM_SWITCH(geom, ndim,
-                   hipLaunchKernelGGL((k_kick<TS, A, TW, G_, D_>), dim3(blocks_for(p.n)), dim3(256),
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_kick<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
                                       0, st, p, boxes, nbox, f, sp, drag_mode, A(dt), vg[0], vg[1],
                                       vg[2], imp[0], imp[1], imp[2], imp[3], dg));
 }
 
 template <typename TS, typename A, typename TW>
-void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                     const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  DUST_GEOM_SWITCH(geom, ndim,
-                   hipLaunchKernelGGL((k_deposit<TS, A, TW, G_, D_>), dim3(blocks_for(p.n)), dim3(256),
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_deposit<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
                                       0, st, p, boxes, nbox, fl, imp[0], imp[1], imp[2], imp[3], dg));
 }
 
@@ -466,7 +499,10 @@ void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st) {
 
 template <typename TS>
 void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, hipStream_t st) {
-  hipLaunchKernelGGL((k_grid_sums<TS>), dim3(blocks_for(B.nstore)), dim3(256), 0, st, B, fl, dg);
+  unsigned nb = blocks_for(B.nstore);
+  if (nb > (unsigned)GRID_SUM_BLOCKS) nb = GRID_SUM_BLOCKS;
+  if (nb == 0) return;
+  hipLaunchKernelGGL((k_grid_sums<TS>), dim3(nb), dim3(256), 0, st, B, fl, dg);
 }
 
 template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st) {
@@ -475,18 +511,18 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
 }
 
 #define DUST_INST(TS, A, TW)                                                                      \
-  template void launch_gather<TS, A, TW>(const PView<TS>&, const Box*, int, int, int,             \
+  template void launch_gather<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int,             \
                                          const FView<TS>&, TW*, TW* const[3], DiagDev*,           \
                                          hipStream_t);                                            \
-  template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, const Forces&, \
+  template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int, const Forces&, \
                                        const Species*, int, double, const TW* const[3],           \
                                        TW* const[4], DiagDev*, hipStream_t);                      \
-  template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, int, int,            \
+  template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int,            \
                                           const FView<TS>&, const TW* const[4], DiagDev*,         \
                                           hipStream_t);
 
 #define DUST_INST_DRIFT(TS, A)                                                                    \
-  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, int, int, const Forces&,   \
+  template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, int, int, int, const Forces&,   \
                                     double, const double*, double, int, DiagDev*, hipStream_t);
 
 DUST_INST_DRIFT(float, double)

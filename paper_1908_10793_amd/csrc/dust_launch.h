@@ -26,20 +26,20 @@ template <typename TS> struct FView {
 };
 
 template <typename TS, typename A>
-void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                   const Forces& f, double h, const double* tdev, double toff, int first,
                   DiagDev* dg, hipStream_t st);
 // TW: type of the per-particle gas-velocity / impulse arrays (the caller's
 // precision for the stage calls, the arithmetic precision inside dust_step).
 template <typename TS, typename A, typename TW>
-void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                    const FView<TS>& fl, TW* rho_p, TW* const vg[3], DiagDev* dg, hipStream_t st);
 template <typename TS, typename A, typename TW>
-void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                  const Forces& f, const Species* sp, int drag_mode, double dt,
                  const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st);
 template <typename TS, typename A, typename TW>
-void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim,
+void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                     const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st);
 
 template <typename TS>

@@ -107,16 +107,15 @@ template <typename A> struct Stencil {
   A w[3][3];
 };
 
-template <typename A, int NDIM>
+template <typename A, int GEOM, int NDIM, bool U>
 __device__ __forceinline__ void stencil_weights(const Box& B, const int idx[3], const A off[3],
                                                 Stencil<A>& s) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (d < NDIM) {
-      axis_weights<A>(B.ax[d], idx[d], off[d], s.w[d]);
-    } else {
-      s.w[d][0] = A(0); s.w[d][1] = A(1); s.w[d][2] = A(0);
-    }
+  axis_weights<A, axis_kind(GEOM, 0), U>(B.ax[0], idx[0], off[0], s.w[0]);
+  axis_weights<A, axis_kind(GEOM, 1), U>(B.ax[1], idx[1], off[1], s.w[1]);
+  if constexpr (NDIM > 2) {
+    axis_weights<A, axis_kind(GEOM, 2), U>(B.ax[2], idx[2], off[2], s.w[2]);
+  } else {
+    s.w[2][0] = A(0); s.w[2][1] = A(1); s.w[2][2] = A(0);
   }
 }
 

@@ -236,6 +236,9 @@ class Context:
         return a.value, b.value
 
     def set_arith(self, arith: str):
+        """Push arithmetic of an FP32 context: "f32" (default) or "f64"."""
+        if arith not in ("f32", "f64"):
+            raise ValueError(f"arith must be 'f32' or 'f64', not {arith!r}")
         _check(load_library().dust_ctx_set_arith(self.handle, ARITH_F32 if arith == "f32" else ARITH_F64))
 
     def set_tile(self, tx=0, ty=0, tz=0, slack=0):

@@ -96,17 +96,8 @@ def test_fused_with_other_tile_shapes():
     assert e.value.code == -5
 
 
-def test_fp32_arithmetic_variant_runs():
-    """The all-FP32 arithmetic variant is kept for comparison; it must stay
-    close to the oracle on the drag-only workload."""
-    dust = _dust()
-    w = small("batched_boxes")
-    ctx = dust.context_for(w)
-    ctx.set_arith("f32")
-    P, F = dust.upload(w, ctx)
-    st_in = download(ctx, P, F, w)
-    ctx.step(P, F, w.dt, dust.forces_for(w), 1, dust.STEP_APPLY_FEEDBACK)
-    st_out = download(ctx, P, F, w)
-    run = OracleRun(workload_from_state(w, st_in, w.t0))
-    run.step(1)
-    compare_step(w, st_in, st_out, run, "f32", label="arith f32")
+@pytest.mark.parametrize("name", ["shearing_box", "batched_boxes"])
+def test_fused_fp64_arithmetic_variant_matches_oracle(name):
+    """FP32 storage with FP64 per-particle arithmetic in the fused kernel (the
+    default of curvilinear boxes) on the Cartesian workloads."""
+    _run(name, fused=True, nsteps=2, arith="f64")
