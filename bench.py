@@ -43,6 +43,16 @@ def parse():
     ap.add_argument("--unfused", action="store_true", help="time the unfused per-phase chain")
     ap.add_argument("--arith", choices=("f64", "f32"), default="f32",
                     help="per-particle arithmetic of the FP32-storage path")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the run, one device-to-device copy of this many MiB (the "
+                         "reference kernel of the HBM byte counters)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("RUN_DIR", "OUT"),
+                    help="write the per-kernel summary of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="write the HBM byte summary of two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) taken with --calib-copy-mb")
+    ap.add_argument("--command", type=str, default="",
+                    help="the profiling command, recorded in the summary")
     return ap.parse_args()
 
 
@@ -54,17 +64,113 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+COUNTER_SUMMARY = os.path.join(HERE, "profiles", "k_fused_shearing_box_128_hbm_bytes.txt")
+FUSED_KERNEL = "k_fused"
+
+
 def counter_traffic(kernel_hash: str, n_particles: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
-    path = os.path.join(HERE, "profiles", "fused_shearing_box_128_counters.json")
-    if not os.path.exists(path):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTER_SUMMARY):
         return None
-    with open(path) as fh:
-        d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_hash or d.get("n_particles") != n_particles:
+    d = {}
+    with open(COUNTER_SUMMARY) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                d[k.strip()] = v.strip()
+    if d.get("kernel_source_hash") != kernel_hash or d.get("n_particles") != str(n_particles):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return float(d["hbm_bytes_per_launch"])
+
+
+def _rocpd(run_dir: str) -> str:
+    import glob
+    dbs = sorted(glob.glob(os.path.join(run_dir, "**", "*.db"), recursive=True))
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 database under {run_dir}")
+    return dbs[0]
+
+
+def _short(name: str) -> str:
+    import re
+    return re.sub(r"\(.*", "", name)
+
+
+def summarize_trace(run_dir: str, out: str, command: str):
+    """Per-kernel calls / total / average / min / max from a --kernel-trace run."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(_rocpd(run_dir))
+    agg = collections.defaultdict(list)
+    for name, t0, t1 in con.execute("select name, start, end from kernels"):
+        agg[_short(name)].append((t1 - t0) * 1e-3)
+    tot = sum(sum(v) for v in agg.values())
+    lines = ["# rocprofv3 kernel trace summary (durations in microseconds)",
+             f"# command: {command}", "",
+             f"{'kernel':64s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} {'min_us':>9s} "
+             f"{'max_us':>9s} {'pct':>6s}"]
+    for nm, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{nm[:64]:64s} {len(v):6d} {sum(v) / 1e3:9.3f} {sum(v) / len(v):9.2f} "
+                     f"{min(v):9.2f} {max(v):9.2f} {100 * sum(v) / tot:6.2f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _counter_per_dispatch(run_dir: str, counter: str):
+    """Value of a counter for every dispatch: {kernel name: [values]}."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(_rocpd(run_dir))
+    per = collections.defaultdict(float)
+    names = {}
+    for di, name, val in con.execute(
+            "select dispatch_id, kernel_name, value from counters_collection where counter_name = ?",
+            (counter,)):
+        per[di] += val
+        names[di] = _short(name)
+    out = collections.defaultdict(list)
+    for di, v in per.items():
+        out[names[di]].append(v)
+    return out
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
+                       n_particles: int, copy_mb: int):
+    """HBM bytes per launch of the fused kernel: FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled by the ratio of known to counted bytes of a
+    device-to-device copy of copy_mb MiB."""
+    fetch = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_dir, "WRITE_SIZE")
+    copy_kib = copy_mb * 1024.0
+    # the calibration copy is the largest copy dispatch of the run
+    def is_copy(k):
+        return "copy" in k.lower() or "elementwise" in k.lower()
+    cf = max(max(v) for k, v in fetch.items() if is_copy(k))
+    cw = max(max(v) for k, v in write.items() if is_copy(k))
+    f_fetch, f_write = copy_kib / cf, copy_kib / cw
+    kf = [sum(v) / len(v) for k, v in fetch.items() if FUSED_KERNEL in k]
+    kw = [sum(v) / len(v) for k, v in write.items() if FUSED_KERNEL in k]
+    fb = kf[0] * f_fetch * 1024.0
+    wb = kw[0] * f_write * 1024.0
+    lines = ["# HBM bytes of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per",
+             "# dispatch), each scaled by known/counted bytes of a device copy of known size",
+             f"# command: {command}",
+             f"kernel: {FUSED_KERNEL}",
+             f"kernel_source_hash: {source_hash()}",
+             f"n_particles: {n_particles}",
+             f"copy_mib: {copy_mb}",
+             f"copy_fetch_kib_counted: {cf:.1f}",
+             f"copy_write_kib_counted: {cw:.1f}",
+             f"fetch_scale: {f_fetch:.4f}",
+             f"write_scale: {f_write:.4f}",
+             f"fused_fetch_kib_counted: {kf[0]:.1f}",
+             f"fused_write_kib_counted: {kw[0]:.1f}",
+             f"fused_fetch_bytes: {fb:.4g}",
+             f"fused_write_bytes: {wb:.4g}",
+             f"hbm_bytes_per_launch: {fb + wb:.6g}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def cpu_baseline(w, sample: int):
@@ -87,6 +193,13 @@ def cpu_baseline(w, sample: int):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.command, 8 * args.n ** 3,
+                           args.calib_copy_mb)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -172,6 +285,14 @@ def main():
                  "n_fallback": diag["n_fallback"], "flags": diag["flag_names"],
                  "steps": diag["steps"]},
     }
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(out), flush=True)

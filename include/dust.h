@@ -248,7 +248,7 @@ dust_status_t dust_fill_ghosts(void *ctx, dust_fields_t *f, const dust_forces_t 
 dust_status_t dust_gather(void *ctx, const dust_particles_t *p, const dust_fields_t *f,
                           void *rho_p, void *vg_p[3], void *stream);
 
-/* Exponential-midpoint push phases (Eq. exp_midpoint; App. A and B).
+/* Exponential-midpoint push phases (Eq. exp_midpoint; App. B).
  * DRIFT1: half drift to x^{n+1/2}, boundary rules at frc->t + dt/2.
  * KICK: p^{n+1} = e^{-dt/tau} p^n + h1 G, h1 = tau (1 - e^{-dt/tau}) (Eq. h1),
  *   with the gas momentum formed from vg_p (physical, as dust_gather

@@ -519,8 +519,9 @@ static void drift_second(int geom, double h, double x[3], const double p[3]) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Exponential-midpoint kick (Eq. exp_midpoint, h1, kick_modified; App. A */
-/* Eq. standard_SB_exp_midpoint; App. B.1 Eq. kick_cylindrical; App. B.2). */
+/* Exponential-midpoint kick (Eq. exp_midpoint, h1, kick_modified; App.   */
+/* B.1 Eq. standard_SB_exp_midpoint; App. B.2 Eq. kick_cylindrical and    */
+/* its spherical analogue).                                               */
 
 /* Inputs: position x at n+1/2, canonical momenta p (level n), canonical gas
  * momenta pg at the particle, inverse stopping time, dt.  Outputs: p at
@@ -594,7 +595,7 @@ static void kick(int geom, int ndim, const orc_forces *f, double dt, double inv_
       gr = -f->GM * R / r3;
       gz = -f->GM * z / r3;
     }
-    /* order v_z, l_phi, v_R (App. B.1) */
+    /* order v_z, l_phi, v_R (App. B.2, cylindrical) */
     p[2] = e * p0[2] + h1 * gz + c * pg[2];
     a[2] = gz;
     double gphi = 0.0; /* axisymmetric potential */
@@ -609,7 +610,7 @@ static void kick(int geom, int ndim, const orc_forces *f, double dt, double inv_
   {
     double r = x[0], th = x[1], s = sin(th), ct = cos(th);
     if (f->kind == F_POINTMASS) gr = -f->GM / (r * r);
-    /* order l_phi, l_theta, v_r (App. B.2); the second average in the
+    /* order l_phi, l_theta, v_r (App. B.2, spherical); the second average in the
      * printed midpoint formula is read as (l_theta^2)^{n+1/2}. */
     double gphi = 0.0; /* axisymmetric potential, g_theta = 0 too */
     p[2] = e * p0[2] + h1 * (r * s * gphi) + c * pg[2];

@@ -65,8 +65,13 @@ struct Ctx {
   size_t ws_bytes = 0;
   // binning workspace
   BinWork bin{};
+  int bin_cur = 0;                // buffer of the last sort's keys / permutation
   size_t bin_bytes = 0;
   void* bin_mem = nullptr;
+  // shadow copy of the particle arrays (binned order) read by the fused step
+  void* shadow_mem = nullptr;
+  size_t shadow_cap = 0;          // bytes
+  char* shadow_ptr[12] = {};
   int64_t* bin_start = nullptr;   // nbins+1 (fused path)
   size_t bin_start_cap = 0;
   TileShape tile{{8, 8, 4}};
@@ -337,6 +342,44 @@ dust_status_t ensure_bin(Ctx* c, int64_t n) {
   return DUST_OK;
 }
 
+// Shadow arrays for the particles of p: one per array that p has.
+dust_status_t ensure_shadow(Ctx* c, const dust_particles_t* p) {
+  size_t rs = real_size(c), n = (size_t)std::max<int64_t>(p->n, 1);
+  auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t sizes[12] = {4, rs, rs, rs, rs, rs, rs, rs, rs, 1, 4, 0};
+  size_t need = 0;
+  for (int k = 0; k < 11; ++k) need += rup(n * sizes[k]);
+  if (need > c->shadow_cap) {
+    if (c->shadow_mem) HIP_TRY(hipFree(c->shadow_mem));
+    c->shadow_mem = nullptr;
+    c->shadow_cap = 0;
+    if (hipMalloc(&c->shadow_mem, need) != hipSuccess)
+      return fail(DUST_ENOMEM, "particle shadow arrays of %zu bytes", need);
+    c->shadow_cap = need;
+  }
+  char* q = (char*)c->shadow_mem;
+  for (int k = 0; k < 11; ++k) {
+    c->shadow_ptr[k] = q;
+    q += rup(n * sizes[k]);
+  }
+  return DUST_OK;
+}
+
+// The shadow arrays as a particle view with the same arrays present as p.
+template <typename TS> PView<TS> shadow_view(Ctx* c, const dust_particles_t* p) {
+  PView<TS> v = pview<TS>(const_cast<dust_particles_t*>(p));
+  v.cell = (int32_t*)c->shadow_ptr[0];
+  for (int d = 0; d < 3; ++d) {
+    v.off[d] = p->off[d] ? (TS*)c->shadow_ptr[1 + d] : nullptr;
+    v.mom[d] = p->mom[d] ? (TS*)c->shadow_ptr[4 + d] : nullptr;
+  }
+  v.drag = p->drag ? (TS*)c->shadow_ptr[7] : nullptr;
+  v.mass = p->mass ? (TS*)c->shadow_ptr[8] : nullptr;
+  v.species = p->species ? (uint8_t*)c->shadow_ptr[9] : nullptr;
+  v.id = p->id ? (int32_t*)c->shadow_ptr[10] : nullptr;
+  return v;
+}
+
 dust_status_t ensure_bin_start(Ctx* c) {
   size_t need = (size_t)c->n_active + 1;
   if (need <= c->bin_start_cap) return DUST_OK;
@@ -350,7 +393,7 @@ dust_status_t ensure_bin_start(Ctx* c) {
 dust_status_t apply_perm(Ctx* c, dust_particles_t* p, hipStream_t st) {
   int64_t n = p->n;
   int rs = (int)real_size(c);
-  const uint32_t* perm = c->bin.val[0];
+  const uint32_t* perm = c->bin.val[c->bin_cur];
   void* tmp = c->bin.gather_tmp;
   auto one = [&](void* a, int bytes) -> dust_status_t {
     if (!a) return DUST_OK;
@@ -420,19 +463,29 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
                          const Forces& F, double dt, int flags, bool rebin, hipStream_t st) {
   int nc = ctx_nc(c);
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
+  // Rebinning: keys of the cells the particles kick in, a stable sort, and
+  // one gather of the particle arrays into the context's shadow copy; the
+  // fused kernel then reads the shadow and writes the caller's arrays in
+  // binned order.  Without rebinning it works in place.
+  PView<TS> src = pv;
   if (rebin) {
-    launch_bin(p->cell, p->n, c->boxes_d, c->boxes.data(), c->nbox, c->n_active, DUST_BIN_TILE,
-               c->tile, c->bin, nullptr, c->bin_start, st);
-    dust_status_t s = apply_perm(c, p, st);
+    dust_status_t s = ensure_shadow(c, p);
     if (s) return s;
+    launch_halfstep_keys<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, dt, c->tdev,
+                                c->n_active, c->tile, c->bin.key[0], c->bin.val[0], st);
+    c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_TILE, c->tile,
+                            c->bin, nullptr, c->bin_start, true, st);
+    src = shadow_view<TS>(c, p);
+    launch_gather_particles<TS>(pv, src, pv, c->bin.val[c->bin_cur], c->bin_start, c->n_active, st);
   }
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
   bool prof = c->prof_used < c->prof_max;
   if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
-  launch_fused<TS, A>(c->plan, pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, F, c->species_d,
-                      c->drag_mode, dt, c->tdev, c->bin_start, c->diag, dg != nullptr, st);
+  launch_fused<TS, A>(c->plan, src, pv, rebin, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, F,
+                      c->species_d, c->drag_mode, dt, c->tdev, c->bin_start, c->diag, dg != nullptr,
+                      st);
   if (prof) {
     HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
     ++c->prof_used;
@@ -591,6 +644,7 @@ dust_status_t dust_ctx_destroy(void* ctx) {
   if (c->tdev) hipFree(c->tdev);
   if (c->ws) hipFree(c->ws);
   if (c->bin_mem) hipFree(c->bin_mem);
+  if (c->shadow_mem) hipFree(c->shadow_mem);
   if (c->bin_start) hipFree(c->bin_start);
   fused_plan_free(c->plan);
   delete c;
@@ -706,8 +760,8 @@ dust_status_t dust_bin(void* ctx, dust_particles_t* p, int32_t key_mode, int32_t
   dust_status_t s = ensure_bin(c, p->n);
   if (s) return s;
   c->last_stream = st;
-  launch_bin(p->cell, p->n, c->boxes_d, c->boxes.data(), c->nbox, c->n_active, key_mode, c->tile,
-             c->bin, perm_out, bin_start_out, st);
+  c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, key_mode, c->tile,
+                          c->bin, perm_out, bin_start_out, false, st);
   if (apply_permutation && p->n > 0) return apply_perm(c, p, st);
   HIP_TRY(hipGetLastError());
   return DUST_OK;
@@ -875,9 +929,9 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   c->last_stream = st;
   if ((s = ensure_ws(c, p->n))) return s;
   if (flags & DUST_STEP_FUSED) {
-    if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c))) return s;
+    if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
-    if (fused_lds_bytes(c->plan, ctx_nc(c)) > 160 * 1024)
+    if (fused_lds_bytes(c->plan, ctx_nc(c), c->prec == DUST_F64 ? 8 : 4) > 160 * 1024)
       return fail(DUST_EUNSUPPORTED, "fused tile window needs more than 160 KiB of LDS");
   }
   Forces F = forces_of(frc);

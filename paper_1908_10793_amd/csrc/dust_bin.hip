@@ -6,31 +6,13 @@
 // Deterministic: no atomics decide an order.
 #include "dust_device.h"
 #include "dust_launch.h"
+#include "dust_particle.h"
 
 namespace dust {
 
 static constexpr int BIN_THREADS = 256;
 static constexpr int BIN_ITEMS = 8;
 static constexpr int BIN_TILE = BIN_THREADS * BIN_ITEMS;  // elements per block
-
-__device__ __forceinline__ uint32_t tile_key(const Box& B, int64_t local, TileShape ts) {
-  int idx[3];
-  unravel(B, local, idx);
-  int n[3] = {B.ax[0].n, B.ax[1].n, B.ndim > 2 ? B.ax[2].n : 1};
-  int t[3] = {ts.t[0], ts.t[1], B.ndim > 2 ? ts.t[2] : 1};
-  int tid[3], ext[3];
-  for (int d = 0; d < 3; ++d) {
-    tid[d] = idx[d] / t[d];
-    int rem = n[d] - tid[d] * t[d];
-    ext[d] = rem < t[d] ? rem : t[d];
-  }
-  int64_t before = (int64_t)tid[2] * t[2] * n[0] * n[1] +
-                   (int64_t)tid[1] * t[1] * n[0] * ext[2] +
-                   (int64_t)tid[0] * t[0] * ext[1] * ext[2];
-  int64_t li = (idx[0] - tid[0] * t[0]) +
-               (int64_t)ext[0] * ((idx[1] - tid[1] * t[1]) + (int64_t)ext[1] * (idx[2] - tid[2] * t[2]));
-  return (uint32_t)(B.cell_base + before + li);
-}
 
 __global__ void k_make_keys(const int32_t* cell, int64_t n, const Box* boxes, int nbox,
                             uint32_t nbins, int key_mode, TileShape ts, uint32_t* key,
@@ -188,18 +170,18 @@ __global__ void k_copy_perm(const uint32_t* v, int64_t n, int32_t* perm) {
   if (i < n) perm[i] = (int32_t)v[i];
 }
 
-void launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, const Box* boxes_host,
-                int nbox, int64_t nbins, int key_mode, TileShape tile, BinWork& w,
-                int32_t* perm_out, int64_t* bin_start_out, hipStream_t st) {
-  (void)boxes_host;
+int launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, int nbox, int64_t nbins,
+               int key_mode, TileShape tile, BinWork& w, int32_t* perm_out,
+               int64_t* bin_start_out, bool keys_ready, hipStream_t st) {
   if (n == 0) {
     if (bin_start_out)
       hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)ceil_div(nbins + 1, 256)), dim3(256), 0, st,
                          bin_start_out, nbins + 1, (int64_t)0);
-    return;
+    return 0;
   }
-  hipLaunchKernelGGL(k_make_keys, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, cell, n,
-                     boxes_dev, nbox, (uint32_t)nbins, key_mode, tile, w.key[0], w.val[0]);
+  if (!keys_ready)
+    hipLaunchKernelGGL(k_make_keys, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, cell, n,
+                       boxes_dev, nbox, (uint32_t)nbins, key_mode, tile, w.key[0], w.val[0]);
   int bits = 1;
   while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)nbins) ++bits;
   int npass = (bits + 7) / 8;
@@ -214,16 +196,13 @@ void launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, const Box*
                        w.val[cur], n, shift, w.hist, nblocks, w.key[1 - cur], w.val[1 - cur]);
     cur = 1 - cur;
   }
-  if (cur != 0) {
-    hipMemcpyAsync(w.key[0], w.key[1], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-    hipMemcpyAsync(w.val[0], w.val[1], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-  }
   if (perm_out)
-    hipLaunchKernelGGL(k_copy_perm, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, w.val[0], n,
+    hipLaunchKernelGGL(k_copy_perm, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, w.val[cur], n,
                        perm_out);
   if (bin_start_out)
-    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, w.key[0], n,
+    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, w.key[cur], n,
                        (uint32_t)nbins, bin_start_out);
+  return cur;
 }
 
 template <int BYTES> struct Blob { unsigned char b[BYTES]; };

@@ -396,15 +396,14 @@ template <typename A> struct KickOut {
 };
 
 // Exponential-midpoint kick (Eq. exp_midpoint with A = -diag(1/tau);
-// App. A Eq. standard_SB_exp_midpoint; App. B.1 Eq. kick_cylindrical; App.
-// B.2) for canonical momenta p, slip s = p_g - p (canonical; the gas
-// momentum at the particle minus p) and inverse stopping time it.
+// App. B.1 Eq. standard_SB_exp_midpoint; App. B.2 Eq. kick_cylindrical and
+// its spherical analogue) for canonical momenta p, slip s = p_g - p (canonical; the gas
+// momentum at the particle minus p) and the drag propagator terms c, psi
+// of h = dt/tau (see propagator()).
 template <typename A, int GEOM, int NDIM>
-__device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A it,
+__device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A c, A psi,
                                      const Where<A>& w, const A p[3], const A s[3],
                                      KickOut<A>& o) {
-  A c, psi;
-  propagator<A>(dt * it, c, psi);
   A h1 = dt + dt * psi;
   A a[3] = {A(0), A(0), A(0)};
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;

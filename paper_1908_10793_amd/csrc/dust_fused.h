@@ -30,13 +30,30 @@ struct FusedPlan {
 
 dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileShape tile, int slack);
 void fused_plan_free(FusedPlan& plan);
-size_t fused_lds_bytes(const FusedPlan& plan, int nc);
+size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes);
 
+// One fused step over every tile: reads the particles from p (binned by
+// tile-major key, bin_start), writes them to q slot for slot (q may be p);
+// copy_attrs copies drag / mass / species / id along.
 template <typename TS, typename A>
-void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, int nbox, int geom,
-                  int ndim, int unif, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
-                  double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg, bool sums,
-                  hipStream_t st);
+void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q, bool copy_attrs,
+                  const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
+                  const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
+                  const int64_t* bin_start, DiagDev* dg, bool sums, hipStream_t st);
+
+// Keys (tile-major) of the cells the particles reach in the first half drift
+// of a step of length dt starting at *tdev; val = identity.
+template <typename TS, typename A>
+void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int geom, int ndim,
+                          int unif, const Forces& f, double dt, const double* tdev, int64_t nbins,
+                          TileShape ts, uint32_t* key, uint32_t* val, hipStream_t st);
+
+// sh = src permuted by perm (all arrays, one launch); then the slots from
+// bin_start[nbins] on (particles without a cell) are copied from sh to dst.
+template <typename TS>
+void launch_gather_particles(const PView<TS>& src, const PView<TS>& sh, const PView<TS>& dst,
+                             const uint32_t* perm, const int64_t* bin_start, int64_t nbins,
+                             hipStream_t st);
 
 void launch_count_step(DiagDev* dg, hipStream_t st);
 

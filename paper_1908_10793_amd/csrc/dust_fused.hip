@@ -102,9 +102,26 @@ void fused_plan_free(FusedPlan& plan) {
   plan.ntiles = 0;
 }
 
-size_t fused_lds_bytes(const FusedPlan& plan, int nc) {
-  return plan.lds_cells * (2 * nc + 1) * sizeof(double);
+// LDS of one workgroup: the FP64 deposit window ((nc+1) channels, padded to
+// 32 bytes), then the gas window as one 4-vector of the storage type per cell
+// (a single 16- or 32-byte LDS read gives every component of a cell).
+static size_t fused_dep_doubles(size_t cells, int nc) { return (cells * (nc + 1) + 3) & ~(size_t)3; }
+
+size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes) {
+  return fused_dep_doubles(plan.lds_cells, nc) * sizeof(double) + plan.lds_cells * 4 * (size_t)ts_bytes;
 }
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+  using type = float4;
+  static __device__ __forceinline__ float4 make(float a, float b, float c) { return make_float4(a, b, c, 0.f); }
+};
+template <> struct Vec4<double> {
+  using type = double4;
+  static __device__ __forceinline__ double4 make(double a, double b, double c) {
+    return make_double4(a, b, c, 0.0);
+  }
+};
 
 // Raw stored state of one particle (prefetched one particle ahead).
 template <typename TS> struct Raw {
@@ -124,21 +141,35 @@ __device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>&
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(FUSED_THREADS)
-    k_fused(const TileDesc* tiles, PView<TS> p, const Box* boxes, FView<TS> fl, Forces f,
-            const Species* sp, int drag_mode, A dt, const double* tdev, const int64_t* bin_start,
-            DiagDev* dg, int sums) {
+    k_fused(const TileDesc* tiles, PView<TS> p, PView<TS> dst, int copy_attrs, const Box* boxes,
+            FView<TS> fl, Forces f, const Species* sp, int drag_mode, A dt, const double* tdev,
+            const int64_t* bin_start, DiagDev* dg, int sums) {
+  // p: particles read (binned order); dst: where the updated particles are
+  // written, slot for slot (dst = p in place; otherwise the attributes that
+  // the step does not change are copied along when copy_attrs is set).
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   constexpr int H = FUSED_HALO;
   constexpr int HZ = NDIM > 2 ? H : 0;
   constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RZ = TZ + 2 * HZ;
   constexpr int RC = RX * RY * RZ;
+  using G4 = typename Vec4<TS>::type;
   extern __shared__ double smem[];
-  double* gas = smem;                 // nc * RC
-  double* dep = smem + nc * RC;       // (nc+1) * RC
+  double* dep = smem;                                                    // (nc+1) * RC
+  G4* gas = reinterpret_cast<G4*>(smem + ((RC * (nc + 1) + 3) & ~3));   // RC cells
+  // per-species drag propagator and mass (species mode: tau depends only on
+  // the species, so c and psi of Eq. phi1 are computed once per workgroup)
+  __shared__ A sp_c[DUST_MAX_SPECIES], sp_psi[DUST_MAX_SPECIES], sp_m[DUST_MAX_SPECIES];
   const TileDesc td = tiles[blockIdx.x];
   const Box& B = boxes[td.box];
   const int ox = td.i0 - H, oy = td.j0 - H, oz = td.k0 - HZ;  // window origin
+  if (threadIdx.x < sp->n) {
+    A c, psi;
+    propagator<A>(dt * A(sp->inv_tau[threadIdx.x]), c, psi);
+    sp_c[threadIdx.x] = c;
+    sp_psi[threadIdx.x] = psi;
+    sp_m[threadIdx.x] = A(sp->mass[threadIdx.x]);
+  }
   const double t0 = *tdev;
   const A h = A(0.5) * dt;
   const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = NDIM > 2 ? B.ax[2].n : 1;
@@ -149,8 +180,12 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     int i = ox + a, j = oy + bq, k = oz + cq;
     bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && (NDIM < 3 || (k >= -1 && k <= n2));
     int64_t id = in ? stored_index(B, i, j, k) : 0;
+    TS gv[3] = {TS(0), TS(0), TS(0)};
+    if (in) {
 #pragma unroll
-    for (int m = 0; m < nc; ++m) gas[m * RC + r] = in ? double(fl.vel[m][id]) : 0.0;
+      for (int m = 0; m < nc; ++m) gv[m] = fl.vel[m][id];
+    }
+    gas[r] = Vec4<TS>::make(gv[0], gv[1], gv[2]);
 #pragma unroll
     for (int m = 0; m <= nc; ++m) dep[m * RC + r] = 0.0;
   }
@@ -161,6 +196,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   const bool own = lx < td.ex && ly < td.ey && lz < td.ez;
   const int mycell[3] = {td.i0 + lx, td.j0 + ly, td.k0 + lz};
   const int mybase = (lx + H) + RX * ((ly + H) + RY * (lz + HZ));  // window index of my cell
+  const int32_t mycid = (int32_t)(B.cell_base + ravel(B, mycell));
   int64_t ps = 0, pe = 0;
   if (own) {
     int64_t key = td.key0 + lx + (int64_t)td.ex * (ly + (int64_t)td.ey * lz);
@@ -175,7 +211,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   for (int o = 0; o < NS; ++o)
 #pragma unroll
     for (int k = 0; k <= nc; ++k) acc[o][k] = TAcc(0);
-  double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0, s_cells = 0;
+  double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0;
+  A a_cells = A(0);
   unsigned long long n_fb = 0;
 
   Raw<TS> nxt;
@@ -192,9 +229,10 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     A off[3] = {A(0), A(0), A(0)}, mom[3] = {A(0), A(0), A(0)};
     const int32_t cid = cur.cell;
     bool live = cid >= 0 && cid >= B.cell_base && cid < B.cell_base + B.ncell;
+    bool removed = false;
     if (cid >= 0 && !live) flag(dg, DUST_FLAG_BAD_CELL);
     if (live) {
-      unravel(B, cid - B.cell_base, idx);
+      if (cid != mycid) unravel(B, cid - B.cell_base, idx);
       bool bad = false;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -205,8 +243,9 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
       // half drift to x^{n+1/2}
       if (!drift<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom)) {
-        store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(h), i, false, idx, off, mom, dg);
+        store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(h), i, false, idx, off, mom, dg);
         live = false;
+        removed = true;
       }
     }
     if (!live) {
@@ -245,9 +284,12 @@ __global__ void __launch_bounds__(FUSED_THREADS)
           const int r0 = base + RX * (bb + RY * c);
           A u[3] = {A(0), A(0), A(0)};
 #pragma unroll
-          for (int a = -1; a <= 1; ++a)
+          for (int a = -1; a <= 1; ++a) {
+            const G4 g = gas[r0 + a];
+            const TS gv[3] = {g.x, g.y, g.z};
 #pragma unroll
-            for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(gas[m * RC + r0 + a]) - up[m]);
+            for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(gv[m]) - up[m]);
+          }
           const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
 #pragma unroll
           for (int m = 0; m < nc; ++m) v[m] += wbc * u[m];
@@ -278,20 +320,31 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       flag(dg, DUST_FLAG_BAD_CELL);
       spc = 0;
     }
-    A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
-    A m = p.mass ? A(p.mass[i]) : A(sp->mass[spc]);
-    A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[spc]), wh);
+    A m = p.mass ? A(p.mass[i]) : sp_m[spc];
+    A c, psi;
+    if (drag_mode == DRAG_SPECIES) {
+      c = sp_c[spc];
+      psi = sp_psi[spc];
+    } else {
+      A it = inverse_tau<A, GEOM>(f, drag_mode, A(p.drag[i]), A(0), wh);
+      propagator<A>(dt * it, c, psi);
+    }
     KickOut<A> o;
-    kick<A, GEOM, NDIM>(B, f, dt, it, wh, mom, sl, o);
+    kick<A, GEOM, NDIM>(B, f, dt, c, psi, wh, mom, sl, o);
     A q[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
     for (int k = 0; k < nc; ++k) {
       q[k] = live ? -m * o.j[k] : A(0);  // deposits carry the minus sign of Eq. dust_feedback_final
       if (sums && live) {
-        A vbar = (mom[k] + A(0.5) * o.dp[k]) / wh.sc[k];
-        A dl = cell_width<A, U>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
-        double cps = fabs(double(vbar * dt / dl));
-        s_cells = cps > s_cells ? cps : s_cells;
+        A cps;
+        if constexpr (GEOM == GEOM_CART && U) {
+          cps = fabs((mom[k] + A(0.5) * o.dp[k]) * dt * A(B.ax[k].inv_d));
+        } else {
+          A vbar = (mom[k] + A(0.5) * o.dp[k]) / wh.sc[k];
+          A dl = cell_width<A, U>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
+          cps = fabs(vbar * dt / dl);
+        }
+        a_cells = cps > a_cells ? cps : a_cells;
         s_j[k] -= double(q[k]);
         s_abs += fabs(double(q[k]));
       }
@@ -356,7 +409,22 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // second half drift to x^{n+1}
     if (live) {
       bool alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
-      store_particle<TS, A, GEOM, NDIM>(p, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+      store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+    }
+    if (copy_attrs) {
+      if (!live) {
+        // removed or cell-less particles keep their last offsets and momenta
+        if (!removed) dst.cell[i] = cid;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d < NDIM) dst.off[d][i] = cur.off[d];
+          if (d < nc) dst.mom[d][i] = cur.mom[d];
+        }
+      }
+      if (p.drag) dst.drag[i] = p.drag[i];
+      if (p.mass) dst.mass[i] = p.mass[i];
+      if (p.species) dst.species[i] = p.species[i];
+      if (p.id) dst.id[i] = p.id[i];
     }
   }
 
@@ -394,6 +462,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 
   if (dg) {
     const int lane = threadIdx.x & 63;
+    double s_cells = double(a_cells);
     if (sums) {
       for (int k = 0; k < 3; ++k) s_j[k] = wave_sum(s_j[k]);
       s_e = wave_sum(s_e);
@@ -418,12 +487,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 }
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
-static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
+static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
+                           bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
                            bool sums, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
-  size_t lds = fused_lds_bytes(plan, nc);
+  size_t lds = fused_lds_bytes(plan, nc, (int)sizeof(TS));
   auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
   if (lds > 64 * 1024) {
     static bool raised = false;
@@ -433,17 +503,20 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const Box*
       raised = true;
     }
   }
-  hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, boxes_d,
-                     fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg, (int)sums);
+  hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, q,
+                     (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg,
+                     (int)sums);
 }
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
-static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
+static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
+                           bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
                            bool sums, hipStream_t st) {
 #define DUST_F(TX, TY, TZ)                                                                         \
-  launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev,  \
+  launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
+                                                   drag_mode, dt, tdev,                            \
                                                 bin_start, dg, sums, st)
   if constexpr (NDIM == 3) {
     switch (plan.shape) {
@@ -465,15 +538,15 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const Box*
 }
 
 template <typename TS, typename A>
-void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d, int nbox, int geom,
-                  int ndim, int unif, const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
-                  double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg, bool sums,
-                  hipStream_t st) {
+void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q, bool copy_attrs,
+                  const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
+                  const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
+                  const int64_t* bin_start, DiagDev* dg, bool sums, hipStream_t st) {
   (void)nbox;
   if (plan.ntiles == 0) return;
 #define DUST_G(G, D, UU)                                                                          \
-  launch_fused_g<TS, A, G, D, UU>(plan, p, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start, dg,  \
-                                  sums, st)
+  launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
+                                  bin_start, dg, sums, st)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
@@ -483,13 +556,127 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const Box* boxes_d,
 #undef DUST_G
 }
 
+// ---------------------------------------------------------------- rebinning by half-step cell
+
+// Tile-major key of the cell each particle reaches in the first half drift
+// (the same drift the fused kernel does, so a particle is normally processed
+// by the thread of the cell it kicks in).  A particle that leaves through an
+// open face keeps the key of its current cell (the fused kernel removes it);
+// a particle without a valid cell gets key nbins.
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
+__global__ void __launch_bounds__(256)
+    k_halfstep_keys(PView<TS> p, const Box* boxes, int nbox, Forces f, A dt, const double* tdev,
+                    uint32_t nbins, TileShape ts, uint32_t* key, uint32_t* val) {
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  val[i] = (uint32_t)i;
+  int64_t c = p.cell[i];
+  uint32_t k = nbins;
+  if (c >= 0 && c < (int64_t)nbins) {
+    const int b = find_box(boxes, nbox, c);
+    const Box& B = boxes[b];
+    int idx[3];
+    A off[3], mom[3];
+    unravel(B, c - B.cell_base, idx);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
+      mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+    }
+    const A h = A(0.5) * dt;
+    int64_t local = c - B.cell_base;
+    if (drift<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)) local = ravel(B, idx);
+    k = tile_key(B, local, ts);
+  }
+  key[i] = k;
+}
+
+template <typename TS, typename A>
+void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int geom, int ndim,
+                          int unif, const Forces& f, double dt, const double* tdev, int64_t nbins,
+                          TileShape ts, uint32_t* key, uint32_t* val, hipStream_t st) {
+  if (p.n == 0) return;
+  unsigned g = (unsigned)((p.n + 255) / 256);
+#define DUST_K(G, D, UU)                                                                          \
+  hipLaunchKernelGGL((k_halfstep_keys<TS, A, G, D, UU>), dim3(g), dim3(256), 0, st, p, boxes_d,     \
+                     nbox, f, A(dt), tdev, (uint32_t)nbins, ts, key, val)
+  if (geom == GEOM_CART && ndim == 2 && unif) DUST_K(GEOM_CART, 2, true);
+  else if (geom == GEOM_CART && ndim == 2) DUST_K(GEOM_CART, 2, false);
+  else if (geom == GEOM_CART && unif) DUST_K(GEOM_CART, 3, true);
+  else if (geom == GEOM_CART) DUST_K(GEOM_CART, 3, false);
+  else if (geom == GEOM_CYL) DUST_K(GEOM_CYL, 3, false);
+  else DUST_K(GEOM_SPH, 3, false);
+#undef DUST_K
+}
+
+// sh[i] = src[perm[i]] for every particle array (one launch).
+template <typename TS>
+__global__ void __launch_bounds__(256)
+    k_gather_particles(PView<TS> src, PView<TS> sh, const uint32_t* perm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= src.n) return;
+  const int64_t j = perm[i];
+  sh.cell[i] = src.cell[j];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (src.off[d]) sh.off[d][i] = src.off[d][j];
+    if (src.mom[d]) sh.mom[d][i] = src.mom[d][j];
+  }
+  if (src.drag) sh.drag[i] = src.drag[j];
+  if (src.mass) sh.mass[i] = src.mass[j];
+  if (src.species) sh.species[i] = src.species[j];
+  if (src.id) sh.id[i] = src.id[j];
+}
+
+// dst[i] = sh[i] for the slots from bin_start[nbins] on (particles without a
+// cell, sorted last and visited by no tile).
+template <typename TS>
+__global__ void __launch_bounds__(256)
+    k_copy_tail(PView<TS> sh, PView<TS> dst, const int64_t* bin_start, int64_t nbins) {
+  const int64_t i = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sh.n) return;
+  dst.cell[i] = sh.cell[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (sh.off[d]) dst.off[d][i] = sh.off[d][i];
+    if (sh.mom[d]) dst.mom[d][i] = sh.mom[d][i];
+  }
+  if (sh.drag) dst.drag[i] = sh.drag[i];
+  if (sh.mass) dst.mass[i] = sh.mass[i];
+  if (sh.species) dst.species[i] = sh.species[i];
+  if (sh.id) dst.id[i] = sh.id[i];
+}
+
+template <typename TS>
+void launch_gather_particles(const PView<TS>& src, const PView<TS>& sh, const PView<TS>& dst,
+                             const uint32_t* perm, const int64_t* bin_start, int64_t nbins,
+                             hipStream_t st) {
+  if (src.n == 0) return;
+  unsigned g = (unsigned)((src.n + 255) / 256);
+  hipLaunchKernelGGL(k_gather_particles<TS>, dim3(g), dim3(256), 0, st, src, sh, perm);
+  // the tail can be anywhere in [0, n]: cover n slots from its start
+  hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, sh, dst, bin_start, nbins);
+}
+
 #define DUST_FUSED_INST(TS, A)                                                                    \
-  template void launch_fused<TS, A>(const FusedPlan&, const PView<TS>&, const Box*, int, int, int, int, \
-                                    const FView<TS>&, const Forces&, const Species*, int, double,  \
-                                    const double*, const int64_t*, DiagDev*, bool, hipStream_t);
+  template void launch_fused<TS, A>(const FusedPlan&, const PView<TS>&, const PView<TS>&, bool,     \
+                                    const Box*, int, int, int, int, const FView<TS>&,              \
+                                    const Forces&, const Species*, int, double, const double*,     \
+                                    const int64_t*, DiagDev*, bool, hipStream_t);                  \
+  template void launch_halfstep_keys<TS, A>(const PView<TS>&, const Box*, int, int, int, int,       \
+                                            const Forces&, double, const double*, int64_t,         \
+                                            TileShape, uint32_t*, uint32_t*, hipStream_t);
 
 DUST_FUSED_INST(float, double)
 DUST_FUSED_INST(float, float)
 DUST_FUSED_INST(double, double)
+
+template void launch_gather_particles<float>(const PView<float>&, const PView<float>&,
+                                             const PView<float>&, const uint32_t*, const int64_t*,
+                                             int64_t, hipStream_t);
+template void launch_gather_particles<double>(const PView<double>&, const PView<double>&,
+                                              const PView<double>&, const uint32_t*, const int64_t*,
+                                              int64_t, hipStream_t);
 
 }  // namespace dust

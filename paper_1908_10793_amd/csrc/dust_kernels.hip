@@ -94,8 +94,10 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
       A m = p.mass ? A(p.mass[i]) : A(sp->mass[s]);
       A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[s]), w);
+      A c, psi;
+      propagator<A>(dt * it, c, psi);
       KickOut<A> o;
-      kick<A, GEOM, NDIM>(B, f, dt, it, w, mom, sl, o);
+      kick<A, GEOM, NDIM>(B, f, dt, c, psi, w, mom, sl, o);
       TW* imp[4] = {imp0, imp1, imp2, imp3};
       bool fin = isfinite(double(o.e));
 #pragma unroll

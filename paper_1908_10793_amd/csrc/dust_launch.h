@@ -66,11 +66,14 @@ struct BinWork {
 };
 size_t bin_scan_tmp_words(int64_t n);
 struct TileShape { int32_t t[3]; };
-// Sort particles by key; writes perm (sorted slot -> input index) and
-// bin_start (nbins+1).  key_mode: DUST_BIN_CELL or DUST_BIN_TILE.
-void launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, const Box* boxes_host,
-                int nbox, int64_t nbins, int key_mode, TileShape tile, BinWork& w,
-                int32_t* perm_out, int64_t* bin_start_out, hipStream_t st);
+// Stable sort of particles by key; writes perm (sorted slot -> input index)
+// and bin_start (nbins+1) if given.  key_mode: DUST_BIN_CELL or DUST_BIN_TILE;
+// keys_ready: w.key[0] / w.val[0] already hold the keys and identity values.
+// Returns the buffer index c with the sorted keys in w.key[c] and the
+// permutation in w.val[c].
+int launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, int nbox, int64_t nbins,
+               int key_mode, TileShape tile, BinWork& w, int32_t* perm_out,
+               int64_t* bin_start_out, bool keys_ready, hipStream_t st);
 // out[i] = in[perm[i]] for an array of `bytes`-sized elements.
 void launch_permute(const void* in, void* out, const uint32_t* perm, int64_t n, int bytes,
                     hipStream_t st);

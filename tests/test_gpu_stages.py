@@ -237,3 +237,59 @@ def test_invalid_arguments_are_rejected():
     F2["dep"] = F["dep"][:1]
     with pytest.raises(dust.DustError):
         ctx.step(P, F2, 0.01, dust.forces_for(w), 1, 0)
+
+
+# ------------------------------------------------------------------ fused rebinning
+
+def _by_id(P):
+    o = torch.argsort(P["id"])
+    return ({k: (v[o] if not isinstance(v, list) else [x[o] for x in v]) for k, v in P.items()})
+
+
+def test_fused_keeps_cellless_particles():
+    """Particles without a cell are sorted last and visited by no tile; the
+    rebinning fused step must still carry them (cell -1, offsets, momenta,
+    attributes unchanged) while the others move."""
+    dust = _dust()
+    w = synth.shearing_box(n=(16, 12, 8), dt=0.02)
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    P["cell"][::7] = -1
+    before = _by_id({k: (v.clone() if not isinstance(v, list) else [x.clone() for x in v])
+                     for k, v in P.items()})
+    ctx.step(P, F, w.dt, dust.forces_for(w), 3, dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK)
+    after = _by_id(P)
+    gone = before["cell"] < 0
+    assert torch.equal(after["cell"][gone], before["cell"][gone])
+    for d in range(3):
+        assert torch.equal(after["off"][d][gone], before["off"][d][gone])
+        assert torch.equal(after["mom"][d][gone], before["mom"][d][gone])
+    assert torch.equal(after["species"], before["species"])
+    assert bool((after["cell"][~gone] >= 0).all())      # periodic / shear box: nobody leaves
+    assert not torch.equal(after["off"][0][~gone], before["off"][0][~gone])
+
+
+@pytest.mark.parametrize("rebin_every", [2, 4])
+def test_stale_bins_match_rebinning_every_step(rebin_every):
+    """Rebinning only every k steps (particles processed away from their
+    binned cell through the LDS-atomic and global paths) gives the same
+    result as rebinning every step, up to the order of FP32 sums."""
+    dust = _dust()
+    w = synth.shearing_box(n=(16, 16, 8), dt=0.05)
+    ctx = dust.context_for(w)
+    P1, F1 = dust.upload(w, ctx)
+    P2, F2 = dust.upload(w, ctx)
+    base = dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
+    ctx.step(P1, F1, w.dt, dust.forces_for(w), 4, base)
+    ctx.step(P2, F2, w.dt, dust.forces_for(w), 4, base | dust.STEP_REBIN_EVERY(rebin_every))
+    torch.cuda.synchronize()
+    a, b = _by_id(P1), _by_id(P2)
+    assert torch.equal(a["cell"], b["cell"])
+    for d in range(3):
+        assert (a["off"][d] - b["off"][d]).abs().max().item() <= 1e-5
+        scale = a["mom"][d].abs().max().item() + 1e-30
+        assert (a["mom"][d] - b["mom"][d]).abs().max().item() <= 1e-5 * scale
+    for c in range(4):
+        x, y = F1["dep"][c], F2["dep"][c]
+        assert (x - y).abs().max().item() <= 1e-5 * max(x.abs().max().item(), 1e-30), c
+    assert ctx.status()["n_fallback"] >= 0

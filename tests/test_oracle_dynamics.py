@@ -4,7 +4,7 @@ Each test checks the oracle against something the paper or the mathematics
 fixes: exact solutions (exponential relaxation, terminal velocity, epicycles,
 circular and Kepler orbits, the NSH radial drift), the paper's printed L1
 errors of the deceleration test (Sec. 4.1), the closed-form inverse of the
-shearing-box kick (App. A), time reversibility (Sec. 3.2.2), exact momentum
+shearing-box kick (App. B.1), time reversibility (Sec. 3.2.2), exact momentum
 conservation and adjointness of gather and deposit (Eq. dust_feedback_final),
 and a brute-force stable sort for binning.
 """
@@ -64,7 +64,7 @@ def test_terminal_velocity_limit(tau):
 
 def test_infinite_stopping_time_reduces_to_stormer_verlet():
     """1/tau = 0: e = 1, h1 = dt, the cylindrical kick is the plain
-    Stormer-Verlet kick with the l^2 average (App. B.1)."""
+    Stormer-Verlet kick with the l^2 average (App. B.2)."""
     F = O.Forces(kind="pointmass", GM=1.0)
     x = np.array([1.3, 0.2, 0.1])
     p = np.array([0.05, 0.9, -0.02])
@@ -79,7 +79,7 @@ def test_infinite_stopping_time_reduces_to_stormer_verlet():
 
 
 def test_shearing_box_kick_matches_closed_form_inverse():
-    """App. A: R v^{n+1} = e v^n + h1 G(x, v^n/2, vg) with
+    """App. B.1: R v^{n+1} = e v^n + h1 G(x, v^n/2, vg) with
     R^-1 = [[1, W, 0], [-W, 1, 0], [0, 0, 1+W^2]]/(1+W^2), W = Omega h1."""
     for _ in range(50):
         Om, q = RNG.uniform(0.5, 2), 1.5
