@@ -284,9 +284,13 @@ dust_status_t dust_apply_feedback(void *ctx, dust_fields_t *f, void *stream);
  * deposit, drift, (with DUST_STEP_DIAG) FP64 conservation sums, fold,
  * (with DUST_STEP_APPLY_FEEDBACK) feedback.  On return dep holds the last
  * step's deposit.  DUST_STEP_FUSED runs the tiled fused kernel, rebinning
- * the particles by tile every DUST_STEP_REBIN_EVERY(k) steps (k = 1 if 0);
- * it reorders the particle arrays (give p->id to follow particles).  DUST_STEP_GRAPH captures the loop in a
- * hipGraph (replayed while arguments are unchanged). */
+ * the particles every DUST_STEP_REBIN_EVERY(k) steps (k = 1 if 0) by the
+ * tile-major key of the cell they reach in the first half drift.  It
+ * reorders the particle arrays (give p->id to follow particles): the
+ * particles of each group of 64 cells of a tile occupy consecutive slots,
+ * level by level (the j-th particle of every cell of the group that has more
+ * than j), and particles without a cell come last.  DUST_STEP_GRAPH captures
+ * the loop in a hipGraph (replayed while arguments are unchanged). */
 dust_status_t dust_step(void *ctx, dust_particles_t *p, dust_fields_t *f, double dt,
                         const dust_forces_t *frc, int32_t nsteps, int32_t flags, void *stream);
 

@@ -58,6 +58,7 @@ struct Ctx {
   int64_t n_stored = 0, n_active = 0;
   std::vector<int64_t> store_off;
   DiagDev* diag = nullptr;
+  double* grid_part = nullptr;    // per-block partials of the grid sums
   double* tdev = nullptr;         // [0] current step start time
   hipStream_t last_stream = nullptr;
   // unfused workspace
@@ -452,7 +453,7 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, cimp, dflags, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
   if (dg)
-    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
+    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, c->grid_part, st);
   for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
   if (flags & DUST_STEP_APPLY_FEEDBACK)
     for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
@@ -476,7 +477,8 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
     c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_TILE, c->tile,
                             c->bin, nullptr, c->bin_start, true, st);
     src = shadow_view<TS>(c, p);
-    launch_gather_particles<TS>(pv, src, pv, c->bin.val[c->bin_cur], c->bin_start, c->n_active, st);
+    launch_gather_particles<TS>(c->plan, pv, src, pv, c->bin.val[c->bin_cur], c->bin_start,
+                                c->n_active, st);
   }
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
@@ -491,7 +493,7 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
     ++c->prof_used;
   }
   if (dg)
-    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, st);
+    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, c->grid_part, st);
   for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
   if (flags & DUST_STEP_APPLY_FEEDBACK)
     for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
@@ -614,6 +616,7 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
       hipMemcpy(c->species_d, &c->species, sizeof(Species), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc((void**)&c->boxes_d, sizeof(Box) * nbox) != hipSuccess ||
       hipMalloc((void**)&c->diag, sizeof(DiagDev)) != hipSuccess ||
+      hipMalloc((void**)&c->grid_part, sizeof(double) * 4 * GRID_SUM_BLOCKS) != hipSuccess ||
       hipMalloc((void**)&c->tdev, 64) != hipSuccess) {
     dust_ctx_destroy(c);
     return fail(DUST_ENOMEM, "context tables");
@@ -641,6 +644,7 @@ dust_status_t dust_ctx_destroy(void* ctx) {
   if (c->boxes_d) hipFree(c->boxes_d);
   if (c->species_d) hipFree(c->species_d);
   if (c->diag) hipFree(c->diag);
+  if (c->grid_part) hipFree(c->grid_part);
   if (c->tdev) hipFree(c->tdev);
   if (c->ws) hipFree(c->ws);
   if (c->bin_mem) hipFree(c->bin_mem);

@@ -26,6 +26,7 @@ struct FusedPlan {
   int rmax[3] = {0, 0, 0};  // largest region extents
   size_t lds_cells = 0;
   TileDesc* tiles_d = nullptr;
+  double* part_d = nullptr;   // per-tile diagnostic partials
 };
 
 dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileShape tile, int slack);
@@ -48,12 +49,14 @@ void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int 
                           int unif, const Forces& f, double dt, const double* tdev, int64_t nbins,
                           TileShape ts, uint32_t* key, uint32_t* val, hipStream_t st);
 
-// sh = src permuted by perm (all arrays, one launch); then the slots from
-// bin_start[nbins] on (particles without a cell) are copied from sh to dst.
+// After a sort (perm, bin_start): sh = the binned particles of src in the
+// fused kernel's level-major layout within each wave's range of slots; the
+// particles without a cell (slots from bin_start[nbins] on) are copied to the
+// same slots of dst.
 template <typename TS>
-void launch_gather_particles(const PView<TS>& src, const PView<TS>& sh, const PView<TS>& dst,
-                             const uint32_t* perm, const int64_t* bin_start, int64_t nbins,
-                             hipStream_t st);
+void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const PView<TS>& sh,
+                             const PView<TS>& dst, const uint32_t* perm, const int64_t* bin_start,
+                             int64_t nbins, hipStream_t st);
 
 void launch_count_step(DiagDev* dg, hipStream_t st);
 

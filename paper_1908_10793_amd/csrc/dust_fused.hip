@@ -28,6 +28,7 @@
 namespace dust {
 
 static constexpr int FUSED_THREADS = 256;
+static constexpr int PART_WORDS = 8;   // per-workgroup diagnostic partials
 static constexpr int FUSED_HALO = 2;
 
 // Supported tile shapes (cells per axis, 256 cells each).
@@ -91,13 +92,18 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
   if (hipMemcpy(plan.tiles_d, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice) !=
       hipSuccess)
     return DUST_EDEVICE;
+  if (hipMalloc((void**)&plan.part_d, sizeof(double) * PART_WORDS * std::max<size_t>(tiles.size(), 1)) !=
+      hipSuccess)
+    return DUST_ENOMEM;
   plan.ok = true;
   return DUST_OK;
 }
 
 void fused_plan_free(FusedPlan& plan) {
-  if (plan.tiles_d) hipFree(plan.tiles_d);
+  if (plan.tiles_d) (void)hipFree(plan.tiles_d);
+  if (plan.part_d) (void)hipFree(plan.part_d);
   plan.tiles_d = nullptr;
+  plan.part_d = nullptr;
   plan.ok = false;
   plan.ntiles = 0;
 }
@@ -123,6 +129,40 @@ template <> struct Vec4<double> {
   }
 };
 
+// Level-major layout of the particles of one wave's cells.  The cells of a
+// wave are consecutive tile-major keys (a wave covers whole rows or layers of
+// its tile), so their particles occupy one range [base, base + total) of
+// slots.  Level j of the range holds the j-th particle of every cell that has
+// more than j, in lane order; the slot of lane l in level j is the level's
+// start plus the number of lower lanes whose cells have more than j.
+struct WaveLevels {
+  int cnt;          // particles of this lane's cell
+  int nlev;         // largest count in the wave
+  int64_t base;     // first slot of the wave's range
+  uint64_t below;   // lanes below this one
+};
+
+__device__ __forceinline__ WaveLevels wave_levels(int cnt, int64_t start) {
+  WaveLevels w;
+  w.cnt = cnt;
+  const int lane = threadIdx.x & 63;
+  w.below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  w.nlev = wave_max(cnt);
+  const uint64_t any = __ballot(cnt > 0);
+  // the first lane with particles has the smallest start of the range
+  w.base = any ? __shfl(start, __ffsll((unsigned long long)any) - 1, 64) : 0;
+  return w;
+}
+
+// Slot of this lane's particle of level j; lvl: start of level j on entry,
+// of level j+1 on return (call once per level, in order, in every lane).
+__device__ __forceinline__ int64_t level_slot(const WaveLevels& w, int j, int64_t& lvl) {
+  const uint64_t m = __ballot(w.cnt > j);
+  const int64_t s = lvl + __popcll(m & w.below);
+  lvl += __popcll(m);
+  return s;
+}
+
 // Raw stored state of one particle (prefetched one particle ahead).
 template <typename TS> struct Raw {
   int32_t cell;
@@ -141,9 +181,14 @@ __device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>&
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(FUSED_THREADS)
-    k_fused(const TileDesc* tiles, PView<TS> p, PView<TS> dst, int copy_attrs, const Box* boxes,
-            FView<TS> fl, Forces f, const Species* sp, int drag_mode, A dt, const double* tdev,
-            const int64_t* bin_start, DiagDev* dg, int sums) {
+    k_fused(const TileDesc* __restrict__ tiles, PView<TS> p, PView<TS> dst, int copy_attrs,
+            const Box* __restrict__ boxes, FView<TS> fl, Forces f, const Species* __restrict__ sp,
+            int drag_mode, A dt, const double* __restrict__ tdev,
+            const int64_t* __restrict__ bin_start, DiagDev* dg, double* __restrict__ part, int sums) {
+  // The descriptors (tiles, boxes, species, time, bin starts) are read-only
+  // and never aliased by the particle and field arrays: __restrict__ lets
+  // their fields stay in scalar registers / the scalar cache, so the loop's
+  // waits on particle loads do not also wait on descriptor reloads.
   // p: particles read (binned order); dst: where the updated particles are
   // written, slot for slot (dst = p in place; otherwise the attributes that
   // the step does not change are copied along when copy_attrs is set).
@@ -215,11 +260,21 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   A a_cells = A(0);
   unsigned long long n_fb = 0;
 
+  // Particle layout of a wave's cells (level-major, see level_slot): in
+  // iteration j every lane whose cell has more than j particles takes its
+  // cell's j-th particle, and those particles are consecutive slots, so the
+  // loads and stores of an iteration are contiguous.
+  const WaveLevels wl = wave_levels(own ? (int)(pe - ps) : 0, ps);
+  int64_t lvl = wl.base;
+  int64_t slot = level_slot(wl, 0, lvl);
   Raw<TS> nxt;
-  if (ps < pe) load_raw<TS, NDIM, nc>(p, ps, nxt);
-  for (int64_t i = ps; i < pe; ++i) {
+  if (wl.cnt > 0) load_raw<TS, NDIM, nc>(p, slot, nxt);
+  for (int j = 0; j < wl.nlev; ++j) {
+    const bool has = wl.cnt > j;
+    const int64_t i = slot;
     const Raw<TS> cur = nxt;
-    if (i + 1 < pe) load_raw<TS, NDIM, nc>(p, i + 1, nxt);   // prefetch the next particle
+    slot = level_slot(wl, j + 1, lvl);
+    if (wl.cnt > j + 1) load_raw<TS, NDIM, nc>(p, slot, nxt);   // prefetch the next particle
     // Lanes of one wave walk different cells, so nothing below branches
     // around the register sums: a particle without a cell, or one that left
     // through an open face, continues as a dummy at the centre of this
@@ -227,7 +282,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // copies of every register sum live).
     int idx[3] = {mycell[0], mycell[1], mycell[2]};
     A off[3] = {A(0), A(0), A(0)}, mom[3] = {A(0), A(0), A(0)};
-    const int32_t cid = cur.cell;
+    const int32_t cid = has ? cur.cell : -1;
     bool live = cid >= 0 && cid >= B.cell_base && cid < B.cell_base + B.ncell;
     bool removed = false;
     if (cid >= 0 && !live) flag(dg, DUST_FLAG_BAD_CELL);
@@ -315,18 +370,18 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     A sl[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
-    int spc = p.species ? p.species[i] : 0;
+    int spc = p.species && live ? p.species[i] : 0;
     if (spc >= sp->n) {
       flag(dg, DUST_FLAG_BAD_CELL);
       spc = 0;
     }
-    A m = p.mass ? A(p.mass[i]) : sp_m[spc];
+    A m = p.mass && live ? A(p.mass[i]) : sp_m[spc];
     A c, psi;
     if (drag_mode == DRAG_SPECIES) {
       c = sp_c[spc];
       psi = sp_psi[spc];
     } else {
-      A it = inverse_tau<A, GEOM>(f, drag_mode, A(p.drag[i]), A(0), wh);
+      A it = inverse_tau<A, GEOM>(f, drag_mode, live ? A(p.drag[i]) : A(1), A(0), wh);
       propagator<A>(dt * it, c, psi);
     }
     KickOut<A> o;
@@ -411,7 +466,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       bool alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
       store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
     }
-    if (copy_attrs) {
+    if (copy_attrs && has) {
       if (!live) {
         // removed or cell-less particles keep their last offsets and momenta
         if (!removed) dst.cell[i] = cid;
@@ -460,8 +515,11 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     }
   }
 
+  // Diagnostics: the workgroup's FP64 sums go to its own slot of `part`
+  // (plain stores; a second kernel adds the slots in a fixed order), so no
+  // atomics contend on the few diagnostic words.
   if (dg) {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double s_cells = double(a_cells);
     if (sums) {
       for (int k = 0; k < 3; ++k) s_j[k] = wave_sum(s_j[k]);
@@ -470,18 +528,61 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       s_cells = wave_max(s_cells);
     }
     unsigned long long fb = wave_sum(n_fb);
+    __shared__ double red[FUSED_THREADS / 64][PART_WORDS];
     if (lane == 0) {
-      if (sums) {
-        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&dg->p_part[k], s_j[k]);
-        unsafeAtomicAdd(&dg->e_part, s_e);
-        unsafeAtomicAdd(&dg->sum_abs_j, s_abs);
-        atomic_max_nonneg(&dg->max_cells_bits, s_cells);
-        if (s_cells > 1.8) atomicOr(&dg->flags, (unsigned)DUST_FLAG_CFL);
+      red[wave][0] = s_j[0];
+      red[wave][1] = s_j[1];
+      red[wave][2] = s_j[2];
+      red[wave][3] = s_e;
+      red[wave][4] = s_abs;
+      red[wave][5] = s_cells;
+      red[wave][6] = double(fb);
+      red[wave][7] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < PART_WORDS) {
+      const int k = threadIdx.x;
+      double v = red[0][k];
+      for (int w = 1; w < FUSED_THREADS / 64; ++w) v = k == 5 ? fmax(v, red[w][k]) : v + red[w][k];
+      part[(size_t)blockIdx.x * PART_WORDS + k] = sums || k >= 6 ? v : 0.0;
+    }
+  }
+}
+
+// Adds the per-workgroup partials of one fused launch to the diagnostics
+// block, in a fixed order (one workgroup).
+__global__ void __launch_bounds__(256)
+    k_reduce_fused_partials(const double* __restrict__ part, int n, DiagDev* dg, int sums) {
+  __shared__ double red[256][PART_WORDS];
+  double acc[PART_WORDS];
+  for (int k = 0; k < PART_WORDS; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < n; b += 256)
+    for (int k = 0; k < PART_WORDS; ++k) {
+      const double v = part[(size_t)b * PART_WORDS + k];
+      acc[k] = k == 5 ? fmax(acc[k], v) : acc[k] + v;
+    }
+  for (int k = 0; k < PART_WORDS; ++k) red[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < PART_WORDS; ++k) {
+        const double o = red[threadIdx.x + h][k];
+        red[threadIdx.x][k] = k == 5 ? fmax(red[threadIdx.x][k], o) : red[threadIdx.x][k] + o;
       }
-      if (fb) {
-        atomicAdd(&dg->n_fallback, fb);
-        atomicOr(&dg->flags, (unsigned)DUST_FLAG_TILE_OVERFLOW);
-      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (sums) {
+      for (int k = 0; k < 3; ++k) dg->p_part[k] += red[0][k];
+      dg->e_part += red[0][3];
+      dg->sum_abs_j += red[0][4];
+      atomic_max_nonneg(&dg->max_cells_bits, red[0][5]);
+      if (red[0][5] > 1.8) atomicOr(&dg->flags, (unsigned)DUST_FLAG_CFL);
+    }
+    const unsigned long long fb = (unsigned long long)red[0][6];
+    if (fb) {
+      dg->n_fallback += fb;
+      atomicOr(&dg->flags, (unsigned)DUST_FLAG_TILE_OVERFLOW);
     }
   }
 }
@@ -491,7 +592,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
-                           bool sums, hipStream_t st) {
+                           double* part, bool sums, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   size_t lds = fused_lds_bytes(plan, nc, (int)sizeof(TS));
   auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
@@ -504,7 +605,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
     }
   }
   hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, q,
-                     (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg,
+                     (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg, part,
                      (int)sums);
 }
 
@@ -513,11 +614,11 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
-                           bool sums, hipStream_t st) {
+                           double* part, bool sums, hipStream_t st) {
 #define DUST_F(TX, TY, TZ)                                                                         \
   launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
                                                    drag_mode, dt, tdev,                            \
-                                                bin_start, dg, sums, st)
+                                                bin_start, dg, part, sums, st)
   if constexpr (NDIM == 3) {
     switch (plan.shape) {
       case 0: DUST_F(8, 8, 4); break;
@@ -544,9 +645,10 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                   const int64_t* bin_start, DiagDev* dg, bool sums, hipStream_t st) {
   (void)nbox;
   if (plan.ntiles == 0) return;
+  double* part = plan.part_d;
 #define DUST_G(G, D, UU)                                                                          \
   launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
-                                  bin_start, dg, sums, st)
+                                  bin_start, dg, part, sums, st)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
@@ -554,6 +656,9 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
   else if (geom == GEOM_CYL) DUST_G(GEOM_CYL, 3, false);
   else DUST_G(GEOM_SPH, 3, false);
 #undef DUST_G
+  if (dg)
+    hipLaunchKernelGGL(k_reduce_fused_partials, dim3(1), dim3(256), 0, st, (const double*)part,
+                       plan.ntiles, dg, (int)sums);
 }
 
 // ---------------------------------------------------------------- rebinning by half-step cell
@@ -610,52 +715,79 @@ void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int 
 #undef DUST_K
 }
 
-// sh[i] = src[perm[i]] for every particle array (one launch).
+// Copy particle `from` of src to slot `to` of dst (every array src has).
 template <typename TS>
-__global__ void __launch_bounds__(256)
-    k_gather_particles(PView<TS> src, PView<TS> sh, const uint32_t* perm) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= src.n) return;
-  const int64_t j = perm[i];
-  sh.cell[i] = src.cell[j];
+__device__ __forceinline__ void copy_particle(const PView<TS>& src, int64_t from, const PView<TS>& dst,
+                                              int64_t to) {
+  dst.cell[to] = src.cell[from];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (src.off[d]) sh.off[d][i] = src.off[d][j];
-    if (src.mom[d]) sh.mom[d][i] = src.mom[d][j];
+    if (src.off[d]) dst.off[d][to] = src.off[d][from];
+    if (src.mom[d]) dst.mom[d][to] = src.mom[d][from];
   }
-  if (src.drag) sh.drag[i] = src.drag[j];
-  if (src.mass) sh.mass[i] = src.mass[j];
-  if (src.species) sh.species[i] = src.species[j];
-  if (src.id) sh.id[i] = src.id[j];
+  if (src.drag) dst.drag[to] = src.drag[from];
+  if (src.mass) dst.mass[to] = src.mass[from];
+  if (src.species) dst.species[to] = src.species[from];
+  if (src.id) dst.id[to] = src.id[from];
 }
 
-// dst[i] = sh[i] for the slots from bin_start[nbins] on (particles without a
-// cell, sorted last and visited by no tile).
+// Gather the binned particles of each tile from src into sh in the fused
+// kernel's level-major layout: one workgroup per tile, one thread per cell
+// (the fused kernel's mapping); sorted slot ps + j of a cell holds the input
+// index perm[ps + j] of its j-th particle.
 template <typename TS>
 __global__ void __launch_bounds__(256)
-    k_copy_tail(PView<TS> sh, PView<TS> dst, const int64_t* bin_start, int64_t nbins) {
-  const int64_t i = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sh.n) return;
-  dst.cell[i] = sh.cell[i];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (sh.off[d]) dst.off[d][i] = sh.off[d][i];
-    if (sh.mom[d]) dst.mom[d][i] = sh.mom[d][i];
+    k_gather_tiled(const TileDesc* __restrict__ tiles, TileShape ts, PView<TS> src, PView<TS> sh,
+                   const uint32_t* __restrict__ perm, const int64_t* __restrict__ bin_start) {
+  const TileDesc td = tiles[blockIdx.x];
+  const int TX = ts.t[0], TY = ts.t[1];
+  const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+  const bool own = lx < td.ex && ly < td.ey && lz < td.ez;
+  int64_t ps = 0, pe = 0;
+  if (own) {
+    const int64_t key = td.key0 + lx + (int64_t)td.ex * (ly + (int64_t)td.ey * lz);
+    ps = bin_start[key];
+    pe = bin_start[key + 1];
   }
-  if (sh.drag) dst.drag[i] = sh.drag[i];
-  if (sh.mass) dst.mass[i] = sh.mass[i];
-  if (sh.species) dst.species[i] = sh.species[i];
-  if (sh.id) dst.id[i] = sh.id[i];
+  const WaveLevels wl = wave_levels(own ? (int)(pe - ps) : 0, ps);
+  int64_t lvl = wl.base;
+  for (int j = 0; j < wl.nlev; ++j) {
+    const int64_t to = level_slot(wl, j, lvl);
+    if (wl.cnt > j) copy_particle(src, (int64_t)perm[ps + j], sh, to);
+  }
+}
+
+// Particles without a cell (sorted last, from slot bin_start[nbins] on):
+// sh[s] = src[perm[s]].  Covers n slots from the tail's start.
+template <typename TS>
+__global__ void __launch_bounds__(256)
+    k_gather_tail(PView<TS> src, PView<TS> sh, const uint32_t* __restrict__ perm,
+                  const int64_t* __restrict__ bin_start, int64_t nbins) {
+  const int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= src.n) return;
+  copy_particle(src, (int64_t)perm[s], sh, s);
+}
+
+// dst[s] = sh[s] for the tail slots (after the gathers, which read src = dst).
+template <typename TS>
+__global__ void __launch_bounds__(256)
+    k_copy_tail(PView<TS> sh, PView<TS> dst, const int64_t* __restrict__ bin_start, int64_t nbins) {
+  const int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= sh.n) return;
+  copy_particle(sh, s, dst, s);
 }
 
 template <typename TS>
-void launch_gather_particles(const PView<TS>& src, const PView<TS>& sh, const PView<TS>& dst,
-                             const uint32_t* perm, const int64_t* bin_start, int64_t nbins,
-                             hipStream_t st) {
+void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const PView<TS>& sh,
+                             const PView<TS>& dst, const uint32_t* perm, const int64_t* bin_start,
+                             int64_t nbins, hipStream_t st) {
   if (src.n == 0) return;
+  TileShape ts = plan.tile;
+  if (plan.ntiles > 0)
+    hipLaunchKernelGGL(k_gather_tiled<TS>, dim3(plan.ntiles), dim3(256), 0, st, plan.tiles_d, ts, src,
+                       sh, perm, bin_start);
   unsigned g = (unsigned)((src.n + 255) / 256);
-  hipLaunchKernelGGL(k_gather_particles<TS>, dim3(g), dim3(256), 0, st, src, sh, perm);
-  // the tail can be anywhere in [0, n]: cover n slots from its start
+  hipLaunchKernelGGL(k_gather_tail<TS>, dim3(g), dim3(256), 0, st, src, sh, perm, bin_start, nbins);
   hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, sh, dst, bin_start, nbins);
 }
 
@@ -672,11 +804,11 @@ DUST_FUSED_INST(float, double)
 DUST_FUSED_INST(float, float)
 DUST_FUSED_INST(double, double)
 
-template void launch_gather_particles<float>(const PView<float>&, const PView<float>&,
-                                             const PView<float>&, const uint32_t*, const int64_t*,
-                                             int64_t, hipStream_t);
-template void launch_gather_particles<double>(const PView<double>&, const PView<double>&,
-                                              const PView<double>&, const uint32_t*, const int64_t*,
-                                              int64_t, hipStream_t);
+template void launch_gather_particles<float>(const FusedPlan&, const PView<float>&,
+                                             const PView<float>&, const PView<float>&,
+                                             const uint32_t*, const int64_t*, int64_t, hipStream_t);
+template void launch_gather_particles<double>(const FusedPlan&, const PView<double>&,
+                                              const PView<double>&, const PView<double>&,
+                                              const uint32_t*, const int64_t*, int64_t, hipStream_t);
 
 }  // namespace dust

@@ -360,10 +360,10 @@ template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
 }
 
 // FP64 sums of dV D over every stored cell of one box: a grid-stride loop,
-// a block reduction, and one atomic per block and channel.
-static constexpr int GRID_SUM_BLOCKS = 512;
-
-template <typename TS> __global__ void __launch_bounds__(256) k_grid_sums(Box B, FView<TS> fl, DiagDev* dg) {
+// a block reduction into the block's slot of `part`, then one workgroup adds
+// the slots in a fixed order (no contended atomics, deterministic).
+template <typename TS>
+__global__ void __launch_bounds__(256) k_grid_sums(Box B, FView<TS> fl, double* __restrict__ part) {
   __shared__ double red[4][4];
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   const double inv_g0 = 1.0 / B.g0, inv_g1 = 1.0 / B.g1;
@@ -391,10 +391,28 @@ template <typename TS> __global__ void __launch_bounds__(256) k_grid_sums(Box B,
   if ((threadIdx.x & 63) == 0)
     for (int c = 0; c < 4; ++c) red[wave][c] = s[c];
   __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    part[(size_t)blockIdx.x * 4 + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_reduce_grid_partials(const double* __restrict__ part, int n, int nc, DiagDev* dg) {
+  __shared__ double red[256][4];
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < n; b += 256)
+    for (int c = 0; c < 4; ++c) acc[c] += part[(size_t)b * 4 + c];
+  for (int c = 0; c < 4; ++c) red[threadIdx.x][c] = acc[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int c = 0; c < 4; ++c) red[threadIdx.x][c] += red[threadIdx.x + h][c];
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    for (int c = 0; c < 4; ++c) s[c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-    for (int c = 0; c < nc; ++c) unsafeAtomicAdd(&dg->p_grid[c], s[c]);
-    unsafeAtomicAdd(&dg->e_grid, s[nc]);
+    for (int c = 0; c < nc; ++c) dg->p_grid[c] += red[0][c];
+    dg->e_grid += red[0][nc];
   }
 }
 
@@ -500,11 +518,14 @@ void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st) {
 }
 
 template <typename TS>
-void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, hipStream_t st) {
+void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, double* part, hipStream_t st) {
   unsigned nb = blocks_for(B.nstore);
   if (nb > (unsigned)GRID_SUM_BLOCKS) nb = GRID_SUM_BLOCKS;
   if (nb == 0) return;
-  hipLaunchKernelGGL((k_grid_sums<TS>), dim3(nb), dim3(256), 0, st, B, fl, dg);
+  hipLaunchKernelGGL((k_grid_sums<TS>), dim3(nb), dim3(256), 0, st, B, fl, part);
+  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
+  hipLaunchKernelGGL(k_reduce_grid_partials, dim3(1), dim3(256), 0, st, (const double*)part, (int)nb,
+                     nc, dg);
 }
 
 template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st) {
@@ -541,7 +562,7 @@ DUST_INST(double, double, double)
   template void launch_fold<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
                                 hipStream_t);                                                     \
   template void launch_feedback<TS>(const Box&, const FView<TS>&, hipStream_t);                   \
-  template void launch_grid_sums<TS>(const Box&, const FView<TS>&, DiagDev*, hipStream_t);        \
+  template void launch_grid_sums<TS>(const Box&, const FView<TS>&, DiagDev*, double*, hipStream_t); \
   template void launch_fill_value<TS>(TS*, int64_t, TS, hipStream_t);
 
 DUST_INST_GRID(float)
