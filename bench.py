@@ -35,8 +35,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--rebin-every", type=int, default=1)
-    ap.add_argument("--tile", type=str, default="8,8,4,1")
+    ap.add_argument("--rebin-every", type=int, default=1, help="with --no-tune")
+    ap.add_argument("--tile", type=str, default="8,8,4,0", help="with --no-tune")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (dust_ctx_autotune) and use --tile / --rebin-every")
     ap.add_argument("--n", type=int, default=128, help="cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
@@ -215,9 +217,18 @@ def main():
     ctx.set_tile(tx, ty, tz, slack)
     ctx.set_arith(args.arith)
     P, F = dust.upload(w, ctx, with_id=False)
-    flags = (dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG | dust.STEP_REBIN_EVERY(args.rebin_every))
-    if not args.unfused:
-        flags |= dust.STEP_FUSED
+    flags = dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
+    tuned = None
+    if args.unfused:
+        pass
+    elif args.no_tune:
+        flags |= dust.STEP_FUSED | dust.STEP_REBIN_EVERY(args.rebin_every)
+    else:
+        # tile shape and rebinning interval from the autotuner (on copies)
+        tuned = ctx.autotune(P, F, w.dt, dust.forces_for(w, 0.0), flags, steps=12)
+        (tx, ty, tz), rebin = tuned["tile"], tuned["rebin_every"]
+        args.rebin_every = rebin
+        flags |= dust.STEP_FUSED           # interval from the context
     K, W = args.steps, args.warmup
     t = 0.0
     torch.cuda.synchronize()
@@ -276,7 +287,8 @@ def main():
                                f"(8/cell, seeded sub-lattice), TSC, FP32 storage, {args.arith.upper()} push "
                                f"arithmetic, dt=0.005, feedback on",
                    "n_particles": N, "grid": [n, n, n], "tile": [tx, ty, tz], "slack": slack,
-                   "rebin_every": args.rebin_every, "fused": not args.unfused, "graph": False,
+                   "rebin_every": args.rebin_every, "autotuned": tuned,
+                   "fused": not args.unfused, "graph": False,
                    "storage": "f32", "push_arith": args.arith,
                    "deposit_accum": "f32 registers per cell, f64 LDS tile window, f32 HBM atomics"},
         "roofline": roof,

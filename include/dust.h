@@ -198,6 +198,20 @@ dust_status_t dust_ctx_set_arith(void *ctx, int32_t arith);
  * 8x32; other shapes give DUST_EUNSUPPORTED.  slack is reserved (0..4). */
 dust_status_t dust_ctx_set_tile(void *ctx, int32_t tx, int32_t ty, int32_t tz, int32_t slack);
 
+/* Autotuner of the fused step (batching and tuning row of the hot path):
+ * runs `steps` fused steps (after one warm-up step) for every compiled tile
+ * shape and rebinning interval 1..4 on device copies of p and f (the
+ * caller's arrays and the context's diagnostics are left unchanged), times
+ * them with HIP events on `stream`, and keeps the fastest tile shape and
+ * interval in the context (the interval is then used by dust_step when its
+ * flags give DUST_STEP_REBIN_EVERY(0)).  flags: any of APPLY_FEEDBACK, DIAG,
+ * NO_FILL (else DUST_EINVAL).  result (nullable): tx, ty, tz, interval;
+ * ms_per_step (nullable): the best time.  Synchronous; allocates copies of
+ * the particles and fields for its duration (DUST_ENOMEM if that fails). */
+dust_status_t dust_ctx_autotune(void *ctx, const dust_particles_t *p, const dust_fields_t *f,
+                                double dt, const dust_forces_t *frc, int32_t flags, int32_t steps,
+                                int32_t *result, float *ms_per_step, void *stream);
+
 /* Kernel timing of the fused path: with max_launches > 0, every dust_step
  * call records a pair of HIP events on its stream around each of its first
  * max_launches fused-kernel launches (also inside a captured graph, as event
@@ -284,7 +298,8 @@ dust_status_t dust_apply_feedback(void *ctx, dust_fields_t *f, void *stream);
  * deposit, drift, (with DUST_STEP_DIAG) FP64 conservation sums, fold,
  * (with DUST_STEP_APPLY_FEEDBACK) feedback.  On return dep holds the last
  * step's deposit.  DUST_STEP_FUSED runs the tiled fused kernel, rebinning
- * the particles every DUST_STEP_REBIN_EVERY(k) steps (k = 1 if 0) by the
+ * the particles every DUST_STEP_REBIN_EVERY(k) steps (k = 0: the context's
+ * interval, 1 unless dust_ctx_autotune chose another) by the
  * tile-major key of the cell they reach in the first half drift.  It
  * reorders the particle arrays (give p->id to follow particles): the
  * particles of each group of 64 cells of a tile occupy consecutive slots,

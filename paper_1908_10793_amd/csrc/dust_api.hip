@@ -59,6 +59,8 @@ struct Ctx {
   std::vector<int64_t> store_off;
   DiagDev* diag = nullptr;
   double* grid_part = nullptr;    // per-block partials of the grid sums
+  double* xg = nullptr;           // FP64 x-ghost gas layers of shear-periodic boxes
+  size_t xg_words = 0;
   double* tdev = nullptr;         // [0] current step start time
   hipStream_t last_stream = nullptr;
   // unfused workspace
@@ -77,6 +79,7 @@ struct Ctx {
   size_t bin_start_cap = 0;
   TileShape tile{{8, 8, 4}};
   int slack = 0;
+  int rebin_default = 1;          // rebinning interval when the step flags give none
   FusedPlan plan{};
   // fused-kernel timing
   std::vector<hipEvent_t> prof_ev;  // 2 per launch
@@ -210,6 +213,7 @@ dust_status_t build_box(Ctx* c, const dust_box_t& in, int ib, int64_t cell_base,
   B.ncell = ncell;
   B.store_base = store_base;
   B.nstore = (int64_t)B.g0 * B.g1 * B.g2;
+  B.xg_base = -1;
   return DUST_OK;
 }
 
@@ -343,6 +347,15 @@ dust_status_t ensure_bin(Ctx* c, int64_t n) {
   return DUST_OK;
 }
 
+// Forget the captured step graph (its nodes point at context buffers).
+void drop_graph(Ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_key = GraphKey{};
+}
+
 // Shadow arrays for the particles of p: one per array that p has.
 dust_status_t ensure_shadow(Ctx* c, const dust_particles_t* p) {
   size_t rs = real_size(c), n = (size_t)std::max<int64_t>(p->n, 1);
@@ -442,10 +455,11 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
   DiagDev* dflags = c->diag;  // sticky flags always recorded
   if (!(flags & DUST_STEP_NO_FILL))
-    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
-  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, (A*)nullptr, vg, dflags, st);
+  launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv,
+                          (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, (A*)nullptr, vg, dflags, st);
   const A* cvg[3] = {vg[0], vg[1], vg[2]};
   launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, cvg, imp,
                         dg ? dg : dflags, st);
@@ -481,13 +495,13 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
                                 c->n_active, st);
   }
   if (!(flags & DUST_STEP_NO_FILL))
-    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
   for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
   bool prof = c->prof_used < c->prof_max;
   if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
   launch_fused<TS, A>(c->plan, src, pv, rebin, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, F,
-                      c->species_d, c->drag_mode, dt, c->tdev, c->bin_start, c->diag, dg != nullptr,
-                      st);
+                      c->species_d, c->drag_mode, dt, c->tdev, c->bin_start,
+                      (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr, st);
   if (prof) {
     HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
     ++c->prof_used;
@@ -506,7 +520,7 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
   PView<TS> pv = pview<TS>(p);
   FView<TS> fv = fview<TS>(f);
   int rebin_every = (flags >> 8) & 0xff;
-  if (rebin_every <= 0) rebin_every = 1;
+  if (rebin_every <= 0) rebin_every = c->rebin_default;
   for (int s = 0; s < nsteps; ++s) {
     if (flags & DUST_STEP_FUSED) {
       dust_status_t e = fused_step<TS, A>(c, p, pv, fv, F, dt, flags, s % rebin_every == 0, st);
@@ -589,6 +603,13 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
     store_base += c->boxes[b].nstore;
   }
   c->store_off[nbox] = store_base;
+  // FP64 x-ghost gas layers of the shear-periodic boxes
+  c->xg_words = 0;
+  for (auto& B : c->boxes)
+    if (B.ax[0].bc_lo == DUST_BC_SHEAR) {
+      B.xg_base = (int64_t)c->xg_words;
+      c->xg_words += (size_t)2 * 3 * B.g1 * B.g2;
+    }
   c->geom = c->boxes[0].geom;
   c->ndim = c->boxes[0].ndim;
   for (int b = 1; b < nbox; ++b)
@@ -617,6 +638,7 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
       hipMalloc((void**)&c->boxes_d, sizeof(Box) * nbox) != hipSuccess ||
       hipMalloc((void**)&c->diag, sizeof(DiagDev)) != hipSuccess ||
       hipMalloc((void**)&c->grid_part, sizeof(double) * 4 * GRID_SUM_BLOCKS) != hipSuccess ||
+      (c->xg_words && hipMalloc((void**)&c->xg, sizeof(double) * c->xg_words) != hipSuccess) ||
       hipMalloc((void**)&c->tdev, 64) != hipSuccess) {
     dust_ctx_destroy(c);
     return fail(DUST_ENOMEM, "context tables");
@@ -645,6 +667,7 @@ dust_status_t dust_ctx_destroy(void* ctx) {
   if (c->species_d) hipFree(c->species_d);
   if (c->diag) hipFree(c->diag);
   if (c->grid_part) hipFree(c->grid_part);
+  if (c->xg) hipFree(c->xg);
   if (c->tdev) hipFree(c->tdev);
   if (c->ws) hipFree(c->ws);
   if (c->bin_mem) hipFree(c->bin_mem);
@@ -672,6 +695,7 @@ dust_status_t dust_ctx_set_tile(void* ctx, int32_t tx, int32_t ty, int32_t tz, i
   }
   if (slack < 0 || slack > 4) return fail(DUST_EINVAL, "slack %d out of 0..4", slack);
   c->slack = slack;
+  drop_graph(c);
   dust_status_t s = fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
   if (s) return fail(s, "tile %dx%dx%d is not one of the compiled fused tile shapes", c->tile.t[0],
                      c->tile.t[1], c->tile.t[2]);
@@ -693,11 +717,7 @@ dust_status_t dust_ctx_set_profile(void* ctx, int32_t max_launches) {
     c->prof_ev.push_back(e);
   }
   c->prof_max = max_launches;
-  // graphs captured before carry no event nodes
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  c->graph_exec = nullptr;
-  c->graph = nullptr;
+  drop_graph(c);  // graphs captured before carry no event nodes
   return DUST_OK;
 }
 
@@ -785,7 +805,7 @@ dust_status_t dust_fill_ghosts(void* ctx, dust_fields_t* f, const dust_forces_t*
   return dispatch(c, [&](auto ts, auto) -> dust_status_t {
     using TS = decltype(ts);
     FView<TS> fv = fview<TS>(f);
-    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.0, fv, st);
+    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.0, fv, c->xg, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -830,7 +850,8 @@ dust_status_t dust_gather(void* ctx, const dust_particles_t* p, const dust_field
     using A = decltype(ta);
     TS* vg[3] = {nullptr, nullptr, nullptr};
     for (int k = 0; k < nc; ++k) vg[k] = (TS*)vg_p[k];
-    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), (TS*)rho_p, vg, c->diag, st);
+    launch_gather<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f),
+                             nullptr, (TS*)rho_p, vg, c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -931,7 +952,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(c->device));
   c->last_stream = st;
-  if ((s = ensure_ws(c, p->n))) return s;
+  if (!(flags & DUST_STEP_FUSED) && (s = ensure_ws(c, p->n))) return s;
   if (flags & DUST_STEP_FUSED) {
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
@@ -969,6 +990,8 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   put(&st, sizeof(st));
   put(&c->arith, sizeof(c->arith));
   put(&c->tile, sizeof(c->tile));
+  put(&c->rebin_default, sizeof(c->rebin_default));
+  put(&c->plan.tiles_d, sizeof(c->plan.tiles_d));
   put(&c->prof_max, sizeof(c->prof_max));
   if (!(c->graph_exec && key == c->graph_key)) {
     if (c->graph_exec) {
@@ -1009,6 +1032,132 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
     c->graph_key = key;
   }
   HIP_TRY(hipGraphLaunch(c->graph_exec, st));
+  return DUST_OK;
+}
+
+
+// Autotuner: times the fused step for every compiled tile shape and
+// rebinning intervals 1..4 on copies of the caller's particles and fields,
+// then keeps the fastest shape and interval in the context.
+dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust_fields_t* f,
+                                double dt, const dust_forces_t* frc, int32_t flags, int32_t steps,
+                                int32_t* result, float* ms_per_step, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, true)) || (s = check_fields(c, f, true, true)) ||
+      (s = check_forces(c, frc)) || (s = check_drag(c, p)))
+    return s;
+  if (!std::isfinite(dt)) return fail(DUST_EINVAL, "dt not finite");
+  if (steps < 1 || steps > 1000) return fail(DUST_EINVAL, "steps out of 1..1000");
+  if (flags & ~(DUST_STEP_APPLY_FEEDBACK | DUST_STEP_DIAG | DUST_STEP_NO_FILL))
+    return fail(DUST_EINVAL, "autotune flags: only APPLY_FEEDBACK, DIAG, NO_FILL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  const size_t n = (size_t)p->n, rs = real_size(c), ns = (size_t)c->n_stored;
+  // scratch copies: particle arrays, then fields
+  struct Arr { const void* src; void** dst; size_t bytes; };
+  dust_particles_t pc = *p;
+  dust_fields_t fc = *f;
+  std::vector<Arr> arrs;
+  auto add = [&](const void* src, void** dst, size_t bytes) {
+    if (src) arrs.push_back({src, dst, bytes});
+  };
+  add(p->cell, (void**)&pc.cell, n * 4);
+  for (int d = 0; d < 3; ++d) {
+    add(p->off[d], &pc.off[d], n * rs);
+    add(p->mom[d], &pc.mom[d], n * rs);
+  }
+  add(p->drag, (void**)&pc.drag, n * rs);
+  add(p->mass, (void**)&pc.mass, n * rs);
+  add(p->species, (void**)&pc.species, n);
+  add(p->id, (void**)&pc.id, n * 4);
+  add(f->rho, &fc.rho, ns * rs);
+  for (int d = 0; d < 3; ++d) add(f->vel[d], &fc.vel[d], ns * rs);
+  for (int d = 0; d < 4; ++d) add(f->dep[d], &fc.dep[d], ns * rs);
+  size_t total = 0;
+  for (auto& a : arrs) total += (a.bytes + 255) & ~(size_t)255;
+  void* mem = nullptr;
+  if (total && hipMalloc(&mem, total) != hipSuccess) return fail(DUST_ENOMEM, "autotune copies of %zu bytes", total);
+  {
+    char* q = (char*)mem;
+    for (auto& a : arrs) {
+      *a.dst = q;
+      q += (a.bytes + 255) & ~(size_t)255;
+    }
+  }
+  auto restore = [&]() -> dust_status_t {
+    for (auto& a : arrs)
+      HIP_TRY(hipMemcpyAsync(*a.dst, a.src, a.bytes, hipMemcpyDeviceToDevice, st));
+    return DUST_OK;
+  };
+  // keep the caller's diagnostics and profiling state
+  DiagDev saved{};
+  HIP_TRY(hipMemcpy(&saved, c->diag, sizeof(DiagDev), hipMemcpyDeviceToHost));
+  const int prof_max = c->prof_max;
+  c->prof_max = 0;
+  const TileShape keep_tile = c->tile;
+  std::vector<TileShape> shapes;
+  if (c->ndim > 2) {
+    const int t3[6][3] = {{8, 8, 4}, {16, 4, 4}, {4, 16, 4}, {4, 4, 16}, {8, 4, 8}, {4, 8, 8}};
+    for (auto& t : t3) shapes.push_back(TileShape{{t[0], t[1], t[2]}});
+  } else {
+    const int t2[3][2] = {{16, 16}, {32, 8}, {8, 32}};
+    for (auto& t : t2) shapes.push_back(TileShape{{t[0], t[1], 1}});
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  TileShape best_tile = keep_tile;
+  int best_k = 1;
+  s = DUST_OK;
+  for (const TileShape& t : shapes) {
+    c->tile = t;
+    drop_graph(c);
+    if (fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack) != DUST_OK) continue;
+    if (fused_lds_bytes(c->plan, ctx_nc(c), (int)rs) > 160 * 1024) continue;
+    for (int k = 1; k <= 4 && !s; ++k) {
+      if ((s = restore())) break;
+      const int32_t fl = flags | DUST_STEP_FUSED | DUST_STEP_REBIN_EVERY(k);
+      if ((s = dust_step(c, &pc, &fc, dt, frc, 1, fl, st))) break;  // warm-up
+      if (hipEventRecord(e0, st) != hipSuccess) { s = fail(DUST_EDEVICE, "event record"); break; }
+      if ((s = dust_step(c, &pc, &fc, dt, frc, steps, fl, st))) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        s = fail(DUST_EDEVICE, "event sync");
+        break;
+      }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { s = fail(DUST_EDEVICE, "event time"); break; }
+      ms /= (float)steps;
+      if (ms < best) {
+        best = ms;
+        best_tile = t;
+        best_k = k;
+      }
+    }
+    if (s) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  if (mem) (void)hipFree(mem);
+  c->prof_max = prof_max;
+  c->tile = s ? keep_tile : best_tile;
+  drop_graph(c);
+  dust_status_t s2 = fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
+  HIP_TRY(hipMemcpy(c->diag, &saved, sizeof(DiagDev), hipMemcpyHostToDevice));
+  if (s) return s;
+  if (s2) return fail(s2, "fused plan");
+  c->rebin_default = best_k;
+  if (result) {
+    result[0] = best_tile.t[0];
+    result[1] = best_tile.t[1];
+    result[2] = best_tile.t[2];
+    result[3] = best_k;
+  }
+  if (ms_per_step) *ms_per_step = best;
   return DUST_OK;
 }
 

@@ -35,12 +35,14 @@ size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes);
 
 // One fused step over every tile: reads the particles from p (binned by
 // tile-major key, bin_start), writes them to q slot for slot (q may be p);
-// copy_attrs copies drag / mass / species / id along.
+// copy_attrs copies drag / mass / species / id along.  xg: the context's
+// FP64 x-ghost gas layers (filled this step), or null.
 template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q, bool copy_attrs,
                   const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
-                  const int64_t* bin_start, DiagDev* dg, bool sums, hipStream_t st);
+                  const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
+                  hipStream_t st);
 
 // Keys (tile-major) of the cells the particles reach in the first half drift
 // of a step of length dt starting at *tdev; val = identity.

@@ -120,12 +120,14 @@ size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes) {
 template <typename T> struct Vec4;
 template <> struct Vec4<float> {
   using type = float4;
-  static __device__ __forceinline__ float4 make(float a, float b, float c) { return make_float4(a, b, c, 0.f); }
+  static __device__ __forceinline__ float4 make(float a, float b, float c, float d) {
+    return make_float4(a, b, c, d);
+  }
 };
 template <> struct Vec4<double> {
   using type = double4;
-  static __device__ __forceinline__ double4 make(double a, double b, double c) {
-    return make_double4(a, b, c, 0.0);
+  static __device__ __forceinline__ double4 make(double a, double b, double c, double d) {
+    return make_double4(a, b, c, d);
   }
 };
 
@@ -184,7 +186,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     k_fused(const TileDesc* __restrict__ tiles, PView<TS> p, PView<TS> dst, int copy_attrs,
             const Box* __restrict__ boxes, FView<TS> fl, Forces f, const Species* __restrict__ sp,
             int drag_mode, A dt, const double* __restrict__ tdev,
-            const int64_t* __restrict__ bin_start, DiagDev* dg, double* __restrict__ part, int sums) {
+            const int64_t* __restrict__ bin_start, const double* __restrict__ xg, DiagDev* dg,
+            double* __restrict__ part, int sums) {
   // The descriptors (tiles, boxes, species, time, bin starts) are read-only
   // and never aliased by the particle and field arrays: __restrict__ lets
   // their fields stay in scalar registers / the scalar cache, so the loop's
@@ -226,11 +229,21 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && (NDIM < 3 || (k >= -1 && k <= n2));
     int64_t id = in ? stored_index(B, i, j, k) : 0;
     TS gv[3] = {TS(0), TS(0), TS(0)};
-    if (in) {
+    TS lo = TS(0);
+    if (in && xg && B.xg_base >= 0 && (i < 0 || i >= n0)) {
+      // x ghost of a shear-periodic box: the FP64 ghost value, its y
+      // component (which carries the shear boost) as a sum of two words
+#pragma unroll
+      for (int m = 0; m < nc; ++m) {
+        const double v = gas_comp(B, fl, xg, m, i, j, k);
+        gv[m] = TS(v);
+        if (m == 1) lo = TS(v - double(gv[m]));
+      }
+    } else if (in) {
 #pragma unroll
       for (int m = 0; m < nc; ++m) gv[m] = fl.vel[m][id];
     }
-    gas[r] = Vec4<TS>::make(gv[0], gv[1], gv[2]);
+    gas[r] = Vec4<TS>::make(gv[0], gv[1], gv[2], lo);
 #pragma unroll
     for (int m = 0; m <= nc; ++m) dep[m * RC + r] = 0.0;
   }
@@ -317,6 +330,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
     const bool inside = la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
                         (c2 == 0 || (lc >= 1 && lc <= RZ - 2));
+
     const bool home = idx[0] == mycell[0] && idx[1] == mycell[1] && (c2 == 0 || idx[2] == mycell[2]);
     // Gather (Eq. Delta_vp) in slip form: the weights sum to one, so the
     // slip p_g - p is sc * sum_i W_i (v_i - u) with u = p / sc the particle's
@@ -344,6 +358,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
             const TS gv[3] = {g.x, g.y, g.z};
 #pragma unroll
             for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(gv[m]) - up[m]);
+            if (nc > 1) u[1] += s.w[0][a + 1] * A(g.w);   // low word (shear x ghosts only)
           }
           const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
 #pragma unroll
@@ -591,8 +606,8 @@ template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, i
 static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
-                           double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
-                           double* part, bool sums, hipStream_t st) {
+                           double dt, const double* tdev, const int64_t* bin_start, const double* xg,
+                           DiagDev* dg, double* part, bool sums, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   size_t lds = fused_lds_bytes(plan, nc, (int)sizeof(TS));
   auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
@@ -605,7 +620,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
     }
   }
   hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, q,
-                     (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, dg, part,
+                     (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, xg, dg, part,
                      (int)sums);
 }
 
@@ -613,12 +628,12 @@ template <typename TS, typename A, int GEOM, int NDIM, bool U>
 static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
-                           double dt, const double* tdev, const int64_t* bin_start, DiagDev* dg,
-                           double* part, bool sums, hipStream_t st) {
+                           double dt, const double* tdev, const int64_t* bin_start, const double* xg,
+                           DiagDev* dg, double* part, bool sums, hipStream_t st) {
 #define DUST_F(TX, TY, TZ)                                                                         \
   launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
                                                    drag_mode, dt, tdev,                            \
-                                                bin_start, dg, part, sums, st)
+                                                bin_start, xg, dg, part, sums, st)
   if constexpr (NDIM == 3) {
     switch (plan.shape) {
       case 0: DUST_F(8, 8, 4); break;
@@ -642,13 +657,14 @@ template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q, bool copy_attrs,
                   const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
-                  const int64_t* bin_start, DiagDev* dg, bool sums, hipStream_t st) {
+                  const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
+                  hipStream_t st) {
   (void)nbox;
   if (plan.ntiles == 0) return;
   double* part = plan.part_d;
 #define DUST_G(G, D, UU)                                                                          \
   launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
-                                  bin_start, dg, part, sums, st)
+                                  bin_start, xg, dg, part, sums, st)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
@@ -795,7 +811,7 @@ void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const 
   template void launch_fused<TS, A>(const FusedPlan&, const PView<TS>&, const PView<TS>&, bool,     \
                                     const Box*, int, int, int, int, const FView<TS>&,              \
                                     const Forces&, const Species*, int, double, const double*,     \
-                                    const int64_t*, DiagDev*, bool, hipStream_t);                  \
+                                    const int64_t*, const double*, DiagDev*, bool, hipStream_t);   \
   template void launch_halfstep_keys<TS, A>(const PView<TS>&, const Box*, int, int, int, int,       \
                                             const Forces&, double, const double*, int64_t,         \
                                             TileShape, uint32_t*, uint32_t*, hipStream_t);

@@ -32,8 +32,8 @@ __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, in
 
 template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, int nbox,
-                                                FView<TS> fl, TW* rho_p, TW* vg0, TW* vg1,
-                                                TW* vg2, DiagDev* dg) {
+                                                FView<TS> fl, const double* xg, TW* rho_p,
+                                                TW* vg0, TW* vg1, TW* vg2, DiagDev* dg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   int idx[3];
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, i
         int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
         if (rho_p) r += w * A(fl.rho[id]);
 #pragma unroll
-        for (int m = 0; m < nc; ++m) v[m] += w * A(fl.vel[m][id]);
+        for (int m = 0; m < nc; ++m) v[m] += w * A(gas_comp(B, fl, xg, m, idx[0] + a, idx[1] + bb, idx[2] + c));
       }
     }
   if (rho_p) rho_p[i] = TW(r);
@@ -226,6 +226,35 @@ __global__ void k_fill_x(Box B, TS* a, int comp_vy, double qOmega, const double*
     a[stored_index(B, -1, j, k)] = a[stored_index(B, n0 - 1, j, k)];
     a[stored_index(B, n0, j, k)] = a[stored_index(B, 0, j, k)];
   }
+}
+
+// FP64 copy of the shear-periodic x-ghost gas of velocity component m, with
+// the y and z ghost rows of the layer (periodic images): the interpolated and
+// boosted ghost values keep their FP64 rounding, so that a particle next to
+// the shear boundary sees the gas at the accuracy of the interior values.
+template <typename TS>
+__global__ void k_fill_xghost(Box B, const TS* a, double* xg, int m, int comp_vy, double qOmega,
+                              const double* tdev, double toff) {
+  const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
+  const int g1 = n1 + 2, g2 = n2 + 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)g1 * g2) return;
+  const Shift sh = make_shift(B, qOmega, *tdev + toff);
+  const int jg = (int)(t % g1), kg = (int)(t / g1);
+  const int j = ((jg - 1) % n1 + n1) % n1, k = ((kg - 1) % n2 + n2) % n2;
+  int jl = j + sh.si;
+  int j0 = ((jl % n1) + n1) % n1, j1 = ((jl + 1) % n1 + n1) % n1;
+  double right = (1.0 - sh.sf) * double(a[stored_index(B, 0, j0, k)]) +
+                 sh.sf * double(a[stored_index(B, 0, j1, k)]) - (comp_vy ? sh.u : 0.0);
+  int jm = j - sh.si - (sh.sf > 0 ? 1 : 0);
+  double frm = sh.sf > 0 ? 1.0 - sh.sf : 0.0;
+  j0 = ((jm % n1) + n1) % n1;
+  j1 = ((jm + 1) % n1 + n1) % n1;
+  double left = (1.0 - frm) * double(a[stored_index(B, n0 - 1, j0, k)]) +
+                frm * double(a[stored_index(B, n0 - 1, j1, k)]) + (comp_vy ? sh.u : 0.0);
+  const int64_t layer = (int64_t)g1 * g2;
+  xg[B.xg_base + (0 * 3 + m) * layer + t] = left;
+  xg[B.xg_base + (1 * 3 + m) * layer + t] = right;
 }
 
 template <typename TS> __global__ void k_fill_y(Box B, TS* a) {
@@ -434,11 +463,12 @@ void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int 
 
 template <typename TS, typename A, typename TW>
 void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
-                   const FView<TS>& fl, TW* rho_p, TW* const vg[3], DiagDev* dg, hipStream_t st) {
+                   const FView<TS>& fl, const double* xg, TW* rho_p, TW* const vg[3], DiagDev* dg,
+                   hipStream_t st) {
   if (p.n == 0) return;
   DUST_GEOM_SWITCH(geom, ndim, unif,
                    hipLaunchKernelGGL((k_gather<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
-                                      0, st, p, boxes, nbox, fl, rho_p, vg[0], vg[1], vg[2], dg));
+                                      0, st, p, boxes, nbox, fl, xg, rho_p, vg[0], vg[1], vg[2], dg));
 }
 
 template <typename TS, typename A, typename TW>
@@ -463,11 +493,15 @@ void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, in
 
 template <typename TS>
 void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
-                 hipStream_t st) {
+                 double* xg, hipStream_t st) {
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   TS* arrs[4] = {fl.rho, fl.vel[0], fl.vel[1], fl.vel[2]};
   const double qOmega = f.q * f.Omega;
+  if (xg && B.xg_base >= 0)
+    for (int m = 0; m < nc; ++m)
+      hipLaunchKernelGGL((k_fill_xghost<TS>), dim3(blocks_for((int64_t)(n1 + 2) * (n2 + 2))), dim3(256),
+                         0, st, B, (const TS*)fl.vel[m], xg, m, (int)(m == 1), qOmega, tdev, toff);
   for (int a = 0; a <= nc; ++a) {
     TS* x = arrs[a];
     if (B.ax[0].bc_lo != BC_OPEN)
@@ -535,7 +569,8 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
 
 #define DUST_INST(TS, A, TW)                                                                      \
   template void launch_gather<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int,             \
-                                         const FView<TS>&, TW*, TW* const[3], DiagDev*,           \
+                                         const FView<TS>&, const double*, TW*, TW* const[3],       \
+                                         DiagDev*,                                                \
                                          hipStream_t);                                            \
   template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int, const Forces&, \
                                        const Species*, int, double, const TW* const[3],           \
@@ -558,6 +593,7 @@ DUST_INST(double, double, double)
 
 #define DUST_INST_GRID(TS)                                                                        \
   template void launch_fill<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
+                                double*,                                                          \
                                 hipStream_t);                                                     \
   template void launch_fold<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
                                 hipStream_t);                                                     \

@@ -32,8 +32,10 @@ void launch_drift(const PView<TS>& p, const Box* boxes, int nbox, int geom, int 
 // TW: type of the per-particle gas-velocity / impulse arrays (the caller's
 // precision for the stage calls, the arithmetic precision inside dust_step).
 template <typename TS, typename A, typename TW>
+// xg: the context's FP64 x-ghost gas layers, or null (ghosts from fl).
 void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
-                   const FView<TS>& fl, TW* rho_p, TW* const vg[3], DiagDev* dg, hipStream_t st);
+                   const FView<TS>& fl, const double* xg, TW* rho_p, TW* const vg[3], DiagDev* dg,
+                   hipStream_t st);
 template <typename TS, typename A, typename TW>
 void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                  const Forces& f, const Species* sp, int drag_mode, double dt,
@@ -42,9 +44,11 @@ template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                     const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st);
 
+// Ghost fill of the gas of one box at *tdev + toff; with xg (the context's
+// FP64 x-ghost buffer), also the FP64 x-ghost layer of a shear-periodic box.
 template <typename TS>
 void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
-                 hipStream_t st);
+                 double* xg, hipStream_t st);
 template <typename TS>
 void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
                  hipStream_t st);

@@ -142,6 +142,20 @@ __device__ __forceinline__ uint32_t tile_key(const Box& B, int64_t local, TileSh
   return (uint32_t)(B.cell_base + before + li);
 }
 
+// Gas velocity component m of stored cell (i, j, k), in FP64: from the FP64
+// x-ghost layer when the cell is an x ghost of a shear-periodic box and the
+// layer is given (xg), else from the field array.
+template <typename TS>
+__device__ __forceinline__ double gas_comp(const Box& B, const FView<TS>& fl, const double* xg, int m,
+                                           int i, int j, int k) {
+  if (xg && B.xg_base >= 0 && (i < 0 || i >= B.ax[0].n)) {
+    const int64_t g1 = B.ax[1].n + 2, layer = g1 * (B.ax[2].n + 2);
+    const int side = i < 0 ? 0 : 1;
+    return xg[B.xg_base + (int64_t)(side * 3 + m) * layer + (int64_t)(k + 1) * g1 + (j + 1)];
+  }
+  return double(fl.vel[m][stored_index(B, i, j, k)]);
+}
+
 // Shear offset (y-cells) split into integer and fractional parts.
 struct Shift {
   int si;      // floor(s)

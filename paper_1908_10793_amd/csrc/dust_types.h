@@ -33,6 +33,8 @@ struct Box {
   int32_t k_off;                // 1 in 3-D, 0 in 2-D
   int64_t cell_base, ncell;     // first global active cell id, active cells
   int64_t store_base, nstore;   // first stored cell in the field arrays, stored cells
+  int64_t xg_base;              // shear-periodic boxes: first word of the box's FP64 x-ghost
+                                // gas layer (2 sides x 3 components x (n1+2)(n2+2)); else -1
   Axis ax[3];
 };
 

@@ -78,7 +78,7 @@ EXPORTS = ["dust_ctx_create", "dust_ctx_destroy", "dust_ctx_set_arith", "dust_ct
            "dust_ctx_grid_size", "dust_ctx_status", "dust_last_error", "dust_bin",
            "dust_fill_ghosts", "dust_gather", "dust_push_expmid", "dust_deposit",
            "dust_fold_ghosts", "dust_apply_feedback", "dust_step", "dust_ctx_set_profile",
-           "dust_ctx_profile"]
+           "dust_ctx_profile", "dust_ctx_autotune"]
 
 _lib = None
 
@@ -117,6 +117,11 @@ def load_library(path: str = LIB_PATH):
     L.dust_apply_feedback.argtypes = [_vp, ctypes.POINTER(dust_fields_t), _vp]
     L.dust_step.argtypes = [_vp, ctypes.POINTER(dust_particles_t), ctypes.POINTER(dust_fields_t),
                             ctypes.c_double, ctypes.POINTER(dust_forces_t), i32, i32, _vp]
+    L.dust_ctx_autotune.argtypes = [_vp, ctypes.POINTER(dust_particles_t),
+                                    ctypes.POINTER(dust_fields_t), ctypes.c_double,
+                                    ctypes.POINTER(dust_forces_t), i32, i32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                    _vp]
     for name in EXPORTS:
         if name != "dust_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -349,6 +354,19 @@ class Context:
         _check(load_library().dust_step(self.handle, ctypes.byref(pt), ctypes.byref(f), float(dt),
                                         ctypes.byref(forces), int(nsteps), int(flags),
                                         _stream(stream)))
+
+    def autotune(self, P, F, dt, forces: dust_forces_t, flags=0, steps=12, stream=None):
+        """dust_ctx_autotune: returns {"tile": (tx, ty, tz), "rebin_every": k,
+        "ms_per_step": t}; the choice stays in the context."""
+        pt, f = self.particles_t(P), self.fields_t(F)
+        res = (ctypes.c_int32 * 4)()
+        ms = ctypes.c_float(0.0)
+        _check(load_library().dust_ctx_autotune(self.handle, ctypes.byref(pt), ctypes.byref(f),
+                                                float(dt), ctypes.byref(forces), int(flags),
+                                                int(steps), res, ctypes.byref(ms),
+                                                _stream(stream)))
+        return {"tile": (res[0], res[1], res[2]), "rebin_every": res[3],
+                "ms_per_step": float(ms.value)}
 
 
 # ---------------------------------------------------------------- workloads

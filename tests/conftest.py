@@ -10,4 +10,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: longer CPU-only checks")
+    config.addinivalue_line("markers", "slow: longer checks (full-size GPU parity, long CPU runs)")

@@ -293,3 +293,39 @@ def test_stale_bins_match_rebinning_every_step(rebin_every):
         x, y = F1["dep"][c], F2["dep"][c]
         assert (x - y).abs().max().item() <= 1e-5 * max(x.abs().max().item(), 1e-30), c
     assert ctx.status()["n_fallback"] >= 0
+
+
+# ------------------------------------------------------------------ autotuner
+
+def test_autotune_leaves_inputs_and_tunes_the_context():
+    dust = _dust()
+    w = synth.shearing_box(n=(16, 16, 8), dt=0.02)
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    snap_p = {k: (v.clone() if not isinstance(v, list) else [x.clone() for x in v]) for k, v in P.items()}
+    snap_f = {k: (v.clone() if not isinstance(v, list) else [x.clone() for x in v]) for k, v in F.items()}
+    d0 = ctx.status()
+    res = ctx.autotune(P, F, w.dt, dust.forces_for(w), dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG, steps=4)
+    print("[autotune]", res, flush=True)
+    assert res["tile"] in [(8, 8, 4), (16, 4, 4), (4, 16, 4), (4, 4, 16), (8, 4, 8), (4, 8, 8)]
+    assert 1 <= res["rebin_every"] <= 4 and res["ms_per_step"] > 0
+    torch.cuda.synchronize()
+    for k, v in P.items():
+        vs = v if isinstance(v, list) else [v]
+        ss = snap_p[k] if isinstance(v, list) else [snap_p[k]]
+        assert all(torch.equal(a, b) for a, b in zip(vs, ss)), k
+    for k, v in F.items():
+        vs = v if isinstance(v, list) else [v]
+        ss = snap_f[k] if isinstance(v, list) else [snap_f[k]]
+        assert all(torch.equal(a, b) for a, b in zip(vs, ss)), k
+    d1 = ctx.status()
+    assert d1["p_part"] == d0["p_part"] and d1["steps"] == d0["steps"]
+    # the tuned context steps correctly (interval from the context: REBIN_EVERY(0))
+    st_in = download(ctx, P, F, w)
+    ctx.step(P, F, w.dt, dust.forces_for(w), 1, dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK)
+    st_out = download(ctx, P, F, w)
+    run = OracleRun(workload_from_state(w, st_in, w.t0))
+    run.step(1)
+    compare_step(w, st_in, st_out, run, "f32", label="tuned")
+    with pytest.raises(dust.DustError):
+        ctx.autotune(P, F, w.dt, dust.forces_for(w), dust.STEP_GRAPH, steps=2)
