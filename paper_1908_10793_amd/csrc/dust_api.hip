@@ -328,7 +328,7 @@ dust_status_t ensure_bin(Ctx* c, int64_t n) {
   if (c->bin_mem) HIP_TRY(hipFree(c->bin_mem));
   c->bin_mem = nullptr;
   int64_t nn = std::max<int64_t>(n, 1);
-  int64_t nblocks = (nn + 2047) / 2048;
+  int64_t nblocks = bin_blocks(nn);
   size_t hist = (size_t)256 * nblocks;
   size_t scan = bin_scan_tmp_words((int64_t)hist);
   auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -487,7 +487,7 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
     dust_status_t s = ensure_shadow(c, p);
     if (s) return s;
     launch_halfstep_keys<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, dt, c->tdev,
-                                c->n_active, c->tile, c->bin.key[0], c->bin.val[0], st);
+                                c->n_active, c->tile, c->bin.key[0], st);
     c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_TILE, c->tile,
                             c->bin, nullptr, c->bin_start, true, st);
     src = shadow_view<TS>(c, p);
@@ -689,16 +689,22 @@ dust_status_t dust_ctx_set_tile(void* ctx, int32_t tx, int32_t ty, int32_t tz, i
   if (check_ctx(ctx)) return DUST_EINVAL;
   Ctx* c = (Ctx*)ctx;
   int32_t t[3] = {tx, ty, tz};
+  TileShape want = c->tile;
   for (int d = 0; d < 3; ++d) {
     if (t[d] < 0 || t[d] > 64) return fail(DUST_EINVAL, "tile extent %d out of 0..64", t[d]);
-    if (t[d] > 0) c->tile.t[d] = t[d];
+    if (t[d] > 0) want.t[d] = t[d];
   }
   if (slack < 0 || slack > 4) return fail(DUST_EINVAL, "slack %d out of 0..4", slack);
-  c->slack = slack;
   drop_graph(c);
-  dust_status_t s = fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
-  if (s) return fail(s, "tile %dx%dx%d is not one of the compiled fused tile shapes", c->tile.t[0],
-                     c->tile.t[1], c->tile.t[2]);
+  dust_status_t s = fused_plan_init(c->plan, c->boxes.data(), c->nbox, want, slack);
+  if (s) {
+    // keep the previous shape (and a valid plan)
+    (void)fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
+    return fail(s, "tile %dx%dx%d is not one of the compiled fused tile shapes", want.t[0], want.t[1],
+                want.t[2]);
+  }
+  c->tile = want;
+  c->slack = slack;
   return DUST_OK;
 }
 

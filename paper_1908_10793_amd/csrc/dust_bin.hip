@@ -11,12 +11,11 @@
 namespace dust {
 
 static constexpr int BIN_THREADS = 256;
-static constexpr int BIN_ITEMS = 8;
+static constexpr int BIN_ITEMS = 16;
 static constexpr int BIN_TILE = BIN_THREADS * BIN_ITEMS;  // elements per block
 
 __global__ void k_make_keys(const int32_t* cell, int64_t n, const Box* boxes, int nbox,
-                            uint32_t nbins, int key_mode, TileShape ts, uint32_t* key,
-                            uint32_t* val) {
+                            uint32_t nbins, int key_mode, TileShape ts, uint32_t* key) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t c = cell[i];
@@ -30,7 +29,6 @@ __global__ void k_make_keys(const int32_t* cell, int64_t n, const Box* boxes, in
     }
   }
   key[i] = k;
-  val[i] = (uint32_t)i;
 }
 
 __global__ void __launch_bounds__(BIN_THREADS) k_digit_hist(const uint32_t* key, int64_t n,
@@ -48,38 +46,72 @@ __global__ void __launch_bounds__(BIN_THREADS) k_digit_hist(const uint32_t* key,
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(BIN_THREADS) k_digit_scatter(const uint32_t* key_in,
-                                                               const uint32_t* val_in, int64_t n,
-                                                               int shift, const uint32_t* offs,
+// One radix pass of one block of BIN_TILE elements: the block's elements
+// are first placed in LDS in stable digit order (wave ballots rank lanes with
+// equal digits, LDS counters carry the ranks across waves and chunks), then
+// written out run by run, so that consecutive threads write consecutive
+// addresses of a digit's output range.  val_in = nullptr: values are the
+// element indices (first pass).
+__global__ void __launch_bounds__(BIN_THREADS) k_digit_scatter(const uint32_t* __restrict__ key_in,
+                                                               const uint32_t* __restrict__ val_in,
+                                                               int64_t n, int shift,
+                                                               const uint32_t* __restrict__ offs,
                                                                int nblocks, uint32_t* key_out,
                                                                uint32_t* val_out) {
-  __shared__ uint32_t running[256];
+  __shared__ uint32_t s_key[BIN_TILE], s_val[BIN_TILE];
+  __shared__ uint32_t lstart[256], running[256], gstart[256];
   __shared__ uint32_t cnt[BIN_THREADS / 64][256];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  running[t] = offs[(int64_t)t * nblocks + blockIdx.x];
-  for (int w = 0; w < BIN_THREADS / 64; ++w) cnt[w][t] = 0;
-  __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * BIN_TILE;
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * BIN_TILE;
+  const int nloc = (int)(n - base < BIN_TILE ? n - base : BIN_TILE);
+  uint32_t k[BIN_ITEMS], v[BIN_ITEMS];
+#pragma unroll
   for (int c = 0; c < BIN_ITEMS; ++c) {
-    int64_t e = base + c * BIN_THREADS + t;
-    bool valid = e < n;
-    uint32_t k = valid ? key_in[e] : 0u;
-    uint32_t v = valid ? val_in[e] : 0u;
-    uint32_t d = (k >> shift) & 255u;
+    const int l = c * BIN_THREADS + t;
+    const bool valid = l < nloc;
+    k[c] = valid ? key_in[base + l] : 0u;
+    v[c] = valid ? (val_in ? val_in[base + l] : (uint32_t)(base + l)) : 0u;
+  }
+  // block histogram of the digit, then its exclusive scan
+  running[t] = 0;
+  for (int w = 0; w < BIN_THREADS / 64; ++w) cnt[w][t] = 0;
+  gstart[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < BIN_ITEMS; ++c)
+    if (c * BIN_THREADS + t < nloc) atomicAdd(&running[(k[c] >> shift) & 255u], 1u);
+  __syncthreads();
+  const uint32_t mine = running[t];
+  lstart[t] = mine;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t x = t >= off ? lstart[t - off] : 0u;
+    __syncthreads();
+    lstart[t] += x;
+    __syncthreads();
+  }
+  lstart[t] -= mine;
+  running[t] = lstart[t];
+  __syncthreads();
+  // stable placement in LDS, chunk by chunk
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int c = 0; c < BIN_ITEMS; ++c) {
+    const bool valid = c * BIN_THREADS + t < nloc;
+    const uint32_t d = (k[c] >> shift) & 255u;
     unsigned long long peers = __ballot(valid);
-    for (int b = 0; b < 8; ++b) {
-      unsigned long long m = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? m : ~m;
+    for (int bt = 0; bt < 8; ++bt) {
+      const unsigned long long m = __ballot((d >> bt) & 1u);
+      peers &= ((d >> bt) & 1u) ? m : ~m;
     }
-    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
     if (valid && rank == 0) cnt[wv][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
       uint32_t pos = running[d] + rank;
       for (int w = 0; w < wv; ++w) pos += cnt[w][d];
-      key_out[pos] = k;
-      val_out[pos] = v;
+      s_key[pos] = k[c];
+      s_val[pos] = v[c];
     }
     __syncthreads();
     uint32_t add = 0;
@@ -89,6 +121,14 @@ __global__ void __launch_bounds__(BIN_THREADS) k_digit_scatter(const uint32_t* k
     }
     running[t] += add;
     __syncthreads();
+  }
+  // write out run by run
+  for (int p = t; p < nloc; p += BIN_THREADS) {
+    const uint32_t kk = s_key[p];
+    const uint32_t d = (kk >> shift) & 255u;
+    const uint32_t o = gstart[d] + (uint32_t)p - lstart[d];
+    key_out[o] = kk;
+    val_out[o] = s_val[p];
   }
 }
 
@@ -128,6 +168,8 @@ __global__ void k_scan_add(uint32_t* a, int64_t n, const uint32_t* block_offs) {
 }
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t bin_blocks(int64_t n) { return ceil_div(n, BIN_TILE); }
 
 size_t bin_scan_tmp_words(int64_t m) {
   size_t words = 0;
@@ -181,7 +223,7 @@ int launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, int nbox, i
   }
   if (!keys_ready)
     hipLaunchKernelGGL(k_make_keys, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, cell, n,
-                       boxes_dev, nbox, (uint32_t)nbins, key_mode, tile, w.key[0], w.val[0]);
+                       boxes_dev, nbox, (uint32_t)nbins, key_mode, tile, w.key[0]);
   int bits = 1;
   while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)nbins) ++bits;
   int npass = (bits + 7) / 8;
@@ -193,7 +235,8 @@ int launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, int nbox, i
                        w.hist, nblocks);
     scan_exclusive(w.hist, (int64_t)256 * nblocks, w.scan_tmp, st);
     hipLaunchKernelGGL(k_digit_scatter, dim3(nblocks), dim3(BIN_THREADS), 0, st, w.key[cur],
-                       w.val[cur], n, shift, w.hist, nblocks, w.key[1 - cur], w.val[1 - cur]);
+                       p == 0 ? (const uint32_t*)nullptr : (const uint32_t*)w.val[cur], n, shift,
+                       w.hist, nblocks, w.key[1 - cur], w.val[1 - cur]);
     cur = 1 - cur;
   }
   if (perm_out)

@@ -275,8 +275,9 @@ __device__ __forceinline__ int move_axis(const Axis& ax, int i, A& delta, A dxi)
 template <typename A>
 __device__ __forceinline__ bool wrap_plain(const Axis& ax, int& i) {
   if (i >= 0 && i < ax.n) return true;
-  int bc = i < 0 ? ax.bc_lo : ax.bc_hi;
-  if (bc == BC_OPEN) return false;
+  // both boundary kinds are read (uniform loads) before the per-lane choice
+  const bool lo_open = ax.bc_lo == BC_OPEN, hi_open = ax.bc_hi == BC_OPEN;
+  if (i < 0 ? lo_open : hi_open) return false;
   i %= ax.n;
   if (i < 0) i += ax.n;
   return true;

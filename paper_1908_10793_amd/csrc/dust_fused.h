@@ -45,11 +45,11 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                   hipStream_t st);
 
 // Keys (tile-major) of the cells the particles reach in the first half drift
-// of a step of length dt starting at *tdev; val = identity.
+// of a step of length dt starting at *tdev.
 template <typename TS, typename A>
 void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int geom, int ndim,
                           int unif, const Forces& f, double dt, const double* tdev, int64_t nbins,
-                          TileShape ts, uint32_t* key, uint32_t* val, hipStream_t st);
+                          TileShape ts, uint32_t* key, hipStream_t st);
 
 // After a sort (perm, bin_start): sh = the binned particles of src in the
 // fused kernel's level-major layout within each wave's range of slots; the

@@ -683,15 +683,16 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
 // (the same drift the fused kernel does, so a particle is normally processed
 // by the thread of the cell it kicks in).  A particle that leaves through an
 // open face keeps the key of its current cell (the fused kernel removes it);
-// a particle without a valid cell gets key nbins.
+// a particle without a valid cell gets key nbins.  (The sort takes the
+// particle indices as values.)
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256)
-    k_halfstep_keys(PView<TS> p, const Box* boxes, int nbox, Forces f, A dt, const double* tdev,
-                    uint32_t nbins, TileShape ts, uint32_t* key, uint32_t* val) {
+    k_halfstep_keys(PView<TS> p, const Box* __restrict__ boxes, int nbox, Forces f, A dt,
+                    const double* __restrict__ tdev, uint32_t nbins, TileShape ts,
+                    uint32_t* __restrict__ key) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  val[i] = (uint32_t)i;
   int64_t c = p.cell[i];
   uint32_t k = nbins;
   if (c >= 0 && c < (int64_t)nbins) {
@@ -706,9 +707,9 @@ __global__ void __launch_bounds__(256)
       mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
     }
     const A h = A(0.5) * dt;
-    int64_t local = c - B.cell_base;
-    if (drift<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)) local = ravel(B, idx);
-    k = tile_key(B, local, ts);
+    int here[3] = {idx[0], idx[1], idx[2]};
+    k = drift<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)
+            ? tile_key_idx(B, idx, ts) : tile_key_idx(B, here, ts);
   }
   key[i] = k;
 }
@@ -716,12 +717,12 @@ __global__ void __launch_bounds__(256)
 template <typename TS, typename A>
 void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int geom, int ndim,
                           int unif, const Forces& f, double dt, const double* tdev, int64_t nbins,
-                          TileShape ts, uint32_t* key, uint32_t* val, hipStream_t st) {
+                          TileShape ts, uint32_t* key, hipStream_t st) {
   if (p.n == 0) return;
   unsigned g = (unsigned)((p.n + 255) / 256);
 #define DUST_K(G, D, UU)                                                                          \
   hipLaunchKernelGGL((k_halfstep_keys<TS, A, G, D, UU>), dim3(g), dim3(256), 0, st, p, boxes_d,     \
-                     nbox, f, A(dt), tdev, (uint32_t)nbins, ts, key, val)
+                     nbox, f, A(dt), tdev, (uint32_t)nbins, ts, key)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_K(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_K(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_K(GEOM_CART, 3, true);
@@ -814,7 +815,7 @@ void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const 
                                     const int64_t*, const double*, DiagDev*, bool, hipStream_t);   \
   template void launch_halfstep_keys<TS, A>(const PView<TS>&, const Box*, int, int, int, int,       \
                                             const Forces&, double, const double*, int64_t,         \
-                                            TileShape, uint32_t*, uint32_t*, hipStream_t);
+                                            TileShape, uint32_t*, hipStream_t);
 
 DUST_FUSED_INST(float, double)
 DUST_FUSED_INST(float, float)

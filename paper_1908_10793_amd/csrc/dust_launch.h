@@ -71,10 +71,11 @@ struct BinWork {
   size_t cap_n;
 };
 size_t bin_scan_tmp_words(int64_t n);
+int64_t bin_blocks(int64_t n);   // radix-pass blocks for n keys (digit histogram columns)
 struct TileShape { int32_t t[3]; };
 // Stable sort of particles by key; writes perm (sorted slot -> input index)
 // and bin_start (nbins+1) if given.  key_mode: DUST_BIN_CELL or DUST_BIN_TILE;
-// keys_ready: w.key[0] / w.val[0] already hold the keys and identity values.
+// keys_ready: w.key[0] already holds the keys (values are the indices).
 // Returns the buffer index c with the sorted keys in w.key[c] and the
 // permutation in w.val[c].
 int launch_bin(const int32_t* cell, int64_t n, const Box* boxes_dev, int nbox, int64_t nbins,

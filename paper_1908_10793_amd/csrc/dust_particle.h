@@ -123,14 +123,15 @@ __device__ __forceinline__ void stencil_weights(const Box& B, const int idx[3], 
 // Tile-major key of active cell `local` of box B: tiles in x-fastest order,
 // cells x-fastest inside a tile (tiles clipped at the box edges), plus the
 // box's first cell id.
-__device__ __forceinline__ uint32_t tile_key(const Box& B, int64_t local, TileShape ts) {
-  int idx[3];
-  unravel(B, local, idx);
+// Tile extents are powers of two (the compiled shapes), so the tile of a
+// cell is a shift.
+__device__ __forceinline__ uint32_t tile_key_idx(const Box& B, const int idx[3], TileShape ts) {
   int n[3] = {B.ax[0].n, B.ax[1].n, B.ndim > 2 ? B.ax[2].n : 1};
   int t[3] = {ts.t[0], ts.t[1], B.ndim > 2 ? ts.t[2] : 1};
   int tid[3], ext[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    tid[d] = idx[d] / t[d];
+    tid[d] = idx[d] >> (__ffs(t[d]) - 1);
     int rem = n[d] - tid[d] * t[d];
     ext[d] = rem < t[d] ? rem : t[d];
   }
@@ -140,6 +141,12 @@ __device__ __forceinline__ uint32_t tile_key(const Box& B, int64_t local, TileSh
   int64_t li = (idx[0] - tid[0] * t[0]) +
                (int64_t)ext[0] * ((idx[1] - tid[1] * t[1]) + (int64_t)ext[1] * (idx[2] - tid[2] * t[2]));
   return (uint32_t)(B.cell_base + before + li);
+}
+
+__device__ __forceinline__ uint32_t tile_key(const Box& B, int64_t local, TileShape ts) {
+  int idx[3];
+  unravel(B, local, idx);
+  return tile_key_idx(B, idx, ts);
 }
 
 // Gas velocity component m of stored cell (i, j, k), in FP64: from the FP64
