@@ -456,7 +456,7 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   DiagDev* dflags = c->diag;  // sticky flags always recorded
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
-  for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
+  launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
   launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv,
                           (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, (A*)nullptr, vg, dflags, st);
@@ -496,7 +496,7 @@ dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const
   }
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
-  for (int k = 0; k <= nc; ++k) launch_fill_value<TS>(fv.dep[k], c->n_stored, TS(0), st);
+  launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
   bool prof = c->prof_used < c->prof_max;
   if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
   launch_fused<TS, A>(c->plan, src, pv, rebin, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, F,

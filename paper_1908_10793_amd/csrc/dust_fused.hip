@@ -780,18 +780,20 @@ template <typename TS>
 __global__ void __launch_bounds__(256)
     k_gather_tail(PView<TS> src, PView<TS> sh, const uint32_t* __restrict__ perm,
                   const int64_t* __restrict__ bin_start, int64_t nbins) {
-  const int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= src.n) return;
-  copy_particle(src, (int64_t)perm[s], sh, s);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < src.n;
+       s += stride)
+    copy_particle(src, (int64_t)perm[s], sh, s);
 }
 
 // dst[s] = sh[s] for the tail slots (after the gathers, which read src = dst).
 template <typename TS>
 __global__ void __launch_bounds__(256)
     k_copy_tail(PView<TS> sh, PView<TS> dst, const int64_t* __restrict__ bin_start, int64_t nbins) {
-  const int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= sh.n) return;
-  copy_particle(sh, s, dst, s);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < sh.n;
+       s += stride)
+    copy_particle(sh, s, dst, s);
 }
 
 template <typename TS>
@@ -803,7 +805,8 @@ void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const 
   if (plan.ntiles > 0)
     hipLaunchKernelGGL(k_gather_tiled<TS>, dim3(plan.ntiles), dim3(256), 0, st, plan.tiles_d, ts, src,
                        sh, perm, bin_start);
-  unsigned g = (unsigned)((src.n + 255) / 256);
+  // the tail (particles without a cell) is usually empty: grid-stride loops
+  unsigned g = (unsigned)std::min<int64_t>((src.n + 255) / 256, 512);
   hipLaunchKernelGGL(k_gather_tail<TS>, dim3(g), dim3(256), 0, st, src, sh, perm, bin_start, nbins);
   hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, sh, dst, bin_start, nbins);
 }

@@ -196,11 +196,19 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
   } while (0)
 
 // ---------------------------------------------------------------- grid kernels
+// Each ghost kernel treats several arrays of one box in one launch: the
+// array is blockIdx.y.
+
+template <typename TS> struct Arr4 {
+  TS* a[4];
+};
 
 // x ghosts of one box: shear-periodic (interpolated in y) or periodic.
 template <typename TS>
-__global__ void k_fill_x(Box B, TS* a, int comp_vy, double qOmega, const double* tdev, double toff,
-                         int shear) {
+__global__ void k_fill_x(Box B, Arr4<TS> arrs, int vy_slot, double qOmega, const double* tdev,
+                         double toff, int shear) {
+  TS* a = arrs.a[blockIdx.y];
+  const int comp_vy = (int)blockIdx.y == vy_slot;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n1 * n2) return;
@@ -233,8 +241,10 @@ __global__ void k_fill_x(Box B, TS* a, int comp_vy, double qOmega, const double*
 // boosted ghost values keep their FP64 rounding, so that a particle next to
 // the shear boundary sees the gas at the accuracy of the interior values.
 template <typename TS>
-__global__ void k_fill_xghost(Box B, const TS* a, double* xg, int m, int comp_vy, double qOmega,
-                              const double* tdev, double toff) {
+__global__ void k_fill_xghost(Box B, Arr4<TS> vel, double* xg, double qOmega, const double* tdev,
+                              double toff) {
+  const int m = blockIdx.y, comp_vy = m == 1;
+  const TS* a = vel.a[m];
   const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
   const int g1 = n1 + 2, g2 = n2 + 2;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -257,7 +267,8 @@ __global__ void k_fill_xghost(Box B, const TS* a, double* xg, int m, int comp_vy
   xg[B.xg_base + (1 * 3 + m) * layer + t] = right;
 }
 
-template <typename TS> __global__ void k_fill_y(Box B, TS* a) {
+template <typename TS> __global__ void k_fill_y(Box B, Arr4<TS> arrs) {
+  TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)(n0 + 2) * n2) return;
@@ -266,7 +277,8 @@ template <typename TS> __global__ void k_fill_y(Box B, TS* a) {
   a[stored_index(B, i, n1, k)] = a[stored_index(B, i, 0, k)];
 }
 
-template <typename TS> __global__ void k_fill_z(Box B, TS* a) {
+template <typename TS> __global__ void k_fill_z(Box B, Arr4<TS> arrs) {
+  TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)(n0 + 2) * (n1 + 2)) return;
@@ -275,7 +287,8 @@ template <typename TS> __global__ void k_fill_z(Box B, TS* a) {
   a[stored_index(B, i, j, n2)] = a[stored_index(B, i, j, 0)];
 }
 
-template <typename TS> __global__ void k_fold_z(Box B, TS* a) {
+template <typename TS> __global__ void k_fold_z(Box B, Arr4<TS> arrs) {
+  TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)(n0 + 2) * (n1 + 2)) return;
@@ -287,7 +300,8 @@ template <typename TS> __global__ void k_fold_z(Box B, TS* a) {
   a[gh] = TS(0);
 }
 
-template <typename TS> __global__ void k_fold_y(Box B, TS* a) {
+template <typename TS> __global__ void k_fold_y(Box B, Arr4<TS> arrs) {
+  TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)(n0 + 2) * n2) return;
@@ -302,8 +316,10 @@ template <typename TS> __global__ void k_fold_y(Box B, TS* a) {
 // x fold, written as a gather over the ghost rows that feed each partner
 // cell (no atomics).  The energy channel (e != NULL) gains +/- u D_y.
 template <typename TS>
-__global__ void k_fold_x(Box B, TS* a, const TS* dy, int is_energy, double qOmega,
+__global__ void k_fold_x(Box B, Arr4<TS> arrs, const TS* dy, int energy_slot, double qOmega,
                          const double* tdev, double toff, int shear) {
+  TS* a = arrs.a[blockIdx.y];
+  const int is_energy = (int)blockIdx.y == energy_slot;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n1 * n2) return;
@@ -340,7 +356,8 @@ __global__ void k_fold_x(Box B, TS* a, const TS* dy, int is_energy, double qOmeg
   a[stored_index(B, n0 - 1, jt, k)] += TS(addn);
 }
 
-template <typename TS> __global__ void k_clear_x_ghosts(Box B, TS* a) {
+template <typename TS> __global__ void k_clear_x_ghosts(Box B, Arr4<TS> arrs) {
+  TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n1 * n2) return;
@@ -362,6 +379,11 @@ void launch_set_time(double* tdev, double v, hipStream_t st) {
 }
 void launch_advance_time(double* tdev, double dt, hipStream_t st) {
   hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, 0.0, dt);
+}
+
+template <typename TS> __global__ void k_fill_values(Arr4<TS> arrs, int64_t n, TS v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) arrs.a[blockIdx.y][i] = v;
 }
 
 template <typename TS> __global__ void k_fill_value(TS* a, int64_t n, TS v) {
@@ -496,25 +518,23 @@ void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff,
                  double* xg, hipStream_t st) {
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  TS* arrs[4] = {fl.rho, fl.vel[0], fl.vel[1], fl.vel[2]};
+  const Arr4<TS> arrs{{fl.rho, fl.vel[0], fl.vel[1], fl.vel[2]}};
+  const Arr4<TS> vel{{fl.vel[0], fl.vel[1], fl.vel[2], nullptr}};
+  const unsigned na = (unsigned)(nc + 1);
   const double qOmega = f.q * f.Omega;
   if (xg && B.xg_base >= 0)
-    for (int m = 0; m < nc; ++m)
-      hipLaunchKernelGGL((k_fill_xghost<TS>), dim3(blocks_for((int64_t)(n1 + 2) * (n2 + 2))), dim3(256),
-                         0, st, B, (const TS*)fl.vel[m], xg, m, (int)(m == 1), qOmega, tdev, toff);
-  for (int a = 0; a <= nc; ++a) {
-    TS* x = arrs[a];
-    if (B.ax[0].bc_lo != BC_OPEN)
-      hipLaunchKernelGGL((k_fill_x<TS>), dim3(blocks_for((int64_t)n1 * n2)), dim3(256), 0, st, B, x,
-                         (int)(B.geom == GEOM_CART && a == 2), qOmega, tdev, toff,
-                         (int)(B.ax[0].bc_lo == BC_SHEAR));
-    if (B.ax[1].bc_lo == BC_PERIODIC)
-      hipLaunchKernelGGL((k_fill_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2)), dim3(256), 0, st,
-                         B, x);
-    if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
-      hipLaunchKernelGGL((k_fill_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2))), dim3(256),
-                         0, st, B, x);
-  }
+    hipLaunchKernelGGL((k_fill_xghost<TS>), dim3(blocks_for((int64_t)(n1 + 2) * (n2 + 2)), (unsigned)nc),
+                       dim3(256), 0, st, B, vel, xg, qOmega, tdev, toff);
+  if (B.ax[0].bc_lo != BC_OPEN)
+    hipLaunchKernelGGL((k_fill_x<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st, B, arrs,
+                       B.geom == GEOM_CART ? 2 : -1, qOmega, tdev, toff,
+                       (int)(B.ax[0].bc_lo == BC_SHEAR));
+  if (B.ax[1].bc_lo == BC_PERIODIC)
+    hipLaunchKernelGGL((k_fill_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2), na), dim3(256), 0, st, B,
+                       arrs);
+  if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
+    hipLaunchKernelGGL((k_fill_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2)), na), dim3(256), 0,
+                       st, B, arrs);
 }
 
 template <typename TS>
@@ -523,25 +543,23 @@ void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff,
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   const double qOmega = f.q * f.Omega;
-  for (int c = 0; c <= nc; ++c) {
-    TS* x = fl.dep[c];
-    if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
-      hipLaunchKernelGGL((k_fold_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2))), dim3(256),
-                         0, st, B, x);
-    if (B.ax[1].bc_lo == BC_PERIODIC)
-      hipLaunchKernelGGL((k_fold_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2)), dim3(256), 0, st,
-                         B, x);
-  }
+  const Arr4<TS> deps{{fl.dep[0], fl.dep[1], fl.dep[2], fl.dep[3]}};
+  const unsigned na = (unsigned)(nc + 1);
+  if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
+    hipLaunchKernelGGL((k_fold_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2)), na), dim3(256), 0,
+                       st, B, deps);
+  if (B.ax[1].bc_lo == BC_PERIODIC)
+    hipLaunchKernelGGL((k_fold_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2), na), dim3(256), 0, st, B,
+                       deps);
   if (B.ax[0].bc_lo != BC_OPEN) {
     int shear = B.ax[0].bc_lo == BC_SHEAR;
-    // energy first: it reads the D_y ghosts before they are cleared
-    for (int c = nc; c >= 0; --c)
-      hipLaunchKernelGGL((k_fold_x<TS>), dim3(blocks_for((int64_t)n1 * n2)), dim3(256), 0, st, B,
-                         fl.dep[c], (const TS*)fl.dep[B.ndim > 1 ? 1 : 0], (int)(c == nc && shear),
-                         qOmega, tdev, toff, shear);
-    for (int c = 0; c <= nc; ++c)
-      hipLaunchKernelGGL((k_clear_x_ghosts<TS>), dim3(blocks_for((int64_t)n1 * n2)), dim3(256), 0, st,
-                         B, fl.dep[c]);
+    // the energy channel reads the D_y ghosts, which no thread of this
+    // launch writes (they are cleared by the next one)
+    hipLaunchKernelGGL((k_fold_x<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st, B, deps,
+                       (const TS*)fl.dep[B.ndim > 1 ? 1 : 0], shear ? nc : -1, qOmega, tdev, toff,
+                       shear);
+    hipLaunchKernelGGL((k_clear_x_ghosts<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st,
+                       B, deps);
   }
 }
 
@@ -560,6 +578,13 @@ void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, double* pa
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   hipLaunchKernelGGL(k_reduce_grid_partials, dim3(1), dim3(256), 0, st, (const double*)part, (int)nb,
                      nc, dg);
+}
+
+template <typename TS> void launch_clear_deposits(const FView<TS>& fl, int nch, int64_t n, hipStream_t st) {
+  if (n <= 0 || nch <= 0) return;
+  const Arr4<TS> deps{{fl.dep[0], fl.dep[1], fl.dep[2], fl.dep[3]}};
+  hipLaunchKernelGGL((k_fill_values<TS>), dim3(blocks_for(n), (unsigned)nch), dim3(256), 0, st, deps, n,
+                     TS(0));
 }
 
 template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st) {
@@ -599,7 +624,8 @@ DUST_INST(double, double, double)
                                 hipStream_t);                                                     \
   template void launch_feedback<TS>(const Box&, const FView<TS>&, hipStream_t);                   \
   template void launch_grid_sums<TS>(const Box&, const FView<TS>&, DiagDev*, double*, hipStream_t); \
-  template void launch_fill_value<TS>(TS*, int64_t, TS, hipStream_t);
+  template void launch_fill_value<TS>(TS*, int64_t, TS, hipStream_t);                              \
+  template void launch_clear_deposits<TS>(const FView<TS>&, int, int64_t, hipStream_t);
 
 DUST_INST_GRID(float)
 DUST_INST_GRID(double)

@@ -60,6 +60,8 @@ static constexpr int GRID_SUM_BLOCKS = 512;
 template <typename TS>
 void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, double* part, hipStream_t st);
 template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st);
+// Zero the first nch deposit channels over n stored cells (one launch).
+template <typename TS> void launch_clear_deposits(const FView<TS>& fl, int nch, int64_t n, hipStream_t st);
 
 // Binning (dust_bin.hip).  Workspace sizes in bytes for n particles.
 struct BinWork {
