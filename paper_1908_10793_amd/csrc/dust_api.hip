@@ -962,6 +962,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   if (flags & DUST_STEP_FUSED) {
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
+    if (fused_plan_reserve(c->plan, p->n) != DUST_OK) return fail(DUST_ENOMEM, "deferred-particle list");
     if (fused_lds_bytes(c->plan, ctx_nc(c), c->prec == DUST_F64 ? 8 : 4) > 160 * 1024)
       return fail(DUST_EUNSUPPORTED, "fused tile window needs more than 160 KiB of LDS");
   }

@@ -26,8 +26,14 @@ struct FusedPlan {
   int rmax[3] = {0, 0, 0};  // largest region extents
   size_t lds_cells = 0;
   TileDesc* tiles_d = nullptr;
-  double* part_d = nullptr;   // per-tile diagnostic partials
+  double* part_d = nullptr;   // per-tile diagnostic partials (+ the deferred kernel's)
+  uint32_t* defer_count = nullptr;   // deferred particles of the current launch
+  uint32_t* defer_list = nullptr;    // their slots (capacity defer_cap)
+  size_t defer_cap = 0;
 };
+
+// Capacity of the deferred-particle list for n particles.
+dust_status_t fused_plan_reserve(FusedPlan& plan, int64_t n);
 
 dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileShape tile, int slack);
 void fused_plan_free(FusedPlan& plan);

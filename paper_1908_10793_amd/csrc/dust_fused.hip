@@ -29,6 +29,7 @@ namespace dust {
 
 static constexpr int FUSED_THREADS = 256;
 static constexpr int PART_WORDS = 8;   // per-workgroup diagnostic partials
+static constexpr int DEFER_BLOCKS = 256;  // workgroups of the deferred-particle kernel
 static constexpr int FUSED_HALO = 2;
 
 // Supported tile shapes (cells per axis, 256 cells each).
@@ -92,8 +93,9 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
   if (hipMemcpy(plan.tiles_d, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice) !=
       hipSuccess)
     return DUST_EDEVICE;
-  if (hipMalloc((void**)&plan.part_d, sizeof(double) * PART_WORDS * std::max<size_t>(tiles.size(), 1)) !=
-      hipSuccess)
+  if (hipMalloc((void**)&plan.part_d, sizeof(double) * PART_WORDS * (tiles.size() + DEFER_BLOCKS)) !=
+          hipSuccess ||
+      hipMalloc((void**)&plan.defer_count, 256) != hipSuccess)
     return DUST_ENOMEM;
   plan.ok = true;
   return DUST_OK;
@@ -102,8 +104,13 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
 void fused_plan_free(FusedPlan& plan) {
   if (plan.tiles_d) (void)hipFree(plan.tiles_d);
   if (plan.part_d) (void)hipFree(plan.part_d);
+  if (plan.defer_count) (void)hipFree(plan.defer_count);
+  if (plan.defer_list) (void)hipFree(plan.defer_list);
   plan.tiles_d = nullptr;
   plan.part_d = nullptr;
+  plan.defer_count = nullptr;
+  plan.defer_list = nullptr;
+  plan.defer_cap = 0;
   plan.ok = false;
   plan.ntiles = 0;
 }
@@ -112,6 +119,17 @@ void fused_plan_free(FusedPlan& plan) {
 // 32 bytes), then the gas window as one 4-vector of the storage type per cell
 // (a single 16- or 32-byte LDS read gives every component of a cell).
 static size_t fused_dep_doubles(size_t cells, int nc) { return (cells * (nc + 1) + 3) & ~(size_t)3; }
+
+dust_status_t fused_plan_reserve(FusedPlan& plan, int64_t n) {
+  if ((size_t)n <= plan.defer_cap && plan.defer_list) return DUST_OK;
+  if (plan.defer_list) (void)hipFree(plan.defer_list);
+  plan.defer_list = nullptr;
+  plan.defer_cap = 0;
+  size_t cap = (size_t)std::max<int64_t>(n, 1);
+  if (hipMalloc((void**)&plan.defer_list, cap * sizeof(uint32_t)) != hipSuccess) return DUST_ENOMEM;
+  plan.defer_cap = cap;
+  return DUST_OK;
+}
 
 size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes) {
   return fused_dep_doubles(plan.lds_cells, nc) * sizeof(double) + plan.lds_cells * 4 * (size_t)ts_bytes;
@@ -187,7 +205,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
             const Box* __restrict__ boxes, FView<TS> fl, Forces f, const Species* __restrict__ sp,
             int drag_mode, A dt, const double* __restrict__ tdev,
             const int64_t* __restrict__ bin_start, const double* __restrict__ xg, DiagDev* dg,
-            double* __restrict__ part, int sums) {
+            double* __restrict__ part, int sums, uint32_t* __restrict__ defer_list,
+            uint32_t* __restrict__ defer_count) {
   // The descriptors (tiles, boxes, species, time, bin starts) are read-only
   // and never aliased by the particle and field arrays: __restrict__ lets
   // their fields stay in scalar registers / the scalar cache, so the loop's
@@ -316,6 +335,28 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         removed = true;
       }
     }
+    // A particle whose stencil leaves the window (it moved more than a cell
+    // since the binning, or wrapped across a periodic face) is left to the
+    // deferred kernel, which does its step against global memory; here it
+    // continues as a dummy.
+    bool deferred = false;
+    if (live) {
+      const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
+      deferred = !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
+                   (c2 == 0 || (lc >= 1 && lc <= RZ - 2)));
+    }
+    {
+      const uint64_t dm = __ballot(deferred);
+      if (dm) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)dm) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(defer_count, (uint32_t)__popcll(dm));
+        base = __shfl(base, leader, 64);
+        if (deferred) defer_list[base + __popcll(dm & wl.below)] = (uint32_t)i;
+      }
+    }
+    if (deferred) live = false;
     if (!live) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -327,9 +368,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // weights at x^{n+1/2}
     Stencil<A> s;
     stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
-    const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
-    const bool inside = la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
-                        (c2 == 0 || (lc >= 1 && lc <= RZ - 2));
+    const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;   // inside the window
 
     const bool home = idx[0] == mycell[0] && idx[1] == mycell[1] && (c2 == 0 || idx[2] == mycell[2]);
     // Gather (Eq. Delta_vp) in slip form: the weights sum to one, so the
@@ -344,7 +383,9 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 #pragma unroll
     for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
     A v[3] = {A(0), A(0), A(0)};
-    if (inside) {
+    // (always true here; kept as a branch, which bounds how far the compiler
+    // hoists the window reads and so the register use)
+    if (la >= 1) {
       const int base = la + RX * (lb + RY * lc);
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
@@ -359,22 +400,6 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 #pragma unroll
             for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(gv[m]) - up[m]);
             if (nc > 1) u[1] += s.w[0][a + 1] * A(g.w);   // low word (shear x ghosts only)
-          }
-          const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-          for (int m = 0; m < nc; ++m) v[m] += wbc * u[m];
-        }
-    } else {
-#pragma unroll
-      for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-        for (int bb = -1; bb <= 1; ++bb) {
-          A u[3] = {A(0), A(0), A(0)};
-#pragma unroll
-          for (int a = -1; a <= 1; ++a) {
-            int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
-#pragma unroll
-            for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(fl.vel[m][id]) - up[m]);
           }
           const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
 #pragma unroll
@@ -446,7 +471,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
           }
         }
     }
-    if (live && !home && inside) {
+    if (live && !home) {
       const int base = la + RX * (lb + RY * lc);
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
@@ -461,27 +486,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
             for (int k = 0; k <= nc; ++k) atomicAdd(&dep[k * RC + r0], w * double(q[k]));
           }
         }
-    } else if (live && !inside) {
-      ++n_fb;
-#pragma unroll
-      for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-        for (int bb = -1; bb <= 1; ++bb)
-#pragma unroll
-          for (int a = -1; a <= 1; ++a) {
-            int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
-            A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1] * A(inv_volume(B, ii, jj, kk));
-            int64_t id = stored_index(B, ii, jj, kk);
-#pragma unroll
-            for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(w * q[k]));
-          }
     }
     // second half drift to x^{n+1}
     if (live) {
       bool alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
       store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
     }
-    if (copy_attrs && has) {
+    if (copy_attrs && has && !deferred) {
       if (!live) {
         // removed or cell-less particles keep their last offsets and momenta
         if (!removed) dst.cell[i] = cid;
@@ -602,12 +613,135 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+__global__ void k_reset_count(uint32_t* c) { *c = 0u; }
+
+// The deferred particles of a fused launch (their stencil at x^{n+1/2} left
+// their tile's window): the same step, one thread per particle, gathering
+// from and depositing to global memory (FP64 x-ghost layer for the shear
+// ghosts).  Their diagnostic sums go to partial slots part0 .. part0 +
+// DEFER_BLOCKS - 1; slot word 6 counts them.
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
+__global__ void __launch_bounds__(256)
+    k_fused_deferred(PView<TS> p, PView<TS> dst, int copy_attrs, const Box* __restrict__ boxes,
+                     int nbox, FView<TS> fl, Forces f, const Species* __restrict__ sp, int drag_mode,
+                     A dt, const double* __restrict__ tdev, const double* __restrict__ xg,
+                     const uint32_t* __restrict__ list, const uint32_t* __restrict__ count,
+                     double* __restrict__ part, int part0, int sums) {
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
+  const uint32_t n = *count;
+  const double t0 = *tdev;
+  const A h = A(0.5) * dt;
+  double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0, s_cells = 0, s_n = 0;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int64_t i = list[e];
+    const int32_t cid = p.cell[i];
+    const int b = find_box(boxes, nbox, cid);
+    const Box& B = boxes[b];
+    int idx[3];
+    A off[3], mom[3];
+    unravel(B, cid - B.cell_base, idx);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
+      mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+    }
+    s_n += 1.0;
+    bool alive = drift<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom);
+    if (alive) {
+      Stencil<A> s;
+      stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
+      Where<A> wh;
+      where<A, GEOM, NDIM, U>(B, idx, off, wh);
+      A up[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
+      A v[3] = {A(0), A(0), A(0)};
+      for (int c = -c2; c <= c2; ++c)
+        for (int bb = -1; bb <= 1; ++bb)
+          for (int a = -1; a <= 1; ++a) {
+            const A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1];
+            for (int m = 0; m < nc; ++m)
+              v[m] += w * A(gas_comp(B, fl, xg, m, idx[0] + a, idx[1] + bb, idx[2] + c) - double(up[m]));
+          }
+      A sl[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
+      int spc = p.species ? p.species[i] : 0;
+      if (spc >= sp->n) spc = 0;
+      const A m = p.mass ? A(p.mass[i]) : A(sp->mass[spc]);
+      A it = drag_mode == DRAG_SPECIES ? A(sp->inv_tau[spc])
+                                       : inverse_tau<A, GEOM>(f, drag_mode, A(p.drag[i]), A(0), wh);
+      A c, psi;
+      propagator<A>(dt * it, c, psi);
+      KickOut<A> o;
+      kick<A, GEOM, NDIM>(B, f, dt, c, psi, wh, mom, sl, o);
+      A q[4] = {A(0), A(0), A(0), A(0)};
+#pragma unroll
+      for (int k = 0; k < nc; ++k) {
+        q[k] = -m * o.j[k];
+        if (sums) {
+          A vbar = (mom[k] + A(0.5) * o.dp[k]) / wh.sc[k];
+          A dl = cell_width<A, U>(B.ax[k], idx[k]) * (GEOM == GEOM_CART || k == 0 ? A(1) : wh.sc[k]);
+          const double cps = fabs(double(vbar * dt / dl));
+          s_cells = cps > s_cells ? cps : s_cells;
+          s_j[k] -= double(q[k]);
+          s_abs += fabs(double(q[k]));
+        }
+        mom[k] += o.dp[k];
+      }
+      q[nc] = -m * o.e;
+      if (sums) s_e -= double(q[nc]);
+      for (int cc = -c2; cc <= c2; ++cc)
+        for (int bb = -1; bb <= 1; ++bb)
+          for (int a = -1; a <= 1; ++a) {
+            const int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + cc;
+            const A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][cc + 1] * A(inv_volume(B, ii, jj, kk));
+            const int64_t id = stored_index(B, ii, jj, kk);
+            for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(w * q[k]));
+          }
+      alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
+      store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, nullptr);
+    } else {
+      store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(h), i, false, idx, off, mom, nullptr);
+    }
+    if (copy_attrs) {
+      if (!alive) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d < NDIM) dst.off[d][i] = p.off[d][i];
+          if (d < nc) dst.mom[d][i] = p.mom[d][i];
+        }
+      }
+      if (p.drag) dst.drag[i] = p.drag[i];
+      if (p.mass) dst.mass[i] = p.mass[i];
+      if (p.species) dst.species[i] = p.species[i];
+      if (p.id) dst.id[i] = p.id[i];
+    }
+  }
+  // block partials (fixed order) into slot part0 + blockIdx.x
+  __shared__ double red[4][PART_WORDS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double vals[PART_WORDS] = {s_j[0], s_j[1], s_j[2], s_e, s_abs, s_cells, s_n, 0.0};
+  for (int k = 0; k < PART_WORDS; ++k) vals[k] = k == 5 ? wave_max(vals[k]) : wave_sum(vals[k]);
+  if (lane == 0)
+    for (int k = 0; k < PART_WORDS; ++k) red[wave][k] = vals[k];
+  __syncthreads();
+  if (threadIdx.x < PART_WORDS) {
+    const int k = threadIdx.x;
+    double v = red[0][k];
+    for (int w = 1; w < 4; ++w) v = k == 5 ? fmax(v, red[w][k]) : v + red[w][k];
+    part[(size_t)(part0 + blockIdx.x) * PART_WORDS + k] = v;
+  }
+}
+
 template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
 static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, const double* xg,
-                           DiagDev* dg, double* part, bool sums, hipStream_t st) {
+                           DiagDev* dg, double* part, bool sums, uint32_t* defer_list,
+                           uint32_t* defer_count, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   size_t lds = fused_lds_bytes(plan, nc, (int)sizeof(TS));
   auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
@@ -621,7 +755,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
   }
   hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, q,
                      (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, xg, dg, part,
-                     (int)sums);
+                     (int)sums, defer_list, defer_count);
 }
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
@@ -629,11 +763,13 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, const double* xg,
-                           DiagDev* dg, double* part, bool sums, hipStream_t st) {
+                           DiagDev* dg, double* part, bool sums, uint32_t* defer_list,
+                           uint32_t* defer_count, int nbox, hipStream_t st) {
 #define DUST_F(TX, TY, TZ)                                                                         \
   launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
                                                    drag_mode, dt, tdev,                            \
-                                                bin_start, xg, dg, part, sums, st)
+                                                bin_start, xg, dg, part, sums, defer_list,      \
+                                                defer_count, st)
   if constexpr (NDIM == 3) {
     switch (plan.shape) {
       case 0: DUST_F(8, 8, 4); break;
@@ -651,6 +787,9 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
     }
   }
 #undef DUST_F
+  hipLaunchKernelGGL((k_fused_deferred<TS, A, GEOM, NDIM, U>), dim3(DEFER_BLOCKS), dim3(256), 0, st, p, q,
+                     (int)copy_attrs, boxes_d, nbox, fl, f, sp, drag_mode, A(dt), tdev, xg,
+                     (const uint32_t*)defer_list, (const uint32_t*)defer_count, part, plan.ntiles, (int)sums);
 }
 
 template <typename TS, typename A>
@@ -659,12 +798,13 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
                   const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
                   hipStream_t st) {
-  (void)nbox;
   if (plan.ntiles == 0) return;
   double* part = plan.part_d;
+  hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, st, plan.defer_count);
 #define DUST_G(G, D, UU)                                                                          \
   launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
-                                  bin_start, xg, dg, part, sums, st)
+                                  bin_start, xg, dg, part, sums, plan.defer_list,                  \
+                                  plan.defer_count, nbox, st)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
@@ -674,7 +814,7 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
 #undef DUST_G
   if (dg)
     hipLaunchKernelGGL(k_reduce_fused_partials, dim3(1), dim3(256), 0, st, (const double*)part,
-                       plan.ntiles, dg, (int)sums);
+                       plan.ntiles + DEFER_BLOCKS, dg, (int)sums);
 }
 
 // ---------------------------------------------------------------- rebinning by half-step cell

@@ -270,29 +270,27 @@ def test_fused_keeps_cellless_particles():
 
 
 @pytest.mark.parametrize("rebin_every", [2, 4])
-def test_stale_bins_match_rebinning_every_step(rebin_every):
-    """Rebinning only every k steps (particles processed away from their
-    binned cell through the LDS-atomic and global paths) gives the same
-    result as rebinning every step, up to the order of FP32 sums."""
+def test_stale_bins_match_oracle(rebin_every):
+    """A step taken with stale bins (particles processed away from the cell
+    they were binned by: LDS-atomic deposits, and the deferred kernel for
+    stencils outside the tile window) against the oracle.  The first step of
+    a call rebins; the second, with DUST_STEP_REBIN_EVERY(k >= 2), does not.
+    The oracle starts from the state after one (rebinning) step."""
     dust = _dust()
     w = synth.shearing_box(n=(16, 16, 8), dt=0.05)
     ctx = dust.context_for(w)
-    P1, F1 = dust.upload(w, ctx)
-    P2, F2 = dust.upload(w, ctx)
     base = dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
-    ctx.step(P1, F1, w.dt, dust.forces_for(w), 4, base)
-    ctx.step(P2, F2, w.dt, dust.forces_for(w), 4, base | dust.STEP_REBIN_EVERY(rebin_every))
-    torch.cuda.synchronize()
-    a, b = _by_id(P1), _by_id(P2)
-    assert torch.equal(a["cell"], b["cell"])
-    for d in range(3):
-        assert (a["off"][d] - b["off"][d]).abs().max().item() <= 1e-5
-        scale = a["mom"][d].abs().max().item() + 1e-30
-        assert (a["mom"][d] - b["mom"][d]).abs().max().item() <= 1e-5 * scale
-    for c in range(4):
-        x, y = F1["dep"][c], F2["dep"][c]
-        assert (x - y).abs().max().item() <= 1e-5 * max(x.abs().max().item(), 1e-30), c
-    assert ctx.status()["n_fallback"] >= 0
+    P0, F0 = dust.upload(w, ctx)
+    ctx.step(P0, F0, w.dt, dust.forces_for(w), 1, base)
+    st1 = download(ctx, P0, F0, w)
+    P, F = dust.upload(w, ctx)
+    ctx.step(P, F, w.dt, dust.forces_for(w), 2, base | dust.STEP_REBIN_EVERY(rebin_every))
+    st2 = download(ctx, P, F, w)
+    t1 = w.t0 + w.dt
+    run = OracleRun(workload_from_state(w, st1, t1))
+    run.step(1)
+    rep = compare_step(w, st1, st2, run, "f32", label=f"stale k={rebin_every}")
+    print("[stale]", rep, ctx.status()["n_fallback"], flush=True)
 
 
 # ------------------------------------------------------------------ autotuner
