@@ -473,35 +473,45 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
     for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
 }
 
+// How a fused step moves the particles between the caller's arrays and the
+// context's shadow copy.
+enum StepMove {
+  STEP_IN_PLACE,   // stale bins: x is updated where it is
+  STEP_REBIN,      // new bins: x is sorted into y (level-major slots)
+  STEP_MOVE,       // stale bins, written to y slot for slot
+};
+
 template <typename TS, typename A>
-dust_status_t fused_step(Ctx* c, dust_particles_t* p, const PView<TS>& pv, const FView<TS>& fv,
-                         const Forces& F, double dt, int flags, bool rebin, hipStream_t st) {
+dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const FView<TS>& fv,
+                         const Forces& F, double dt, int flags, StepMove mv, hipStream_t st) {
   int nc = ctx_nc(c);
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
-  // Rebinning: keys of the cells the particles kick in, a stable sort, and
-  // one gather of the particle arrays into the context's shadow copy; the
-  // fused kernel then reads the shadow and writes the caller's arrays in
-  // binned order.  Without rebinning it works in place.
-  PView<TS> src = pv;
-  if (rebin) {
-    dust_status_t s = ensure_shadow(c, p);
-    if (s) return s;
-    launch_halfstep_keys<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, dt, c->tdev,
+  // Rebinning: keys of the cells the particles kick in, a stable sort, and the
+  // source index of every slot in the fused kernel's order, through which
+  // the fused kernel reads x while writing y in binned order (the particles
+  // without a cell are copied across).
+  const uint32_t* src_index = nullptr;
+  if (mv == STEP_REBIN) {
+    launch_halfstep_keys<TS, A>(x, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, dt, c->tdev,
                                 c->n_active, c->tile, c->bin.key[0], st);
-    c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_TILE, c->tile,
+    c->bin_cur = launch_bin(x.cell, x.n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_TILE, c->tile,
                             c->bin, nullptr, c->bin_start, true, st);
-    src = shadow_view<TS>(c, p);
-    launch_gather_particles<TS>(c->plan, pv, src, pv, c->bin.val[c->bin_cur], c->bin_start,
-                                c->n_active, st);
+    uint32_t* lm = c->bin.val[1 - c->bin_cur];   // free once the sort is done
+    launch_level_perm<TS>(c->plan, x, y, c->bin.val[c->bin_cur], c->bin_start, c->n_active, lm, st);
+    src_index = lm;
+  } else if (mv == STEP_MOVE) {
+    launch_copy_tail<TS>(x, y, c->bin_start, c->n_active, st);
   }
+  const PView<TS>& out = mv == STEP_IN_PLACE ? x : y;
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
   launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
   bool prof = c->prof_used < c->prof_max;
   if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
-  launch_fused<TS, A>(c->plan, src, pv, rebin, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, F,
-                      c->species_d, c->drag_mode, dt, c->tdev, c->bin_start,
-                      (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr, st);
+  launch_fused<TS, A>(c->plan, x, out, mv != STEP_IN_PLACE, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif,
+                      fv, F, c->species_d, c->drag_mode, dt, c->tdev, c->bin_start,
+                      (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr, src_index,
+                      st);
   if (prof) {
     HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
     ++c->prof_used;
@@ -521,18 +531,38 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
   FView<TS> fv = fview<TS>(f);
   int rebin_every = (flags >> 8) & 0xff;
   if (rebin_every <= 0) rebin_every = c->rebin_default;
-  for (int s = 0; s < nsteps; ++s) {
-    if (flags & DUST_STEP_FUSED) {
-      dust_status_t e = fused_step<TS, A>(c, p, pv, fv, F, dt, flags, s % rebin_every == 0, st);
-      if (e) return e;
-    } else {
+  if (!(flags & DUST_STEP_FUSED)) {
+    for (int s = 0; s < nsteps; ++s) {
       // the unfused chain passes gathered velocities and impulses through
       // memory, where FP32 would lose the slip: it computes in FP64
       unfused_step<TS, double>(c, pv, fv, F, dt, flags, st);
+      launch_advance_time(c->tdev, dt, st);
+      if (flags & DUST_STEP_DIAG) launch_count_step(c->diag, st);
     }
+    return DUST_OK;
+  }
+  // Every rebinning moves the particles to the other buffer (the caller's
+  // arrays or the shadow copy).  With an odd number of rebinnings the last
+  // step with stale bins is done out of place instead, so that the call ends
+  // in the caller's arrays; with none, a copy at the end.
+  PView<TS> sh = shadow_view<TS>(c, p);
+  int nrebin = (nsteps + rebin_every - 1) / rebin_every;
+  int last_stale = -1;
+  for (int s = 0; s < nsteps; ++s)
+    if (s % rebin_every) last_stale = s;
+  const bool odd = nrebin % 2 == 1;
+  bool in_shadow = false;
+  for (int s = 0; s < nsteps; ++s) {
+    StepMove mv = s % rebin_every == 0 ? STEP_REBIN : (odd && s == last_stale) ? STEP_MOVE : STEP_IN_PLACE;
+    const PView<TS>& x = in_shadow ? sh : pv;
+    const PView<TS>& y = in_shadow ? pv : sh;
+    dust_status_t e = fused_step<TS, A>(c, x, y, fv, F, dt, flags, mv, st);
+    if (e) return e;
+    if (mv != STEP_IN_PLACE) in_shadow = !in_shadow;
     launch_advance_time(c->tdev, dt, st);
     if (flags & DUST_STEP_DIAG) launch_count_step(c->diag, st);
   }
+  if (in_shadow) launch_copy_particles<TS>(sh, pv, st);
   return DUST_OK;
 }
 
@@ -999,6 +1029,11 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   put(&c->tile, sizeof(c->tile));
   put(&c->rebin_default, sizeof(c->rebin_default));
   put(&c->plan.tiles_d, sizeof(c->plan.tiles_d));
+  put(&c->plan.defer_list, sizeof(c->plan.defer_list));
+  put(&c->shadow_mem, sizeof(c->shadow_mem));
+  put(&c->bin_mem, sizeof(c->bin_mem));
+  put(&c->bin_start, sizeof(c->bin_start));
+  put(&c->ws, sizeof(c->ws));
   put(&c->prof_max, sizeof(c->prof_max));
   if (!(c->graph_exec && key == c->graph_key)) {
     if (c->graph_exec) {

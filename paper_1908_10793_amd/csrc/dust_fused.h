@@ -28,7 +28,7 @@ struct FusedPlan {
   TileDesc* tiles_d = nullptr;
   double* part_d = nullptr;   // per-tile diagnostic partials (+ the deferred kernel's)
   uint32_t* defer_count = nullptr;   // deferred particles of the current launch
-  uint32_t* defer_list = nullptr;    // their slots (capacity defer_cap)
+  uint32_t* defer_list = nullptr;    // their (slot, source) pairs (capacity defer_cap pairs)
   size_t defer_cap = 0;
 };
 
@@ -39,16 +39,17 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
 void fused_plan_free(FusedPlan& plan);
 size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes);
 
-// One fused step over every tile: reads the particles from p (binned by
-// tile-major key, bin_start), writes them to q slot for slot (q may be p);
-// copy_attrs copies drag / mass / species / id along.  xg: the context's
-// FP64 x-ghost gas layers (filled this step), or null.
+// One fused step over every tile (binned by tile-major key, bin_start):
+// slot s of q receives the update of particle src_index[s] of p, or of
+// particle s when src_index is null (then q may be p: in place); copy_attrs
+// copies drag / mass / species / id along.  xg: the context's FP64 x-ghost
+// gas layers (filled this step), or null.
 template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q, bool copy_attrs,
                   const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
                   const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
-                  hipStream_t st);
+                  const uint32_t* src_index, hipStream_t st);
 
 // Keys (tile-major) of the cells the particles reach in the first half drift
 // of a step of length dt starting at *tdev.
@@ -57,14 +58,25 @@ void launch_halfstep_keys(const PView<TS>& p, const Box* boxes_d, int nbox, int 
                           int unif, const Forces& f, double dt, const double* tdev, int64_t nbins,
                           TileShape ts, uint32_t* key, hipStream_t st);
 
-// After a sort (perm, bin_start): sh = the binned particles of src in the
-// fused kernel's level-major layout within each wave's range of slots; the
-// particles without a cell (slots from bin_start[nbins] on) are copied to the
-// same slots of dst.
+// After a sort of src (perm, bin_start): lm = the source index of every
+// binned slot in the fused kernel's level-major layout within each wave's
+// range of slots; the particles without a cell (sorted slots from
+// bin_start[nbins] on, which no tile visits) are copied to the same slots of
+// dst (distinct from src).
 template <typename TS>
-void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const PView<TS>& sh,
-                             const PView<TS>& dst, const uint32_t* perm, const int64_t* bin_start,
-                             int64_t nbins, hipStream_t st);
+void launch_level_perm(const FusedPlan& plan, const PView<TS>& src, const PView<TS>& dst,
+                       const uint32_t* perm, const int64_t* bin_start, int64_t nbins, uint32_t* lm,
+                       hipStream_t st);
+
+// The particles without a cell (slots from bin_start[nbins] on): dst[s] =
+// src[s] (distinct arrays).
+template <typename TS>
+void launch_copy_tail(const PView<TS>& src, const PView<TS>& dst, const int64_t* bin_start, int64_t nbins,
+                      hipStream_t st);
+
+// dst = src, every particle array.
+template <typename TS>
+void launch_copy_particles(const PView<TS>& src, const PView<TS>& dst, hipStream_t st);
 
 void launch_count_step(DiagDev* dg, hipStream_t st);
 

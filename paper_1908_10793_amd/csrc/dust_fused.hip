@@ -126,7 +126,8 @@ dust_status_t fused_plan_reserve(FusedPlan& plan, int64_t n) {
   plan.defer_list = nullptr;
   plan.defer_cap = 0;
   size_t cap = (size_t)std::max<int64_t>(n, 1);
-  if (hipMalloc((void**)&plan.defer_list, cap * sizeof(uint32_t)) != hipSuccess) return DUST_ENOMEM;
+  // (slot written, particle read) pairs
+  if (hipMalloc((void**)&plan.defer_list, 2 * cap * sizeof(uint32_t)) != hipSuccess) return DUST_ENOMEM;
   plan.defer_cap = cap;
   return DUST_OK;
 }
@@ -206,14 +207,15 @@ __global__ void __launch_bounds__(FUSED_THREADS)
             int drag_mode, A dt, const double* __restrict__ tdev,
             const int64_t* __restrict__ bin_start, const double* __restrict__ xg, DiagDev* dg,
             double* __restrict__ part, int sums, uint32_t* __restrict__ defer_list,
-            uint32_t* __restrict__ defer_count) {
+            uint32_t* __restrict__ defer_count, const uint32_t* __restrict__ src_index) {
   // The descriptors (tiles, boxes, species, time, bin starts) are read-only
   // and never aliased by the particle and field arrays: __restrict__ lets
   // their fields stay in scalar registers / the scalar cache, so the loop's
   // waits on particle loads do not also wait on descriptor reloads.
-  // p: particles read (binned order); dst: where the updated particles are
-  // written, slot for slot (dst = p in place; otherwise the attributes that
-  // the step does not change are copied along when copy_attrs is set).
+  // p: particles read; dst: where the updated particles are written, in the
+  // binned (level-major) slot order.  Slot i reads particle src_index[i] of
+  // p (right after a rebinning, dst != p), or particle i (src_index null, in
+  // place).  copy_attrs copies the attributes the step does not change.
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   constexpr int H = FUSED_HALO;
@@ -300,13 +302,21 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   int64_t lvl = wl.base;
   int64_t slot = level_slot(wl, 0, lvl);
   Raw<TS> nxt;
-  if (wl.cnt > 0) load_raw<TS, NDIM, nc>(p, slot, nxt);
+  int64_t nxt_si = 0;
+  if (wl.cnt > 0) {
+    nxt_si = src_index ? (int64_t)src_index[slot] : slot;
+    load_raw<TS, NDIM, nc>(p, nxt_si, nxt);
+  }
   for (int j = 0; j < wl.nlev; ++j) {
     const bool has = wl.cnt > j;
-    const int64_t i = slot;
+    const int64_t i = slot;        // slot written
+    const int64_t si = nxt_si;     // particle read
     const Raw<TS> cur = nxt;
     slot = level_slot(wl, j + 1, lvl);
-    if (wl.cnt > j + 1) load_raw<TS, NDIM, nc>(p, slot, nxt);   // prefetch the next particle
+    if (wl.cnt > j + 1) {          // prefetch the next particle
+      nxt_si = src_index ? (int64_t)src_index[slot] : slot;
+      load_raw<TS, NDIM, nc>(p, nxt_si, nxt);
+    }
     // Lanes of one wave walk different cells, so nothing below branches
     // around the register sums: a particle without a cell, or one that left
     // through an open face, continues as a dummy at the centre of this
@@ -353,7 +363,10 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         uint32_t base = 0;
         if (lane == leader) base = atomicAdd(defer_count, (uint32_t)__popcll(dm));
         base = __shfl(base, leader, 64);
-        if (deferred) defer_list[base + __popcll(dm & wl.below)] = (uint32_t)i;
+        if (deferred) {
+          defer_list[2 * (base + __popcll(dm & wl.below))] = (uint32_t)i;
+          defer_list[2 * (base + __popcll(dm & wl.below)) + 1] = (uint32_t)si;
+        }
       }
     }
     if (deferred) live = false;
@@ -410,18 +423,18 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     A sl[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
-    int spc = p.species && live ? p.species[i] : 0;
+    int spc = p.species && live ? p.species[si] : 0;
     if (spc >= sp->n) {
       flag(dg, DUST_FLAG_BAD_CELL);
       spc = 0;
     }
-    A m = p.mass && live ? A(p.mass[i]) : sp_m[spc];
+    A m = p.mass && live ? A(p.mass[si]) : sp_m[spc];
     A c, psi;
     if (drag_mode == DRAG_SPECIES) {
       c = sp_c[spc];
       psi = sp_psi[spc];
     } else {
-      A it = inverse_tau<A, GEOM>(f, drag_mode, live ? A(p.drag[i]) : A(1), A(0), wh);
+      A it = inverse_tau<A, GEOM>(f, drag_mode, live ? A(p.drag[si]) : A(1), A(0), wh);
       propagator<A>(dt * it, c, psi);
     }
     KickOut<A> o;
@@ -502,10 +515,10 @@ __global__ void __launch_bounds__(FUSED_THREADS)
           if (d < nc) dst.mom[d][i] = cur.mom[d];
         }
       }
-      if (p.drag) dst.drag[i] = p.drag[i];
-      if (p.mass) dst.mass[i] = p.mass[i];
-      if (p.species) dst.species[i] = p.species[i];
-      if (p.id) dst.id[i] = p.id[i];
+      if (p.drag) dst.drag[i] = p.drag[si];
+      if (p.mass) dst.mass[i] = p.mass[si];
+      if (p.species) dst.species[i] = p.species[si];
+      if (p.id) dst.id[i] = p.id[si];
     }
   }
 
@@ -634,8 +647,8 @@ __global__ void __launch_bounds__(256)
   const A h = A(0.5) * dt;
   double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0, s_cells = 0, s_n = 0;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-    const int64_t i = list[e];
-    const int32_t cid = p.cell[i];
+    const int64_t i = list[2 * e], si = list[2 * e + 1];   // slot written, particle read
+    const int32_t cid = p.cell[si];
     const int b = find_box(boxes, nbox, cid);
     const Box& B = boxes[b];
     int idx[3];
@@ -643,8 +656,8 @@ __global__ void __launch_bounds__(256)
     unravel(B, cid - B.cell_base, idx);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
-      mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+      off[d] = d < NDIM ? A(p.off[d][si]) : A(0);
+      mom[d] = d < nc ? A(p.mom[d][si]) : A(0);
     }
     s_n += 1.0;
     bool alive = drift<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom);
@@ -667,11 +680,11 @@ __global__ void __launch_bounds__(256)
       A sl[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
-      int spc = p.species ? p.species[i] : 0;
+      int spc = p.species ? p.species[si] : 0;
       if (spc >= sp->n) spc = 0;
-      const A m = p.mass ? A(p.mass[i]) : A(sp->mass[spc]);
+      const A m = p.mass ? A(p.mass[si]) : A(sp->mass[spc]);
       A it = drag_mode == DRAG_SPECIES ? A(sp->inv_tau[spc])
-                                       : inverse_tau<A, GEOM>(f, drag_mode, A(p.drag[i]), A(0), wh);
+                                       : inverse_tau<A, GEOM>(f, drag_mode, A(p.drag[si]), A(0), wh);
       A c, psi;
       propagator<A>(dt * it, c, psi);
       KickOut<A> o;
@@ -709,14 +722,14 @@ __global__ void __launch_bounds__(256)
       if (!alive) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          if (d < NDIM) dst.off[d][i] = p.off[d][i];
-          if (d < nc) dst.mom[d][i] = p.mom[d][i];
+          if (d < NDIM) dst.off[d][i] = p.off[d][si];
+          if (d < nc) dst.mom[d][i] = p.mom[d][si];
         }
       }
-      if (p.drag) dst.drag[i] = p.drag[i];
-      if (p.mass) dst.mass[i] = p.mass[i];
-      if (p.species) dst.species[i] = p.species[i];
-      if (p.id) dst.id[i] = p.id[i];
+      if (p.drag) dst.drag[i] = p.drag[si];
+      if (p.mass) dst.mass[i] = p.mass[si];
+      if (p.species) dst.species[i] = p.species[si];
+      if (p.id) dst.id[i] = p.id[si];
     }
   }
   // block partials (fixed order) into slot part0 + blockIdx.x
@@ -741,7 +754,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, const double* xg,
                            DiagDev* dg, double* part, bool sums, uint32_t* defer_list,
-                           uint32_t* defer_count, hipStream_t st) {
+                           uint32_t* defer_count, const uint32_t* src_index, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   size_t lds = fused_lds_bytes(plan, nc, (int)sizeof(TS));
   auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
@@ -755,7 +768,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
   }
   hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, p, q,
                      (int)copy_attrs, boxes_d, fl, f, sp, drag_mode, A(dt), tdev, bin_start, xg, dg, part,
-                     (int)sums, defer_list, defer_count);
+                     (int)sums, defer_list, defer_count, src_index);
 }
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
@@ -764,12 +777,13 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                            double dt, const double* tdev, const int64_t* bin_start, const double* xg,
                            DiagDev* dg, double* part, bool sums, uint32_t* defer_list,
-                           uint32_t* defer_count, int nbox, hipStream_t st) {
+                           uint32_t* defer_count, const uint32_t* src_index, int nbox,
+                           hipStream_t st) {
 #define DUST_F(TX, TY, TZ)                                                                         \
   launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
                                                    drag_mode, dt, tdev,                            \
                                                 bin_start, xg, dg, part, sums, defer_list,      \
-                                                defer_count, st)
+                                                defer_count, src_index, st)
   if constexpr (NDIM == 3) {
     switch (plan.shape) {
       case 0: DUST_F(8, 8, 4); break;
@@ -797,14 +811,14 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                   const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
                   const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
-                  hipStream_t st) {
+                  const uint32_t* src_index, hipStream_t st) {
   if (plan.ntiles == 0) return;
   double* part = plan.part_d;
   hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, st, plan.defer_count);
 #define DUST_G(G, D, UU)                                                                          \
   launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
                                   bin_start, xg, dg, part, sums, plan.defer_list,                  \
-                                  plan.defer_count, nbox, st)
+                                  plan.defer_count, src_index, nbox, st)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
@@ -888,14 +902,13 @@ __device__ __forceinline__ void copy_particle(const PView<TS>& src, int64_t from
   if (src.id) dst.id[to] = src.id[from];
 }
 
-// Gather the binned particles of each tile from src into sh in the fused
-// kernel's level-major layout: one workgroup per tile, one thread per cell
-// (the fused kernel's mapping); sorted slot ps + j of a cell holds the input
-// index perm[ps + j] of its j-th particle.
-template <typename TS>
+// The level-major order of each tile's binned particles as a permutation:
+// lm[slot] = perm[ps + j] for the j-th particle of a cell whose sorted range
+// starts at ps (one workgroup per tile, one thread per cell: the fused
+// kernel's mapping).
 __global__ void __launch_bounds__(256)
-    k_gather_tiled(const TileDesc* __restrict__ tiles, TileShape ts, PView<TS> src, PView<TS> sh,
-                   const uint32_t* __restrict__ perm, const int64_t* __restrict__ bin_start) {
+    k_level_perm(const TileDesc* __restrict__ tiles, TileShape ts, const uint32_t* __restrict__ perm,
+                 const int64_t* __restrict__ bin_start, uint32_t* __restrict__ lm) {
   const TileDesc td = tiles[blockIdx.x];
   const int TX = ts.t[0], TY = ts.t[1];
   const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
@@ -910,52 +923,66 @@ __global__ void __launch_bounds__(256)
   int64_t lvl = wl.base;
   for (int j = 0; j < wl.nlev; ++j) {
     const int64_t to = level_slot(wl, j, lvl);
-    if (wl.cnt > j) copy_particle(src, (int64_t)perm[ps + j], sh, to);
+    if (wl.cnt > j) lm[to] = perm[ps + j];
   }
 }
 
-// Particles without a cell (sorted last, from slot bin_start[nbins] on):
-// sh[s] = src[perm[s]].  Covers n slots from the tail's start.
+// Particles without a cell (sorted last, from slot bin_start[nbins] on), which
+// no tile visits: dst[s] = src[perm[s]], or src[s] when perm is null (src and
+// dst distinct).
 template <typename TS>
 __global__ void __launch_bounds__(256)
-    k_gather_tail(PView<TS> src, PView<TS> sh, const uint32_t* __restrict__ perm,
-                  const int64_t* __restrict__ bin_start, int64_t nbins) {
+    k_copy_tail(PView<TS> src, PView<TS> dst, const uint32_t* __restrict__ perm,
+                const int64_t* __restrict__ bin_start, int64_t nbins) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < src.n;
        s += stride)
-    copy_particle(src, (int64_t)perm[s], sh, s);
+    copy_particle(src, perm ? (int64_t)perm[s] : s, dst, s);
 }
 
-// dst[s] = sh[s] for the tail slots (after the gathers, which read src = dst).
+// dst = src, every array.
 template <typename TS>
-__global__ void __launch_bounds__(256)
-    k_copy_tail(PView<TS> sh, PView<TS> dst, const int64_t* __restrict__ bin_start, int64_t nbins) {
+__global__ void __launch_bounds__(256) k_copy_particles(PView<TS> src, PView<TS> dst) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t s = bin_start[nbins] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < sh.n;
-       s += stride)
-    copy_particle(sh, s, dst, s);
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < src.n; s += stride)
+    copy_particle(src, s, dst, s);
 }
 
 template <typename TS>
-void launch_gather_particles(const FusedPlan& plan, const PView<TS>& src, const PView<TS>& sh,
-                             const PView<TS>& dst, const uint32_t* perm, const int64_t* bin_start,
-                             int64_t nbins, hipStream_t st) {
+void launch_level_perm(const FusedPlan& plan, const PView<TS>& src, const PView<TS>& dst,
+                       const uint32_t* perm, const int64_t* bin_start, int64_t nbins, uint32_t* lm,
+                       hipStream_t st) {
   if (src.n == 0) return;
-  TileShape ts = plan.tile;
   if (plan.ntiles > 0)
-    hipLaunchKernelGGL(k_gather_tiled<TS>, dim3(plan.ntiles), dim3(256), 0, st, plan.tiles_d, ts, src,
-                       sh, perm, bin_start);
-  // the tail (particles without a cell) is usually empty: grid-stride loops
+    hipLaunchKernelGGL(k_level_perm, dim3(plan.ntiles), dim3(256), 0, st, plan.tiles_d, plan.tile, perm,
+                       bin_start, lm);
+  // the tail is usually empty: a grid-stride loop
   unsigned g = (unsigned)std::min<int64_t>((src.n + 255) / 256, 512);
-  hipLaunchKernelGGL(k_gather_tail<TS>, dim3(g), dim3(256), 0, st, src, sh, perm, bin_start, nbins);
-  hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, sh, dst, bin_start, nbins);
+  hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, src, dst, perm, bin_start, nbins);
+}
+
+template <typename TS>
+void launch_copy_tail(const PView<TS>& src, const PView<TS>& dst, const int64_t* bin_start, int64_t nbins,
+                      hipStream_t st) {
+  if (src.n == 0) return;
+  unsigned g = (unsigned)std::min<int64_t>((src.n + 255) / 256, 512);
+  hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, src, dst, (const uint32_t*)nullptr,
+                     bin_start, nbins);
+}
+
+template <typename TS>
+void launch_copy_particles(const PView<TS>& src, const PView<TS>& dst, hipStream_t st) {
+  if (src.n == 0) return;
+  unsigned g = (unsigned)std::min<int64_t>((src.n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_copy_particles<TS>, dim3(g), dim3(256), 0, st, src, dst);
 }
 
 #define DUST_FUSED_INST(TS, A)                                                                    \
   template void launch_fused<TS, A>(const FusedPlan&, const PView<TS>&, const PView<TS>&, bool,     \
                                     const Box*, int, int, int, int, const FView<TS>&,              \
                                     const Forces&, const Species*, int, double, const double*,     \
-                                    const int64_t*, const double*, DiagDev*, bool, hipStream_t);   \
+                                    const int64_t*, const double*, DiagDev*, bool, const uint32_t*, \
+                                    hipStream_t);                                                  \
   template void launch_halfstep_keys<TS, A>(const PView<TS>&, const Box*, int, int, int, int,       \
                                             const Forces&, double, const double*, int64_t,         \
                                             TileShape, uint32_t*, hipStream_t);
@@ -964,11 +991,17 @@ DUST_FUSED_INST(float, double)
 DUST_FUSED_INST(float, float)
 DUST_FUSED_INST(double, double)
 
-template void launch_gather_particles<float>(const FusedPlan&, const PView<float>&,
-                                             const PView<float>&, const PView<float>&,
-                                             const uint32_t*, const int64_t*, int64_t, hipStream_t);
-template void launch_gather_particles<double>(const FusedPlan&, const PView<double>&,
-                                              const PView<double>&, const PView<double>&,
-                                              const uint32_t*, const int64_t*, int64_t, hipStream_t);
+template void launch_level_perm<float>(const FusedPlan&, const PView<float>&, const PView<float>&,
+                                       const uint32_t*, const int64_t*, int64_t, uint32_t*,
+                                       hipStream_t);
+template void launch_level_perm<double>(const FusedPlan&, const PView<double>&, const PView<double>&,
+                                        const uint32_t*, const int64_t*, int64_t, uint32_t*,
+                                        hipStream_t);
+template void launch_copy_tail<float>(const PView<float>&, const PView<float>&, const int64_t*, int64_t,
+                                      hipStream_t);
+template void launch_copy_tail<double>(const PView<double>&, const PView<double>&, const int64_t*,
+                                       int64_t, hipStream_t);
+template void launch_copy_particles<float>(const PView<float>&, const PView<float>&, hipStream_t);
+template void launch_copy_particles<double>(const PView<double>&, const PView<double>&, hipStream_t);
 
 }  // namespace dust

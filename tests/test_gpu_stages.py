@@ -1,5 +1,7 @@
 """GPU tests of the individual C-ABI calls: binning (bit exact), ghost fill
 and fold, gather, the unfused phase chain, graphs, edge cases and errors."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -151,19 +153,20 @@ def test_phase_chain_equals_step():
 
 # ------------------------------------------------------------------ graphs
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("nsteps,rebin_every", [(4, 1), (5, 2)])
+def test_graph_replay_matches_eager(nsteps, rebin_every):
     dust = _dust()
     w = synth.shearing_box(n=(16, 12, 8), dt=0.02)
     ctx = dust.context_for(w)
     P1, F1 = dust.upload(w, ctx)
     P2, F2 = dust.upload(w, ctx)
-    flags = dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK
+    flags = dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK | dust.STEP_REBIN_EVERY(rebin_every)
     t = 0.0
     for rep in range(3):
-        ctx.step(P1, F1, w.dt, dust.forces_for(w, t), 4, flags)
-        ctx.step(P2, F2, w.dt, dust.forces_for(w, t), 4, flags | dust.STEP_GRAPH)
+        ctx.step(P1, F1, w.dt, dust.forces_for(w, t), nsteps, flags)
+        ctx.step(P2, F2, w.dt, dust.forces_for(w, t), nsteps, flags | dust.STEP_GRAPH)
         torch.cuda.synchronize()
-        t += 4 * w.dt
+        t += nsteps * w.dt
         o1 = torch.argsort(P1["id"])
         o2 = torch.argsort(P2["id"])
         assert torch.equal(P1["cell"][o1], P2["cell"][o2])
@@ -269,28 +272,58 @@ def test_fused_keeps_cellless_particles():
     assert not torch.equal(after["off"][0][~gone], before["off"][0][~gone])
 
 
-@pytest.mark.parametrize("rebin_every", [2, 4])
-def test_stale_bins_match_oracle(rebin_every):
-    """A step taken with stale bins (particles processed away from the cell
-    they were binned by: LDS-atomic deposits, and the deferred kernel for
-    stencils outside the tile window) against the oracle.  The first step of
-    a call rebins; the second, with DUST_STEP_REBIN_EVERY(k >= 2), does not.
-    The oracle starts from the state after one (rebinning) step."""
+def _small(name):
+    if name == "shearing_box":
+        return synth.shearing_box(n=(16, 16, 8), dt=0.05)
+    return synth.cylindrical_disk(n=(16, 12, 8), npart=3000, dt=0.05)
+
+
+# (steps in one call, rebinning interval): the kind of the call's last step
+# and where the particles are before it (the context alternates between the
+# caller's arrays and its shadow copy at each rebinning, and moves them back
+# with the last stale step, or a copy, when the count is odd)
+SCHEDULES = [
+    (2, 4),   # rebin, stale written across (ends in the caller's arrays)
+    (3, 3),   # rebin, stale in place, stale written across
+    (3, 2),   # rebin, stale in place in the shadow, rebin back
+    (4, 2),   # rebin, stale, rebin back, stale in place in the caller's arrays
+    (3, 1),   # three rebinnings, then a copy back
+    (5, 2),   # rebin, stale, rebin back, stale written across, rebin back
+]
+
+
+@pytest.mark.parametrize("name", ["shearing_box", "cylindrical_disk"])
+@pytest.mark.parametrize("nsteps,rebin_every", SCHEDULES)
+def test_multi_step_schedules_match_oracle(name, nsteps, rebin_every):
+    """The last step of a call of nsteps fused steps with
+    DUST_STEP_REBIN_EVERY(k), whatever its kind (rebinning, stale bins in
+    place or written across buffers; stale steps process particles away from
+    the cell they were binned by: LDS-atomic deposits, and the deferred
+    kernel for stencils outside the tile window), against the oracle started
+    from the state after nsteps-1 steps of a call with the same interval.
+    Without feedback the gas does not change, so those first nsteps-1 steps
+    are the same computation in both calls."""
     dust = _dust()
-    w = synth.shearing_box(n=(16, 16, 8), dt=0.05)
+    w = dataclasses.replace(_small(name), apply_feedback=False)
     ctx = dust.context_for(w)
-    base = dust.STEP_FUSED | dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
+    flags = dust.STEP_FUSED | dust.STEP_DIAG | dust.STEP_REBIN_EVERY(rebin_every)
     P0, F0 = dust.upload(w, ctx)
-    ctx.step(P0, F0, w.dt, dust.forces_for(w), 1, base)
-    st1 = download(ctx, P0, F0, w)
+    ctx.step(P0, F0, w.dt, dust.forces_for(w), nsteps - 1, flags)
+    st_a = download(ctx, P0, F0, w)
     P, F = dust.upload(w, ctx)
-    ctx.step(P, F, w.dt, dust.forces_for(w), 2, base | dust.STEP_REBIN_EVERY(rebin_every))
-    st2 = download(ctx, P, F, w)
-    t1 = w.t0 + w.dt
-    run = OracleRun(workload_from_state(w, st1, t1))
+    ctx.step(P, F, w.dt, dust.forces_for(w), nsteps, flags)
+    st_b = download(ctx, P, F, w)
+    # every array comes back to the caller: attributes by id unchanged
+    order = np.argsort(st_b["id"])
+    order0 = np.argsort(st_a["id"])
+    for k in ("drag", "mass", "species"):
+        if st_b[k] is not None:
+            assert np.array_equal(st_b[k][order], st_a[k][order0]), k
+    assert np.array_equal(np.sort(st_b["id"]), np.arange(len(st_b["id"])))
+    run = OracleRun(workload_from_state(w, st_a, w.t0 + (nsteps - 1) * w.dt))
     run.step(1)
-    rep = compare_step(w, st1, st2, run, "f32", label=f"stale k={rebin_every}")
-    print("[stale]", rep, ctx.status()["n_fallback"], flush=True)
+    rep = compare_step(w, st_a, st_b, run, "f32", label=f"{name} {nsteps}x k={rebin_every}")
+    print("[schedule]", rep, ctx.status()["n_fallback"], flush=True)
 
 
 # ------------------------------------------------------------------ autotuner
