@@ -159,7 +159,7 @@ template <> struct Vec4<double> {
 struct WaveLevels {
   int cnt;          // particles of this lane's cell
   int nlev;         // largest count in the wave
-  int64_t base;     // first slot of the wave's range
+  uint32_t base;    // first slot of the wave's range (counts are below 2^31)
   uint64_t below;   // lanes below this one
 };
 
@@ -171,16 +171,16 @@ __device__ __forceinline__ WaveLevels wave_levels(int cnt, int64_t start) {
   w.nlev = wave_max(cnt);
   const uint64_t any = __ballot(cnt > 0);
   // the first lane with particles has the smallest start of the range
-  w.base = any ? __shfl(start, __ffsll((unsigned long long)any) - 1, 64) : 0;
+  w.base = any ? (uint32_t)__shfl(start, __ffsll((unsigned long long)any) - 1, 64) : 0u;
   return w;
 }
 
 // Slot of this lane's particle of level j; lvl: start of level j on entry,
 // of level j+1 on return (call once per level, in order, in every lane).
-__device__ __forceinline__ int64_t level_slot(const WaveLevels& w, int j, int64_t& lvl) {
+__device__ __forceinline__ uint32_t level_slot(const WaveLevels& w, int j, uint32_t& lvl) {
   const uint64_t m = __ballot(w.cnt > j);
-  const int64_t s = lvl + __popcll(m & w.below);
-  lvl += __popcll(m);
+  const uint32_t s = lvl + (uint32_t)__popcll(m & w.below);
+  lvl += (uint32_t)__popcll(m);
   return s;
 }
 
@@ -200,8 +200,18 @@ __device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>&
   }
 }
 
+// Register budget: the FP32 kernel needs about 250 VGPRs (108 of them the
+// register sums); the compiler keeps every shape but one under 256 (2
+// waves/SIMD) by itself, and the 4x4x16 shape with an explicit target (an
+// explicit target on the others costs them time).
+template <typename A, typename TS, int TX, int TY>
+constexpr int fused_waves_target() {
+  return sizeof(A) == 4 && sizeof(TS) == 4 && TX * TY <= 16 ? 2 : 1;
+}
+
 template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(FUSED_THREADS)
+    __attribute__((amdgpu_waves_per_eu(fused_waves_target<A, TS, TX, TY>())))
     k_fused(const TileDesc* __restrict__ tiles, PView<TS> p, PView<TS> dst, int copy_attrs,
             const Box* __restrict__ boxes, FView<TS> fl, Forces f, const Species* __restrict__ sp,
             int drag_mode, A dt, const double* __restrict__ tdev,
@@ -299,22 +309,22 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   // cell's j-th particle, and those particles are consecutive slots, so the
   // loads and stores of an iteration are contiguous.
   const WaveLevels wl = wave_levels(own ? (int)(pe - ps) : 0, ps);
-  int64_t lvl = wl.base;
-  int64_t slot = level_slot(wl, 0, lvl);
+  uint32_t lvl = wl.base;
+  uint32_t slot = level_slot(wl, 0, lvl);
   Raw<TS> nxt;
-  int64_t nxt_si = 0;
+  uint32_t nxt_si = 0;
   if (wl.cnt > 0) {
-    nxt_si = src_index ? (int64_t)src_index[slot] : slot;
+    nxt_si = src_index ? src_index[slot] : slot;
     load_raw<TS, NDIM, nc>(p, nxt_si, nxt);
   }
   for (int j = 0; j < wl.nlev; ++j) {
     const bool has = wl.cnt > j;
-    const int64_t i = slot;        // slot written
-    const int64_t si = nxt_si;     // particle read
+    const uint32_t i = slot;       // slot written
+    const uint32_t si = nxt_si;    // particle read
     const Raw<TS> cur = nxt;
     slot = level_slot(wl, j + 1, lvl);
     if (wl.cnt > j + 1) {          // prefetch the next particle
-      nxt_si = src_index ? (int64_t)src_index[slot] : slot;
+      nxt_si = src_index ? src_index[slot] : slot;
       load_raw<TS, NDIM, nc>(p, nxt_si, nxt);
     }
     // Lanes of one wave walk different cells, so nothing below branches
@@ -364,8 +374,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         if (lane == leader) base = atomicAdd(defer_count, (uint32_t)__popcll(dm));
         base = __shfl(base, leader, 64);
         if (deferred) {
-          defer_list[2 * (base + __popcll(dm & wl.below))] = (uint32_t)i;
-          defer_list[2 * (base + __popcll(dm & wl.below)) + 1] = (uint32_t)si;
+          defer_list[2 * (base + __popcll(dm & wl.below))] = i;
+          defer_list[2 * (base + __popcll(dm & wl.below)) + 1] = si;
         }
       }
     }
@@ -595,7 +605,20 @@ __global__ void __launch_bounds__(256)
   __shared__ double red[256][PART_WORDS];
   double acc[PART_WORDS];
   for (int k = 0; k < PART_WORDS; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < n; b += 256)
+  // slots b, b + 256, ... in order; four slots' loads in flight at a time
+  int b = threadIdx.x;
+  for (; b + 3 * 256 < n; b += 4 * 256) {
+    double v[4][PART_WORDS];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < PART_WORDS; ++k) v[u][k] = part[(size_t)(b + u * 256) * PART_WORDS + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < PART_WORDS; ++k) acc[k] = k == 5 ? fmax(acc[k], v[u][k]) : acc[k] + v[u][k];
+  }
+  for (; b < n; b += 256)
     for (int k = 0; k < PART_WORDS; ++k) {
       const double v = part[(size_t)b * PART_WORDS + k];
       acc[k] = k == 5 ? fmax(acc[k], v) : acc[k] + v;
@@ -847,19 +870,20 @@ __global__ void __launch_bounds__(256)
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  int64_t c = p.cell[i];
+  // every load issued before the cell is examined (one memory latency)
+  const int64_t c = p.cell[i];
+  A off[3], mom[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
+    mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+  }
   uint32_t k = nbins;
   if (c >= 0 && c < (int64_t)nbins) {
     const int b = find_box(boxes, nbox, c);
     const Box& B = boxes[b];
     int idx[3];
-    A off[3], mom[3];
     unravel(B, c - B.cell_base, idx);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
-      mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
-    }
     const A h = A(0.5) * dt;
     int here[3] = {idx[0], idx[1], idx[2]};
     k = drift<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)
@@ -920,9 +944,9 @@ __global__ void __launch_bounds__(256)
     pe = bin_start[key + 1];
   }
   const WaveLevels wl = wave_levels(own ? (int)(pe - ps) : 0, ps);
-  int64_t lvl = wl.base;
+  uint32_t lvl = wl.base;
   for (int j = 0; j < wl.nlev; ++j) {
-    const int64_t to = level_slot(wl, j, lvl);
+    const uint32_t to = level_slot(wl, j, lvl);
     if (wl.cnt > j) lm[to] = perm[ps + j];
   }
 }

@@ -396,7 +396,9 @@ template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n0 * n1 * n2) return;
-  int i = (int)(t % n0), j = (int)((t / n0) % n1), k = (int)(t / ((int64_t)n0 * n1));
+  int idx[3];
+  unravel(B, t, idx);   // (active cell counts are below 2^31)
+  const int i = idx[0], j = idx[1], k = idx[2];
   int64_t id = stored_index(B, i, j, k);
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   double sc[3] = {1.0, 1.0, 1.0};
@@ -452,6 +454,7 @@ __global__ void __launch_bounds__(256)
     k_reduce_grid_partials(const double* __restrict__ part, int n, int nc, DiagDev* dg) {
   __shared__ double red[256][4];
   double acc[4] = {0, 0, 0, 0};
+#pragma unroll 4
   for (int b = threadIdx.x; b < n; b += 256)
     for (int c = 0; c < 4; ++c) acc[c] += part[(size_t)b * 4 + c];
   for (int c = 0; c < 4; ++c) red[threadIdx.x][c] = acc[c];

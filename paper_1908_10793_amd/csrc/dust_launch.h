@@ -56,7 +56,7 @@ void launch_set_time(double* tdev, double v, hipStream_t st);
 void launch_advance_time(double* tdev, double dt, hipStream_t st);
 template <typename TS> void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st);
 // FP64 grid sums of one box; part: GRID_SUM_BLOCKS * 4 doubles of scratch.
-static constexpr int GRID_SUM_BLOCKS = 512;
+static constexpr int GRID_SUM_BLOCKS = 2048;
 template <typename TS>
 void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, double* part, hipStream_t st);
 template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st);
