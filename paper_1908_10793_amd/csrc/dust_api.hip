@@ -993,7 +993,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
     if (fused_plan_reserve(c->plan, p->n) != DUST_OK) return fail(DUST_ENOMEM, "deferred-particle list");
-    if (fused_lds_bytes(c->plan, ctx_nc(c), c->prec == DUST_F64 ? 8 : 4) > 160 * 1024)
+    if (fused_lds_bytes(c->plan, ctx_nc(c), c->prec == DUST_F64 ? 8 : 4) + FUSED_STATIC_LDS > 160 * 1024)
       return fail(DUST_EUNSUPPORTED, "fused tile window needs more than 160 KiB of LDS");
   }
   Forces F = forces_of(frc);
@@ -1159,7 +1159,7 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
     c->tile = t;
     drop_graph(c);
     if (fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack) != DUST_OK) continue;
-    if (fused_lds_bytes(c->plan, ctx_nc(c), (int)rs) > 160 * 1024) continue;
+    if (fused_lds_bytes(c->plan, ctx_nc(c), (int)rs) + FUSED_STATIC_LDS > 160 * 1024) continue;
     for (int k = 1; k <= 4 && !s; ++k) {
       if ((s = restore())) break;
       const int32_t fl = flags | DUST_STEP_FUSED | DUST_STEP_REBIN_EVERY(k);

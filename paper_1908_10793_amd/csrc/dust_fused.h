@@ -37,7 +37,10 @@ dust_status_t fused_plan_reserve(FusedPlan& plan, int64_t n);
 
 dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileShape tile, int slack);
 void fused_plan_free(FusedPlan& plan);
+// LDS of one fused workgroup: the dynamic part (windows), and the static
+// part (per-thread diagnostic sums, species tables) as an upper bound.
 size_t fused_lds_bytes(const FusedPlan& plan, int nc, int ts_bytes);
+static constexpr size_t FUSED_STATIC_LDS = 5 * 256 * sizeof(double) + 3 * DUST_MAX_SPECIES * sizeof(double) + 256;
 
 // One fused step over every tile (binned by tile-major key, bin_start):
 // slot s of q receives the update of particle src_index[s] of p, or of

@@ -156,18 +156,20 @@ template <> struct Vec4<double> {
 // slots.  Level j of the range holds the j-th particle of every cell that has
 // more than j, in lane order; the slot of lane l in level j is the level's
 // start plus the number of lower lanes whose cells have more than j.
+// Set bits of a wave mask in the lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 struct WaveLevels {
   int cnt;          // particles of this lane's cell
   int nlev;         // largest count in the wave
   uint32_t base;    // first slot of the wave's range (counts are below 2^31)
-  uint64_t below;   // lanes below this one
 };
 
 __device__ __forceinline__ WaveLevels wave_levels(int cnt, int64_t start) {
   WaveLevels w;
   w.cnt = cnt;
-  const int lane = threadIdx.x & 63;
-  w.below = lane ? (~0ull >> (64 - lane)) : 0ull;
   w.nlev = wave_max(cnt);
   const uint64_t any = __ballot(cnt > 0);
   // the first lane with particles has the smallest start of the range
@@ -179,7 +181,7 @@ __device__ __forceinline__ WaveLevels wave_levels(int cnt, int64_t start) {
 // of level j+1 on return (call once per level, in order, in every lane).
 __device__ __forceinline__ uint32_t level_slot(const WaveLevels& w, int j, uint32_t& lvl) {
   const uint64_t m = __ballot(w.cnt > j);
-  const uint32_t s = lvl + (uint32_t)__popcll(m & w.below);
+  const uint32_t s = lvl + lanes_below(m);
   lvl += (uint32_t)__popcll(m);
   return s;
 }
@@ -300,7 +302,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   for (int o = 0; o < NS; ++o)
 #pragma unroll
     for (int k = 0; k <= nc; ++k) acc[o][k] = TAcc(0);
-  double s_j[3] = {0, 0, 0}, s_e = 0, s_abs = 0;
+  // FP64 diagnostic sums of this thread (impulse, energy, |impulse|): kept
+  // in LDS, each thread its own words, rather than in registers, which the
+  // register sums need
+  __shared__ double dsum[5][FUSED_THREADS];
+  static_assert(FUSED_THREADS <= 256, "static LDS bound");
+#pragma unroll
+  for (int k = 0; k < 5; ++k) dsum[k][threadIdx.x] = 0.0;
   A a_cells = A(0);
   unsigned long long n_fb = 0;
 
@@ -374,8 +382,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         if (lane == leader) base = atomicAdd(defer_count, (uint32_t)__popcll(dm));
         base = __shfl(base, leader, 64);
         if (deferred) {
-          defer_list[2 * (base + __popcll(dm & wl.below))] = i;
-          defer_list[2 * (base + __popcll(dm & wl.below)) + 1] = si;
+          defer_list[2 * (base + lanes_below(dm))] = i;
+          defer_list[2 * (base + lanes_below(dm)) + 1] = si;
         }
       }
     }
@@ -393,7 +401,9 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
     const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;   // inside the window
 
-    const bool home = idx[0] == mycell[0] && idx[1] == mycell[1] && (c2 == 0 || idx[2] == mycell[2]);
+    // cell of the particle relative to this thread's cell
+    const int sx = idx[0] - mycell[0], sy = idx[1] - mycell[1], sz = c2 ? idx[2] - mycell[2] : 0;
+    const bool near = sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1 && sz >= -1 && sz <= 1;
     // Gather (Eq. Delta_vp) in slip form: the weights sum to one, so the
     // slip p_g - p is sc * sum_i W_i (v_i - u) with u = p / sc the particle's
     // physical velocity.  Each v_i - u is exact or nearly so when the gas
@@ -463,19 +473,85 @@ __global__ void __launch_bounds__(FUSED_THREADS)
           cps = fabs(vbar * dt / dl);
         }
         a_cells = cps > a_cells ? cps : a_cells;
-        s_j[k] -= double(q[k]);
-        s_abs += fabs(double(q[k]));
       }
       mom[k] += o.dp[k];
     }
     q[nc] = live ? -m * o.e : A(0);
-    if (sums) s_e -= double(q[nc]);
-    // deposit (same weights and cells as the gather): register sums for a
-    // particle still in this thread's cell (zero otherwise), unconditionally
+    if (sums && live) {
+      double ab = 0.0;
+#pragma unroll
+      for (int k = 0; k < nc; ++k) {
+        atomicAdd(&dsum[k][threadIdx.x], -double(q[k]));
+        ab += fabs(double(q[k]));
+      }
+      atomicAdd(&dsum[3][threadIdx.x], -double(q[nc]));
+      atomicAdd(&dsum[4][threadIdx.x], ab);
+    }
+    // Deposit (same weights and cells as the gather).  The register sums
+    // cover the 27 cells around this thread's cell.  A particle in that cell
+    // or a neighbour (sx, sy, sz in -1..1) adds the part of its stencil that
+    // falls inside them to the register sums, through its weights shifted by
+    // (sx, sy, sz); the rest, one 3x3 plane per axis it moved along, goes to
+    // the window with FP64 LDS atomics.  A particle further away (stale bins)
+    // deposits its whole stencil with LDS atomics.
     {
+      const int base = la + RX * (lb + RY * lc);
+      auto lds_add = [&](int a, int bb, int c, double w) {
+        const int r0 = base + a + RX * (bb + RY * c);
+#pragma unroll
+        for (int k = 0; k <= nc; ++k) atomicAdd(&dep[k * RC + r0], w * double(q[k]));
+      };
+      if (live && !near) {
+#pragma unroll
+        for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+          for (int bb = -1; bb <= 1; ++bb) {
+            const double wbc = double(s.w[1][bb + 1] * s.w[2][c + 1]);
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) lds_add(a, bb, c, double(s.w[0][a + 1]) * wbc);
+          }
+      }
+      // spill planes: particle-relative row sy (all a, c); column sx (rows
+      // other than sy); layer sz (the cells in neither)
+      if (live && near && sy != 0) {
+        const A wy = sy > 0 ? s.w[1][2] : s.w[1][0];
+#pragma unroll
+        for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) lds_add(a, sy, c, double(s.w[0][a + 1] * wy * s.w[2][c + 1]));
+      }
+      if (live && near && sx != 0) {
+        const A wx = sx > 0 ? s.w[0][2] : s.w[0][0];
+#pragma unroll
+        for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+          for (int bb = -1; bb <= 1; ++bb)
+            if (sy == 0 || bb != sy) lds_add(sx, bb, c, double(wx * s.w[1][bb + 1] * s.w[2][c + 1]));
+      }
+      if (c2 && live && near && sz != 0) {
+        const A wz = sz > 0 ? s.w[2][2] : s.w[2][0];
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a)
+            if ((sy == 0 || bb != sy) && (sx == 0 || a != sx))
+              lds_add(a, bb, sz, double(s.w[0][a + 1] * s.w[1][bb + 1] * wz));
+      }
+    }
+    {
+      // weights shifted to this thread's cell (zero where the stencil leaves
+      // its 27 cells), in place: w'[m] = w[m - s]
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int sd = d == 0 ? sx : d == 1 ? sy : sz;
+        const A w0 = s.w[d][0], w1 = s.w[d][1], w2 = s.w[d][2];
+        s.w[d][0] = sd == 0 ? w0 : sd < 0 ? w1 : A(0);
+        s.w[d][1] = sd == 0 ? w1 : sd < 0 ? w2 : w0;
+        s.w[d][2] = sd == 0 ? w2 : sd < 0 ? A(0) : w1;
+      }
       TAcc qf[4], wa[3];
 #pragma unroll
-      for (int k = 0; k <= nc; ++k) qf[k] = home ? TAcc(q[k]) : TAcc(0);
+      for (int k = 0; k <= nc; ++k) qf[k] = live && near ? TAcc(q[k]) : TAcc(0);
 #pragma unroll
       for (int a = 0; a < 3; ++a) wa[a] = TAcc(s.w[0][a]);
 #pragma unroll
@@ -491,22 +567,6 @@ __global__ void __launch_bounds__(FUSED_THREADS)
             const int oo = (a + 1) + 3 * ((bb + 1) + 3 * (c + c2));
 #pragma unroll
             for (int k = 0; k <= nc; ++k) acc[oo][k] += wa[a + 1] * qb[k];
-          }
-        }
-    }
-    if (live && !home) {
-      const int base = la + RX * (lb + RY * lc);
-#pragma unroll
-      for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-        for (int bb = -1; bb <= 1; ++bb) {
-          const double wbc = double(s.w[1][bb + 1] * s.w[2][c + 1]);
-#pragma unroll
-          for (int a = -1; a <= 1; ++a) {
-            const double w = double(s.w[0][a + 1]) * wbc;
-            const int r0 = base + a + RX * (bb + RY * c);
-#pragma unroll
-            for (int k = 0; k <= nc; ++k) atomicAdd(&dep[k * RC + r0], w * double(q[k]));
           }
         }
     }
@@ -570,6 +630,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   if (dg) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double s_cells = double(a_cells);
+    double s_j[3] = {dsum[0][threadIdx.x], dsum[1][threadIdx.x], dsum[2][threadIdx.x]};
+    double s_e = dsum[3][threadIdx.x], s_abs = dsum[4][threadIdx.x];
     if (sums) {
       for (int k = 0; k < 3; ++k) s_j[k] = wave_sum(s_j[k]);
       s_e = wave_sum(s_e);
