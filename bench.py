@@ -105,16 +105,18 @@ def summarize_trace(run_dir: str, out: str, command: str):
     import sqlite3
     con = sqlite3.connect(_rocpd(run_dir))
     agg = collections.defaultdict(list)
-    for name, t0, t1 in con.execute("select name, start, end from kernels"):
+    for name, t0, t1 in con.execute("select name, start, end from kernels order by start"):
         agg[_short(name)].append((t1 - t0) * 1e-3)
     tot = sum(sum(v) for v in agg.values())
-    lines = ["# rocprofv3 kernel trace summary (durations in microseconds)",
+    lines = ["# rocprofv3 kernel trace summary (durations in microseconds; avg_warm_us leaves",
+             "# out each kernel's first, cold launch)",
              f"# command: {command}", "",
-             f"{'kernel':64s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} {'min_us':>9s} "
-             f"{'max_us':>9s} {'pct':>6s}"]
+             f"{'kernel':64s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} {'avg_warm_us':>11s} "
+             f"{'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
     for nm, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        warm = v[1:] if len(v) > 1 else v
         lines.append(f"{nm[:64]:64s} {len(v):6d} {sum(v) / 1e3:9.3f} {sum(v) / len(v):9.2f} "
-                     f"{min(v):9.2f} {max(v):9.2f} {100 * sum(v) / tot:6.2f}")
+                     f"{sum(warm) / len(warm):11.2f} {min(v):9.2f} {max(v):9.2f} {100 * sum(v) / tot:6.2f}")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -132,8 +134,8 @@ def _counter_per_dispatch(run_dir: str, counter: str):
         per[di] += val
         names[di] = _short(name)
     out = collections.defaultdict(list)
-    for di, v in per.items():
-        out[names[di]].append(v)
+    for di in sorted(per):
+        out[names[di]].append(per[di])
     return out
 
 
@@ -151,8 +153,14 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
     cf = max(max(v) for k, v in fetch.items() if is_copy(k))
     cw = max(max(v) for k, v in write.items() if is_copy(k))
     f_fetch, f_write = copy_kib / cf, copy_kib / cw
-    kf = [sum(v) / len(v) for k, v in fetch.items() if FUSED_KERNEL in k]
-    kw = [sum(v) / len(v) for k, v in write.items() if FUSED_KERNEL in k]
+    # mean over the fused dispatches after the first (cold) one
+    def warm_mean(v):
+        w = v[1:] if len(v) > 1 else v
+        return sum(w) / len(w), len(w)
+    kf = [warm_mean(v) for k, v in fetch.items() if FUSED_KERNEL + "<" in k]
+    kw = [warm_mean(v) for k, v in write.items() if FUSED_KERNEL + "<" in k]
+    (kf, nfd), (kw, nwd) = kf[0], kw[0]
+    kf, kw = [kf], [kw]
     fb = kf[0] * f_fetch * 1024.0
     wb = kw[0] * f_write * 1024.0
     lines = ["# HBM bytes of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per",
@@ -166,6 +174,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
              f"copy_write_kib_counted: {cw:.1f}",
              f"fetch_scale: {f_fetch:.4f}",
              f"write_scale: {f_write:.4f}",
+             f"fused_dispatches_averaged: {nfd} (FETCH), {nwd} (WRITE); the first, cold one left out",
              f"fused_fetch_kib_counted: {kf[0]:.1f}",
              f"fused_write_kib_counted: {kw[0]:.1f}",
              f"fused_fetch_bytes: {fb:.4g}",

@@ -214,8 +214,9 @@ dust_status_t dust_ctx_autotune(void *ctx, const dust_particles_t *p, const dust
 
 /* Kernel timing of the fused path: with max_launches > 0, every dust_step
  * call records a pair of HIP events on its stream around each of its first
- * max_launches fused-kernel launches (also inside a captured graph, as event
- * nodes); dust_ctx_profile then returns, after synchronising, the elapsed
+ * max_launches fused tile-kernel launches (the tile kernel alone, not the
+ * deferred-particle kernel that follows it; also inside a captured graph,
+ * as event nodes); dust_ctx_profile then returns, after synchronising, the elapsed
  * milliseconds of the launches of the last dust_step call (count_out of
  * them, at most max_out).  max_launches = 0 turns it off. */
 dust_status_t dust_ctx_set_profile(void *ctx, int32_t max_launches);

@@ -506,16 +506,15 @@ dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const F
   if (!(flags & DUST_STEP_NO_FILL))
     for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
   launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
-  bool prof = c->prof_used < c->prof_max;
-  if (prof) HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used], st));
+  const bool prof = c->prof_used < c->prof_max;
+  hipEvent_t ev0 = prof ? c->prof_ev[2 * c->prof_used] : nullptr;
+  hipEvent_t ev1 = prof ? c->prof_ev[2 * c->prof_used + 1] : nullptr;
   launch_fused<TS, A>(c->plan, x, out, mv != STEP_IN_PLACE, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif,
                       fv, F, c->species_d, c->drag_mode, dt, c->tdev, c->bin_start,
                       (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr, src_index,
-                      st);
-  if (prof) {
-    HIP_TRY(hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st));
-    ++c->prof_used;
-  }
+                      ev0, ev1, st);
+  HIP_TRY(hipGetLastError());
+  if (prof) ++c->prof_used;
   if (dg)
     for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, c->grid_part, st);
   for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);

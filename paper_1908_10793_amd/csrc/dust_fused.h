@@ -46,13 +46,14 @@ static constexpr size_t FUSED_STATIC_LDS = 5 * 256 * sizeof(double) + 3 * DUST_M
 // slot s of q receives the update of particle src_index[s] of p, or of
 // particle s when src_index is null (then q may be p: in place); copy_attrs
 // copies drag / mass / species / id along.  xg: the context's FP64 x-ghost
-// gas layers (filled this step), or null.
+// gas layers (filled this step), or null.  ev0 / ev1 (nullable) are recorded
+// around the tile kernel alone (not the deferred-particle kernel).
 template <typename TS, typename A>
 void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q, bool copy_attrs,
                   const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
                   const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
-                  const uint32_t* src_index, hipStream_t st);
+                  const uint32_t* src_index, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
 
 // Keys (tile-major) of the cells the particles reach in the first half drift
 // of a step of length dt starting at *tdev.

@@ -755,10 +755,15 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
       A v[3] = {A(0), A(0), A(0)};
+      // (unrolled: the stencil's global loads are issued together)
+#pragma unroll
       for (int c = -c2; c <= c2; ++c)
+#pragma unroll
         for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
           for (int a = -1; a <= 1; ++a) {
             const A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
             for (int m = 0; m < nc; ++m)
               v[m] += w * A(gas_comp(B, fl, xg, m, idx[0] + a, idx[1] + bb, idx[2] + c) - double(up[m]));
           }
@@ -790,12 +795,16 @@ __global__ void __launch_bounds__(256)
       }
       q[nc] = -m * o.e;
       if (sums) s_e -= double(q[nc]);
+#pragma unroll
       for (int cc = -c2; cc <= c2; ++cc)
+#pragma unroll
         for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
           for (int a = -1; a <= 1; ++a) {
             const int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + cc;
             const A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][cc + 1] * A(inv_volume(B, ii, jj, kk));
             const int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
             for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(w * q[k]));
           }
       alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
@@ -863,7 +872,8 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
                            double dt, const double* tdev, const int64_t* bin_start, const double* xg,
                            DiagDev* dg, double* part, bool sums, uint32_t* defer_list,
                            uint32_t* defer_count, const uint32_t* src_index, int nbox,
-                           hipStream_t st) {
+                           hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
+  if (ev0) (void)hipEventRecord(ev0, st);   // the tile kernel alone is timed
 #define DUST_F(TX, TY, TZ)                                                                         \
   launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
                                                    drag_mode, dt, tdev,                            \
@@ -886,6 +896,7 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
     }
   }
 #undef DUST_F
+  if (ev1) (void)hipEventRecord(ev1, st);
   hipLaunchKernelGGL((k_fused_deferred<TS, A, GEOM, NDIM, U>), dim3(DEFER_BLOCKS), dim3(256), 0, st, p, q,
                      (int)copy_attrs, boxes_d, nbox, fl, f, sp, drag_mode, A(dt), tdev, xg,
                      (const uint32_t*)defer_list, (const uint32_t*)defer_count, part, plan.ntiles, (int)sums);
@@ -896,14 +907,14 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                   const Box* boxes_d, int nbox, int geom, int ndim, int unif, const FView<TS>& fl,
                   const Forces& f, const Species* sp, int drag_mode, double dt, const double* tdev,
                   const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
-                  const uint32_t* src_index, hipStream_t st) {
+                  const uint32_t* src_index, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   if (plan.ntiles == 0) return;
   double* part = plan.part_d;
   hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, st, plan.defer_count);
 #define DUST_G(G, D, UU)                                                                          \
   launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
                                   bin_start, xg, dg, part, sums, plan.defer_list,                  \
-                                  plan.defer_count, src_index, nbox, st)
+                                  plan.defer_count, src_index, nbox, ev0, ev1, st)
   if (geom == GEOM_CART && ndim == 2 && unif) DUST_G(GEOM_CART, 2, true);
   else if (geom == GEOM_CART && ndim == 2) DUST_G(GEOM_CART, 2, false);
   else if (geom == GEOM_CART && unif) DUST_G(GEOM_CART, 3, true);
@@ -1068,7 +1079,7 @@ void launch_copy_particles(const PView<TS>& src, const PView<TS>& dst, hipStream
                                     const Box*, int, int, int, int, const FView<TS>&,              \
                                     const Forces&, const Species*, int, double, const double*,     \
                                     const int64_t*, const double*, DiagDev*, bool, const uint32_t*, \
-                                    hipStream_t);                                                  \
+                                    hipEvent_t, hipEvent_t, hipStream_t);                          \
   template void launch_halfstep_keys<TS, A>(const PView<TS>&, const Box*, int, int, int, int,       \
                                             const Forces&, double, const double*, int64_t,         \
                                             TileShape, uint32_t*, hipStream_t);
