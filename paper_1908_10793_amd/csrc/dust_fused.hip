@@ -755,18 +755,35 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
       A v[3] = {A(0), A(0), A(0)};
-      // (unrolled: the stencil's global loads are issued together)
+      // The stencil's field values are loaded unconditionally, so that the
+      // loads issue together; x ghosts of a shear-periodic box then take the
+      // FP64 ghost layer's value (a rare branch).
+      const bool xghost = xg && B.xg_base >= 0 && (idx[0] <= 0 || idx[0] >= B.ax[0].n - 1);
 #pragma unroll
       for (int c = -c2; c <= c2; ++c)
 #pragma unroll
-        for (int bb = -1; bb <= 1; ++bb)
+        for (int bb = -1; bb <= 1; ++bb) {
+          double g[3][3];
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            const int64_t id = stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + c);
+#pragma unroll
+            for (int m = 0; m < nc; ++m) g[a + 1][m] = double(fl.vel[m][id]);
+          }
+          if (xghost) {
+#pragma unroll
+            for (int a = -1; a <= 1; ++a)
+#pragma unroll
+              for (int m = 0; m < nc; ++m)
+                g[a + 1][m] = gas_comp(B, fl, xg, m, idx[0] + a, idx[1] + bb, idx[2] + c);
+          }
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
             const A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1];
 #pragma unroll
-            for (int m = 0; m < nc; ++m)
-              v[m] += w * A(gas_comp(B, fl, xg, m, idx[0] + a, idx[1] + bb, idx[2] + c) - double(up[m]));
+            for (int m = 0; m < nc; ++m) v[m] += w * A(g[a + 1][m] - double(up[m]));
           }
+        }
       A sl[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
