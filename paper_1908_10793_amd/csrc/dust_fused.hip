@@ -186,20 +186,29 @@ __device__ __forceinline__ uint32_t level_slot(const WaveLevels& w, int j, uint3
   return s;
 }
 
-// Raw stored state of one particle (prefetched one particle ahead).
+// Raw stored state of one particle (prefetched one particle ahead), with the
+// attributes the kick reads (species, mass, drag: each only if present) and,
+// when the attributes are copied to another buffer, the id: no load of the
+// loop's body waits on memory.
 template <typename TS> struct Raw {
   int32_t cell;
   TS off[3], mom[3];
+  int32_t species, id;
+  TS mass, drag;
 };
 
 template <typename TS, int NDIM, int NC>
-__device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>& r) {
+__device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>& r, bool with_id) {
+  r.id = with_id && p.id ? p.id[i] : 0;
   r.cell = p.cell[i];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     r.off[d] = d < NDIM ? p.off[d][i] : TS(0);
     r.mom[d] = d < NC ? p.mom[d][i] : TS(0);
   }
+  r.species = p.species ? (int32_t)p.species[i] : 0;
+  r.mass = p.mass ? p.mass[i] : TS(0);
+  r.drag = p.drag ? p.drag[i] : TS(1);
 }
 
 // Register budget: the FP32 kernel needs about 250 VGPRs (108 of them the
@@ -323,7 +332,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   uint32_t nxt_si = 0;
   if (wl.cnt > 0) {
     nxt_si = src_index ? src_index[slot] : slot;
-    load_raw<TS, NDIM, nc>(p, nxt_si, nxt);
+    load_raw<TS, NDIM, nc>(p, nxt_si, nxt, copy_attrs);
   }
   for (int j = 0; j < wl.nlev; ++j) {
     const bool has = wl.cnt > j;
@@ -333,7 +342,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     slot = level_slot(wl, j + 1, lvl);
     if (wl.cnt > j + 1) {          // prefetch the next particle
       nxt_si = src_index ? src_index[slot] : slot;
-      load_raw<TS, NDIM, nc>(p, nxt_si, nxt);
+      load_raw<TS, NDIM, nc>(p, nxt_si, nxt, copy_attrs);
     }
     // Lanes of one wave walk different cells, so nothing below branches
     // around the register sums: a particle without a cell, or one that left
@@ -443,18 +452,18 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     A sl[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
-    int spc = p.species && live ? p.species[si] : 0;
+    int spc = live ? cur.species : 0;
     if (spc >= sp->n) {
       flag(dg, DUST_FLAG_BAD_CELL);
       spc = 0;
     }
-    A m = p.mass && live ? A(p.mass[si]) : sp_m[spc];
+    A m = p.mass && live ? A(cur.mass) : sp_m[spc];
     A c, psi;
     if (drag_mode == DRAG_SPECIES) {
       c = sp_c[spc];
       psi = sp_psi[spc];
     } else {
-      A it = inverse_tau<A, GEOM>(f, drag_mode, live ? A(p.drag[si]) : A(1), A(0), wh);
+      A it = inverse_tau<A, GEOM>(f, drag_mode, live ? A(cur.drag) : A(1), A(0), wh);
       propagator<A>(dt * it, c, psi);
     }
     KickOut<A> o;
@@ -585,10 +594,10 @@ __global__ void __launch_bounds__(FUSED_THREADS)
           if (d < nc) dst.mom[d][i] = cur.mom[d];
         }
       }
-      if (p.drag) dst.drag[i] = p.drag[si];
-      if (p.mass) dst.mass[i] = p.mass[si];
-      if (p.species) dst.species[i] = p.species[si];
-      if (p.id) dst.id[i] = p.id[si];
+      if (p.drag) dst.drag[i] = cur.drag;
+      if (p.mass) dst.mass[i] = cur.mass;
+      if (p.species) dst.species[i] = (uint8_t)cur.species;
+      if (p.id) dst.id[i] = cur.id;
     }
   }
 
