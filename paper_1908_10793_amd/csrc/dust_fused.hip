@@ -326,24 +326,29 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   // cell's j-th particle, and those particles are consecutive slots, so the
   // loads and stores of an iteration are contiguous.
   const WaveLevels wl = wave_levels(own ? (int)(pe - ps) : 0, ps);
+  // The particle state is loaded one level ahead of its use, its source
+  // index (after a rebinning) two levels ahead.
   uint32_t lvl = wl.base;
   uint32_t slot = level_slot(wl, 0, lvl);
+  uint32_t slot_b = level_slot(wl, 1, lvl);
   Raw<TS> nxt;
-  uint32_t nxt_si = 0;
+  uint32_t nxt_si = 0, si_b = slot_b;
   if (wl.cnt > 0) {
     nxt_si = src_index ? src_index[slot] : slot;
     load_raw<TS, NDIM, nc>(p, nxt_si, nxt, copy_attrs);
   }
+  if (src_index && wl.cnt > 1) si_b = src_index[slot_b];
   for (int j = 0; j < wl.nlev; ++j) {
     const bool has = wl.cnt > j;
     const uint32_t i = slot;       // slot written
     const uint32_t si = nxt_si;    // particle read
     const Raw<TS> cur = nxt;
-    slot = level_slot(wl, j + 1, lvl);
-    if (wl.cnt > j + 1) {          // prefetch the next particle
-      nxt_si = src_index ? src_index[slot] : slot;
-      load_raw<TS, NDIM, nc>(p, nxt_si, nxt, copy_attrs);
-    }
+    slot = slot_b;
+    nxt_si = si_b;
+    slot_b = level_slot(wl, j + 2, lvl);
+    if (wl.cnt > j + 1) load_raw<TS, NDIM, nc>(p, nxt_si, nxt, copy_attrs);   // next particle
+    si_b = slot_b;
+    if (src_index && wl.cnt > j + 2) si_b = src_index[slot_b];               // and the index after
     // Lanes of one wave walk different cells, so nothing below branches
     // around the register sums: a particle without a cell, or one that left
     // through an open face, continues as a dummy at the centre of this
