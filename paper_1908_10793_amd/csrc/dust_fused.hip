@@ -156,6 +156,26 @@ template <> struct Vec4<double> {
 // slots.  Level j of the range holds the j-th particle of every cell that has
 // more than j, in lane order; the slot of lane l in level j is the level's
 // start plus the number of lower lanes whose cells have more than j.
+// Periodic axes in the tile window: the window holds the periodic images of
+// the cells beyond the box (not the ghost layer), and a particle that
+// crossed a periodic face since the binning is placed at its image next to
+// the window, so it stays with its tile.  win_coord: window coordinate of
+// cell i along an axis whose window starts at o (R cells), the periodic
+// image inside the window's interior [1, R-2] when one lies within a box
+// length (a particle further away is deferred).
+__device__ __forceinline__ int win_coord(int i, int o, int n, int R, bool periodic) {
+  int l = i - o;
+  if (periodic) l += l < 1 ? n : l > R - 2 ? -n : 0;
+  return l;
+}
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+__device__ __forceinline__ bool axis_periodic(const Axis& ax) {
+  return ax.bc_lo == BC_PERIODIC && ax.bc_hi == BC_PERIODIC;
+}
+
 // Set bits of a wave mask in the lanes below this one.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -264,10 +284,15 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   const A h = A(0.5) * dt;
   const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = NDIM > 2 ? B.ax[2].n : 1;
 
-  // stage the gas window, clear the deposit window
+  const bool per0 = axis_periodic(B.ax[0]), per1 = axis_periodic(B.ax[1]);
+  const bool per2 = NDIM > 2 && axis_periodic(B.ax[2]);
+  // stage the gas window (periodic images beyond the box), clear the deposit window
   for (int r = threadIdx.x; r < RC; r += FUSED_THREADS) {
     int a = r % RX, bq = (r / RX) % RY, cq = r / (RX * RY);
     int i = ox + a, j = oy + bq, k = oz + cq;
+    if (per0) i = wrap_index(i, n0);
+    if (per1) j = wrap_index(j, n1);
+    if (per2) k = wrap_index(k, n2);
     bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && (NDIM < 3 || (k >= -1 && k <= n2));
     int64_t id = in ? stored_index(B, i, j, k) : 0;
     TS gv[3] = {TS(0), TS(0), TS(0)};
@@ -382,8 +407,12 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // deferred kernel, which does its step against global memory; here it
     // continues as a dummy.
     bool deferred = false;
+    // window coordinates (this thread's cell for a dummy)
+    int la = lx + H, lb = ly + H, lc = c2 ? lz + HZ : 0;
     if (live) {
-      const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;
+      la = win_coord(idx[0], ox, n0, RX, per0);
+      lb = win_coord(idx[1], oy, n1, RY, per1);
+      lc = c2 ? win_coord(idx[2], oz, n2, RZ, per2) : 0;
       deferred = !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
                    (c2 == 0 || (lc >= 1 && lc <= RZ - 2)));
     }
@@ -409,14 +438,15 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         off[d] = A(0);
         mom[d] = A(0);
       }
+      la = lx + H;
+      lb = ly + H;
+      lc = c2 ? lz + HZ : 0;
     }
     // weights at x^{n+1/2}
     Stencil<A> s;
     stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
-    const int la = idx[0] - ox, lb = idx[1] - oy, lc = idx[2] - oz;   // inside the window
-
     // cell of the particle relative to this thread's cell
-    const int sx = idx[0] - mycell[0], sy = idx[1] - mycell[1], sz = c2 ? idx[2] - mycell[2] : 0;
+    const int sx = la - (lx + H), sy = lb - (ly + H), sz = c2 ? lc - (lz + HZ) : 0;
     const bool near = sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1 && sz >= -1 && sz <= 1;
     // Gather (Eq. Delta_vp) in slip form: the weights sum to one, so the
     // slip p_g - p is sc * sum_i W_i (v_i - u) with u = p / sc the particle's
@@ -623,10 +653,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   }
   __syncthreads();
 
-  // add the deposit window to the grid
+  // add the deposit window to the grid (periodic images to their cells)
   for (int r = threadIdx.x; r < RC; r += FUSED_THREADS) {
     int a = r % RX, bq = (r / RX) % RY, cq = r / (RX * RY);
     int i = ox + a, j = oy + bq, k = oz + cq;
+    if (per0) i = wrap_index(i, n0);
+    if (per1) j = wrap_index(j, n1);
+    if (per2) k = wrap_index(k, n2);
     bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && (NDIM < 3 || (k >= -1 && k <= n2));
     if (!in) continue;
     int64_t id = stored_index(B, i, j, k);
