@@ -25,7 +25,7 @@
 enum { G_CART = 0, G_CYL = 1, G_SPH = 2 };
 enum { BC_PERIODIC = 0, BC_SHEAR = 1, BC_OPEN = 2 };
 enum { SH_CIC = 0, SH_TSC = 1 };
-enum { F_NONE = 0, F_SHEARBOX = 1, F_POINTMASS = 2, F_CONST = 3 };
+enum { F_NONE = 0, F_SHEARBOX = 1, F_POINTMASS = 2, F_CONST = 3, F_SHEARBOX_FARGO = 4 };
 enum { DRAG_TAU = 0, DRAG_STOKES = 1 };
 
 typedef struct {
@@ -380,14 +380,17 @@ void orc_fill_ghosts(const orc_box *b, const orc_forces *f, double t, orc_fields
   int nc = b->ndim;
   fill_ghosts_one(b, f, t, fl->rho, 0);
   for (int c = 0; c < nc; ++c)
-    fill_ghosts_one(b, f, t, fl->vel[c], b->geom == G_CART && c == 1 && b->bc_lo[0] == BC_SHEAR);
+    fill_ghosts_one(b, f, t, fl->vel[c], b->geom == G_CART && c == 1 && b->bc_lo[0] == BC_SHEAR &&
+                                             f->kind == F_SHEARBOX);
 }
 
 /* Fold deposits made into periodic / shear-periodic ghosts back onto their
  * partners: the exact transpose of the fill, applied in the reverse axis
  * order, then zero those ghosts.  The energy channel crossing a shear face
  * gains u * D_y, the work of the momentum change in the partner's frame
- * (reading: the gas kinetic energy differs by the boost u = q Omega L_x). */
+ * (reading: the gas kinetic energy differs by the boost u = q Omega L_x).
+ * With orbital advection (Eq. FARGO_SB_p) velocities are residuals, which
+ * carry no boost across the face: no energy term. */
 void orc_fold_ghosts(const orc_box *b, const orc_forces *f, double t, orc_fields *fl) {
   int nc = b->ndim;
   int n0 = b->n[0], n1 = b->n[1], n2 = b->ndim > 2 ? b->n[2] : 1;
@@ -412,7 +415,7 @@ void orc_fold_ghosts(const orc_box *b, const orc_forces *f, double t, orc_fields
   }
   if (b->bc_lo[0] == BC_SHEAR) {
     double s = shear_cells(b, f, t);
-    double u = f->q * f->Omega * (b->faces[0][n0] - b->faces[0][0]);
+    double u = f->kind == F_SHEARBOX ? f->q * f->Omega * (b->faces[0][n0] - b->faces[0][0]) : 0.0;
     double *dy = fl->dep[1];
     for (int k = 0; k < n2; ++k)
       for (int j = 0; j < n1; ++j) {
@@ -455,8 +458,9 @@ void orc_fold_ghosts(const orc_box *b, const orc_forces *f, double t, orc_fields
 /* Particle boundary handling after a drift.                            */
 
 /* Bring x back into the domain at time t: periodic images, the
- * shear-periodic image (x -/+ L_x, y +/- q Omega L_x t, v_y +/- q Omega L_x)
- * and removal through open faces (reading; the paper removes particles that
+ * shear-periodic image (x -/+ L_x, y +/- q Omega L_x t, v_y +/- q Omega L_x;
+ * with orbital advection the residual v_y is continuous: no boost) and
+ * removal through open faces (reading; the paper removes particles that
  * leave a global disk). Returns 0 if the particle was removed. */
 static int wrap_particle(const orc_box *b, const orc_forces *f, double t, double x[3],
                          double p[3]) {
@@ -468,9 +472,9 @@ static int wrap_particle(const orc_box *b, const orc_forces *f, double t, double
     if (bc == BC_OPEN) return 0;
     if (bc == BC_SHEAR) {
       double u = f->q * f->Omega * L;
-      double sy = u * t;
-      while (x[0] >= hi) { x[0] -= L; x[1] += sy; p[1] += u; }
-      while (x[0] < lo) { x[0] += L; x[1] -= sy; p[1] -= u; }
+      double sy = u * t, boost = f->kind == F_SHEARBOX ? u : 0.0;
+      while (x[0] >= hi) { x[0] -= L; x[1] += sy; p[1] += boost; }
+      while (x[0] < lo) { x[0] += L; x[1] -= sy; p[1] -= boost; }
     } else {
       double r = fmod(x[d] - lo, L);
       if (r < 0) r += L;
@@ -487,8 +491,16 @@ static int wrap_particle(const orc_box *b, const orc_forces *f, double t, double
 /* radius (and theta) already advanced to n+1/2; in the second drift all  */
 /* metric factors are those of level n+1/2, frozen before the update.     */
 
-static void drift_first(int geom, double h, double x[3], const double p[3]) {
-  if (geom == G_CART) {
+/* Orbital advection (Eq. FARGO_SB_p): p holds the residual velocity v' and
+ * y is also carried by the mean shear -q Omega x; reading: the shear term
+ * takes x^{n+1/2}, so x moves first in the first drift and last in the
+ * second (as the radius does in the curvilinear drifts). */
+static void drift_first(int geom, const orc_forces *f, double h, double x[3], const double p[3]) {
+  if (geom == G_CART && f->kind == F_SHEARBOX_FARGO) {
+    x[0] += h * p[0];
+    x[1] += h * (p[1] - f->q * f->Omega * x[0]);
+    x[2] += h * p[2];
+  } else if (geom == G_CART) {
     for (int d = 0; d < 3; ++d) x[d] += h * p[d];
   } else if (geom == G_CYL) {
     x[0] += h * p[0];
@@ -502,8 +514,12 @@ static void drift_first(int geom, double h, double x[3], const double p[3]) {
   }
 }
 
-static void drift_second(int geom, double h, double x[3], const double p[3]) {
-  if (geom == G_CART) {
+static void drift_second(int geom, const orc_forces *f, double h, double x[3], const double p[3]) {
+  if (geom == G_CART && f->kind == F_SHEARBOX_FARGO) {
+    x[1] += h * (p[1] - f->q * f->Omega * x[0]);
+    x[0] += h * p[0];
+    x[2] += h * p[2];
+  } else if (geom == G_CART) {
     for (int d = 0; d < 3; ++d) x[d] += h * p[d];
   } else if (geom == G_CYL) {
     double R = x[0];
@@ -536,6 +552,28 @@ static void kick(int geom, int ndim, const orc_forces *f, double dt, double inv_
   int nc = geom == G_CART ? ndim : 3;
   double p0[3] = {p[0], p[1], p[2]};
 
+  if (geom == G_CART && f->kind == F_SHEARBOX_FARGO) {
+    /* Orbital advection (App. B.1, Eq. FARGO_SB_exp_midpoint): residual
+     * velocities, G(x, v', v'_g) = (2 Omega v'_y, (q - 2) Omega v'_x,
+     * -Omega^2 z) + v'_g/tau, kick taken with v' = (v'^n + v'^{n+1})/2:
+     * the 2x2 block solved by Cramer's rule. */
+    double Om = f->Omega, q = f->q;
+    double gz = f->vertical_gravity ? -Om * Om * x[2] : 0.0;
+    /* row x: v'_x - h1 Om v'_y = e v_x + h1 Om v_y + c vg_x */
+    double a00 = 1.0, a01 = -h1 * Om, r0 = e * p0[0] + h1 * Om * p0[1] + c * pg[0];
+    /* row y: v'_y - h1 (q-2) Om v'_x / 2 = e v_y + h1 (q-2) Om v_x / 2 + c vg_y */
+    double a10 = -0.5 * h1 * (q - 2.0) * Om, a11 = 1.0;
+    double r1 = e * p0[1] + 0.5 * h1 * (q - 2.0) * Om * p0[0] + c * pg[1];
+    double det = a00 * a11 - a01 * a10;
+    p[0] = (r0 * a11 - a01 * r1) / det;
+    p[1] = (a00 * r1 - a10 * r0) / det;
+    p[2] = e * p0[2] + h1 * gz + c * pg[2];
+    double vbx = 0.5 * (p0[0] + p[0]), vby = 0.5 * (p0[1] + p[1]);
+    a[0] = 2.0 * Om * vby;
+    a[1] = (q - 2.0) * Om * vbx;
+    a[2] = gz;
+    return;
+  }
   if (geom == G_CART && f->kind == F_SHEARBOX) {
     /* G(x, v, v_g) = (2 Omega (v_y + q Omega x), -2 Omega v_x,
      * -Omega^2 z) + v_g/tau, kick taken with v = (v^n + v^{n+1})/2: solve
@@ -732,7 +770,7 @@ int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles
     double x[3], p[3], p0[3];
     for (int d = 0; d < 3; ++d) { x[d] = P->x[d][ip]; p[d] = P->p[d][ip]; }
     /* drift by dt/2 to x^{n+1/2} */
-    drift_first(b->geom, h, x, p);
+    drift_first(b->geom, f, h, x, p);
     if (!wrap_particle(b, f, th, x, p)) {
       P->active[ip] = 0;
       for (int d = 0; d < 3; ++d) { P->x[d][ip] = x[d]; P->p[d][ip] = p[d]; }
@@ -771,7 +809,7 @@ int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles
       if (cps > dg->max_cells_per_step) dg->max_cells_per_step = cps;
     }
     /* drift by dt/2 to x^{n+1} */
-    drift_second(b->geom, h, x, p);
+    drift_second(b->geom, f, h, x, p);
     if (!wrap_particle(b, f, t + dt, x, p)) P->active[ip] = 0;
     for (int d = 0; d < 3; ++d) { P->x[d][ip] = x[d]; P->p[d][ip] = p[d]; }
   }
@@ -817,13 +855,13 @@ typedef void (*orc_gas_fn)(const double *x, double *vg);
 void orc_push_one(int geom, int ndim, const orc_forces *f, int drag_mode, double dragval,
                   double dt, double *x, double *p, orc_gas_fn gas, double *a_out) {
   double vg[3] = {0, 0, 0}, pg[3], sc[3];
-  drift_first(geom, 0.5 * dt, x, p);
+  drift_first(geom, f, 0.5 * dt, x, p);
   if (gas) gas(x, vg);
   canon_scale(geom, x, sc);
   for (int m = 0; m < 3; ++m) pg[m] = vg[m] * sc[m];
   double it = inverse_tau(geom, drag_mode, f, dragval, x);
   kick(geom, ndim, f, dt, it, x, p, pg, a_out);
-  drift_second(geom, 0.5 * dt, x, p);
+  drift_second(geom, f, 0.5 * dt, x, p);
 }
 
 /* ------------------------------------------------------------------ */

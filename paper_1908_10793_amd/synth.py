@@ -125,12 +125,14 @@ def cart2d_periodic(n=(64, 64), ppc=16, tau=0.1, dt=0.01, nsteps=10, dtype="f64"
 
 
 def shearing_box(n=(128, 128, 128), L=2.0, Omega=1.0, q=1.5, tau_omega=0.1, A=0.01, dt=0.005,
-                 nsteps=10, dtype="f32", seed=1, shape="tsc") -> Workload:
+                 nsteps=10, dtype="f32", seed=1, shape="tsc", fargo=False) -> Workload:
     """Unstratified standard shearing box [-L/2, L/2]^3: 8 particles per cell
     on the 2x2x2 sub-lattice (+-1/4 cell), displaced along x by
     xi_x = (A/k_x)(-sin(k_x x) + (A/2) sin(2 k_x x)) with k_x = 2 pi/L_x,
     moving with the shear (0, -q Omega x, 0); gas rho = 1 + A cos(k_x x),
-    v = (0, -q Omega x, 0) + N(0, 1e-3)."""
+    v = (0, -q Omega x, 0) + N(0, 1e-3).  fargo: the orbital-advection form
+    (Eq. FARGO_SB_p): particle and gas velocities are the residuals
+    v' = v + q Omega x e_y (the same draws, without the mean shear)."""
     r = rng(seed)
     dt_np = np.float64 if dtype == "f64" else np.float32
     dx = L / n[0]
@@ -151,7 +153,7 @@ def shearing_box(n=(128, 128, 128), L=2.0, Omega=1.0, q=1.5, tau_omega=0.1, A=0.
     off = off.astype(dt_np)
     x_p = xc[np.repeat(ci, 8)] + off[:, 0].astype(np.float64) * dx
     mom = np.zeros((N, 3))
-    mom[:, 1] = -q * Omega * x_p
+    mom[:, 1] = 0.0 if fargo else -q * Omega * x_p
     mom = mom.astype(dt_np)
     perm = r.permutation(N)
     cell, off, mom = cell[perm], off[perm], mom[perm]
@@ -159,13 +161,14 @@ def shearing_box(n=(128, 128, 128), L=2.0, Omega=1.0, q=1.5, tau_omega=0.1, A=0.
     xg = _ghosted_centres(faces[0])[None, None, :]
     rho = np.broadcast_to(1.0 + A * np.cos(kx * xg), gs).copy()
     vx = 1e-3 * r.standard_normal(gs)
-    vy = -q * Omega * xg + 1e-3 * r.standard_normal(gs)
+    vy = (0.0 if fargo else -q * Omega * xg) + 1e-3 * r.standard_normal(gs)
     vz = 1e-3 * r.standard_normal(gs)
     m = 1.0 * dx ** 3 / 8.0
     box = dict(geom="cart", ndim=3, n=tuple(n), bc_lo=("shear", "periodic", "periodic"),
                bc_hi=("shear", "periodic", "periodic"), shape=(shape,) * 3, faces=faces)
     return Workload("shearing_box", dtype, [box],
-                    dict(kind="shearbox", Omega=Omega, q=q, vertical_gravity=False),
+                    dict(kind="shearbox_fargo" if fargo else "shearbox", Omega=Omega, q=q,
+                         vertical_gravity=False),
                     "species", cell, off, mom,
                     [dict(rho=rho.astype(dt_np), vel=[vx.astype(dt_np), vy.astype(dt_np),
                                                        vz.astype(dt_np)])],

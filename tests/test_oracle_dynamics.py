@@ -120,6 +120,77 @@ def test_epicycle_energy_bounded():
     assert errs[-25:].max() < 1.5 * errs[:25].max() + 1e-12
 
 
+def test_fargo_sb_kick_matches_closed_form():
+    """Orbital-advection shearing-box kick (App. B.1, Eq.
+    FARGO_SB_exp_midpoint): the oracle solves the 2x2 block by Cramer's
+    rule; the paper's inverse R^-1 = [[1, W1, 0], [-W2, 1, 0], [0, 0,
+    1 + W1 W2]] / (1 + W1 W2), W1 = Omega h1, W2 = W1 (1 - q/2), applied to
+    e v + h1 G(x, v/2, v_g) with G = (2 Omega v_y, (q - 2) Omega v_x,
+    -Omega^2 z) + v_g/tau, must give the same v^{n+1}."""
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        Om, q = rng.uniform(0.5, 2.0), rng.uniform(0.5, 1.9)
+        tau, dt = 10 ** rng.uniform(-3, 2), rng.uniform(1e-3, 0.5)
+        F = O.Forces(kind="shearbox_fargo", Omega=Om, q=q, vertical_gravity=True)
+        x, v, vg = rng.normal(size=3), rng.normal(size=3), rng.normal(size=3)
+        pn, a = O.kick("cart", 3, F, dt, 1.0 / tau, x, v, vg)
+        e = math.exp(-dt / tau)
+        h1 = tau * (1.0 - e)
+        G = np.array([2 * Om * v[1] / 2, (q - 2) * Om * v[0] / 2, -Om * Om * x[2]]) + vg / tau
+        W1 = Om * h1
+        W2 = W1 * (1 - q / 2)
+        Rinv = np.array([[1, W1, 0], [-W2, 1, 0], [0, 0, 1 + W1 * W2]]) / (1 + W1 * W2)
+        np.testing.assert_allclose(pn, Rinv @ (e * v + h1 * G), rtol=1e-12, atol=1e-14)
+        # the non-drag acceleration at the mean velocity (impulse of Eq. dust_feedback_final)
+        vb = 0.5 * (v + pn)
+        np.testing.assert_allclose(a, [2 * Om * vb[1], (q - 2) * Om * vb[0], -Om * Om * x[2]],
+                                   rtol=1e-12, atol=1e-14)
+
+
+def test_fargo_epicycle_energy_is_exact():
+    """Orbital advection, tau = inf, A = 0.4, dt = 0.4, t_f = 40 (Sec. 4.2):
+    the paper finds the epicyclic energy E = v^2/2 - q Omega^2 x^2 (v the
+    total velocity v' - q Omega x e_y) conserved exactly; so is the
+    residual-velocity invariant (2 - q) v'_x^2 + 2 v'_y^2 of the kick."""
+    Om, q, A = 1.0, 1.5, 0.4
+    omega = Om * math.sqrt(4 - 2 * q)
+    F = O.Forces(kind="shearbox_fargo", Omega=Om, q=q)
+    x = np.array([A, 0.0, 0.0])
+    p = np.array([0.0, -2 * Om * A + q * Om * A, 0.0])   # v' = v + q Omega x
+    E0 = omega ** 2 * A ** 2 / 2
+    Q0 = (2 - q) * p[0] ** 2 + 2 * p[1] ** 2
+    for _ in range(100):
+        O.push_one("cart", F, "tau", np.inf, 0.4, x, p)
+        vy = p[1] - q * Om * x[0]
+        E = 0.5 * (p[0] ** 2 + vy ** 2) - q * Om * Om * x[0] ** 2
+        assert abs(E - E0) <= 1e-13 * E0
+        assert abs((2 - q) * p[0] ** 2 + 2 * p[1] ** 2 - Q0) <= 1e-13 * Q0
+
+
+def test_fargo_epicycle_converges_at_second_order():
+    """Orbital advection at small dt against the exact epicycle (Eq.
+    epicyclic): x = A cos(omega t), y = -(2 Omega/omega) A sin(omega t);
+    halving dt divides the error by 4, and the phase error is below the
+    standard form's (Sec. 4.2)."""
+    Om, q, A = 1.0, 1.5, 0.4
+    omega = Om * math.sqrt(4 - 2 * q)
+
+    def err(kind, dt, T=10.0):
+        F = O.Forces(kind=kind, Omega=Om, q=q)
+        x = np.array([A, 0.0, 0.0])
+        vy0 = -2 * Om * A + (q * Om * A if kind == "shearbox_fargo" else 0.0)
+        p = np.array([0.0, vy0, 0.0])
+        n = int(round(T / dt))
+        for _ in range(n):
+            O.push_one("cart", F, "tau", np.inf, dt, x, p)
+        t = n * dt
+        return math.hypot(x[0] - A * math.cos(omega * t), x[1] + 2 * Om / omega * A * math.sin(omega * t))
+
+    e1, e2 = err("shearbox_fargo", 0.01), err("shearbox_fargo", 0.005)
+    assert 3.8 < e1 / e2 < 4.2
+    assert e1 < err("shearbox", 0.01)
+
+
 def test_circular_orbit_is_exact():
     """Kepler, zero inclination, e = 0: integration is exact (Sec. 4.4)."""
     F = O.Forces(kind="pointmass", GM=1.0)
@@ -317,6 +388,8 @@ def _small(name):
         return synth.cart2d_periodic(n=(8, 8), ppc=4, nsteps=2)
     if name == "sb":
         return synth.shearing_box(n=(8, 8, 8), nsteps=2, dtype="f64", dt=0.05)
+    if name == "sb_fargo":
+        return synth.shearing_box(n=(8, 8, 8), nsteps=2, dtype="f64", dt=0.05, fargo=True)
     if name == "cyl":
         return synth.cylindrical_disk(n=(8, 16, 4), npart=300, nsteps=2, dtype="f64", dt=0.05)
     if name == "sph":
@@ -324,7 +397,7 @@ def _small(name):
     return synth.batched_boxes(sizes=(4, 6), max_per_species=2, nsteps=2, dtype="f64")
 
 
-@pytest.mark.parametrize("name", ["cart2d", "sb", "cyl", "sph", "batch"])
+@pytest.mark.parametrize("name", ["cart2d", "sb", "sb_fargo", "cyl", "sph", "batch"])
 def test_step_conserves_total_momentum(name):
     """Sum_p J_p + Sum_i dV_i D_i = 0 up to FP64 round-off (Sec. 3.1, the
     deposit of Eq. dust_feedback_final), also for the energy channel."""
@@ -413,6 +486,37 @@ def test_fill_and_fold_are_transposes():
     ghost[1:-1, 1:-1, 1:-1] = False
     assert np.all(fd.dep[0][ghost] == 0.0)
     assert abs(fd.dep[0].sum() - dep[0].sum()) < 1e-12
+
+
+def test_fargo_ghosts_carry_no_boost():
+    """Orbital advection keeps residual velocities, continuous across the
+    shear-periodic x faces: its x ghosts of v_y are the standard ones
+    without the -/+ q Omega L_x boost, every other ghost and array equal."""
+    n = (6, 5, 4)
+    faces = [np.linspace(-1, 1, n[0] + 1), np.linspace(0, 1, n[1] + 1), np.linspace(0, 1, n[2] + 1)]
+    box = O.Box("cart", n, ("shear", "periodic", "periodic"), ("shear", "periodic", "periodic"),
+                ("tsc",) * 3, faces)
+    gs = box.ghosted_shape
+    rho = np.zeros(gs)
+    vel = [np.zeros(gs) for _ in range(3)]
+    rho[1:-1, 1:-1, 1:-1] = 1 + RNG.random((n[2], n[1], n[0]))
+    for c in range(3):
+        vel[c][1:-1, 1:-1, 1:-1] = RNG.standard_normal((n[2], n[1], n[0]))
+    out = {}
+    for kind in ("shearbox", "shearbox_fargo"):
+        F = O.Forces(kind=kind, Omega=1.3, q=1.5)
+        f = O.Fields(box, rho.copy(), [v.copy() for v in vel])
+        O.fill_ghosts(box, F, 0.37, f)
+        out[kind] = f
+    u = 1.5 * 1.3 * 2.0
+    s, fg = out["shearbox"], out["shearbox_fargo"]
+    np.testing.assert_array_equal(s.rho, fg.rho)
+    for c in (0, 2):
+        np.testing.assert_array_equal(s.vel[c], fg.vel[c])
+    act = (slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(fg.vel[1][act + (-1,)] - u, s.vel[1][act + (-1,)], atol=1e-14)
+    np.testing.assert_allclose(fg.vel[1][act + (0,)] + u, s.vel[1][act + (0,)], atol=1e-14)
+    np.testing.assert_array_equal(s.vel[1][:, :, 1:-1], fg.vel[1][:, :, 1:-1])
 
 
 def test_bin_reference_is_a_stable_sort():
