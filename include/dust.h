@@ -67,7 +67,7 @@ enum { DUST_F32 = 0, DUST_F64 = 1 };                          /* storage     */
 enum { DUST_ARITH_F64 = 0, DUST_ARITH_F32 = 1 };              /* push math   */
 enum { DUST_BC_PERIODIC = 0, DUST_BC_SHEAR = 1, DUST_BC_OPEN = 2 };
 enum { DUST_FORCE_NONE = 0, DUST_FORCE_SHEARBOX = 1, DUST_FORCE_POINTMASS = 2,
-       DUST_FORCE_CONST = 3 };
+       DUST_FORCE_CONST = 3, DUST_FORCE_SHEARBOX_FARGO = 4 };
 enum { DUST_DRAG_TAU = 0, DUST_DRAG_STOKES = 1, DUST_DRAG_SPECIES = 2 };
 enum { DUST_PHASE_DRIFT1 = 1, DUST_PHASE_KICK = 2, DUST_PHASE_DRIFT2 = 4 };
 enum { DUST_BIN_CELL = 0, DUST_BIN_TILE = 1 };
@@ -109,9 +109,13 @@ typedef struct {
 
 /* External accelerations a_p (Eq. dust_ode).  SHEARBOX: standard
  * shearing box (Eq. standard_SB_p) with Omega, q and, if vertical_gravity,
- * -Omega^2 z.  POINTMASS: g = -GM x/|x|^3 (curvilinear boxes).  CONST: a
- * constant Cartesian g[3].  t: time at the start of the step (shear-periodic
- * offset q Omega L_x t). */
+ * -Omega^2 z.  SHEARBOX_FARGO: the orbital-advection form (Eq. FARGO_SB_p;
+ * kick of App. B.1 Eq. FARGO_SB_exp_midpoint): particle momenta and gas
+ * velocities are residuals v' = v + q Omega x e_y, y is carried by the mean
+ * shear -q Omega x (taken at x^{n+1/2}) in the drifts, and nothing is
+ * boosted across the shear-periodic x faces.  POINTMASS: g = -GM x/|x|^3
+ * (curvilinear boxes).  CONST: a constant Cartesian g[3].  t: time at the
+ * start of the step (shear-periodic offset q Omega L_x t). */
 typedef struct {
   int32_t kind, vertical_gravity;
   double Omega, q, GM;

@@ -259,14 +259,15 @@ dust_status_t check_ctx(void* ctx) {
 
 dust_status_t check_forces(Ctx* c, const dust_forces_t* f) {
   if (!f) return fail(DUST_EINVAL, "forces is NULL");
-  if (f->kind < DUST_FORCE_NONE || f->kind > DUST_FORCE_CONST)
+  if (f->kind < DUST_FORCE_NONE || f->kind > DUST_FORCE_SHEARBOX_FARGO)
     return fail(DUST_EINVAL, "unknown force kind %d", f->kind);
+  const bool sb = f->kind == DUST_FORCE_SHEARBOX || f->kind == DUST_FORCE_SHEARBOX_FARGO;
   for (auto& b : c->boxes) {
-    if (f->kind == DUST_FORCE_SHEARBOX && (b.geom != GEOM_CART || b.ndim != 3))
+    if (sb && (b.geom != GEOM_CART || b.ndim != 3))
       return fail(DUST_EUNSUPPORTED, "shearing-box forces need 3-D Cartesian boxes");
     if (f->kind == DUST_FORCE_POINTMASS && b.geom == GEOM_CART)
       return fail(DUST_EUNSUPPORTED, "point-mass gravity is for curvilinear boxes");
-    if (b.ax[0].bc_lo == BC_SHEAR && f->kind != DUST_FORCE_SHEARBOX)
+    if (b.ax[0].bc_lo == BC_SHEAR && !sb)
       return fail(DUST_EINVAL, "a shear-periodic box needs shearing-box forces");
   }
   if (c->drag_mode == DUST_DRAG_STOKES && !(f->GM > 0))

@@ -284,8 +284,14 @@ __device__ __forceinline__ bool wrap_plain(const Axis& ax, int& i) {
 }
 
 // Shear-periodic image across the x faces at time t (Sec. 2.1): x -/+ L_x,
-// y +/- q Omega L_x t (as a shift in y-cells), v_y +/- q Omega L_x.
-template <typename A>
+// y +/- q Omega L_x t (as a shift in y-cells), v_y +/- q Omega L_x (not for
+// the residual velocities of orbital advection, FG).
+//
+// FG (here and in drift, kick, finalize, store_particle): the forces are
+// the orbital-advection shearing box (Eq. FARGO_SB_p).  It is a template
+// flag, so that the standard form's code is not touched by it; the *_any
+// wrappers pick it at run time.
+template <typename A, bool FG = false>
 __device__ __forceinline__ void shear_image(const Box& b, const Forces& f, double t, int idx[3],
                                             A off[3], A mom[3]) {
   const Axis& ax = b.ax[0];
@@ -304,7 +310,7 @@ __device__ __forceinline__ void shear_image(const Box& b, const Forces& f, doubl
   else if (off[1] < A(-0.5)) { off[1] += A(1); --idx[1]; }
   idx[1] %= b.ax[1].n;
   if (idx[1] < 0) idx[1] += b.ax[1].n;
-  mom[1] += A(sign) * A(u);
+  if constexpr (!FG) mom[1] += A(sign) * A(u);
 }
 
 // Drift by a half step h (Eq. exp_midpoint; Eq. drift1_cylindrical,
@@ -312,14 +318,26 @@ __device__ __forceinline__ void shear_image(const Box& b, const Forces& f, doubl
 // theta) already moved to n+1/2; otherwise all metric factors are those at
 // the start of this half drift.  t_after: time the boundary rules use.
 // Returns false if the particle left through an open face.
-template <typename A, int GEOM, int NDIM, bool U>
+template <typename A, int GEOM, int NDIM, bool U, bool FG = false>
 __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first, A h,
                                       double t_after, int idx[3], A off[3], A mom[3]) {
   if constexpr (GEOM == GEOM_CART) {
-    A dx[3] = {h * mom[0], h * mom[1], NDIM > 2 ? h * mom[2] : A(0)};
+    if constexpr (FG && NDIM == 3) {
+      // orbital advection: y is also carried by the mean shear -q Omega x,
+      // taken at x^{n+1/2} (x moves first in the first drift, last in the
+      // second)
+      const A qO = A(f.q * f.Omega);
+      if (first) idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
+      const A xh = cell_centre<A, U>(b.ax[0], idx[0]) + off[0] * cell_width<A, U>(b.ax[0], idx[0]);
+      idx[1] = move_axis<A, U>(b.ax[1], idx[1], off[1], h * (mom[1] - qO * xh));
+      if (!first) idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
+      idx[2] = move_axis<A, U>(b.ax[2], idx[2], off[2], h * mom[2]);
+    } else {
+      A dx[3] = {h * mom[0], h * mom[1], NDIM > 2 ? h * mom[2] : A(0)};
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) idx[d] = move_axis<A, U>(b.ax[d], idx[d], off[d], dx[d]);
-    if (NDIM == 3 && b.ax[0].bc_lo == BC_SHEAR) shear_image<A>(b, f, t_after, idx, off, mom);
+      for (int d = 0; d < NDIM; ++d) idx[d] = move_axis<A, U>(b.ax[d], idx[d], off[d], dx[d]);
+    }
+    if (NDIM == 3 && b.ax[0].bc_lo == BC_SHEAR) shear_image<A, FG>(b, f, t_after, idx, off, mom);
 #pragma unroll
     for (int d = 0; d < NDIM; ++d)
       if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
@@ -401,7 +419,7 @@ template <typename A> struct KickOut {
 // its spherical analogue) for canonical momenta p, slip s = p_g - p (canonical; the gas
 // momentum at the particle minus p) and the drag propagator terms c, psi
 // of h = dt/tau (see propagator()).
-template <typename A, int GEOM, int NDIM>
+template <typename A, int GEOM, int NDIM, bool FG = false>
 __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A c, A psi,
                                      const Where<A>& w, const A p[3], const A s[3],
                                      KickOut<A>& o) {
@@ -409,7 +427,22 @@ __device__ __forceinline__ void kick(const Box& b, const Forces& f, A dt, A c, A
   A a[3] = {A(0), A(0), A(0)};
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   if constexpr (GEOM == GEOM_CART) {
-    if (NDIM == 3 && f.kind == FORCE_SHEARBOX) {
+    if constexpr (FG && NDIM == 3) {
+      // orbital advection (App. B.1, Eq. FARGO_SB_exp_midpoint), residual
+      // velocities: R dp = c s + h1 a(p^n), R = [[1, -W1], [W2, 1]],
+      // W1 = Omega h1, W2 = W1 (1 - q/2)
+      A Om = A(f.Omega), q = A(f.q);
+      A gz = f.vertical_gravity ? -Om * Om * w.x[2] : A(0);
+      A an[3] = {A(2) * Om * p[1], (q - A(2)) * Om * p[0], gz};
+      A r[3] = {c * s[0] + h1 * an[0], c * s[1] + h1 * an[1], c * s[2] + h1 * an[2]};
+      A W1 = Om * h1, W2 = W1 * (A(1) - A(0.5) * q), den = A(1) / (A(1) + W1 * W2);
+      o.dp[0] = (r[0] + W1 * r[1]) * den;
+      o.dp[1] = (r[1] - W2 * r[0]) * den;
+      o.dp[2] = r[2];
+      a[0] = an[0] + Om * o.dp[1];
+      a[1] = an[1] + A(0.5) * (q - A(2)) * Om * o.dp[0];
+      a[2] = gz;
+    } else if (NDIM == 3 && f.kind == FORCE_SHEARBOX) {
       // R dp = c s + h1 a(x, p^n), R = I - W J_rot, W = Omega h1
       A Om = A(f.Omega), q = A(f.q);
       A gz = f.vertical_gravity ? -Om * Om * w.x[2] : A(0);

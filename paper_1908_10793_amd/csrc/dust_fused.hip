@@ -232,17 +232,18 @@ __device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>&
 }
 
 // Register budget: the FP32 kernel needs about 250 VGPRs (108 of them the
-// register sums); the compiler keeps every shape but one under 256 (2
-// waves/SIMD) by itself, and the 4x4x16 shape with an explicit target (an
-// explicit target on the others costs them time).
-template <typename A, typename TS, int TX, int TY>
+// register sums); the compiler keeps the standard-form shapes but one under
+// 256 (2 waves/SIMD) by itself, and 4x4x16 and the orbital-advection
+// kernels with an explicit target (an explicit target where it is not
+// needed costs time: about 25 us of 900).
+template <typename A, typename TS, int TX, int TY, bool FG>
 constexpr int fused_waves_target() {
-  return sizeof(A) == 4 && sizeof(TS) == 4 && TX * TY <= 16 ? 2 : 1;
+  return sizeof(A) == 4 && sizeof(TS) == 4 && (FG || TX * TY <= 16) ? 2 : 1;
 }
 
-template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
+template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ, bool FG>
 __global__ void __launch_bounds__(FUSED_THREADS)
-    __attribute__((amdgpu_waves_per_eu(fused_waves_target<A, TS, TX, TY>())))
+    __attribute__((amdgpu_waves_per_eu(fused_waves_target<A, TS, TX, TY, FG>())))
     k_fused(const TileDesc* __restrict__ tiles, PView<TS> p, PView<TS> dst, int copy_attrs,
             const Box* __restrict__ boxes, FView<TS> fl, Forces f, const Species* __restrict__ sp,
             int drag_mode, A dt, const double* __restrict__ tdev,
@@ -257,6 +258,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   // binned (level-major) slot order.  Slot i reads particle src_index[i] of
   // p (right after a rebinning, dst != p), or particle i (src_index null, in
   // place).  copy_attrs copies the attributes the step does not change.
+  // FG: the forces are the orbital-advection shearing box (kernels of their
+  // own, so that neither form's code costs the other registers)
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   constexpr int H = FUSED_HALO;
@@ -396,8 +399,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       }
       if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
       // half drift to x^{n+1/2}
-      if (!drift<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom)) {
-        store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(h), i, false, idx, off, mom, dg);
+      if (!drift<A, GEOM, NDIM, U, FG>(B, f, true, h, t0 + double(h), idx, off, mom)) {
+        store_particle<TS, A, GEOM, NDIM, FG>(dst, B, f, t0 + double(h), i, false, idx, off, mom, dg);
         live = false;
         removed = true;
       }
@@ -502,7 +505,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       propagator<A>(dt * it, c, psi);
     }
     KickOut<A> o;
-    kick<A, GEOM, NDIM>(B, f, dt, c, psi, wh, mom, sl, o);
+    kick<A, GEOM, NDIM, FG>(B, f, dt, c, psi, wh, mom, sl, o);
     A q[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
     for (int k = 0; k < nc; ++k) {
@@ -616,8 +619,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     }
     // second half drift to x^{n+1}
     if (live) {
-      bool alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
-      store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
+      bool alive = drift<A, GEOM, NDIM, U, FG>(B, f, false, h, t0 + double(dt), idx, off, mom);
+      store_particle<TS, A, GEOM, NDIM, FG>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, dg);
     }
     if (copy_attrs && has && !deferred) {
       if (!live) {
@@ -792,7 +795,7 @@ __global__ void __launch_bounds__(256)
       mom[d] = d < nc ? A(p.mom[d][si]) : A(0);
     }
     s_n += 1.0;
-    bool alive = drift<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom);
+    bool alive = drift_any<A, GEOM, NDIM, U>(B, f, true, h, t0 + double(h), idx, off, mom);
     if (alive) {
       Stencil<A> s;
       stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
@@ -842,7 +845,7 @@ __global__ void __launch_bounds__(256)
       A c, psi;
       propagator<A>(dt * it, c, psi);
       KickOut<A> o;
-      kick<A, GEOM, NDIM>(B, f, dt, c, psi, wh, mom, sl, o);
+      kick_any<A, GEOM, NDIM>(B, f, dt, c, psi, wh, mom, sl, o);
       A q[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
       for (int k = 0; k < nc; ++k) {
@@ -871,10 +874,10 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(w * q[k]));
           }
-      alive = drift<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
-      store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, nullptr);
+      alive = drift_any<A, GEOM, NDIM, U>(B, f, false, h, t0 + double(dt), idx, off, mom);
+      store_particle_any<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(dt), i, alive, idx, off, mom, nullptr);
     } else {
-      store_particle<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(h), i, false, idx, off, mom, nullptr);
+      store_particle_any<TS, A, GEOM, NDIM>(dst, B, f, t0 + double(h), i, false, idx, off, mom, nullptr);
     }
     if (copy_attrs) {
       if (!alive) {
@@ -906,7 +909,7 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ>
+template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ, bool FG>
 static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                            bool copy_attrs, const Box* boxes_d,
                            const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
@@ -915,7 +918,7 @@ static void launch_fused_t(const FusedPlan& plan, const PView<TS>& p, const PVie
                            uint32_t* defer_count, const uint32_t* src_index, hipStream_t st) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   size_t lds = fused_lds_bytes(plan, nc, (int)sizeof(TS));
-  auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ>;
+  auto kern = k_fused<TS, A, GEOM, NDIM, U, TX, TY, TZ, FG>;
   if (lds > 64 * 1024) {
     static bool raised = false;
     if (!raised) {
@@ -938,12 +941,30 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
                            uint32_t* defer_count, const uint32_t* src_index, int nbox,
                            hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   if (ev0) (void)hipEventRecord(ev0, st);   // the tile kernel alone is timed
-#define DUST_F(TX, TY, TZ)                                                                         \
-  launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,        \
-                                                   drag_mode, dt, tdev,                            \
-                                                bin_start, xg, dg, part, sums, defer_list,      \
-                                                defer_count, src_index, st)
-  if constexpr (NDIM == 3) {
+#define DUST_FK(TX, TY, TZ, FK)                                                                    \
+  launch_fused_t<TS, A, GEOM, NDIM, U, TX, TY, TZ, FK>(plan, p, q, copy_attrs, boxes_d, fl, f, sp,    \
+                                                       drag_mode, dt, tdev, bin_start, xg, dg, part, \
+                                                       sums, defer_list, defer_count, src_index, st)
+#define DUST_F(TX, TY, TZ) DUST_FK(TX, TY, TZ, false)
+  if constexpr (NDIM == 3 && GEOM == GEOM_CART) {
+    // the orbital-advection shearing box has kernels of its own
+#define DUST_F3(TX, TY, TZ)                      \
+  do {                                           \
+    if (f.kind == FORCE_FARGO)                   \
+      DUST_FK(TX, TY, TZ, true);                 \
+    else                                         \
+      DUST_FK(TX, TY, TZ, false);                \
+  } while (0)
+    switch (plan.shape) {
+      case 0: DUST_F3(8, 8, 4); break;
+      case 1: DUST_F3(16, 4, 4); break;
+      case 2: DUST_F3(4, 16, 4); break;
+      case 3: DUST_F3(4, 4, 16); break;
+      case 4: DUST_F3(8, 4, 8); break;
+      default: DUST_F3(4, 8, 8); break;
+    }
+#undef DUST_F3
+  } else if constexpr (NDIM == 3) {
     switch (plan.shape) {
       case 0: DUST_F(8, 8, 4); break;
       case 1: DUST_F(16, 4, 4); break;
@@ -960,6 +981,7 @@ static void launch_fused_g(const FusedPlan& plan, const PView<TS>& p, const PVie
     }
   }
 #undef DUST_F
+#undef DUST_FK
   if (ev1) (void)hipEventRecord(ev1, st);
   hipLaunchKernelGGL((k_fused_deferred<TS, A, GEOM, NDIM, U>), dim3(DEFER_BLOCKS), dim3(256), 0, st, p, q,
                      (int)copy_attrs, boxes_d, nbox, fl, f, sp, drag_mode, A(dt), tdev, xg,
@@ -1023,7 +1045,7 @@ __global__ void __launch_bounds__(256)
     unravel(B, c - B.cell_base, idx);
     const A h = A(0.5) * dt;
     int here[3] = {idx[0], idx[1], idx[2]};
-    k = drift<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)
+    k = drift_any<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)
             ? tile_key_idx(B, idx, ts) : tile_key_idx(B, here, ts);
   }
   key[i] = k;

@@ -26,8 +26,8 @@ __global__ void __launch_bounds__(256) k_drift(PView<TS> p, const Box* boxes, in
   int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
   if (b < 0) return;
   const Box& B = boxes[b];
-  bool alive = drift<A, GEOM, NDIM, U>(B, f, first != 0, h, t_after, idx, off, mom);
-  store_particle<TS, A, GEOM, NDIM>(p, B, f, t_after, i, alive, idx, off, mom, dg);
+  bool alive = drift_any<A, GEOM, NDIM, U>(B, f, first != 0, h, t_after, idx, off, mom);
+  store_particle_any<TS, A, GEOM, NDIM>(p, B, f, t_after, i, alive, idx, off, mom, dg);
 }
 
 template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       A c, psi;
       propagator<A>(dt * it, c, psi);
       KickOut<A> o;
-      kick<A, GEOM, NDIM>(B, f, dt, c, psi, w, mom, sl, o);
+      kick_any<A, GEOM, NDIM>(B, f, dt, c, psi, w, mom, sl, o);
       TW* imp[4] = {imp0, imp1, imp2, imp3};
       bool fin = isfinite(double(o.e));
 #pragma unroll
@@ -242,8 +242,8 @@ __global__ void k_fill_x(Box B, Arr4<TS> arrs, int vy_slot, double qOmega, const
 // the shear boundary sees the gas at the accuracy of the interior values.
 template <typename TS>
 __global__ void k_fill_xghost(Box B, Arr4<TS> vel, double* xg, double qOmega, const double* tdev,
-                              double toff) {
-  const int m = blockIdx.y, comp_vy = m == 1;
+                              double toff, int boost) {
+  const int m = blockIdx.y, comp_vy = boost && m == 1;
   const TS* a = vel.a[m];
   const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
   const int g1 = n1 + 2, g2 = n2 + 2;
@@ -525,12 +525,15 @@ void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff,
   const Arr4<TS> vel{{fl.vel[0], fl.vel[1], fl.vel[2], nullptr}};
   const unsigned na = (unsigned)(nc + 1);
   const double qOmega = f.q * f.Omega;
+  // the v_y ghosts across a shear face carry the boost -/+ q Omega L_x,
+  // except for the residual velocities of orbital advection
+  const bool boost = f.kind == FORCE_SHEARBOX;
   if (xg && B.xg_base >= 0)
     hipLaunchKernelGGL((k_fill_xghost<TS>), dim3(blocks_for((int64_t)(n1 + 2) * (n2 + 2)), (unsigned)nc),
-                       dim3(256), 0, st, B, vel, xg, qOmega, tdev, toff);
+                       dim3(256), 0, st, B, vel, xg, qOmega, tdev, toff, (int)boost);
   if (B.ax[0].bc_lo != BC_OPEN)
     hipLaunchKernelGGL((k_fill_x<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st, B, arrs,
-                       B.geom == GEOM_CART ? 2 : -1, qOmega, tdev, toff,
+                       B.geom == GEOM_CART && boost ? 2 : -1, qOmega, tdev, toff,
                        (int)(B.ax[0].bc_lo == BC_SHEAR));
   if (B.ax[1].bc_lo == BC_PERIODIC)
     hipLaunchKernelGGL((k_fill_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2), na), dim3(256), 0, st, B,
@@ -558,9 +561,10 @@ void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff,
     int shear = B.ax[0].bc_lo == BC_SHEAR;
     // the energy channel reads the D_y ghosts, which no thread of this
     // launch writes (they are cleared by the next one)
+    // (the energy term of the boost: standard shearing box only)
     hipLaunchKernelGGL((k_fold_x<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st, B, deps,
-                       (const TS*)fl.dep[B.ndim > 1 ? 1 : 0], shear ? nc : -1, qOmega, tdev, toff,
-                       shear);
+                       (const TS*)fl.dep[B.ndim > 1 ? 1 : 0],
+                       shear && f.kind == FORCE_SHEARBOX ? nc : -1, qOmega, tdev, toff, shear);
     hipLaunchKernelGGL((k_clear_x_ghosts<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st,
                        B, deps);
   }

@@ -60,7 +60,7 @@ __device__ __forceinline__ int load_particle(const PView<TS>& p, const Box* boxe
 
 // Round the offsets to storage precision; an offset that rounds onto the
 // upper face moves to the next cell (same point), with the boundary rules.
-template <typename TS, typename A, int GEOM, int NDIM>
+template <typename TS, typename A, int GEOM, int NDIM, bool FG = false>
 __device__ __forceinline__ bool finalize(const Box& B, const Forces& f, double t, int idx[3],
                                          A off[3], A mom[3], TS out[3]) {
 #pragma unroll
@@ -71,7 +71,7 @@ __device__ __forceinline__ bool finalize(const Box& B, const Forces& f, double t
       off[d] = A(-0.5);
       idx[d] += 1;
       if (GEOM == GEOM_CART && NDIM == 3 && d == 0 && B.ax[0].bc_lo == BC_SHEAR) {
-        shear_image<A>(B, f, t, idx, off, mom);
+        shear_image<A, FG>(B, f, t, idx, off, mom);
         out[1] = TS(off[1]);
       }
       if (!wrap_plain<A>(B.ax[d], idx[d])) return false;
@@ -80,12 +80,12 @@ __device__ __forceinline__ bool finalize(const Box& B, const Forces& f, double t
   return true;
 }
 
-template <typename TS, typename A, int GEOM, int NDIM>
+template <typename TS, typename A, int GEOM, int NDIM, bool FG = false>
 __device__ __forceinline__ void store_particle(const PView<TS>& p, const Box& B, const Forces& f,
                                                double t, int64_t i, bool alive, int idx[3],
                                                A off[3], A mom[3], DiagDev* dg) {
   TS o[3];
-  if (alive) alive = finalize<TS, A, GEOM, NDIM>(B, f, t, idx, off, mom, o);
+  if (alive) alive = finalize<TS, A, GEOM, NDIM, FG>(B, f, t, idx, off, mom, o);
   if (!alive) {
     p.cell[i] = -1;
     if (dg) {
@@ -183,5 +183,31 @@ __device__ __forceinline__ Shift make_shift(const Box& B, double qOmega, double 
   return sh;
 }
 
+
+// The orbital-advection flag picked at run time (kernels off the hot loop).
+template <typename A, int GEOM, int NDIM, bool U>
+__device__ __forceinline__ bool drift_any(const Box& b, const Forces& f, bool first, A h, double t_after,
+                                          int idx[3], A off[3], A mom[3]) {
+  if (GEOM == GEOM_CART && NDIM == 3 && f.kind == FORCE_FARGO)
+    return drift<A, GEOM, NDIM, U, true>(b, f, first, h, t_after, idx, off, mom);
+  return drift<A, GEOM, NDIM, U, false>(b, f, first, h, t_after, idx, off, mom);
+}
+template <typename A, int GEOM, int NDIM>
+__device__ __forceinline__ void kick_any(const Box& b, const Forces& f, A dt, A c, A psi, const Where<A>& w,
+                                         const A p[3], const A s[3], KickOut<A>& o) {
+  if (GEOM == GEOM_CART && NDIM == 3 && f.kind == FORCE_FARGO)
+    kick<A, GEOM, NDIM, true>(b, f, dt, c, psi, w, p, s, o);
+  else
+    kick<A, GEOM, NDIM, false>(b, f, dt, c, psi, w, p, s, o);
+}
+template <typename TS, typename A, int GEOM, int NDIM>
+__device__ __forceinline__ void store_particle_any(const PView<TS>& p, const Box& B, const Forces& f,
+                                                   double t, int64_t i, bool alive, int idx[3], A off[3],
+                                                   A mom[3], DiagDev* dg) {
+  if (GEOM == GEOM_CART && NDIM == 3 && f.kind == FORCE_FARGO)
+    store_particle<TS, A, GEOM, NDIM, true>(p, B, f, t, i, alive, idx, off, mom, dg);
+  else
+    store_particle<TS, A, GEOM, NDIM, false>(p, B, f, t, i, alive, idx, off, mom, dg);
+}
 
 }  // namespace dust

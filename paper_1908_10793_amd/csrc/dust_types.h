@@ -12,7 +12,8 @@ enum { GEOM_CART = DUST_CART, GEOM_CYL = DUST_CYL, GEOM_SPH = DUST_SPH };
 enum { SHAPE_CIC = DUST_CIC, SHAPE_TSC = DUST_TSC };
 enum { BC_PERIODIC = DUST_BC_PERIODIC, BC_SHEAR = DUST_BC_SHEAR, BC_OPEN = DUST_BC_OPEN };
 enum { FORCE_NONE = DUST_FORCE_NONE, FORCE_SHEARBOX = DUST_FORCE_SHEARBOX,
-       FORCE_POINTMASS = DUST_FORCE_POINTMASS, FORCE_CONST = DUST_FORCE_CONST };
+       FORCE_POINTMASS = DUST_FORCE_POINTMASS, FORCE_CONST = DUST_FORCE_CONST,
+       FORCE_FARGO = DUST_FORCE_SHEARBOX_FARGO };
 enum { DRAG_TAU = DUST_DRAG_TAU, DRAG_STOKES = DUST_DRAG_STOKES, DRAG_SPECIES = DUST_DRAG_SPECIES };
 
 // Weight formula of an axis: plain b-spline overlap (Cartesian, phi, z),

@@ -27,6 +27,8 @@ def small(name):
         return synth.cart2d_periodic()
     if name == "shearing_box":
         return synth.shearing_box(n=(20, 20, 12), dt=0.05)
+    if name == "shearing_box_fargo":   # orbital advection: residual velocities
+        return synth.shearing_box(n=(20, 20, 12), dt=0.05, fargo=True)
     if name == "cylindrical_disk":
         return synth.cylindrical_disk(n=(24, 40, 12), npart=30000, dt=0.02)
     if name == "spherical_disk":
@@ -36,7 +38,8 @@ def small(name):
     raise KeyError(name)
 
 
-WORKLOADS = ["cart2d_f64", "shearing_box", "cylindrical_disk", "spherical_disk", "batched_boxes"]
+WORKLOADS = ["cart2d_f64", "shearing_box", "shearing_box_fargo", "cylindrical_disk", "spherical_disk",
+             "batched_boxes"]
 
 
 def _run(name, fused, nsteps=3, arith=None, tile=None):

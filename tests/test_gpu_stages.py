@@ -275,6 +275,8 @@ def test_fused_keeps_cellless_particles():
 def _small(name):
     if name == "shearing_box":
         return synth.shearing_box(n=(16, 16, 8), dt=0.05)
+    if name == "shearing_box_fargo":
+        return synth.shearing_box(n=(16, 16, 8), dt=0.05, fargo=True)
     return synth.cylindrical_disk(n=(16, 12, 8), npart=3000, dt=0.05)
 
 
@@ -292,7 +294,7 @@ SCHEDULES = [
 ]
 
 
-@pytest.mark.parametrize("name", ["shearing_box", "cylindrical_disk"])
+@pytest.mark.parametrize("name", ["shearing_box", "shearing_box_fargo", "cylindrical_disk"])
 @pytest.mark.parametrize("nsteps,rebin_every", SCHEDULES)
 def test_multi_step_schedules_match_oracle(name, nsteps, rebin_every):
     """The last step of a call of nsteps fused steps with
