@@ -536,8 +536,7 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
       // the unfused chain passes gathered velocities and impulses through
       // memory, where FP32 would lose the slip: it computes in FP64
       unfused_step<TS, double>(c, pv, fv, F, dt, flags, st);
-      launch_advance_time(c->tdev, dt, st);
-      if (flags & DUST_STEP_DIAG) launch_count_step(c->diag, st);
+      launch_advance_time(c->tdev, dt, (flags & DUST_STEP_DIAG) ? c->diag : nullptr, st);
     }
     return DUST_OK;
   }
@@ -559,8 +558,7 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
     dust_status_t e = fused_step<TS, A>(c, x, y, fv, F, dt, flags, mv, st);
     if (e) return e;
     if (mv != STEP_IN_PLACE) in_shadow = !in_shadow;
-    launch_advance_time(c->tdev, dt, st);
-    if (flags & DUST_STEP_DIAG) launch_count_step(c->diag, st);
+    launch_advance_time(c->tdev, dt, (flags & DUST_STEP_DIAG) ? c->diag : nullptr, st);
   }
   if (in_shadow) launch_copy_particles<TS>(sh, pv, st);
   return DUST_OK;

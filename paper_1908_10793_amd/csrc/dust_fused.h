@@ -82,6 +82,5 @@ void launch_copy_tail(const PView<TS>& src, const PView<TS>& dst, const int64_t*
 template <typename TS>
 void launch_copy_particles(const PView<TS>& src, const PView<TS>& dst, hipStream_t st);
 
-void launch_count_step(DiagDev* dg, hipStream_t st);
 
 }  // namespace dust

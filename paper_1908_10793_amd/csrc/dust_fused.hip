@@ -97,6 +97,7 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
           hipSuccess ||
       hipMalloc((void**)&plan.defer_count, 256) != hipSuccess)
     return DUST_ENOMEM;
+  if (hipMemset(plan.defer_count, 0, 256) != hipSuccess) return DUST_EDEVICE;
   plan.ok = true;
   return DUST_OK;
 }
@@ -712,41 +713,48 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 
 // Adds the per-workgroup partials of one fused launch to the diagnostics
 // block, in a fixed order (one workgroup).
-__global__ void __launch_bounds__(256)
-    k_reduce_fused_partials(const double* __restrict__ part, int n, DiagDev* dg, int sums) {
-  __shared__ double red[256][PART_WORDS];
+static constexpr int REDUCE_THREADS = 1024;
+__global__ void __launch_bounds__(REDUCE_THREADS)
+    k_reduce_fused_partials(const double* __restrict__ part, int n, DiagDev* dg, int sums,
+                            uint32_t* defer_count) {
+  constexpr int NW = REDUCE_THREADS / 64;
+  __shared__ double wred[NW][PART_WORDS];
+  __shared__ double red[1][PART_WORDS];
   double acc[PART_WORDS];
   for (int k = 0; k < PART_WORDS; ++k) acc[k] = 0.0;
-  // slots b, b + 256, ... in order; four slots' loads in flight at a time
+  // slots b, b + REDUCE_THREADS, ... in order; four slots' loads in flight
   int b = threadIdx.x;
-  for (; b + 3 * 256 < n; b += 4 * 256) {
+  for (; b + 3 * REDUCE_THREADS < n; b += 4 * REDUCE_THREADS) {
     double v[4][PART_WORDS];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int k = 0; k < PART_WORDS; ++k) v[u][k] = part[(size_t)(b + u * 256) * PART_WORDS + k];
+      for (int k = 0; k < PART_WORDS; ++k) v[u][k] = part[(size_t)(b + u * REDUCE_THREADS) * PART_WORDS + k];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int k = 0; k < PART_WORDS; ++k) acc[k] = k == 5 ? fmax(acc[k], v[u][k]) : acc[k] + v[u][k];
   }
-  for (; b < n; b += 256)
+  for (; b < n; b += REDUCE_THREADS)
     for (int k = 0; k < PART_WORDS; ++k) {
       const double v = part[(size_t)b * PART_WORDS + k];
       acc[k] = k == 5 ? fmax(acc[k], v) : acc[k] + v;
     }
-  for (int k = 0; k < PART_WORDS; ++k) red[threadIdx.x][k] = acc[k];
+  // fixed-pattern wave reductions, then the waves in order
+#pragma unroll
+  for (int k = 0; k < PART_WORDS; ++k) acc[k] = k == 5 ? wave_max(acc[k]) : wave_sum(acc[k]);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < PART_WORDS; ++k) wred[threadIdx.x >> 6][k] = acc[k];
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
-      for (int k = 0; k < PART_WORDS; ++k) {
-        const double o = red[threadIdx.x + h][k];
-        red[threadIdx.x][k] = k == 5 ? fmax(red[threadIdx.x][k], o) : red[threadIdx.x][k] + o;
-      }
-    __syncthreads();
+  if (threadIdx.x < PART_WORDS) {
+    const int k = threadIdx.x;
+    double v = wred[0][k];
+    for (int w = 1; w < NW; ++w) v = k == 5 ? fmax(v, wred[w][k]) : v + wred[w][k];
+    red[0][k] = v;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (sums) {
+    if (dg && sums) {
       for (int k = 0; k < 3; ++k) dg->p_part[k] += red[0][k];
       dg->e_part += red[0][3];
       dg->sum_abs_j += red[0][4];
@@ -754,14 +762,14 @@ __global__ void __launch_bounds__(256)
       if (red[0][5] > 1.8) atomicOr(&dg->flags, (unsigned)DUST_FLAG_CFL);
     }
     const unsigned long long fb = (unsigned long long)red[0][6];
-    if (fb) {
+    if (dg && fb) {
       dg->n_fallback += fb;
       atomicOr(&dg->flags, (unsigned)DUST_FLAG_TILE_OVERFLOW);
     }
+    *defer_count = 0u;   // ready for the next launch (zeroed at set-up too)
   }
 }
 
-__global__ void k_reset_count(uint32_t* c) { *c = 0u; }
 
 // The deferred particles of a fused launch (their stencil at x^{n+1/2} left
 // their tile's window): the same step, one thread per particle, gathering
@@ -996,7 +1004,8 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
                   const uint32_t* src_index, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   if (plan.ntiles == 0) return;
   double* part = plan.part_d;
-  hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, st, plan.defer_count);
+  // (the deferred-particle count is zero here: set at set-up, and reset by
+  // the partial reduction that ends every launch)
 #define DUST_G(G, D, UU)                                                                          \
   launch_fused_g<TS, A, G, D, UU>(plan, p, q, copy_attrs, boxes_d, fl, f, sp, drag_mode, dt, tdev, \
                                   bin_start, xg, dg, part, sums, plan.defer_list,                  \
@@ -1008,9 +1017,8 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
   else if (geom == GEOM_CYL) DUST_G(GEOM_CYL, 3, false);
   else DUST_G(GEOM_SPH, 3, false);
 #undef DUST_G
-  if (dg)
-    hipLaunchKernelGGL(k_reduce_fused_partials, dim3(1), dim3(256), 0, st, (const double*)part,
-                       plan.ntiles + DEFER_BLOCKS, dg, (int)sums);
+  hipLaunchKernelGGL(k_reduce_fused_partials, dim3(1), dim3(REDUCE_THREADS), 0, st, (const double*)part,
+                     plan.ntiles + DEFER_BLOCKS, dg, (int)sums, plan.defer_count);
 }
 
 // ---------------------------------------------------------------- rebinning by half-step cell

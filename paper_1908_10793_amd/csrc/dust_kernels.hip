@@ -366,19 +366,18 @@ template <typename TS> __global__ void k_clear_x_ghosts(Box B, Arr4<TS> arrs) {
   a[stored_index(B, n0, j, k)] = TS(0);
 }
 
-__global__ void k_set_time(double* t, double v, double add) { t[0] = add != 0.0 ? t[0] + add : v; }
-
-__global__ void k_count_step(DiagDev* dg) { dg->steps += 1; }
-
-void launch_count_step(DiagDev* dg, hipStream_t st) {
-  hipLaunchKernelGGL(k_count_step, dim3(1), dim3(1), 0, st, dg);
+// Step start time (set, or advanced by dt), and the diagnostics' step count
+// when dg is given (one launch per step).
+__global__ void k_set_time(double* t, double v, double add, DiagDev* dg) {
+  t[0] = add != 0.0 ? t[0] + add : v;
+  if (dg) dg->steps += 1;
 }
 
 void launch_set_time(double* tdev, double v, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, v, 0.0);
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, v, 0.0, (DiagDev*)nullptr);
 }
-void launch_advance_time(double* tdev, double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, 0.0, dt);
+void launch_advance_time(double* tdev, double dt, DiagDev* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, st, tdev, 0.0, dt, count);
 }
 
 template <typename TS> __global__ void k_fill_values(Arr4<TS> arrs, int64_t n, TS v) {

@@ -53,7 +53,8 @@ template <typename TS>
 void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
                  hipStream_t st);
 void launch_set_time(double* tdev, double v, hipStream_t st);
-void launch_advance_time(double* tdev, double dt, hipStream_t st);
+// advance the step time by dt; count: the diagnostics whose step count goes up (or null)
+void launch_advance_time(double* tdev, double dt, DiagDev* count, hipStream_t st);
 template <typename TS> void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st);
 // FP64 grid sums of one box; part: GRID_SUM_BLOCKS * 4 doubles of scratch.
 static constexpr int GRID_SUM_BLOCKS = 2048;
