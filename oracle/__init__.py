@@ -75,7 +75,7 @@ class _Box(ctypes.Structure):
 class _Forces(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("vertical_gravity", ctypes.c_int32),
                 ("Omega", ctypes.c_double), ("q", ctypes.c_double),
-                ("GM", ctypes.c_double), ("g", ctypes.c_double * 3)]
+                ("GM", ctypes.c_double), ("g", ctypes.c_double * 3), ("integrator", ctypes.c_int32)]
 
 
 class _Particles(ctypes.Structure):
@@ -182,10 +182,12 @@ class Forces:
     GM: float = 0.0
     vertical_gravity: bool = False
     g: tuple = (0.0, 0.0, 0.0)
+    integrator: str = "em"   # "em" exponential midpoint, "si" semi-implicit (Cartesian)
 
     def c(self) -> _Forces:
         f = _Forces()
         f.kind = FORCE[self.kind]
+        f.integrator = {"em": 0, "si": 1}[self.integrator]
         f.vertical_gravity = int(self.vertical_gravity)
         f.Omega, f.q, f.GM = self.Omega, self.q, self.GM
         for d in range(3):

@@ -41,6 +41,7 @@ typedef struct {
   int32_t vertical_gravity;
   double Omega, q, GM;
   double g[3];
+  int32_t integrator;   /* 0 exponential midpoint, 1 semi-implicit (Cartesian) */
 } orc_forces;
 
 /* Particle set in global FP64 coordinates.  p[] are canonical momenta:
@@ -543,8 +544,67 @@ static void drift_second(int geom, const orc_forces *f, double h, double x[3], c
  * momenta pg at the particle, inverse stopping time, dt.  Outputs: p at
  * n+1 (in place) and a[] = the non-drag part of G evaluated as in the kick
  * (the a_p^{n+1/2} of Eq. dust_feedback_final). */
+/* Semi-implicit kick (Sec. 3.2, Eq. semi-implicit, a_linear, Lambda; the
+ * comparison integrator of BS10), Cartesian: Lambda dv = dt a_tot(x, v^n,
+ * v_g) with Lambda = I - (dt/2) d a_tot / d v, solved by Gaussian
+ * elimination; a = the non-drag acceleration at (v^n + v^{n+1})/2 (linear
+ * in v, so exactly the non-drag part of the linearised a_tot^{n+1/2}). */
+static void kick_semi_implicit(int ndim, const orc_forces *f, double dt, double inv_tau,
+                               const double x[3], double p[3], const double pg[3], double a[3]) {
+  double Om = f->Omega, q = f->q;
+  double ae[3] = {0, 0, 0}, Ja[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (ndim == 3 && f->kind == F_SHEARBOX) {
+    ae[0] = 2.0 * Om * (p[1] + q * Om * x[0]);
+    ae[1] = -2.0 * Om * p[0];
+    Ja[0][1] = 2.0 * Om;
+    Ja[1][0] = -2.0 * Om;
+  } else if (ndim == 3 && f->kind == F_SHEARBOX_FARGO) {
+    ae[0] = 2.0 * Om * p[1];
+    ae[1] = (q - 2.0) * Om * p[0];
+    Ja[0][1] = 2.0 * Om;
+    Ja[1][0] = (q - 2.0) * Om;
+  } else if (f->kind == F_CONST) {
+    for (int d = 0; d < 3; ++d) ae[d] = f->g[d];
+  }
+  if ((f->kind == F_SHEARBOX || f->kind == F_SHEARBOX_FARGO) && f->vertical_gravity && ndim == 3)
+    ae[2] = -Om * Om * x[2];
+  double M[3][4];
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) M[r][k] = (r == k ? 1.0 + 0.5 * dt * inv_tau : 0.0) - 0.5 * dt * Ja[r][k];
+    M[r][3] = dt * (ae[r] + (pg[r] - p[r]) * inv_tau);
+  }
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+    if (piv != col)
+      for (int k = 0; k < 4; ++k) { double tmp = M[col][k]; M[col][k] = M[piv][k]; M[piv][k] = tmp; }
+    for (int r = col + 1; r < 3; ++r) {
+      double fct = M[r][col] / M[col][col];
+      for (int k = col; k < 4; ++k) M[r][k] -= fct * M[col][k];
+    }
+  }
+  double dv[3];
+  for (int r = 2; r >= 0; --r) {
+    double s = M[r][3];
+    for (int k = r + 1; k < 3; ++k) s -= M[r][k] * dv[k];
+    dv[r] = s / M[r][r];
+  }
+  for (int d = ndim; d < 3; ++d) dv[d] = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    /* non-drag acceleration at the mean velocity */
+    a[d] = ae[d];
+    for (int k = 0; k < 3; ++k) a[d] += 0.5 * Ja[d][k] * dv[k];
+    p[d] += dv[d];
+  }
+}
+
 static void kick(int geom, int ndim, const orc_forces *f, double dt, double inv_tau,
                  const double x[3], double p[3], const double pg[3], double a[3]) {
+  if (f->integrator == 1 && geom == G_CART) {
+    kick_semi_implicit(ndim, f, dt, inv_tau, x, p, pg, a);
+    return;
+  }
   double hh = dt * inv_tau;                       /* Delta t / tau_s          */
   double e = exp(-hh);                            /* e^{A Delta t}            */
   double c = -expm1(-hh);                         /* 1 - e = h1 / tau_s       */

@@ -22,7 +22,7 @@ def make_box(bd: dict) -> Box:
 def make_forces(fd: dict) -> Forces:
     return Forces(kind=fd.get("kind", "none"), Omega=fd.get("Omega", 0.0), q=fd.get("q", 0.0),
                   GM=fd.get("GM", 0.0), vertical_gravity=bool(fd.get("vertical_gravity", False)),
-                  g=tuple(fd.get("g", (0.0, 0.0, 0.0))))
+                  g=tuple(fd.get("g", (0.0, 0.0, 0.0))), integrator=fd.get("integrator", "em"))
 
 
 def locate_cells(box: Box, x: np.ndarray):

@@ -191,6 +191,50 @@ def test_fargo_epicycle_converges_at_second_order():
     assert e1 < err("shearbox", 0.01)
 
 
+@pytest.mark.parametrize("kind", ["shearbox", "shearbox_fargo", "none"])
+def test_semi_implicit_kick_matches_printed_lambda(kind):
+    """Semi-implicit kick (Sec. 3.2, Eq. semi-implicit, a_linear, Lambda):
+    the oracle solves Lambda dv = dt a_tot by elimination from the Jacobian;
+    the paper prints Lambda for plain drag (diag(1 + b), b = dt/(2 tau)), the
+    standard shearing box ([[1+b, -Omega dt], [Omega dt, 1+b]]) and orbital
+    advection ([[1+b, -Omega dt], [(1 - q/2) Omega dt, 1+b]])."""
+    rng = np.random.default_rng(13)
+    for _ in range(30):
+        Om, q = rng.uniform(0.5, 2.0), rng.uniform(0.5, 1.9)
+        tau, dt = 10 ** rng.uniform(-2, 2), rng.uniform(1e-3, 0.5)
+        F = O.Forces(kind=kind, Omega=Om, q=q, vertical_gravity=kind != "none", integrator="si")
+        x, v, vg = rng.normal(size=3), rng.normal(size=3), rng.normal(size=3)
+        pn, a = O.kick("cart", 3, F, dt, 1.0 / tau, x, v, vg)
+        b = dt / (2 * tau)
+        if kind == "shearbox":
+            ae = np.array([2 * Om * (v[1] + q * Om * x[0]), -2 * Om * v[0], -Om * Om * x[2]])
+            L = np.array([[1 + b, -Om * dt, 0], [Om * dt, 1 + b, 0], [0, 0, 1 + b]])
+        elif kind == "shearbox_fargo":
+            ae = np.array([2 * Om * v[1], (q - 2) * Om * v[0], -Om * Om * x[2]])
+            L = np.array([[1 + b, -Om * dt, 0], [(1 - q / 2) * Om * dt, 1 + b, 0], [0, 0, 1 + b]])
+        else:
+            ae = np.zeros(3)
+            L = np.diag([1 + b] * 3)
+        dv = np.linalg.solve(L, dt * (ae + (vg - v) / tau))
+        np.testing.assert_allclose(pn, v + dv, rtol=1e-12, atol=1e-14)
+
+
+def test_semi_implicit_equals_exponential_midpoint_without_drag():
+    """tau = inf: the semi-implicit and exponential midpoint kicks coincide
+    (Sec. 4.2: identical results in this limit)."""
+    Om, q, A = 1.0, 1.5, 0.4
+    for kind, vy0 in (("shearbox", -2 * Om * A), ("shearbox_fargo", (q - 2) * Om * A)):
+        xe, pe = np.array([A, 0.0, 0.0]), np.array([0.0, vy0, 0.0])
+        xs, ps = xe.copy(), pe.copy()
+        Fe = O.Forces(kind=kind, Omega=Om, q=q)
+        Fs = O.Forces(kind=kind, Omega=Om, q=q, integrator="si")
+        for _ in range(50):
+            O.push_one("cart", Fe, "tau", np.inf, 0.4, xe, pe)
+            O.push_one("cart", Fs, "tau", np.inf, 0.4, xs, ps)
+        np.testing.assert_allclose(xs, xe, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(ps, pe, rtol=0, atol=1e-12)
+
+
 def test_circular_orbit_is_exact():
     """Kepler, zero inclination, e = 0: integration is exact (Sec. 4.4)."""
     F = O.Forces(kind="pointmass", GM=1.0)
@@ -331,11 +375,19 @@ def test_deceleration_test_reproduces_printed_l1_errors():
                        np.array([vgh, 0, 0]))
         return pn[0]
 
+    Fs = O.Forces(integrator="si")
+
+    def si(vp, vgh, tau, dt):
+        pn, _ = O.kick("cart", 3, Fs, dt, 1.0 / tau, np.zeros(3), np.array([vp, 0, 0]),
+                       np.array([vgh, 0, 0]))
+        return pn[0]
+
     for key, tau in (("tau_0.2", 0.2), ("tau_0.02", 0.02)):
-        got = _decel_l1(tau, em)
-        want = gold["exponential_midpoint"][key]
-        # two printed significant digits
-        assert abs(got - want) <= 0.05 * want + 1e-30, (key, got, want)
+        for name, kick in (("exponential_midpoint", em), ("semi_implicit", si)):
+            got = _decel_l1(tau, kick)
+            want = gold[name][key]
+            # two printed significant digits
+            assert abs(got - want) <= 0.05 * want + 1e-30, (name, key, got, want)
 
 
 def test_deceleration_second_order_in_time():
