@@ -69,6 +69,12 @@ enum { DUST_BC_PERIODIC = 0, DUST_BC_SHEAR = 1, DUST_BC_OPEN = 2 };
 enum { DUST_FORCE_NONE = 0, DUST_FORCE_SHEARBOX = 1, DUST_FORCE_POINTMASS = 2,
        DUST_FORCE_CONST = 3, DUST_FORCE_SHEARBOX_FARGO = 4 };
 enum { DUST_DRAG_TAU = 0, DUST_DRAG_STOKES = 1, DUST_DRAG_SPECIES = 2 };
+/* Kick of the drift-kick-drift step: the exponential midpoint (Eq.
+ * exp_midpoint, the method of the paper), or the semi-implicit kick of Sec.
+ * 3.2 (Eq. semi-implicit with Eq. a_linear and the Lambda matrices), kept for
+ * comparison: Cartesian boxes and the unfused step / phase calls only
+ * (DUST_EUNSUPPORTED otherwise). */
+enum { DUST_INTEGRATOR_EXPMID = 0, DUST_INTEGRATOR_SEMI_IMPLICIT = 1 };
 enum { DUST_PHASE_DRIFT1 = 1, DUST_PHASE_KICK = 2, DUST_PHASE_DRIFT2 = 4 };
 enum { DUST_BIN_CELL = 0, DUST_BIN_TILE = 1 };
 
@@ -121,6 +127,7 @@ typedef struct {
   double Omega, q, GM;
   double g[3];
   double t;
+  int32_t integrator;   /* DUST_INTEGRATOR_*: 0 = exponential midpoint */
 } dust_forces_t;
 
 /* Particle set, structure of arrays of length n (device memory).

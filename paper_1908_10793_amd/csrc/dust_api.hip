@@ -249,6 +249,7 @@ Forces forces_of(const dust_forces_t* f) {
   F.q = f->q;
   F.GM = f->GM;
   for (int d = 0; d < 3; ++d) F.g[d] = f->g[d];
+  F.integrator = f->integrator;
   return F;
 }
 
@@ -272,6 +273,10 @@ dust_status_t check_forces(Ctx* c, const dust_forces_t* f) {
   }
   if (c->drag_mode == DUST_DRAG_STOKES && !(f->GM > 0))
     return fail(DUST_EINVAL, "Stokes-number drag needs GM > 0");
+  if (f->integrator != DUST_INTEGRATOR_EXPMID && f->integrator != DUST_INTEGRATOR_SEMI_IMPLICIT)
+    return fail(DUST_EINVAL, "unknown integrator %d", f->integrator);
+  if (f->integrator == DUST_INTEGRATOR_SEMI_IMPLICIT && c->geom != GEOM_CART)
+    return fail(DUST_EUNSUPPORTED, "the semi-implicit kick is for Cartesian boxes");
   return DUST_OK;
 }
 
@@ -988,6 +993,8 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   c->last_stream = st;
   if (!(flags & DUST_STEP_FUSED) && (s = ensure_ws(c, p->n))) return s;
   if (flags & DUST_STEP_FUSED) {
+    if (frc->integrator != DUST_INTEGRATOR_EXPMID)
+      return fail(DUST_EUNSUPPORTED, "the fused step takes the exponential midpoint kick only");
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
     if (fused_plan_reserve(c->plan, p->n) != DUST_OK) return fail(DUST_ENOMEM, "deferred-particle list");
@@ -1091,6 +1098,8 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
     return s;
   if (!std::isfinite(dt)) return fail(DUST_EINVAL, "dt not finite");
   if (steps < 1 || steps > 1000) return fail(DUST_EINVAL, "steps out of 1..1000");
+  if (frc && frc->integrator != DUST_INTEGRATOR_EXPMID)
+    return fail(DUST_EUNSUPPORTED, "the autotuner times the fused step (exponential midpoint kick)");
   if (flags & ~(DUST_STEP_APPLY_FEEDBACK | DUST_STEP_DIAG | DUST_STEP_NO_FILL))
     return fail(DUST_EINVAL, "autotune flags: only APPLY_FEEDBACK, DIAG, NO_FILL");
   hipStream_t st = (hipStream_t)stream;

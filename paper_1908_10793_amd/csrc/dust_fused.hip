@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(256)
       A c, psi;
       propagator<A>(dt * it, c, psi);
       KickOut<A> o;
-      kick_any<A, GEOM, NDIM>(B, f, dt, c, psi, wh, mom, sl, o);
+      kick_any<A, GEOM, NDIM>(B, f, dt, it, c, psi, wh, mom, sl, o);
       A q[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
       for (int k = 0; k < nc; ++k) {

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       A c, psi;
       propagator<A>(dt * it, c, psi);
       KickOut<A> o;
-      kick_any<A, GEOM, NDIM>(B, f, dt, c, psi, w, mom, sl, o);
+      kick_any<A, GEOM, NDIM>(B, f, dt, it, c, psi, w, mom, sl, o);
       TW* imp[4] = {imp0, imp1, imp2, imp3};
       bool fin = isfinite(double(o.e));
 #pragma unroll

@@ -192,9 +192,59 @@ __device__ __forceinline__ bool drift_any(const Box& b, const Forces& f, bool fi
     return drift<A, GEOM, NDIM, U, true>(b, f, first, h, t_after, idx, off, mom);
   return drift<A, GEOM, NDIM, U, false>(b, f, first, h, t_after, idx, off, mom);
 }
+// Semi-implicit kick (Sec. 3.2, Eq. semi-implicit, a_linear, Lambda),
+// Cartesian, in the increment form of kick(): Lambda dp = dt (a(x, p^n) +
+// s it) with Lambda = I - (dt/2) d a_tot/dv (diagonal 1 + dt it / 2, the
+// rotation block of the shearing box), it = 1/tau; o.j = dp - dt a(p_bar),
+// o.e = p_bar . o.j.  A comparison integrator: the unfused kernels only.
+template <typename A, int NDIM>
+__device__ __forceinline__ void kick_si(const Forces& f, A dt, A it, const Where<A>& w, const A p[3],
+                                        const A s[3], KickOut<A>& o) {
+  A ae[3] = {A(0), A(0), A(0)};
+  A j01 = A(0), j10 = A(0);   // d a_x / d v_y, d a_y / d v_x
+  const A Om = A(f.Omega), q = A(f.q);
+  if (NDIM == 3 && (f.kind == FORCE_SHEARBOX || f.kind == FORCE_FARGO)) {
+    const bool fg = f.kind == FORCE_FARGO;
+    j01 = A(2) * Om;
+    j10 = fg ? (q - A(2)) * Om : A(-2) * Om;
+    ae[0] = A(2) * Om * (p[1] + (fg ? A(0) : q * Om * w.x[0]));
+    ae[1] = j10 * p[0];
+    if (f.vertical_gravity) ae[2] = -Om * Om * w.x[2];
+  } else if (f.kind == FORCE_CONST) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ae[d] = A(f.g[d]);
+  }
+  const A dg = A(1) + A(0.5) * dt * it;   // diagonal of Lambda
+  A r[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r[d] = d < NDIM ? dt * (ae[d] + s[d] * it) : A(0);
+  // [[dg, -dt/2 j01], [-dt/2 j10, dg]] (dp_x, dp_y) = (r_x, r_y)
+  const A m01 = A(-0.5) * dt * j01, m10 = A(-0.5) * dt * j10;
+  const A den = A(1) / (dg * dg - m01 * m10);
+  o.dp[0] = (dg * r[0] - m01 * r[1]) * den;
+  o.dp[1] = (dg * r[1] - m10 * r[0]) * den;
+  o.dp[2] = NDIM > 2 ? r[2] / dg : A(0);
+  if (NDIM < 2) o.dp[1] = A(0);
+  const A a[3] = {ae[0] + A(0.5) * j01 * o.dp[1], ae[1] + A(0.5) * j10 * o.dp[0], ae[2]};
+  o.e = A(0);
+  o.cells = A(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    o.j[d] = d < NDIM ? o.dp[d] - dt * a[d] : A(0);
+    if (d < NDIM) o.e += (p[d] + A(0.5) * o.dp[d]) * o.j[d];
+  }
+}
+
+// (it: 1/tau, which the semi-implicit kick takes instead of c and psi)
 template <typename A, int GEOM, int NDIM>
-__device__ __forceinline__ void kick_any(const Box& b, const Forces& f, A dt, A c, A psi, const Where<A>& w,
-                                         const A p[3], const A s[3], KickOut<A>& o) {
+__device__ __forceinline__ void kick_any(const Box& b, const Forces& f, A dt, A it, A c, A psi,
+                                         const Where<A>& w, const A p[3], const A s[3], KickOut<A>& o) {
+  if constexpr (GEOM == GEOM_CART) {
+    if (f.integrator == DUST_INTEGRATOR_SEMI_IMPLICIT) {
+      kick_si<A, NDIM>(f, dt, it, w, p, s, o);
+      return;
+    }
+  }
   if (GEOM == GEOM_CART && NDIM == 3 && f.kind == FORCE_FARGO)
     kick<A, GEOM, NDIM, true>(b, f, dt, c, psi, w, p, s, o);
   else

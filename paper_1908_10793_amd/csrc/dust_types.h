@@ -43,6 +43,7 @@ struct Forces {
   int32_t kind, vertical_gravity;
   double Omega, q, GM;
   double g[3];
+  int32_t integrator;   // DUST_INTEGRATOR_*
 };
 
 #define DUST_MAX_SPECIES 16

@@ -54,7 +54,7 @@ class dust_box_t(ctypes.Structure):
 class dust_forces_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("vertical_gravity", ctypes.c_int32),
                 ("Omega", ctypes.c_double), ("q", ctypes.c_double), ("GM", ctypes.c_double),
-                ("g", ctypes.c_double * 3), ("t", ctypes.c_double)]
+                ("g", ctypes.c_double * 3), ("t", ctypes.c_double), ("integrator", ctypes.c_int32)]
 
 
 class dust_particles_t(ctypes.Structure):
@@ -158,10 +158,14 @@ def _stream(stream):
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+INTEGRATOR = {"em": 0, "si": 1}
+
+
 def forces_t(kind="none", Omega=0.0, q=0.0, GM=0.0, vertical_gravity=False, g=(0.0, 0.0, 0.0),
-             t=0.0) -> dust_forces_t:
+             t=0.0, integrator="em") -> dust_forces_t:
     f = dust_forces_t()
     f.kind = FORCE[kind] if isinstance(kind, str) else int(kind)
+    f.integrator = INTEGRATOR[integrator] if isinstance(integrator, str) else int(integrator)
     f.vertical_gravity = int(bool(vertical_gravity))
     f.Omega, f.q, f.GM, f.t = float(Omega), float(q), float(GM), float(t)
     for d in range(3):
@@ -411,4 +415,5 @@ def forces_for(w, t=None) -> dust_forces_t:
     fd = w.forces
     return forces_t(fd.get("kind", "none"), fd.get("Omega", 0.0), fd.get("q", 0.0),
                     fd.get("GM", 0.0), fd.get("vertical_gravity", False),
-                    fd.get("g", (0.0, 0.0, 0.0)), w.t0 if t is None else t)
+                    fd.get("g", (0.0, 0.0, 0.0)), w.t0 if t is None else t,
+                    fd.get("integrator", "em"))

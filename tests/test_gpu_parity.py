@@ -4,6 +4,8 @@ Every workload is one of the paper-shaped synthetic inputs at a size the
 oracle finishes in seconds, spanning several fused tiles with ragged edges.
 Each step is compared from identical inputs (see gpu_common).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -42,9 +44,11 @@ WORKLOADS = ["cart2d_f64", "shearing_box", "shearing_box_fargo", "cylindrical_di
              "batched_boxes"]
 
 
-def _run(name, fused, nsteps=3, arith=None, tile=None):
+def _run(name, fused, nsteps=3, arith=None, tile=None, integrator=None):
     dust = _dust()
     w = small(name)
+    if integrator:
+        w = dataclasses.replace(w, forces={**w.forces, "integrator": integrator})
     print(f"[parity] {name} fused={fused} n={w.n}", flush=True)
     ctx = dust.context_for(w)
     if arith:
@@ -104,3 +108,20 @@ def test_fused_fp64_arithmetic_variant_matches_oracle(name):
     """FP32 storage with FP64 per-particle arithmetic in the fused kernel (the
     default of curvilinear boxes) on the Cartesian workloads."""
     _run(name, fused=True, nsteps=2, arith="f64")
+
+
+@pytest.mark.parametrize("name", ["cart2d_f64", "shearing_box", "shearing_box_fargo", "batched_boxes"])
+def test_semi_implicit_unfused_step_matches_oracle(name):
+    """The semi-implicit comparison kick (Sec. 3.2) through the unfused step."""
+    _run(name, fused=False, integrator="si")
+
+
+def test_semi_implicit_is_refused_by_the_fused_step():
+    dust = _dust()
+    w = small("shearing_box")
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    fr = dust.forces_for(w)
+    fr.integrator = dust.INTEGRATOR["si"]
+    with pytest.raises(dust.DustError):
+        ctx.step(P, F, w.dt, fr, 1, dust.STEP_FUSED)
