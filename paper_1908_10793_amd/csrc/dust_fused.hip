@@ -1,22 +1,24 @@
 // Fused gather - exponential-midpoint push - deposit kernel (gfx950).
 //
 // One workgroup per grid tile of 256 cells and one thread per cell.  The
-// particles are binned tile by tile (tile-major keys), so the particles of a
-// cell are one contiguous range, and the thread of a cell walks that range.
+// particles are binned tile by tile (tile-major keys of the cell each reaches
+// in the first half drift); the particles of a wave's cells occupy one range
+// of slots, level-major (iteration j of the wave touches consecutive slots).
 // The workgroup stages the gas velocity of the tile plus a two-cell halo in
-// LDS (FP64).  For every particle the thread does the half drift, the weights
-// at x^{n+1/2}, the gather from LDS, the kick, the drag impulse and energy,
-// the second half drift and the store.  Deposits of particles whose cell at
-// x^{n+1/2} is still the thread's own cell are summed in registers over the
-// 27-cell stencil of that cell; the sums go to an FP64 deposit window in LDS
-// once per thread.  Particles that moved to a neighbouring cell add their 27
-// contributions to the window with FP64 LDS atomics (gfx950 executes FP64 and
-// integer LDS atomics about twenty times faster than FP32 ones).  The window
-// is then added to the global deposit arrays with one atomic per touched cell
-// and channel, scaled by the inverse cell volume.  A particle whose stencil
-// at x^{n+1/2} leaves the window (it moved more than one cell since the last
-// binning, or wrapped across a periodic face) does the same arithmetic
-// against global memory.
+// LDS (one 4-vector of the storage type per cell; periodic images beyond the
+// box along periodic axes).  For every particle the thread does the half
+// drift, the weights at x^{n+1/2}, the gather from LDS, the kick, the drag
+// impulse and energy, the second half drift and the store.  Deposits are
+// summed in registers over the 27 cells around the thread's cell: fully for
+// a particle in that cell, through weights shifted to it for a particle in a
+// neighbouring cell (the stencil planes outside go to an FP64 LDS window with
+// atomics, which gfx950 executes about twenty times faster than FP32 ones);
+// the sums go to the window once per thread.  The window is then added to the
+// global deposit arrays with one atomic per touched cell and channel, scaled
+// by the inverse cell volume.  A particle whose stencil at x^{n+1/2} leaves
+// the window (it moved more than one cell beyond its tile since the binning,
+// or crossed a shear-periodic face) is stepped by a second kernel against
+// global memory.
 #include <algorithm>
 #include <vector>
 
