@@ -119,6 +119,10 @@ def _declare(L):
                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
                            ctypes.POINTER(_Diag)]
     L.orc_step.restype = ctypes.c_int
+    L.orc_drag_source.argtypes = [ctypes.POINTER(_Box), ctypes.POINTER(_Forces), ctypes.c_int,
+                                  ctypes.POINTER(_Particles), ctypes.POINTER(_Fields),
+                                  ctypes.c_double]
+    L.orc_drag_source.restype = None
     L.orc_gl_integrate_poly.argtypes = [_dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     L.orc_gl_integrate_poly.restype = ctypes.c_double
     L.orc_push_one.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Forces), ctypes.c_int,
@@ -410,6 +414,32 @@ def step(box: Box, forces: Forces, drag_mode: str, x, p, drag, mass, active,
         p[:, d] = ps[d]
     return Diag(np.array(dg.p_part[:]), np.array(dg.p_grid[:]), dg.e_part, dg.e_grid,
                 dg.sum_abs_j, dg.max_cells_per_step, dg.n_inactive)
+
+
+def drag_source(box: Box, forces: Forces, drag_mode: str, x, p, drag, mass, active,
+                fields: Fields, dt: float) -> None:
+    """Drag source of the gas predictor (Sec. 3.1, Eq. Delta_vp and f_D with
+    tau <- max(tau, dt)) at the particles' current positions, accumulated
+    into the momentum channels of fields.dep (force densities, canonical
+    components); the energy channel is left as it is."""
+    for a in (x, p):
+        assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape[1] == 3
+    xs = [np.ascontiguousarray(x[:, d]) for d in range(3)]
+    ps = [np.ascontiguousarray(p[:, d]) for d in range(3)]
+    drag = np.ascontiguousarray(drag, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    assert active.dtype == np.int32 and active.flags.c_contiguous
+    P = _Particles()
+    P.n = x.shape[0]
+    for d in range(3):
+        P.x[d] = _ptr(xs[d])
+        P.p[d] = _ptr(ps[d])
+    P.drag = _ptr(drag)
+    P.mass = _ptr(mass)
+    P.active = active.ctypes.data_as(_ip)
+    fc = fields.c()
+    lib().orc_drag_source(ctypes.byref(box.c()), ctypes.byref(forces.c()), DRAG[drag_mode],
+                          ctypes.byref(P), ctypes.byref(fc), dt)
 
 
 # --------------------------------------------------------------------------

@@ -906,6 +906,49 @@ int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles
 }
 
 /* ------------------------------------------------------------------ */
+/* Drag source of the gas predictor (Sec. 3.1, Eq. Delta_vp and f_D):    */
+/* at the particles' current positions x^n, the slip between the        */
+/* weighted gas velocity and the particle velocity, times m_p / tau_s,p, */
+/* deposited with the same weights as a force density:                  */
+/*   <f_D>_i -= (1/dV_i) sum_p (m_p / tau'_p) W(x_p - x_i) dv_p,          */
+/* with the stiffness limiter tau' = max(tau, dt) the paper takes from   */
+/* Bai & Stone (2010).  reading: the momentum channels are the canonical */
+/* ones of the step's deposit, so the slip is taken between canonical    */
+/* momenta at the particle (the phi components become torques, R_p f_phi */
+/* or r_p f_theta and r_p sin(theta_p) f_phi).  Accumulates into the     */
+/* momentum channels; the energy channel is not touched (the predictor's */
+/* source has no energy part).                                           */
+
+void orc_drag_source(const orc_box *b, const orc_forces *f, int drag_mode,
+                     const orc_particles *P, orc_fields *fl, double dt) {
+  int nc = b->geom == G_CART ? b->ndim : 3;
+  int c2 = b->ndim > 2 ? 1 : 0;
+  for (int64_t ip = 0; ip < P->n; ++ip) {
+    if (!P->active[ip]) continue;
+    double x[3] = {P->x[0][ip], P->x[1][ip], P->x[2][ip]};
+    stencil s;
+    if (!make_stencil(b, x, &s)) continue;
+    double rho_p, vg[3], sc[3];
+    gather(b, fl, &s, &rho_p, vg);
+    canon_scale(b->geom, x, sc);
+    double tau = 1.0 / inverse_tau(b->geom, drag_mode, f, P->drag[ip], x);
+    double tau_lim = tau > dt ? tau : dt;
+    double k = P->mass[ip] / tau_lim;
+    double q[3];
+    for (int m = 0; m < nc; ++m) q[m] = k * (vg[m] * sc[m] - P->p[m][ip]);
+    for (int c = -c2; c <= c2; ++c)
+      for (int bb = -1; bb <= 1; ++bb)
+        for (int a = -1; a <= 1; ++a) {
+          double w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1];
+          int i = s.cell[0] + a, j = s.cell[1] + bb, kk = s.cell[2] + c;
+          int64_t id = gidx(b, i, j, kk);
+          double dv = cell_volume(b, i, j, kk);
+          for (int m = 0; m < nc; ++m) fl->dep[m][id] -= w * q[m] / dv;
+        }
+  }
+}
+
+/* ------------------------------------------------------------------ */
 /* One particle pushed through gas given as a function of position      */
 /* (physical components in the local basis): drift, kick, drift, with no */
 /* grid and no boundaries.  For tests against analytic solutions.       */

@@ -394,7 +394,8 @@ def test_deceleration_second_order_in_time():
     """Sec. 4.1 temporal study, tau = 2, t_f = 1, with the gas predictor /
     corrector of Sec. 3.1 wrapped around the full oracle step (drift,
     gather, kick, deposit): the gas is advanced to the half step with the
-    drag source of Eq. f_D before the step and corrected with the deposited
+    drag source of Eq. f_D deposited on the grid (oracle drag_source) before
+    the step and corrected with the deposited
     impulse after it.  The position error against the exact solution (Eq.
     deceleration_solution) falls as dt^2 and total momentum stays at
     round-off."""
@@ -418,8 +419,16 @@ def test_deceleration_second_order_in_time():
         active = np.ones(N, np.int32)
         t = 0.0
         for s in range(int(round(1.0 / dt))):
-            # predictor: uniform gas, drag source of Eq. f_D with tau <- max(tau, dt)
-            vgh = vg + 0.5 * dt * eps * (p[0, 0] - vg) / max(tau, dt)
+            # predictor: drag source of Eq. f_D (tau <- max(tau, dt)) at x^n,
+            # deposited on the grid; gas at the half level (v^n + v*)/2
+            fields.vel[0][...] = vg
+            for dd in fields.dep:
+                dd[...] = 0.0
+            O.drag_source(box, O.Forces(), "tau", x, p, np.full(N, tau), mass, active, fields, dt)
+            O.fold_ghosts(box, O.Forces(), t, fields)
+            fD = fields.dep[0][0, 1:-1, 1:-1]
+            assert np.ptp(fD) <= 1e-13 * max(abs(fD).max(), 1e-300)
+            vgh = vg + 0.5 * dt * fD.mean() / 1.0
             fields.vel[0][...] = vgh
             d = O.step(box, O.Forces(), "tau", x, p, np.full(N, tau), mass, active, fields, dt,
                        t, apply_feedback=False)
