@@ -295,6 +295,24 @@ dust_status_t dust_push_expmid(void *ctx, dust_particles_t *p, const void *const
 dust_status_t dust_deposit(void *ctx, const dust_particles_t *p, const void *const impulse[4],
                            dust_fields_t *f, void *stream);
 
+/* Drag source of the gas predictor (Sec. 3.1, Eq. Delta_vp and f_D): for
+ * each particle with a cell, at its current position x^n, the slip between
+ * the gas velocity weighted as in dust_gather and the particle velocity,
+ * times m_p / tau'_p with the stiffness limiter tau' = max(tau, dt) of Bai &
+ * Stone (2010), is subtracted from the momentum channels with the gather's
+ * weights over the cell volume:
+ *   dep[c] -= (1/dV) W (m_p / tau'_p) (s_c v_g,c - p_c),
+ * c < nc, s_c the canonical factor of the particle (1, R, r, r sin theta),
+ * so dep holds force densities in canonical components (torques for the
+ * angular channels).  Accumulates (does not clear); the energy channel is
+ * neither read nor written, but must be given.  Reads the gas ghosts as
+ * stored.  tau = +inf contributes nothing; tau <= dt is limited to dt.
+ * The drag mode's arrays (drag, mass or the species tables) are required
+ * as for the kick; frc (required) gives GM for Stokes numbers.  dt: finite
+ * and > 0, else DUST_EINVAL. */
+dust_status_t dust_drag_source(void *ctx, const dust_particles_t *p, dust_fields_t *f, double dt,
+                               const dust_forces_t *frc, void *stream);
+
 /* Fold deposits in periodic / shear-periodic ghosts onto their partners
  * (the transpose of dust_fill_ghosts at time t; the energy channel crossing a
  * shear face gains +/- q Omega L_x D_y) and clear those ghosts. */

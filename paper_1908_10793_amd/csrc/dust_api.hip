@@ -958,6 +958,30 @@ dust_status_t dust_deposit(void* ctx, const dust_particles_t* p, const void* con
   });
 }
 
+dust_status_t dust_drag_source(void* ctx, const dust_particles_t* p, dust_fields_t* f, double dt,
+                               const dust_forces_t* frc, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, true)) || (s = check_fields(c, f, true, true)) ||
+      (s = check_forces(c, frc)) || (s = check_drag(c, p)))
+    return s;
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(DUST_EINVAL, "dt must be finite and positive");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  Forces F = forces_of(frc);
+  return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+    using TS = decltype(ts);
+    using A = decltype(ta);
+    launch_drag_source<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), F,
+                              c->species_d, c->drag_mode, dt, c->diag, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
 dust_status_t dust_apply_feedback(void* ctx, dust_fields_t* f, void* stream) {
   g_err.clear();
   if (check_ctx(ctx)) return DUST_EINVAL;

@@ -165,6 +165,73 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
     }
 }
 
+// Drag source of the gas predictor (Sec. 3.1, Eq. Delta_vp and f_D): at the
+// particle's current position, the canonical slip between the weighted gas
+// velocity and the particle, times m / max(tau, dt) (the stiffness limiter
+// of Bai & Stone 2010), subtracted from the momentum channels with the
+// gather's weights over the cell volume.  inv_dt = 1/dt.
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
+__global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* boxes, int nbox,
+                                                     FView<TS> fl, Forces f, const Species* sp,
+                                                     int drag_mode, A inv_dt, DiagDev* dg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  int idx[3];
+  A off[3], mom[3];
+  int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
+  if (b < 0) return;
+  const Box& B = boxes[b];
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
+  Stencil<A> s;
+  stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
+  Where<A> w;
+  where<A, GEOM, NDIM, U>(B, idx, off, w);
+  // slip s_c v_g,c - p_c as a weighted sum of per-cell differences (keeps
+  // its relative accuracy where the velocities are much larger than it)
+  A sl[3] = {A(0), A(0), A(0)};
+#pragma unroll
+  for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+    for (int bb = -1; bb <= 1; ++bb) {
+      A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) {
+        A wt = s.w[0][a + 1] * wbc;
+#pragma unroll
+        for (int m = 0; m < nc; ++m)
+          sl[m] += wt * (A(gas_comp(B, fl, nullptr, m, idx[0] + a, idx[1] + bb, idx[2] + c)) * w.sc[m] -
+                         mom[m]);
+      }
+    }
+  int sidx = p.species ? p.species[i] : 0;
+  if (sidx >= sp->n) {
+    flag(dg, DUST_FLAG_BAD_CELL);
+    sidx = 0;
+  }
+  A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
+  A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
+  A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
+  A k = m * (it < inv_dt ? it : inv_dt);
+  A q[3];
+#pragma unroll
+  for (int c = 0; c < nc; ++c) q[c] = k * sl[c];
+#pragma unroll
+  for (int c = -c2; c <= c2; ++c)
+#pragma unroll
+    for (int bb = -1; bb <= 1; ++bb) {
+      A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) {
+        int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
+        A wv = s.w[0][a + 1] * wbc * A(inv_volume(B, ii, jj, kk));
+        int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
+        for (int m2 = 0; m2 < nc; ++m2) unsafeAtomicAdd(&fl.dep[m2][id], TS(-wv * q[m2]));
+      }
+    }
+}
+
 // Dispatch on the (geometry, dimension) shared by the context's boxes.
 #define DUST_GEOM_SWITCH(geom, ndim, unif, CALL)                      \
   do {                                                                \
@@ -515,6 +582,17 @@ void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, in
                                       0, st, p, boxes, nbox, fl, imp[0], imp[1], imp[2], imp[3], dg));
 }
 
+template <typename TS, typename A>
+void launch_drag_source(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
+                        const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
+                        double dt, DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_drag_source<TS, A, G_, D_, U_>), dim3(blocks_for(p.n)),
+                                      dim3(256), 0, st, p, boxes, nbox, fl, f, sp, drag_mode,
+                                      A(1.0 / dt), dg));
+}
+
 template <typename TS>
 void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
                  double* xg, hipStream_t st) {
@@ -612,7 +690,10 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
 
 #define DUST_INST_DRIFT(TS, A)                                                                    \
   template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, int, int, int, const Forces&,   \
-                                    double, const double*, double, int, DiagDev*, hipStream_t);
+                                    double, const double*, double, int, DiagDev*, hipStream_t);         \
+  template void launch_drag_source<TS, A>(const PView<TS>&, const Box*, int, int, int, int,        \
+                                          const FView<TS>&, const Forces&, const Species*, int,     \
+                                          double, DiagDev*, hipStream_t);
 
 DUST_INST_DRIFT(float, double)
 DUST_INST_DRIFT(float, float)

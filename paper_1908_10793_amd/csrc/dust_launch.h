@@ -44,6 +44,13 @@ template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                     const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st);
 
+// Drag source of the gas predictor (Eq. f_D, tau <- max(tau, dt)) at the
+// particles' current positions, accumulated into the momentum channels of fl.
+template <typename TS, typename A>
+void launch_drag_source(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
+                        const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
+                        double dt, DiagDev* dg, hipStream_t st);
+
 // Ghost fill of the gas of one box at *tdev + toff; with xg (the context's
 // FP64 x-ghost buffer), also the FP64 x-ghost layer of a shear-periodic box.
 template <typename TS>

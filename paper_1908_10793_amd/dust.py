@@ -78,7 +78,7 @@ EXPORTS = ["dust_ctx_create", "dust_ctx_destroy", "dust_ctx_set_arith", "dust_ct
            "dust_ctx_grid_size", "dust_ctx_status", "dust_last_error", "dust_bin",
            "dust_fill_ghosts", "dust_gather", "dust_push_expmid", "dust_deposit",
            "dust_fold_ghosts", "dust_apply_feedback", "dust_step", "dust_ctx_set_profile",
-           "dust_ctx_profile", "dust_ctx_autotune"]
+           "dust_ctx_profile", "dust_ctx_autotune", "dust_drag_source"]
 
 _lib = None
 
@@ -115,6 +115,9 @@ def load_library(path: str = LIB_PATH):
     L.dust_deposit.argtypes = [_vp, ctypes.POINTER(dust_particles_t), _vp * 4,
                                ctypes.POINTER(dust_fields_t), _vp]
     L.dust_apply_feedback.argtypes = [_vp, ctypes.POINTER(dust_fields_t), _vp]
+    L.dust_drag_source.argtypes = [_vp, ctypes.POINTER(dust_particles_t),
+                                   ctypes.POINTER(dust_fields_t), ctypes.c_double,
+                                   ctypes.POINTER(dust_forces_t), _vp]
     L.dust_step.argtypes = [_vp, ctypes.POINTER(dust_particles_t), ctypes.POINTER(dust_fields_t),
                             ctypes.c_double, ctypes.POINTER(dust_forces_t), i32, i32, _vp]
     L.dust_ctx_autotune.argtypes = [_vp, ctypes.POINTER(dust_particles_t),
@@ -348,6 +351,13 @@ class Context:
                           for d in range(4)])
         _check(load_library().dust_deposit(self.handle, ctypes.byref(pt), imp, ctypes.byref(f),
                                            _stream(stream)))
+
+    def drag_source(self, P, F, dt, forces: dust_forces_t, stream=None):
+        """dust_drag_source: the predictor's drag force density (Eq. f_D with
+        tau <- max(tau, dt)) added to F["dep"]'s momentum channels."""
+        pt, f = self.particles_t(P), self.fields_t(F)
+        _check(load_library().dust_drag_source(self.handle, ctypes.byref(pt), ctypes.byref(f),
+                                               float(dt), ctypes.byref(forces), _stream(stream)))
 
     def apply_feedback(self, F, stream=None):
         f = self.fields_t(F)
