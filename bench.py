@@ -13,7 +13,9 @@ region.
 
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
 (the fused tile kernel, timed with HIP events on its own stream inside the
-timed region) and the FP64 CPU oracle timed on a bounded sample.
+timed region) and the FP64 CPU oracle timed on a bounded sample; beside
+them, outside the timed step, the gas predictor's drag source on the same
+particles and gas ("drag_source").
 """
 from __future__ import annotations
 
@@ -287,6 +289,22 @@ def main():
     graph_value = N * K / (e0.elapsed_time(e1) * 1e-3)
     t += K * w.dt
     ctx.status()
+    # the gas predictor's drag source (Eq. f_D) on the same particles and gas,
+    # reported beside the step (not part of it): one launch per call
+    fr = dust.forces_for(w, t)
+    ctx.drag_source(P, F, w.dt, fr)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(K):
+        ctx.drag_source(P, F, w.dt, fr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ds_s = e0.elapsed_time(e1) * 1e-3 / K
+    ds_bytes = (28.0 + 1.0 + 36.0 / ppc) * N       # state + species + gas read / deposit RMW
+    drag_source = {"kernel": "k_drag_source", "us_per_launch": round(ds_s * 1e6, 2),
+                   "algorithmic_bytes_per_launch": ds_bytes,
+                   "achieved": round(ds_bytes / ds_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(ds_bytes / ds_s / 1e9 / HBM_PEAK_GBS, 4)}
     out = {
         "metric": "particle-steps/s (gather+exp-midpoint push+deposit)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -302,6 +320,7 @@ def main():
                    "deposit_accum": "f32 registers per cell, f64 LDS tile window, f32 HBM atomics"},
         "roofline": roof,
         "graph_value": graph_value,
+        "drag_source": drag_source,
         "diag": {"momentum_residual": res, "max_cells_per_step": diag["max_cells_per_step"],
                  "n_fallback": diag["n_fallback"], "flags": diag["flag_names"],
                  "steps": diag["steps"]},

@@ -170,66 +170,257 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
 // velocity and the particle, times m / max(tau, dt) (the stiffness limiter
 // of Bai & Stone 2010), subtracted from the momentum channels with the
 // gather's weights over the cell volume.  inv_dt = 1/dt.
+// Each thread takes DS_PPT particles 64 slots apart (a workgroup covers
+// 256 * DS_PPT consecutive slots) and sums the contributions of consecutive
+// ones with the same host cell in registers (the particles of a cell sit 64
+// slots apart in the level-major layout of the fused step), so a cell's
+// stencil is deposited once per run instead of once per particle.  Where
+// the workgroup's particles share a box and their stencils fit a window of
+// DS_WIN_BYTES per array, the box is workgroup-uniform, the window's gas
+// velocity is staged in LDS, the gathers read it there, the deposits go to
+// an LDS window and that window is added to HBM once; otherwise gathers and
+// deposits go to HBM.  Correct for any particle order.
+static constexpr int DS_WIN_BYTES = 24 * 1024;
+static constexpr int DS_PPT = 8;
+
+struct DsWindow {
+  int o[3], ext[3];
+  int64_t cells;
+};
+
+// The particles of one thread (see k_drag_source).  WIN: every particle
+// with a cell lies in box ub (workgroup-uniform) inside window wd.
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool WIN>
+__device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxes, int nbox, int ub,
+                                             const FView<TS>& fl, const Forces& f, const Species* sp,
+                                             int drag_mode, A inv_dt, DiagDev* dg, int64_t base,
+                                             TS* win, const TS* gwin, const DsWindow& wd) {
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
+  constexpr int NT = NDIM > 2 ? 27 : 9;
+  // register sums of the current run of particles with host cell `cur`
+  A acc[NT][3];
+  int64_t cur = -1;
+  int cb = 0, cidx[3] = {0, 0, 0};
+  auto flush = [&]() {
+    const Box& B = WIN ? boxes[ub] : boxes[cb];
+    double iv[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) iv[d][a] = d < NDIM ? B.ax[d].ivol[cidx[d] + a] : 1.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int a = t % 3, bb = (t / 3) % 3, cc = NDIM > 2 ? t / 9 : 1;
+      const int ii = cidx[0] + a - 1, jj = cidx[1] + bb - 1, kk = cidx[2] + cc - 1;
+      const A v = A(iv[0][a] * iv[1][bb] * iv[2][cc]);
+      if constexpr (WIN) {
+        const int64_t e = (ii - wd.o[0]) + (int64_t)wd.ext[0] * ((jj - wd.o[1]) + (int64_t)wd.ext[1] * (kk - wd.o[2]));
+#pragma unroll
+        for (int m = 0; m < nc; ++m) atomicAdd(&win[m * wd.cells + e], TS(-acc[t][m] * v));
+      } else {
+        const int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
+        for (int m = 0; m < nc; ++m) unsafeAtomicAdd(&fl.dep[m][id], TS(-acc[t][m] * v));
+      }
+    }
+  };
+  for (int j = 0; j < DS_PPT; ++j) {
+    const int64_t i = base + 64 * j;
+    if (i >= p.n) break;
+    int idx[3];
+    A off[3], mom[3];
+    int b;
+    if constexpr (WIN) {
+      // every particle with a valid cell is in box ub (the window test)
+      const Box& B = boxes[ub];
+      const int64_t c = p.cell[i];
+      if (c < 0) continue;
+      if (c < B.cell_base || c >= B.cell_base + B.ncell) {
+        flag(dg, DUST_FLAG_BAD_CELL);
+        continue;
+      }
+      unravel(B, c - B.cell_base, idx);
+      bool bad = false, nonfinite = false;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
+        mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+        bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
+        nonfinite |= !isfinite(double(mom[d]));
+      }
+      if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+      if (nonfinite) flag(dg, DUST_FLAG_NONFINITE);
+      b = ub;
+    } else {
+      b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
+      if (b < 0) continue;
+    }
+    const Box& B = WIN ? boxes[ub] : boxes[b];
+    const int64_t c = p.cell[i];
+    if (c != cur) {
+      if (cur >= 0) flush();
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc[t][m] = A(0);
+      cur = c;
+      cb = b;
+      cidx[0] = idx[0];
+      cidx[1] = idx[1];
+      cidx[2] = idx[2];
+    }
+    Stencil<A> s;
+    stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
+    Where<A> w;
+    where<A, GEOM, NDIM, U>(B, idx, off, w);
+    // slip s_c v_g,c - p_c as a weighted sum of per-cell differences (keeps
+    // its relative accuracy where the velocities are much larger than it)
+    A sl[3] = {A(0), A(0), A(0)};
+    int64_t e0 = 0;
+    if constexpr (WIN)
+      e0 = (idx[0] - wd.o[0]) + (int64_t)wd.ext[0] * ((idx[1] - wd.o[1]) + (int64_t)wd.ext[1] * (idx[2] - wd.o[2]));
+#pragma unroll
+    for (int cc = -c2; cc <= c2; ++cc)
+#pragma unroll
+      for (int bb = -1; bb <= 1; ++bb) {
+        A wbc = s.w[1][bb + 1] * s.w[2][cc + 1];
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+          A wt = s.w[0][a + 1] * wbc;
+#pragma unroll
+          for (int m = 0; m < nc; ++m) {
+            A g;
+            if constexpr (WIN)
+              g = A(gwin[m * wd.cells + e0 + a + (int64_t)wd.ext[0] * (bb + (int64_t)wd.ext[1] * cc)]);
+            else
+              g = A(gas_comp(B, fl, nullptr, m, idx[0] + a, idx[1] + bb, idx[2] + cc));
+            sl[m] += wt * (g * w.sc[m] - mom[m]);
+          }
+        }
+      }
+    int sidx = p.species ? p.species[i] : 0;
+    if (sidx >= sp->n) {
+      flag(dg, DUST_FLAG_BAD_CELL);
+      sidx = 0;
+    }
+    A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
+    A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
+    A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
+    A k = m * (it < inv_dt ? it : inv_dt);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      A wt = s.w[0][t % 3] * s.w[1][(t / 3) % 3] * s.w[2][NDIM > 2 ? t / 9 : 1];
+#pragma unroll
+      for (int mm = 0; mm < nc; ++mm) acc[t][mm] += wt * (k * sl[mm]);
+    }
+  }
+  if (cur >= 0) flush();
+}
+
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* boxes, int nbox,
                                                      FView<TS> fl, Forces f, const Species* sp,
                                                      int drag_mode, A inv_dt, DiagDev* dg) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  int idx[3];
-  A off[3], mom[3];
-  int b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
-  if (b < 0) return;
-  const Box& B = boxes[b];
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
-  constexpr int c2 = NDIM > 2 ? 1 : 0;
-  Stencil<A> s;
-  stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
-  Where<A> w;
-  where<A, GEOM, NDIM, U>(B, idx, off, w);
-  // slip s_c v_g,c - p_c as a weighted sum of per-cell differences (keeps
-  // its relative accuracy where the velocities are much larger than it)
-  A sl[3] = {A(0), A(0), A(0)};
-#pragma unroll
-  for (int c = -c2; c <= c2; ++c)
-#pragma unroll
-    for (int bb = -1; bb <= 1; ++bb) {
-      A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
-#pragma unroll
-      for (int a = -1; a <= 1; ++a) {
-        A wt = s.w[0][a + 1] * wbc;
-#pragma unroll
-        for (int m = 0; m < nc; ++m)
-          sl[m] += wt * (A(gas_comp(B, fl, nullptr, m, idx[0] + a, idx[1] + bb, idx[2] + c)) * w.sc[m] -
-                         mom[m]);
-      }
+  constexpr int WINN = DS_WIN_BYTES / (int)sizeof(TS);
+  __shared__ TS win[WINN];
+  __shared__ TS gwin[WINN];
+  __shared__ int s_lo[3], s_hi[3], s_blo, s_bhi;
+  if (threadIdx.x == 0) {
+    for (int d = 0; d < 3; ++d) {
+      s_lo[d] = 0x7fffffff;
+      s_hi[d] = -0x7fffffff;
     }
-  int sidx = p.species ? p.species[i] : 0;
-  if (sidx >= sp->n) {
-    flag(dg, DUST_FLAG_BAD_CELL);
-    sidx = 0;
+    s_blo = 0x7fffffff;
+    s_bhi = -1;
   }
-  A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
-  A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
-  A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
-  A k = m * (it < inv_dt ? it : inv_dt);
-  A q[3];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (256 * DS_PPT) + (int64_t)(threadIdx.x >> 6) * (64 * DS_PPT) +
+                       (threadIdx.x & 63);
+  // bounding box of the workgroup's host cells
+  {
+    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+    int blo = 0x7fffffff, bhi = -1;
+    for (int j = 0; j < DS_PPT; ++j) {
+      int64_t i = base + 64 * j;
+      if (i >= p.n) break;
+      int64_t c = p.cell[i];
+      if (c < 0) continue;
+      int b = find_box(boxes, nbox, c);
+      const Box& B = boxes[b];
+      if (c >= B.cell_base + B.ncell) continue;
+      int idx[3];
+      unravel(B, c - B.cell_base, idx);
 #pragma unroll
-  for (int c = 0; c < nc; ++c) q[c] = k * sl[c];
+      for (int d = 0; d < NDIM; ++d) {
+        lo[d] = idx[d] < lo[d] ? idx[d] : lo[d];
+        hi[d] = idx[d] > hi[d] ? idx[d] : hi[d];
+      }
+      blo = b < blo ? b : blo;
+      bhi = b > bhi ? b : bhi;
+    }
+    if (bhi >= 0) {
 #pragma unroll
-  for (int c = -c2; c <= c2; ++c)
+      for (int d = 0; d < NDIM; ++d) {
+        atomicMin(&s_lo[d], lo[d]);
+        atomicMax(&s_hi[d], hi[d]);
+      }
+      atomicMin(&s_blo, blo);
+      atomicMax(&s_bhi, bhi);
+    }
+  }
+  __syncthreads();
+  // window: the host cells' bounding box plus one cell on each side
+  const bool any = s_bhi >= 0;
+  DsWindow wd;
 #pragma unroll
-    for (int bb = -1; bb <= 1; ++bb) {
-      A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
+  for (int d = 0; d < 3; ++d) {
+    wd.o[d] = 0;
+    wd.ext[d] = 1;
+  }
+  if (any) {
 #pragma unroll
-      for (int a = -1; a <= 1; ++a) {
-        int ii = idx[0] + a, jj = idx[1] + bb, kk = idx[2] + c;
-        A wv = s.w[0][a + 1] * wbc * A(inv_volume(B, ii, jj, kk));
-        int64_t id = stored_index(B, ii, jj, kk);
+    for (int d = 0; d < NDIM; ++d) {
+      wd.o[d] = s_lo[d] - 1;
+      wd.ext[d] = s_hi[d] - s_lo[d] + 3;
+    }
+  }
+  wd.cells = (int64_t)wd.ext[0] * wd.ext[1] * wd.ext[2];
+  const bool use_win = any && s_blo == s_bhi && wd.cells * nc <= WINN;   // uniform
+  if (use_win) {
+    const int ub = __builtin_amdgcn_readfirstlane(s_blo);
+    const Box& B = boxes[ub];
+    for (int64_t e = threadIdx.x; e < wd.cells; e += blockDim.x) {
+      int ii = wd.o[0] + (int)(e % wd.ext[0]);
+      int jj = wd.o[1] + (int)((e / wd.ext[0]) % wd.ext[1]);
+      int kk = wd.o[2] + (int)(e / ((int64_t)wd.ext[0] * wd.ext[1]));
+      int64_t id = stored_index(B, ii, jj, kk);
 #pragma unroll
-        for (int m2 = 0; m2 < nc; ++m2) unsafeAtomicAdd(&fl.dep[m2][id], TS(-wv * q[m2]));
+      for (int m = 0; m < nc; ++m) {
+        win[m * wd.cells + e] = TS(0);
+        gwin[m * wd.cells + e] = fl.vel[m][id];
       }
     }
+    __syncthreads();
+    ds_particles<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
+                                             win, gwin, wd);
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < wd.cells; e += blockDim.x) {
+      int ii = wd.o[0] + (int)(e % wd.ext[0]);
+      int jj = wd.o[1] + (int)((e / wd.ext[0]) % wd.ext[1]);
+      int kk = wd.o[2] + (int)(e / ((int64_t)wd.ext[0] * wd.ext[1]));
+      int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
+      for (int m = 0; m < nc; ++m) {
+        TS v = win[m * wd.cells + e];
+        if (v != TS(0)) unsafeAtomicAdd(&fl.dep[m][id], v);
+      }
+    }
+  } else {
+    ds_particles<TS, A, GEOM, NDIM, U, false>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
+                                              win, gwin, wd);
+  }
 }
 
 // Dispatch on the (geometry, dimension) shared by the context's boxes.
@@ -588,7 +779,7 @@ void launch_drag_source(const PView<TS>& p, const Box* boxes, int nbox, int geom
                         double dt, DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
   DUST_GEOM_SWITCH(geom, ndim, unif,
-                   hipLaunchKernelGGL((k_drag_source<TS, A, G_, D_, U_>), dim3(blocks_for(p.n)),
+                   hipLaunchKernelGGL((k_drag_source<TS, A, G_, D_, U_>), dim3(blocks_for(p.n, 256 * DS_PPT)),
                                       dim3(256), 0, st, p, boxes, nbox, fl, f, sp, drag_mode,
                                       A(1.0 / dt), dg));
 }

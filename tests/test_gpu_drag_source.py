@@ -3,6 +3,8 @@ Eq. Delta_vp and f_D with tau <- max(tau, dt)) against the oracle, through
 the C ABI: element by element on small boxes of every geometry and drag
 mode, sampled cells of the 128^3 shearing box with 2^24 particles, extreme
 stopping times, removed particles, empty input and argument errors."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -109,6 +111,27 @@ def test_drag_source_matches_oracle(name, dtype):
     ref = _oracle_source(w, st, t, dt)
     err = _compare(w, st, ref, TOL[dtype], f"{name} {dtype}")
     print(f"[drag_source] {name} {dtype} n={w.n} err={err:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("name,dtype", [("shearing_box", "f32"), ("cylindrical_disk", "f64"),
+                                        ("batched", "f32")])
+def test_drag_source_any_particle_order(name, dtype):
+    """Shuffled particles (workgroups whose stencils do not fit the LDS
+    window deposit straight to HBM) and particles sorted by cell (window
+    path) both match the oracle."""
+    w = _workload(name, dtype)
+    rng = np.random.default_rng(8)
+    for label, perm in (("shuffled", rng.permutation(w.n)),
+                        ("sorted", np.argsort(w.cell, kind="stable"))):
+        kw = dict(cell=w.cell[perm], off=w.off[perm], mom=w.mom[perm])
+        for k in ("drag", "mass", "species"):
+            if getattr(w, k) is not None:
+                kw[k] = getattr(w, k)[perm]
+        wp = dataclasses.replace(w, **kw)
+        st = _gpu_source(wp, 0.1, float(w.dt))
+        ref = _oracle_source(wp, st, 0.1, float(w.dt))
+        err = _compare(wp, st, ref, TOL[dtype], f"{name} {label}")
+        print(f"[drag_source] {name} {dtype} {label} err={err:.2e}", flush=True)
 
 
 def test_drag_source_limiter_and_extreme_stopping_times():
