@@ -176,12 +176,15 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
 // slots apart in the level-major layout of the fused step), so a cell's
 // stencil is deposited once per run instead of once per particle.  Where
 // the workgroup's particles share a box and their stencils fit a window of
-// DS_WIN_BYTES per array, the box is workgroup-uniform, the window's gas
+// ds_win_cells<TS>() cells, the box is workgroup-uniform, the window's gas
 // velocity is staged in LDS, the gathers read it there, the deposits go to
-// an LDS window and that window is added to HBM once; otherwise gathers and
+// an FP64 LDS window (FP64 LDS atomics run ~20x faster than FP32 ones on
+// gfx950) and that window is added to HBM once; otherwise gathers and
 // deposits go to HBM.  Correct for any particle order.
-static constexpr int DS_WIN_BYTES = 24 * 1024;
 static constexpr int DS_PPT = 8;
+// window capacity in cells: 3 FP64 deposit channels + 3 gas components in
+// storage precision within 64 KiB of LDS
+template <typename TS> constexpr int ds_win_cells() { return sizeof(TS) == 4 ? 1600 : 1300; }
 
 struct DsWindow {
   int o[3], ext[3];
@@ -194,7 +197,7 @@ template <typename TS, typename A, int GEOM, int NDIM, bool U, bool WIN>
 __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxes, int nbox, int ub,
                                              const FView<TS>& fl, const Forces& f, const Species* sp,
                                              int drag_mode, A inv_dt, DiagDev* dg, int64_t base,
-                                             TS* win, const TS* gwin, const DsWindow& wd) {
+                                             double* win, const TS* gwin, const DsWindow& wd) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   constexpr int NT = NDIM > 2 ? 27 : 9;
@@ -217,7 +220,7 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
       if constexpr (WIN) {
         const int64_t e = (ii - wd.o[0]) + (int64_t)wd.ext[0] * ((jj - wd.o[1]) + (int64_t)wd.ext[1] * (kk - wd.o[2]));
 #pragma unroll
-        for (int m = 0; m < nc; ++m) atomicAdd(&win[m * wd.cells + e], TS(-acc[t][m] * v));
+        for (int m = 0; m < nc; ++m) atomicAdd(&win[m * wd.cells + e], double(-acc[t][m] * v));
       } else {
         const int64_t id = stored_index(B, ii, jj, kk);
 #pragma unroll
@@ -318,27 +321,75 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
   if (cur >= 0) flush();
 }
 
+// Window over the host cells [lo, hi] (plus one cell on each side) if it
+// holds at most cap cells.
+template <int NDIM>
+__device__ __forceinline__ bool ds_window(const int lo[3], const int hi[3], int64_t cap, DsWindow& wd) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    wd.o[d] = d < NDIM ? lo[d] - 1 : 0;
+    wd.ext[d] = d < NDIM ? hi[d] - lo[d] + 3 : 1;
+  }
+  wd.cells = (int64_t)wd.ext[0] * wd.ext[1] * wd.ext[2];
+  return wd.cells <= cap;
+}
+
+template <typename TS, int NC>
+__device__ __forceinline__ void ds_stage(const Box& B, const FView<TS>& fl, const DsWindow& wd, double* win,
+                                         TS* gwin, int lane, int nlanes) {
+  for (int64_t e = lane; e < wd.cells; e += nlanes) {
+    int ii = wd.o[0] + (int)(e % wd.ext[0]);
+    int jj = wd.o[1] + (int)((e / wd.ext[0]) % wd.ext[1]);
+    int kk = wd.o[2] + (int)(e / ((int64_t)wd.ext[0] * wd.ext[1]));
+    int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      win[m * wd.cells + e] = 0.0;
+      gwin[m * wd.cells + e] = fl.vel[m][id];
+    }
+  }
+}
+
+template <typename TS, int NC>
+__device__ __forceinline__ void ds_add_window(const Box& B, const FView<TS>& fl, const DsWindow& wd,
+                                              const double* win, int lane, int nlanes) {
+  for (int64_t e = lane; e < wd.cells; e += nlanes) {
+    int ii = wd.o[0] + (int)(e % wd.ext[0]);
+    int jj = wd.o[1] + (int)((e / wd.ext[0]) % wd.ext[1]);
+    int kk = wd.o[2] + (int)(e / ((int64_t)wd.ext[0] * wd.ext[1]));
+    int64_t id = stored_index(B, ii, jj, kk);
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      double v = win[m * wd.cells + e];
+      if (v != 0.0) unsafeAtomicAdd(&fl.dep[m][id], TS(v));
+    }
+  }
+}
+
+// Windows: one for the workgroup when its particles' window fits the LDS
+// capacity, else one per wave (a quarter of the capacity each) for the waves
+// whose particles' window fits that; the other waves go to HBM.
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* boxes, int nbox,
                                                      FView<TS> fl, Forces f, const Species* sp,
                                                      int drag_mode, A inv_dt, DiagDev* dg) {
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
-  constexpr int WINN = DS_WIN_BYTES / (int)sizeof(TS);
-  __shared__ TS win[WINN];
-  __shared__ TS gwin[WINN];
-  __shared__ int s_lo[3], s_hi[3], s_blo, s_bhi;
-  if (threadIdx.x == 0) {
+  constexpr int CAP = ds_win_cells<TS>();
+  __shared__ double win[3 * CAP];
+  __shared__ TS gwin[3 * CAP];
+  __shared__ int s_lo[4][3], s_hi[4][3], s_blo[4], s_bhi[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
     for (int d = 0; d < 3; ++d) {
-      s_lo[d] = 0x7fffffff;
-      s_hi[d] = -0x7fffffff;
+      s_lo[wave][d] = 0x7fffffff;
+      s_hi[wave][d] = -0x7fffffff;
     }
-    s_blo = 0x7fffffff;
-    s_bhi = -1;
+    s_blo[wave] = 0x7fffffff;
+    s_bhi[wave] = -1;
   }
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * (256 * DS_PPT) + (int64_t)(threadIdx.x >> 6) * (64 * DS_PPT) +
-                       (threadIdx.x & 63);
-  // bounding box of the workgroup's host cells
+  const int64_t base = (int64_t)blockIdx.x * (256 * DS_PPT) + (int64_t)wave * (64 * DS_PPT) + lane;
+  // bounding box of each wave's host cells
   {
     int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
     int blo = 0x7fffffff, bhi = -1;
@@ -363,64 +414,67 @@ __global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* box
     if (bhi >= 0) {
 #pragma unroll
       for (int d = 0; d < NDIM; ++d) {
-        atomicMin(&s_lo[d], lo[d]);
-        atomicMax(&s_hi[d], hi[d]);
+        atomicMin(&s_lo[wave][d], lo[d]);
+        atomicMax(&s_hi[wave][d], hi[d]);
       }
-      atomicMin(&s_blo, blo);
-      atomicMax(&s_bhi, bhi);
+      atomicMin(&s_blo[wave], blo);
+      atomicMax(&s_bhi[wave], bhi);
     }
   }
   __syncthreads();
-  // window: the host cells' bounding box plus one cell on each side
-  const bool any = s_bhi >= 0;
-  DsWindow wd;
+  // workgroup window (uniform decision)
+  int glo[3], ghi[3], gblo = 0x7fffffff, gbhi = -1;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    wd.o[d] = 0;
-    wd.ext[d] = 1;
+    glo[d] = 0x7fffffff;
+    ghi[d] = -0x7fffffff;
   }
-  if (any) {
+  for (int w = 0; w < 4; ++w) {
+    if (s_bhi[w] < 0) continue;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
-      wd.o[d] = s_lo[d] - 1;
-      wd.ext[d] = s_hi[d] - s_lo[d] + 3;
+      glo[d] = s_lo[w][d] < glo[d] ? s_lo[w][d] : glo[d];
+      ghi[d] = s_hi[w][d] > ghi[d] ? s_hi[w][d] : ghi[d];
     }
+    gblo = s_blo[w] < gblo ? s_blo[w] : gblo;
+    gbhi = s_bhi[w] > gbhi ? s_bhi[w] : gbhi;
   }
-  wd.cells = (int64_t)wd.ext[0] * wd.ext[1] * wd.ext[2];
-  const bool use_win = any && s_blo == s_bhi && wd.cells * nc <= WINN;   // uniform
-  if (use_win) {
-    const int ub = __builtin_amdgcn_readfirstlane(s_blo);
+  DsWindow wd;
+  const bool wg_win = gbhi >= 0 && gblo == gbhi && ds_window<NDIM>(glo, ghi, CAP * 3 / nc, wd);
+  if (wg_win) {
+    const int ub = __builtin_amdgcn_readfirstlane(gblo);
     const Box& B = boxes[ub];
-    for (int64_t e = threadIdx.x; e < wd.cells; e += blockDim.x) {
-      int ii = wd.o[0] + (int)(e % wd.ext[0]);
-      int jj = wd.o[1] + (int)((e / wd.ext[0]) % wd.ext[1]);
-      int kk = wd.o[2] + (int)(e / ((int64_t)wd.ext[0] * wd.ext[1]));
-      int64_t id = stored_index(B, ii, jj, kk);
-#pragma unroll
-      for (int m = 0; m < nc; ++m) {
-        win[m * wd.cells + e] = TS(0);
-        gwin[m * wd.cells + e] = fl.vel[m][id];
-      }
-    }
+    ds_stage<TS, nc>(B, fl, wd, win, gwin, threadIdx.x, blockDim.x);
     __syncthreads();
     ds_particles<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
                                              win, gwin, wd);
     __syncthreads();
-    for (int64_t e = threadIdx.x; e < wd.cells; e += blockDim.x) {
-      int ii = wd.o[0] + (int)(e % wd.ext[0]);
-      int jj = wd.o[1] + (int)((e / wd.ext[0]) % wd.ext[1]);
-      int kk = wd.o[2] + (int)(e / ((int64_t)wd.ext[0] * wd.ext[1]));
-      int64_t id = stored_index(B, ii, jj, kk);
-#pragma unroll
-      for (int m = 0; m < nc; ++m) {
-        TS v = win[m * wd.cells + e];
-        if (v != TS(0)) unsafeAtomicAdd(&fl.dep[m][id], v);
-      }
-    }
-  } else {
-    ds_particles<TS, A, GEOM, NDIM, U, false>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
-                                              win, gwin, wd);
+    ds_add_window<TS, nc>(B, fl, wd, win, threadIdx.x, blockDim.x);
+    return;   // uniform: the whole workgroup leaves here
   }
+  // per-wave windows (each wave decides for itself; barriers stay uniform)
+  int wlo[3], whi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    wlo[d] = s_lo[wave][d];
+    whi[d] = s_hi[wave][d];
+  }
+  const int qcap = CAP / 4;
+  double* wwin = win + wave * 3 * qcap;
+  TS* wgwin = gwin + wave * 3 * qcap;
+  const bool w_win = s_bhi[wave] >= 0 && s_blo[wave] == s_bhi[wave] &&
+                     ds_window<NDIM>(wlo, whi, qcap * 3 / nc, wd);
+  const int ub = __builtin_amdgcn_readfirstlane(s_blo[wave]);
+  if (w_win) ds_stage<TS, nc>(boxes[ub], fl, wd, wwin, wgwin, lane, 64);
+  __syncthreads();
+  if (w_win)
+    ds_particles<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
+                                             wwin, wgwin, wd);
+  else
+    ds_particles<TS, A, GEOM, NDIM, U, false>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
+                                              wwin, wgwin, wd);
+  __syncthreads();
+  if (w_win) ds_add_window<TS, nc>(boxes[ub], fl, wd, wwin, lane, 64);
 }
 
 // Dispatch on the (geometry, dimension) shared by the context's boxes.
