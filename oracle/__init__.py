@@ -123,6 +123,8 @@ def _declare(L):
                                   ctypes.POINTER(_Particles), ctypes.POINTER(_Fields),
                                   ctypes.c_double]
     L.orc_drag_source.restype = None
+    L.orc_deposit_mass.argtypes = [ctypes.POINTER(_Box), ctypes.POINTER(_Particles), _dp]
+    L.orc_deposit_mass.restype = None
     L.orc_gl_integrate_poly.argtypes = [_dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     L.orc_gl_integrate_poly.restype = ctypes.c_double
     L.orc_push_one.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Forces), ctypes.c_int,
@@ -440,6 +442,28 @@ def drag_source(box: Box, forces: Forces, drag_mode: str, x, p, drag, mass, acti
     fc = fields.c()
     lib().orc_drag_source(ctypes.byref(box.c()), ctypes.byref(forces.c()), DRAG[drag_mode],
                           ctypes.byref(P), ctypes.byref(fc), dt)
+
+
+def deposit_mass(box: Box, x, mass, active, rho_d) -> None:
+    """Dust density of the particles at global positions x (N,3): each
+    mass spread with the gather's weights over the cell volumes, added to
+    the ghosted array rho_d (ghosts included, unfolded)."""
+    assert x.dtype == np.float64 and x.flags.c_contiguous and x.shape[1] == 3
+    assert rho_d.dtype == np.float64 and rho_d.flags.c_contiguous
+    assert rho_d.size == int(np.prod(box.ghosted_shape))
+    xs = [np.ascontiguousarray(x[:, d]) for d in range(3)]
+    zeros = np.zeros(x.shape[0])
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    active = np.ascontiguousarray(active, dtype=np.int32)
+    P = _Particles()
+    P.n = x.shape[0]
+    for d in range(3):
+        P.x[d] = _ptr(xs[d])
+        P.p[d] = _ptr(zeros)
+    P.drag = _ptr(zeros)
+    P.mass = _ptr(mass)
+    P.active = active.ctypes.data_as(_ip)
+    lib().orc_deposit_mass(ctypes.byref(box.c()), ctypes.byref(P), _ptr(rho_d))
 
 
 # --------------------------------------------------------------------------

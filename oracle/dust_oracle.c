@@ -949,6 +949,30 @@ void orc_drag_source(const orc_box *b, const orc_forces *f, int drag_mode,
 }
 
 /* ------------------------------------------------------------------ */
+/* Dust density on the grid: each particle's mass spread with the same  */
+/* weights as the gather and the deposit, as a density (Sec. 3.4: the    */
+/* shape function is the particle's density profile; Sec. 4.3.1 compares */
+/* the resulting rho_D with eps rho_g).  Accumulates into rho_d (ghosts  */
+/* included, to be folded like the deposit).                             */
+
+void orc_deposit_mass(const orc_box *b, const orc_particles *P, double *rho_d) {
+  int c2 = b->ndim > 2 ? 1 : 0;
+  for (int64_t ip = 0; ip < P->n; ++ip) {
+    if (!P->active[ip]) continue;
+    double x[3] = {P->x[0][ip], P->x[1][ip], P->x[2][ip]};
+    stencil s;
+    if (!make_stencil(b, x, &s)) continue;
+    for (int c = -c2; c <= c2; ++c)
+      for (int bb = -1; bb <= 1; ++bb)
+        for (int a = -1; a <= 1; ++a) {
+          double w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1];
+          int i = s.cell[0] + a, j = s.cell[1] + bb, k = s.cell[2] + c;
+          rho_d[gidx(b, i, j, k)] += w * P->mass[ip] / cell_volume(b, i, j, k);
+        }
+  }
+}
+
+/* ------------------------------------------------------------------ */
 /* One particle pushed through gas given as a function of position      */
 /* (physical components in the local basis): drift, kick, drift, with no */
 /* grid and no boundaries.  For tests against analytic solutions.       */

@@ -20,6 +20,8 @@ Workloads (recipes in the design notes):
                      profile of the radial-drift test), Stokes numbers
   spherical_disk     the same disk in (r, theta, phi), stiff stopping times
   batched_boxes      several periodic 3-D boxes, four dust species
+  rigid_disk         uniform dust density in a cylindrical grid, radii from
+                     the inverse cumulative distribution (particle assignment)
 """
 from __future__ import annotations
 
@@ -231,6 +233,45 @@ def cylindrical_disk(n=(256, 512, 64), npart=2 ** 25, Rin=0.4, Rout=2.5, zh=0.15
                     [dict(rho=rho.astype(dt_np), vel=[zero.astype(dt_np), vphi.astype(dt_np),
                                                        zero.astype(dt_np)])],
                     dt, nsteps, drag=St, mass=np.full(npart, m, dtype=dt_np),
+                    apply_feedback=False)
+
+
+def rigid_disk(n_r=50, ratio=4, rb=0.5, re=5.5, nphi=4, nz=2, eps=1.0, shape="tsc",
+               dtype="f64", seed=5) -> Workload:
+    """Uniform dust density eps * rho_g (rho_g = 1) on a cylindrical grid
+    with n_r uniform radial zones in [rb, re] (Sec. 4.3.1, particle
+    assignment): N_p = ratio * n_r particles with radii from the inverse of
+    the cumulative distribution, R(xi) = sqrt(xi (re^2 - rb^2) + rb^2)
+    (Eq. Rxi_constant), xi = (k + 1/2) / N_p equally spaced; phi and z
+    uniform random (periodic, nphi x nz zones); gas at rest."""
+    r = rng(seed)
+    dt_np = np.float64 if dtype == "f64" else np.float32
+    npart = int(ratio * n_r)
+    fR = _uniform_faces(rb, re, n_r)
+    fP = _uniform_faces(0.0, 2 * np.pi, nphi)
+    fZ = _uniform_faces(-0.5, 0.5, nz)
+    xi = (np.arange(npart) + 0.5) / npart
+    R = np.sqrt(xi * (re ** 2 - rb ** 2) + rb ** 2)
+    phi = r.uniform(0.0, 2 * np.pi, npart)
+    z = r.uniform(-0.5, 0.5, npart)
+    idx, off = [], np.zeros((npart, 3))
+    for d, (x, f) in enumerate(((R, fR), (phi, fP), (z, fZ))):
+        i = np.clip(np.searchsorted(f, x, side="right") - 1, 0, len(f) - 2)
+        o = (x - 0.5 * (f[i] + f[i + 1])) / (f[i + 1] - f[i])
+        off[:, d] = np.clip(o, -0.5, np.nextafter(dt_np(0.5), dt_np(0)))
+        idx.append(i)
+    cell = (idx[0] + n_r * (idx[1] + nphi * idx[2])).astype(np.int32)
+    n = (n_r, nphi, nz)
+    gs = _ghost_shape(n, 3)
+    zero = np.zeros(gs, dtype=dt_np)
+    vol = np.pi * (re ** 2 - rb ** 2) * 1.0
+    m = eps * 1.0 * vol / npart
+    box = dict(geom="cyl", ndim=3, n=n, bc_lo=("open", "periodic", "periodic"),
+               bc_hi=("open", "periodic", "periodic"), shape=(shape,) * 3, faces=[fR, fP, fZ])
+    return Workload("rigid_disk", dtype, [box], dict(kind="none"), "tau", cell,
+                    off.astype(dt_np), np.zeros((npart, 3), dtype=dt_np),
+                    [dict(rho=np.ones(gs, dtype=dt_np), vel=[zero, zero, zero])], 0.01, 1,
+                    drag=np.ones(npart, dtype=dt_np), mass=np.full(npart, m, dtype=dt_np),
                     apply_feedback=False)
 
 
