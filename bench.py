@@ -15,7 +15,8 @@ Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
 (the fused tile kernel, timed with HIP events on its own stream inside the
 timed region) and the FP64 CPU oracle timed on a bounded sample; beside
 them, outside the timed step, the gas predictor's drag source on the same
-particles and gas ("drag_source").
+particles and gas ("drag_source") and the dust density deposit
+("mass_density").
 """
 from __future__ import annotations
 
@@ -305,6 +306,22 @@ def main():
                    "algorithmic_bytes_per_launch": ds_bytes,
                    "achieved": round(ds_bytes / ds_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(ds_bytes / ds_s / 1e9 / HBM_PEAK_GBS, 4)}
+    # the dust density deposit on the same particles (beside the step)
+    rho_d = torch.zeros_like(F["rho"])
+    ctx.deposit_mass(P, rho_d)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(K):
+        ctx.deposit_mass(P, rho_d)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    md_s = e0.elapsed_time(e1) * 1e-3 / K
+    md_bytes = (16.0 + 1.0 + 8.0 / ppc) * N          # cell + offsets + species, density RMW
+    mass_density = {"kernel": "k_mass_density", "us_per_launch": round(md_s * 1e6, 2),
+                    "algorithmic_bytes_per_launch": md_bytes,
+                    "achieved": round(md_bytes / md_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(md_bytes / md_s / 1e9 / HBM_PEAK_GBS, 4)}
+    del rho_d
     out = {
         "metric": "particle-steps/s (gather+exp-midpoint push+deposit)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -321,6 +338,7 @@ def main():
         "roofline": roof,
         "graph_value": graph_value,
         "drag_source": drag_source,
+        "mass_density": mass_density,
         "diag": {"momentum_residual": res, "max_cells_per_step": diag["max_cells_per_step"],
                  "n_fallback": diag["n_fallback"], "flags": diag["flag_names"],
                  "steps": diag["steps"]},

@@ -313,6 +313,16 @@ dust_status_t dust_deposit(void *ctx, const dust_particles_t *p, const void *con
 dust_status_t dust_drag_source(void *ctx, const dust_particles_t *p, dust_fields_t *f, double dt,
                                const dust_forces_t *frc, void *stream);
 
+/* Dust density on the grid (the particle mass spread with the shape
+ * function of Sec. 3.4, Eq. weight; compared with eps rho_g in Sec. 4.3.1):
+ * for each particle with a cell, rho_d += W m_p / dV on the 3^ndim stencil
+ * of its current position, with exactly the weights of dust_gather.
+ * rho_d: one ghosted array in the layout of the fields (all boxes, the
+ * context's precision); accumulates (does not clear); ghosts receive their
+ * share (fold them as a deposit channel with dust_fold_ghosts).  Masses
+ * from p->mass or the species mass table (else DUST_EINVAL). */
+dust_status_t dust_deposit_mass(void *ctx, const dust_particles_t *p, void *rho_d, void *stream);
+
 /* Fold deposits in periodic / shear-periodic ghosts onto their partners
  * (the transpose of dust_fill_ghosts at time t; the energy channel crossing a
  * shear face gains +/- q Omega L_x D_y) and clear those ghosts. */

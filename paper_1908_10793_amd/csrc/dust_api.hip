@@ -982,6 +982,28 @@ dust_status_t dust_drag_source(void* ctx, const dust_particles_t* p, dust_fields
   });
 }
 
+dust_status_t dust_deposit_mass(void* ctx, const dust_particles_t* p, void* rho_d, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  dust_status_t s;
+  if ((s = check_particles(c, p, false))) return s;
+  if (p->n > 0 && !p->mass && !c->have_mass_table)
+    return fail(DUST_EINVAL, "no per-particle mass and no species mass table");
+  if (!rho_d) return fail(DUST_EINVAL, "rho_d is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  c->last_stream = st;
+  return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+    using TS = decltype(ts);
+    using A = decltype(ta);
+    launch_mass_density<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, (TS*)rho_d,
+                               c->species_d, c->diag, st);
+    HIP_TRY(hipGetLastError());
+    return DUST_OK;
+  });
+}
+
 dust_status_t dust_apply_feedback(void* ctx, dust_fields_t* f, void* stream) {
   g_err.clear();
   if (check_ctx(ctx)) return DUST_EINVAL;

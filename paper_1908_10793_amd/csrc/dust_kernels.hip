@@ -191,14 +191,39 @@ struct DsWindow {
   int64_t cells;
 };
 
+// Host cell and offsets of particle i (the dust density needs no momenta):
+// the box index, or -1 without a cell (flags as load_particle).
+template <typename TS, typename A, int NDIM>
+__device__ __forceinline__ int load_position(const PView<TS>& p, const Box* boxes, int nbox, int64_t i,
+                                             int idx[3], A off[3], DiagDev* dg) {
+  const int64_t c = p.cell[i];
+  if (c < 0) return -1;
+  const int b = find_box(boxes, nbox, c);
+  const Box& B = boxes[b];
+  if (c >= B.cell_base + B.ncell) {
+    flag(dg, DUST_FLAG_BAD_CELL);
+    return -1;
+  }
+  unravel(B, c - B.cell_base, idx);
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
+    bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
+  }
+  if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+  return b;
+}
+
 // The particles of one thread (see k_drag_source).  WIN: every particle
 // with a cell lies in box ub (workgroup-uniform) inside window wd.
-template <typename TS, typename A, int GEOM, int NDIM, bool U, bool WIN>
+// MASS: the dust density instead (one channel, the particle mass, no gas).
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool WIN, bool MASS>
 __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxes, int nbox, int ub,
                                              const FView<TS>& fl, const Forces& f, const Species* sp,
                                              int drag_mode, A inv_dt, DiagDev* dg, int64_t base,
                                              double* win, const TS* gwin, const DsWindow& wd) {
-  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  constexpr int nc = MASS ? 1 : (GEOM == GEOM_CART ? NDIM : 3);
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   constexpr int NT = NDIM > 2 ? 27 : 9;
   // register sums of the current run of particles with host cell `cur`
@@ -217,14 +242,15 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
       const int a = t % 3, bb = (t / 3) % 3, cc = NDIM > 2 ? t / 9 : 1;
       const int ii = cidx[0] + a - 1, jj = cidx[1] + bb - 1, kk = cidx[2] + cc - 1;
       const A v = A(iv[0][a] * iv[1][bb] * iv[2][cc]);
+      constexpr A sgn = MASS ? A(1) : A(-1);   // the drag source is subtracted
       if constexpr (WIN) {
         const int64_t e = (ii - wd.o[0]) + (int64_t)wd.ext[0] * ((jj - wd.o[1]) + (int64_t)wd.ext[1] * (kk - wd.o[2]));
 #pragma unroll
-        for (int m = 0; m < nc; ++m) atomicAdd(&win[m * wd.cells + e], double(-acc[t][m] * v));
+        for (int m = 0; m < nc; ++m) atomicAdd(&win[m * wd.cells + e], double(sgn * acc[t][m] * v));
       } else {
         const int64_t id = stored_index(B, ii, jj, kk);
 #pragma unroll
-        for (int m = 0; m < nc; ++m) unsafeAtomicAdd(&fl.dep[m][id], TS(-acc[t][m] * v));
+        for (int m = 0; m < nc; ++m) unsafeAtomicAdd(&fl.dep[m][id], TS(sgn * acc[t][m] * v));
       }
     }
   };
@@ -244,17 +270,21 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
         continue;
       }
       unravel(B, c - B.cell_base, idx);
+      constexpr int nm = MASS ? 0 : nc;
       bool bad = false, nonfinite = false;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         off[d] = d < NDIM ? A(p.off[d][i]) : A(0);
-        mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
+        mom[d] = d < nm ? A(p.mom[d][i]) : A(0);
         bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
         nonfinite |= !isfinite(double(mom[d]));
       }
       if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
       if (nonfinite) flag(dg, DUST_FLAG_NONFINITE);
       b = ub;
+    } else if constexpr (MASS) {
+      b = load_position<TS, A, NDIM>(p, boxes, nbox, i, idx, off, dg);
+      if (b < 0) continue;
     } else {
       b = load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
       if (b < 0) continue;
@@ -275,47 +305,59 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
     }
     Stencil<A> s;
     stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
-    Where<A> w;
-    where<A, GEOM, NDIM, U>(B, idx, off, w);
-    // slip s_c v_g,c - p_c as a weighted sum of per-cell differences (keeps
-    // its relative accuracy where the velocities are much larger than it)
-    A sl[3] = {A(0), A(0), A(0)};
-    int64_t e0 = 0;
-    if constexpr (WIN)
-      e0 = (idx[0] - wd.o[0]) + (int64_t)wd.ext[0] * ((idx[1] - wd.o[1]) + (int64_t)wd.ext[1] * (idx[2] - wd.o[2]));
+    A q[3] = {A(0), A(0), A(0)};
+    if constexpr (MASS) {
+      int sidx = p.species ? p.species[i] : 0;
+      if (sidx >= sp->n) {
+        flag(dg, DUST_FLAG_BAD_CELL);
+        sidx = 0;
+      }
+      q[0] = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
+    } else {
+      Where<A> w;
+      where<A, GEOM, NDIM, U>(B, idx, off, w);
+      // slip s_c v_g,c - p_c as a weighted sum of per-cell differences (keeps
+      // its relative accuracy where the velocities are much larger than it)
+      A sl[3] = {A(0), A(0), A(0)};
+      int64_t e0 = 0;
+      if constexpr (WIN)
+        e0 = (idx[0] - wd.o[0]) + (int64_t)wd.ext[0] * ((idx[1] - wd.o[1]) + (int64_t)wd.ext[1] * (idx[2] - wd.o[2]));
 #pragma unroll
-    for (int cc = -c2; cc <= c2; ++cc)
+      for (int cc = -c2; cc <= c2; ++cc)
 #pragma unroll
-      for (int bb = -1; bb <= 1; ++bb) {
-        A wbc = s.w[1][bb + 1] * s.w[2][cc + 1];
+        for (int bb = -1; bb <= 1; ++bb) {
+          A wbc = s.w[1][bb + 1] * s.w[2][cc + 1];
 #pragma unroll
-        for (int a = -1; a <= 1; ++a) {
-          A wt = s.w[0][a + 1] * wbc;
+          for (int a = -1; a <= 1; ++a) {
+            A wt = s.w[0][a + 1] * wbc;
 #pragma unroll
-          for (int m = 0; m < nc; ++m) {
-            A g;
-            if constexpr (WIN)
-              g = A(gwin[m * wd.cells + e0 + a + (int64_t)wd.ext[0] * (bb + (int64_t)wd.ext[1] * cc)]);
-            else
-              g = A(gas_comp(B, fl, nullptr, m, idx[0] + a, idx[1] + bb, idx[2] + cc));
-            sl[m] += wt * (g * w.sc[m] - mom[m]);
+            for (int m = 0; m < nc; ++m) {
+              A g;
+              if constexpr (WIN)
+                g = A(gwin[m * wd.cells + e0 + a + (int64_t)wd.ext[0] * (bb + (int64_t)wd.ext[1] * cc)]);
+              else
+                g = A(gas_comp(B, fl, nullptr, m, idx[0] + a, idx[1] + bb, idx[2] + cc));
+              sl[m] += wt * (g * w.sc[m] - mom[m]);
+            }
           }
         }
+      int sidx = p.species ? p.species[i] : 0;
+      if (sidx >= sp->n) {
+        flag(dg, DUST_FLAG_BAD_CELL);
+        sidx = 0;
       }
-    int sidx = p.species ? p.species[i] : 0;
-    if (sidx >= sp->n) {
-      flag(dg, DUST_FLAG_BAD_CELL);
-      sidx = 0;
+      A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
+      A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
+      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
+      A k = m * (it < inv_dt ? it : inv_dt);
+#pragma unroll
+      for (int mm = 0; mm < nc; ++mm) q[mm] = k * sl[mm];
     }
-    A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
-    A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
-    A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
-    A k = m * (it < inv_dt ? it : inv_dt);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       A wt = s.w[0][t % 3] * s.w[1][(t / 3) % 3] * s.w[2][NDIM > 2 ? t / 9 : 1];
 #pragma unroll
-      for (int mm = 0; mm < nc; ++mm) acc[t][mm] += wt * (k * sl[mm]);
+      for (int mm = 0; mm < nc; ++mm) acc[t][mm] += wt * q[mm];
     }
   }
   if (cur >= 0) flush();
@@ -334,7 +376,7 @@ __device__ __forceinline__ bool ds_window(const int lo[3], const int hi[3], int6
   return wd.cells <= cap;
 }
 
-template <typename TS, int NC>
+template <typename TS, int NC, bool GAS>
 __device__ __forceinline__ void ds_stage(const Box& B, const FView<TS>& fl, const DsWindow& wd, double* win,
                                          TS* gwin, int lane, int nlanes) {
   for (int64_t e = lane; e < wd.cells; e += nlanes) {
@@ -345,7 +387,7 @@ __device__ __forceinline__ void ds_stage(const Box& B, const FView<TS>& fl, cons
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
       win[m * wd.cells + e] = 0.0;
-      gwin[m * wd.cells + e] = fl.vel[m][id];
+      if constexpr (GAS) gwin[m * wd.cells + e] = fl.vel[m][id];
     }
   }
 }
@@ -369,11 +411,11 @@ __device__ __forceinline__ void ds_add_window(const Box& B, const FView<TS>& fl,
 // Windows: one for the workgroup when its particles' window fits the LDS
 // capacity, else one per wave (a quarter of the capacity each) for the waves
 // whose particles' window fits that; the other waves go to HBM.
-template <typename TS, typename A, int GEOM, int NDIM, bool U>
-__global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* boxes, int nbox,
-                                                     FView<TS> fl, Forces f, const Species* sp,
-                                                     int drag_mode, A inv_dt, DiagDev* dg) {
-  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool MASS>
+__device__ __forceinline__ void ds_body(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl,
+                                        const Forces& f, const Species* sp, int drag_mode, A inv_dt,
+                                        DiagDev* dg) {
+  constexpr int nc = MASS ? 1 : (GEOM == GEOM_CART ? NDIM : 3);
   constexpr int CAP = ds_win_cells<TS>();
   __shared__ double win[3 * CAP];
   __shared__ TS gwin[3 * CAP];
@@ -444,9 +486,9 @@ __global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* box
   if (wg_win) {
     const int ub = __builtin_amdgcn_readfirstlane(gblo);
     const Box& B = boxes[ub];
-    ds_stage<TS, nc>(B, fl, wd, win, gwin, threadIdx.x, blockDim.x);
+    ds_stage<TS, nc, !MASS>(B, fl, wd, win, gwin, threadIdx.x, blockDim.x);
     __syncthreads();
-    ds_particles<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
+    ds_particles<TS, A, GEOM, NDIM, U, true, MASS>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
                                              win, gwin, wd);
     __syncthreads();
     ds_add_window<TS, nc>(B, fl, wd, win, threadIdx.x, blockDim.x);
@@ -465,16 +507,30 @@ __global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* box
   const bool w_win = s_bhi[wave] >= 0 && s_blo[wave] == s_bhi[wave] &&
                      ds_window<NDIM>(wlo, whi, qcap * 3 / nc, wd);
   const int ub = __builtin_amdgcn_readfirstlane(s_blo[wave]);
-  if (w_win) ds_stage<TS, nc>(boxes[ub], fl, wd, wwin, wgwin, lane, 64);
+  if (w_win) ds_stage<TS, nc, !MASS>(boxes[ub], fl, wd, wwin, wgwin, lane, 64);
   __syncthreads();
   if (w_win)
-    ds_particles<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
+    ds_particles<TS, A, GEOM, NDIM, U, true, MASS>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
                                              wwin, wgwin, wd);
   else
-    ds_particles<TS, A, GEOM, NDIM, U, false>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
+    ds_particles<TS, A, GEOM, NDIM, U, false, MASS>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
                                               wwin, wgwin, wd);
   __syncthreads();
   if (w_win) ds_add_window<TS, nc>(boxes[ub], fl, wd, wwin, lane, 64);
+}
+
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
+__global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* boxes, int nbox,
+                                                     FView<TS> fl, Forces f, const Species* sp,
+                                                     int drag_mode, A inv_dt, DiagDev* dg) {
+  ds_body<TS, A, GEOM, NDIM, U, false>(p, boxes, nbox, fl, f, sp, drag_mode, inv_dt, dg);
+}
+
+// Dust density: rho_d (fl.dep[0]) += m W / dV with the gather's weights.
+template <typename TS, typename A, int GEOM, int NDIM, bool U>
+__global__ void __launch_bounds__(256) k_mass_density(PView<TS> p, const Box* boxes, int nbox,
+                                                      FView<TS> fl, const Species* sp, DiagDev* dg) {
+  ds_body<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, fl, Forces{}, sp, DRAG_TAU, A(0), dg);
 }
 
 // Dispatch on the (geometry, dimension) shared by the context's boxes.
@@ -838,6 +894,17 @@ void launch_drag_source(const PView<TS>& p, const Box* boxes, int nbox, int geom
                                       A(1.0 / dt), dg));
 }
 
+template <typename TS, typename A>
+void launch_mass_density(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
+                         TS* rho_d, const Species* sp, DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  FView<TS> fl{};
+  fl.dep[0] = rho_d;
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_mass_density<TS, A, G_, D_, U_>), dim3(blocks_for(p.n, 256 * DS_PPT)),
+                                      dim3(256), 0, st, p, boxes, nbox, fl, sp, dg));
+}
+
 template <typename TS>
 void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
                  double* xg, hipStream_t st) {
@@ -938,7 +1005,9 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
                                     double, const double*, double, int, DiagDev*, hipStream_t);         \
   template void launch_drag_source<TS, A>(const PView<TS>&, const Box*, int, int, int, int,        \
                                           const FView<TS>&, const Forces&, const Species*, int,     \
-                                          double, DiagDev*, hipStream_t);
+                                          double, DiagDev*, hipStream_t);                          \
+  template void launch_mass_density<TS, A>(const PView<TS>&, const Box*, int, int, int, int, TS*,  \
+                                           const Species*, DiagDev*, hipStream_t);
 
 DUST_INST_DRIFT(float, double)
 DUST_INST_DRIFT(float, float)

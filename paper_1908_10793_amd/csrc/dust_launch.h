@@ -51,6 +51,11 @@ void launch_drag_source(const PView<TS>& p, const Box* boxes, int nbox, int geom
                         const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                         double dt, DiagDev* dg, hipStream_t st);
 
+// Dust density rho_d += m W / dV at the particles' current positions.
+template <typename TS, typename A>
+void launch_mass_density(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
+                         TS* rho_d, const Species* sp, DiagDev* dg, hipStream_t st);
+
 // Ghost fill of the gas of one box at *tdev + toff; with xg (the context's
 // FP64 x-ghost buffer), also the FP64 x-ghost layer of a shear-periodic box.
 template <typename TS>

@@ -78,7 +78,8 @@ EXPORTS = ["dust_ctx_create", "dust_ctx_destroy", "dust_ctx_set_arith", "dust_ct
            "dust_ctx_grid_size", "dust_ctx_status", "dust_last_error", "dust_bin",
            "dust_fill_ghosts", "dust_gather", "dust_push_expmid", "dust_deposit",
            "dust_fold_ghosts", "dust_apply_feedback", "dust_step", "dust_ctx_set_profile",
-           "dust_ctx_profile", "dust_ctx_autotune", "dust_drag_source"]
+           "dust_ctx_profile", "dust_ctx_autotune", "dust_drag_source",
+           "dust_deposit_mass"]
 
 _lib = None
 
@@ -115,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     L.dust_deposit.argtypes = [_vp, ctypes.POINTER(dust_particles_t), _vp * 4,
                                ctypes.POINTER(dust_fields_t), _vp]
     L.dust_apply_feedback.argtypes = [_vp, ctypes.POINTER(dust_fields_t), _vp]
+    L.dust_deposit_mass.argtypes = [_vp, ctypes.POINTER(dust_particles_t), _vp, _vp]
     L.dust_drag_source.argtypes = [_vp, ctypes.POINTER(dust_particles_t),
                                    ctypes.POINTER(dust_fields_t), ctypes.c_double,
                                    ctypes.POINTER(dust_forces_t), _vp]
@@ -358,6 +360,15 @@ class Context:
         pt, f = self.particles_t(P), self.fields_t(F)
         _check(load_library().dust_drag_source(self.handle, ctypes.byref(pt), ctypes.byref(f),
                                                float(dt), ctypes.byref(forces), _stream(stream)))
+
+    def deposit_mass(self, P, rho_d, stream=None):
+        """dust_deposit_mass: rho_d (one ghosted array) += m W / dV."""
+        if rho_d is not None and rho_d.numel() < self.grid_size()[0]:
+            raise ValueError("rho_d: fewer elements than the stored cells")
+        pt = self.particles_t(P)
+        _check(load_library().dust_deposit_mass(self.handle, ctypes.byref(pt),
+                                                _ptr(rho_d, self.real_dtype, "rho_d"),
+                                                _stream(stream)))
 
     def apply_feedback(self, F, stream=None):
         f = self.fields_t(F)
