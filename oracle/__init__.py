@@ -30,7 +30,7 @@ GEOM = {"cart": 0, "cyl": 1, "sph": 2}
 BC = {"periodic": 0, "shear": 1, "open": 2}
 SHAPE = {"cic": 0, "tsc": 1}
 FORCE = {"none": 0, "shearbox": 1, "pointmass": 2, "const": 3, "shearbox_fargo": 4}
-DRAG = {"tau": 0, "stokes": 1}
+DRAG = {"tau": 0, "stokes": 1, "epstein": 2}
 STEP_APPLY_FEEDBACK = 1
 STEP_FILL_GHOSTS = 2
 

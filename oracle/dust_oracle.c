@@ -26,7 +26,7 @@ enum { G_CART = 0, G_CYL = 1, G_SPH = 2 };
 enum { BC_PERIODIC = 0, BC_SHEAR = 1, BC_OPEN = 2 };
 enum { SH_CIC = 0, SH_TSC = 1 };
 enum { F_NONE = 0, F_SHEARBOX = 1, F_POINTMASS = 2, F_CONST = 3, F_SHEARBOX_FARGO = 4 };
-enum { DRAG_TAU = 0, DRAG_STOKES = 1 };
+enum { DRAG_TAU = 0, DRAG_STOKES = 1, DRAG_EPSTEIN = 2 };
 
 typedef struct {
   int32_t geom, ndim;
@@ -52,7 +52,8 @@ typedef struct {
   int64_t n;
   double *x[3];
   double *p[3];
-  const double *drag;  /* tau (DRAG_TAU, +inf allowed) or St (DRAG_STOKES) */
+  const double *drag;  /* tau (DRAG_TAU, +inf allowed), St (DRAG_STOKES) or
+                          rho_s a / v_t (DRAG_EPSTEIN) */
   const double *mass;
   int32_t *active;     /* 1 active, 0 removed through an open face */
 } orc_particles;
@@ -738,8 +739,11 @@ static void canon_scale(int geom, const double x[3], double sc[3]) {
   if (geom == G_SPH) { sc[1] = x[0]; sc[2] = x[0] * sin(x[1]); }
 }
 
+/* rho_p: the gas density weighted to the particle (Epstein regime, Sec. 2:
+ * tau_s = rho_s a / (rho_g v_t), the drag value holding rho_s a / v_t). */
 static double inverse_tau(int geom, int drag_mode, const orc_forces *f, double dval,
-                          const double x[3]) {
+                          const double x[3], double rho_p) {
+  if (drag_mode == DRAG_EPSTEIN) return rho_p / dval;
   if (drag_mode == DRAG_STOKES) {
     /* St = tau Omega_K with Omega_K = sqrt(GM/R^3), R the cylindrical radius */
     double R = geom == G_SPH ? x[0] * sin(x[1]) : x[0];
@@ -845,7 +849,7 @@ int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles
     canon_scale(b->geom, x, sc);
     for (int m = 0; m < 3; ++m) pg[m] = vg[m] * sc[m];
     /* kick */
-    double it = inverse_tau(b->geom, drag_mode, f, P->drag[ip], x), a[3] = {0, 0, 0};
+    double it = inverse_tau(b->geom, drag_mode, f, P->drag[ip], x, rho_p), a[3] = {0, 0, 0};
     kick(b->geom, b->ndim, f, dt, it, x, p, pg, a);
     /* drag impulse J = m (Delta p - dt a) and energy e = m vbar . dv */
     double m = P->mass[ip], q[4], e = 0.0;
@@ -931,7 +935,7 @@ void orc_drag_source(const orc_box *b, const orc_forces *f, int drag_mode,
     double rho_p, vg[3], sc[3];
     gather(b, fl, &s, &rho_p, vg);
     canon_scale(b->geom, x, sc);
-    double tau = 1.0 / inverse_tau(b->geom, drag_mode, f, P->drag[ip], x);
+    double tau = 1.0 / inverse_tau(b->geom, drag_mode, f, P->drag[ip], x, rho_p);
     double tau_lim = tau > dt ? tau : dt;
     double k = P->mass[ip] / tau_lim;
     double q[3];
@@ -986,7 +990,7 @@ void orc_push_one(int geom, int ndim, const orc_forces *f, int drag_mode, double
   if (gas) gas(x, vg);
   canon_scale(geom, x, sc);
   for (int m = 0; m < 3; ++m) pg[m] = vg[m] * sc[m];
-  double it = inverse_tau(geom, drag_mode, f, dragval, x);
+  double it = inverse_tau(geom, drag_mode, f, dragval, x, 1.0); /* no grid: unit density */
   kick(geom, ndim, f, dt, it, x, p, pg, a_out);
   drift_second(geom, f, 0.5 * dt, x, p);
 }
