@@ -68,7 +68,7 @@ enum { DUST_ARITH_F64 = 0, DUST_ARITH_F32 = 1 };              /* push math   */
 enum { DUST_BC_PERIODIC = 0, DUST_BC_SHEAR = 1, DUST_BC_OPEN = 2 };
 enum { DUST_FORCE_NONE = 0, DUST_FORCE_SHEARBOX = 1, DUST_FORCE_POINTMASS = 2,
        DUST_FORCE_CONST = 3, DUST_FORCE_SHEARBOX_FARGO = 4 };
-enum { DUST_DRAG_TAU = 0, DUST_DRAG_STOKES = 1, DUST_DRAG_SPECIES = 2 };
+enum { DUST_DRAG_TAU = 0, DUST_DRAG_STOKES = 1, DUST_DRAG_SPECIES = 2, DUST_DRAG_EPSTEIN = 3 };
 /* Kick of the drift-kick-drift step: the exponential midpoint (Eq.
  * exp_midpoint, the method of the paper), or the semi-implicit kick of Sec.
  * 3.2 (Eq. semi-implicit with Eq. a_linear and the Lambda matrices), kept for
@@ -132,7 +132,12 @@ typedef struct {
 
 /* Particle set, structure of arrays of length n (device memory).
  * drag: tau (DUST_DRAG_TAU; +inf allowed = no drag) or Stokes number
- *   St = tau Omega_K(R) (DUST_DRAG_STOKES); NULL with DUST_DRAG_SPECIES.
+ *   St = tau Omega_K(R) (DUST_DRAG_STOKES); NULL with DUST_DRAG_SPECIES;
+ *   with DUST_DRAG_EPSTEIN the constant C = rho_s a / v_t of the Epstein
+ *   stopping time tau = C / rho_g (Sec. 2), rho_g the gas density weighted
+ *   to the particle (at x^{n+1/2} in the step, at x^n in dust_drag_source;
+ *   the unfused step and dust_drag_source only: the fused step, the
+ *   autotuner and dust_push_expmid's KICK give DUST_EUNSUPPORTED).
  * mass: per particle, or NULL to take the species table.
  * species: uint8 index into the species table, or NULL (species 0).
  * id: optional int32 label carried along when particles are reordered

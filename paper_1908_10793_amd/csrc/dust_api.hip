@@ -442,7 +442,8 @@ void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phase
   if (phases & DUST_PHASE_DRIFT1)
     launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
   if (phases & DUST_PHASE_KICK)
-    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, vg, imp, dg, st);
+    launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt,
+                           nullptr, vg, imp, dg, st);
   if (phases & DUST_PHASE_DRIFT2)
     launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
 }
@@ -456,6 +457,7 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   A* ws = (A*)c->ws;  // gathered gas and impulses kept in the arithmetic precision
   A* vg[3] = {ws, ws + n, ws + 2 * n};
   A* imp[4] = {ws + 3 * n, ws + 4 * n, ws + 5 * n, ws + 6 * n};
+  A* rho_p = c->drag_mode == DUST_DRAG_EPSTEIN ? ws + 7 * n : nullptr;   // Epstein: gathered density
   for (int k = nc; k < 3; ++k) vg[k] = nullptr;
   for (int k = nc + 1; k < 4; ++k) imp[k] = nullptr;
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
@@ -465,10 +467,10 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
   launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv,
-                          (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, (A*)nullptr, vg, dflags, st);
+                          (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, rho_p, vg, dflags, st);
   const A* cvg[3] = {vg[0], vg[1], vg[2]};
-  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, cvg, imp,
-                        dg ? dg : dflags, st);
+  launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, rho_p,
+                        cvg, imp, dg ? dg : dflags, st);
   const A* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
   launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, cimp, dflags, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
@@ -592,7 +594,7 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
   *ctx = nullptr;
   if (!boxes || nbox < 1 || nbox > 4096) return fail(DUST_EINVAL, "need 1..4096 boxes");
   if (prec != DUST_F32 && prec != DUST_F64) return fail(DUST_EINVAL, "unknown precision %d", prec);
-  if (drag_mode < DUST_DRAG_TAU || drag_mode > DUST_DRAG_SPECIES)
+  if (drag_mode < DUST_DRAG_TAU || drag_mode > DUST_DRAG_EPSTEIN)
     return fail(DUST_EINVAL, "unknown drag mode %d", drag_mode);
   if (nspecies < 0 || nspecies > DUST_MAX_SPECIES)
     return fail(DUST_EINVAL, "nspecies must be 0..%d", DUST_MAX_SPECIES);
@@ -909,6 +911,8 @@ dust_status_t dust_push_expmid(void* ctx, dust_particles_t* p, const void* const
   int nc = ctx_nc(c);
   if (phases & DUST_PHASE_KICK) {
     if ((s = check_drag(c, p))) return s;
+    if (c->drag_mode == DUST_DRAG_EPSTEIN)
+      return fail(DUST_EUNSUPPORTED, "Epstein drag needs the gathered density: use the unfused dust_step");
     if (!vg_p) return fail(DUST_EINVAL, "vg_p is NULL");
     for (int k = 0; k < nc; ++k)
       if (p->n > 0 && !vg_p[k]) return fail(DUST_EINVAL, "vg_p[%d] is NULL", k);
@@ -1041,6 +1045,8 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   if (flags & DUST_STEP_FUSED) {
     if (frc->integrator != DUST_INTEGRATOR_EXPMID)
       return fail(DUST_EUNSUPPORTED, "the fused step takes the exponential midpoint kick only");
+    if (c->drag_mode == DUST_DRAG_EPSTEIN)
+      return fail(DUST_EUNSUPPORTED, "the fused step has no Epstein drag (unfused step only)");
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
     if (fused_plan_reserve(c->plan, p->n) != DUST_OK) return fail(DUST_ENOMEM, "deferred-particle list");
@@ -1146,6 +1152,8 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
   if (steps < 1 || steps > 1000) return fail(DUST_EINVAL, "steps out of 1..1000");
   if (frc && frc->integrator != DUST_INTEGRATOR_EXPMID)
     return fail(DUST_EUNSUPPORTED, "the autotuner times the fused step (exponential midpoint kick)");
+  if (c->drag_mode == DUST_DRAG_EPSTEIN)
+    return fail(DUST_EUNSUPPORTED, "the autotuner times the fused step (no Epstein drag)");
   if (flags & ~(DUST_STEP_APPLY_FEEDBACK | DUST_STEP_DIAG | DUST_STEP_NO_FILL))
     return fail(DUST_EINVAL, "autotune flags: only APPLY_FEEDBACK, DIAG, NO_FILL");
   hipStream_t st = (hipStream_t)stream;

@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(256) k_gather(PView<TS> p, const Box* boxes, i
 
 template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int nbox, Forces f,
-                                              const Species* sp, int drag_mode, A dt, const TW* vg0,
+                                              const Species* sp, int drag_mode, A dt, const TW* rho_p,
+                                              const TW* vg0,
                                               const TW* vg1, const TW* vg2, TW* imp0, TW* imp1,
                                               TW* imp2, TW* imp3, DiagDev* dg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,7 +94,9 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
       }
       A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
       A m = p.mass ? A(p.mass[i]) : A(sp->mass[s]);
-      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[s]), w);
+      // Epstein: tau = C / rho_g with the density gathered at x^{n+1/2}
+      A it = drag_mode == DRAG_EPSTEIN ? A(rho_p[i]) / dval
+                                       : inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[s]), w);
       A c, psi;
       propagator<A>(dt * it, c, psi);
       KickOut<A> o;
@@ -319,6 +322,8 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
       // slip s_c v_g,c - p_c as a weighted sum of per-cell differences (keeps
       // its relative accuracy where the velocities are much larger than it)
       A sl[3] = {A(0), A(0), A(0)};
+      A rg = A(0);   // gas density at the particle (Epstein drag)
+      const bool epstein = drag_mode == DRAG_EPSTEIN;
       int64_t e0 = 0;
       if constexpr (WIN)
         e0 = (idx[0] - wd.o[0]) + (int64_t)wd.ext[0] * ((idx[1] - wd.o[1]) + (int64_t)wd.ext[1] * (idx[2] - wd.o[2]));
@@ -330,6 +335,7 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
             A wt = s.w[0][a + 1] * wbc;
+            if (epstein) rg += wt * A(fl.rho[stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + cc)]);
 #pragma unroll
             for (int m = 0; m < nc; ++m) {
               A g;
@@ -348,7 +354,7 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
       }
       A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
       A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
-      A it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
+      A it = epstein ? rg / dval : inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
       A k = m * (it < inv_dt ? it : inv_dt);
 #pragma unroll
       for (int mm = 0; mm < nc; ++mm) q[mm] = k * sl[mm];
@@ -865,12 +871,12 @@ void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int
 
 template <typename TS, typename A, typename TW>
 void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
-                 const Forces& f, const Species* sp, int drag_mode, double dt,
+                 const Forces& f, const Species* sp, int drag_mode, double dt, const TW* rho_p,
                  const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
   DUST_GEOM_SWITCH(geom, ndim, unif,
                    hipLaunchKernelGGL((k_kick<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
-                                      0, st, p, boxes, nbox, f, sp, drag_mode, A(dt), vg[0], vg[1],
+                                      0, st, p, boxes, nbox, f, sp, drag_mode, A(dt), rho_p, vg[0], vg[1],
                                       vg[2], imp[0], imp[1], imp[2], imp[3], dg));
 }
 
@@ -994,7 +1000,7 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
                                          DiagDev*,                                                \
                                          hipStream_t);                                            \
   template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int, const Forces&, \
-                                       const Species*, int, double, const TW* const[3],           \
+                                       const Species*, int, double, const TW*, const TW* const[3], \
                                        TW* const[4], DiagDev*, hipStream_t);                      \
   template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int,            \
                                           const FView<TS>&, const TW* const[4], DiagDev*,         \

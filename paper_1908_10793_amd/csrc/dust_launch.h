@@ -37,8 +37,9 @@ void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int
                    const FView<TS>& fl, const double* xg, TW* rho_p, TW* const vg[3], DiagDev* dg,
                    hipStream_t st);
 template <typename TS, typename A, typename TW>
+// rho_p: the gathered gas density (Epstein drag; else unused, may be null).
 void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
-                 const Forces& f, const Species* sp, int drag_mode, double dt,
+                 const Forces& f, const Species* sp, int drag_mode, double dt, const TW* rho_p,
                  const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st);
 template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,

@@ -14,7 +14,8 @@ enum { BC_PERIODIC = DUST_BC_PERIODIC, BC_SHEAR = DUST_BC_SHEAR, BC_OPEN = DUST_
 enum { FORCE_NONE = DUST_FORCE_NONE, FORCE_SHEARBOX = DUST_FORCE_SHEARBOX,
        FORCE_POINTMASS = DUST_FORCE_POINTMASS, FORCE_CONST = DUST_FORCE_CONST,
        FORCE_FARGO = DUST_FORCE_SHEARBOX_FARGO };
-enum { DRAG_TAU = DUST_DRAG_TAU, DRAG_STOKES = DUST_DRAG_STOKES, DRAG_SPECIES = DUST_DRAG_SPECIES };
+enum { DRAG_TAU = DUST_DRAG_TAU, DRAG_STOKES = DUST_DRAG_STOKES, DRAG_SPECIES = DUST_DRAG_SPECIES,
+       DRAG_EPSTEIN = DUST_DRAG_EPSTEIN };
 
 // Weight formula of an axis: plain b-spline overlap (Cartesian, phi, z),
 // cylindrical radius, spherical radius, spherical polar angle.

@@ -23,7 +23,7 @@ BC = {"periodic": 0, "shear": 1, "open": 2}
 GEOM = {"cart": CART, "cyl": CYL, "sph": SPH}
 SHAPE = {"cic": CIC, "tsc": TSC}
 FORCE = {"none": 0, "shearbox": 1, "pointmass": 2, "const": 3, "shearbox_fargo": 4}
-DRAG = {"tau": 0, "stokes": 1, "species": 2}
+DRAG = {"tau": 0, "stokes": 1, "species": 2, "epstein": 3}
 PHASE_DRIFT1, PHASE_KICK, PHASE_DRIFT2 = 1, 2, 4
 BIN_CELL, BIN_TILE = 0, 1
 STEP_APPLY_FEEDBACK, STEP_FUSED, STEP_DIAG, STEP_GRAPH, STEP_NO_FILL = 1, 2, 4, 8, 16
