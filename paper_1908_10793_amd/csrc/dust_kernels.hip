@@ -221,7 +221,8 @@ __device__ __forceinline__ int load_position(const PView<TS>& p, const Box* boxe
 // The particles of one thread (see k_drag_source).  WIN: every particle
 // with a cell lies in box ub (workgroup-uniform) inside window wd.
 // MASS: the dust density instead (one channel, the particle mass, no gas).
-template <typename TS, typename A, int GEOM, int NDIM, bool U, bool WIN, bool MASS>
+// EPS: Epstein drag (stopping time from the gathered gas density).
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool WIN, bool MASS, bool EPS>
 __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxes, int nbox, int ub,
                                              const FView<TS>& fl, const Forces& f, const Species* sp,
                                              int drag_mode, A inv_dt, DiagDev* dg, int64_t base,
@@ -323,7 +324,6 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
       // its relative accuracy where the velocities are much larger than it)
       A sl[3] = {A(0), A(0), A(0)};
       A rg = A(0);   // gas density at the particle (Epstein drag)
-      const bool epstein = drag_mode == DRAG_EPSTEIN;
       int64_t e0 = 0;
       if constexpr (WIN)
         e0 = (idx[0] - wd.o[0]) + (int64_t)wd.ext[0] * ((idx[1] - wd.o[1]) + (int64_t)wd.ext[1] * (idx[2] - wd.o[2]));
@@ -335,7 +335,7 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
             A wt = s.w[0][a + 1] * wbc;
-            if (epstein) rg += wt * A(fl.rho[stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + cc)]);
+            if constexpr (EPS) rg += wt * A(fl.rho[stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + cc)]);
 #pragma unroll
             for (int m = 0; m < nc; ++m) {
               A g;
@@ -354,7 +354,11 @@ __device__ __forceinline__ void ds_particles(const PView<TS>& p, const Box* boxe
       }
       A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
       A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
-      A it = epstein ? rg / dval : inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
+      A it;
+      if constexpr (EPS)
+        it = rg / dval;
+      else
+        it = inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
       A k = m * (it < inv_dt ? it : inv_dt);
 #pragma unroll
       for (int mm = 0; mm < nc; ++mm) q[mm] = k * sl[mm];
@@ -417,7 +421,7 @@ __device__ __forceinline__ void ds_add_window(const Box& B, const FView<TS>& fl,
 // Windows: one for the workgroup when its particles' window fits the LDS
 // capacity, else one per wave (a quarter of the capacity each) for the waves
 // whose particles' window fits that; the other waves go to HBM.
-template <typename TS, typename A, int GEOM, int NDIM, bool U, bool MASS>
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool MASS, bool EPS>
 __device__ __forceinline__ void ds_body(const PView<TS>& p, const Box* boxes, int nbox, const FView<TS>& fl,
                                         const Forces& f, const Species* sp, int drag_mode, A inv_dt,
                                         DiagDev* dg) {
@@ -494,7 +498,7 @@ __device__ __forceinline__ void ds_body(const PView<TS>& p, const Box* boxes, in
     const Box& B = boxes[ub];
     ds_stage<TS, nc, !MASS>(B, fl, wd, win, gwin, threadIdx.x, blockDim.x);
     __syncthreads();
-    ds_particles<TS, A, GEOM, NDIM, U, true, MASS>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
+    ds_particles<TS, A, GEOM, NDIM, U, true, MASS, EPS>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
                                              win, gwin, wd);
     __syncthreads();
     ds_add_window<TS, nc>(B, fl, wd, win, threadIdx.x, blockDim.x);
@@ -516,27 +520,27 @@ __device__ __forceinline__ void ds_body(const PView<TS>& p, const Box* boxes, in
   if (w_win) ds_stage<TS, nc, !MASS>(boxes[ub], fl, wd, wwin, wgwin, lane, 64);
   __syncthreads();
   if (w_win)
-    ds_particles<TS, A, GEOM, NDIM, U, true, MASS>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
+    ds_particles<TS, A, GEOM, NDIM, U, true, MASS, EPS>(p, boxes, nbox, ub, fl, f, sp, drag_mode, inv_dt, dg, base,
                                              wwin, wgwin, wd);
   else
-    ds_particles<TS, A, GEOM, NDIM, U, false, MASS>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
+    ds_particles<TS, A, GEOM, NDIM, U, false, MASS, EPS>(p, boxes, nbox, 0, fl, f, sp, drag_mode, inv_dt, dg, base,
                                               wwin, wgwin, wd);
   __syncthreads();
   if (w_win) ds_add_window<TS, nc>(boxes[ub], fl, wd, wwin, lane, 64);
 }
 
-template <typename TS, typename A, int GEOM, int NDIM, bool U>
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool EPS>
 __global__ void __launch_bounds__(256) k_drag_source(PView<TS> p, const Box* boxes, int nbox,
                                                      FView<TS> fl, Forces f, const Species* sp,
                                                      int drag_mode, A inv_dt, DiagDev* dg) {
-  ds_body<TS, A, GEOM, NDIM, U, false>(p, boxes, nbox, fl, f, sp, drag_mode, inv_dt, dg);
+  ds_body<TS, A, GEOM, NDIM, U, false, EPS>(p, boxes, nbox, fl, f, sp, drag_mode, inv_dt, dg);
 }
 
 // Dust density: rho_d (fl.dep[0]) += m W / dV with the gather's weights.
 template <typename TS, typename A, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256) k_mass_density(PView<TS> p, const Box* boxes, int nbox,
                                                       FView<TS> fl, const Species* sp, DiagDev* dg) {
-  ds_body<TS, A, GEOM, NDIM, U, true>(p, boxes, nbox, fl, Forces{}, sp, DRAG_TAU, A(0), dg);
+  ds_body<TS, A, GEOM, NDIM, U, true, false>(p, boxes, nbox, fl, Forces{}, sp, DRAG_TAU, A(0), dg);
 }
 
 // Dispatch on the (geometry, dimension) shared by the context's boxes.
@@ -894,10 +898,16 @@ void launch_drag_source(const PView<TS>& p, const Box* boxes, int nbox, int geom
                         const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode,
                         double dt, DiagDev* dg, hipStream_t st) {
   if (p.n == 0) return;
-  DUST_GEOM_SWITCH(geom, ndim, unif,
-                   hipLaunchKernelGGL((k_drag_source<TS, A, G_, D_, U_>), dim3(blocks_for(p.n, 256 * DS_PPT)),
-                                      dim3(256), 0, st, p, boxes, nbox, fl, f, sp, drag_mode,
-                                      A(1.0 / dt), dg));
+  if (drag_mode == DRAG_EPSTEIN)
+    DUST_GEOM_SWITCH(geom, ndim, unif,
+                     hipLaunchKernelGGL((k_drag_source<TS, A, G_, D_, U_, true>),
+                                        dim3(blocks_for(p.n, 256 * DS_PPT)), dim3(256), 0, st, p, boxes,
+                                        nbox, fl, f, sp, drag_mode, A(1.0 / dt), dg));
+  else
+    DUST_GEOM_SWITCH(geom, ndim, unif,
+                     hipLaunchKernelGGL((k_drag_source<TS, A, G_, D_, U_, false>),
+                                        dim3(blocks_for(p.n, 256 * DS_PPT)), dim3(256), 0, st, p, boxes,
+                                        nbox, fl, f, sp, drag_mode, A(1.0 / dt), dg));
 }
 
 template <typename TS, typename A>
