@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
 // an FP64 LDS window (FP64 LDS atomics run ~20x faster than FP32 ones on
 // gfx950) and that window is added to HBM once; otherwise gathers and
 // deposits go to HBM.  Correct for any particle order.
-static constexpr int DS_PPT = 8;
+static constexpr int DS_PPT = 4;
 // window capacity in cells: 3 FP64 deposit channels + 3 gas components in
 // storage precision within 64 KiB of LDS
 template <typename TS> constexpr int ds_win_cells() { return sizeof(TS) == 4 ? 1600 : 1300; }
