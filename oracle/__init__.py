@@ -28,7 +28,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 GEOM = {"cart": 0, "cyl": 1, "sph": 2}
 BC = {"periodic": 0, "shear": 1, "open": 2}
-SHAPE = {"cic": 0, "tsc": 1}
+SHAPE = {"cic": 0, "tsc": 1, "vol": 2}   # vol: cylindrical radius only
 FORCE = {"none": 0, "shearbox": 1, "pointmass": 2, "const": 3, "shearbox_fargo": 4}
 DRAG = {"tau": 0, "stokes": 1, "epstein": 2}
 STEP_APPLY_FEEDBACK = 1
@@ -165,6 +165,8 @@ class Box:
                 b.bc_lo[d] = BC[self.bc_lo[d]] if d < self.ndim else 0
                 b.bc_hi[d] = BC[self.bc_hi[d]] if d < self.ndim else 0
                 b.shape[d] = SHAPE[self.shape[d]] if d < self.ndim else 0
+                if d < self.ndim and self.shape[d] == "vol" and (self.geom != "cyl" or d != 0):
+                    raise ValueError("volume weighting is for the cylindrical radius only")
                 b.faces[d] = _ptr(self.faces[d])
             self._c = b
         return self._c

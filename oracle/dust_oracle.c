@@ -24,7 +24,7 @@
 
 enum { G_CART = 0, G_CYL = 1, G_SPH = 2 };
 enum { BC_PERIODIC = 0, BC_SHEAR = 1, BC_OPEN = 2 };
-enum { SH_CIC = 0, SH_TSC = 1 };
+enum { SH_CIC = 0, SH_TSC = 1, SH_VOL = 2 };
 enum { F_NONE = 0, F_SHEARBOX = 1, F_POINTMASS = 2, F_CONST = 3, F_SHEARBOX_FARGO = 4 };
 enum { DRAG_TAU = 0, DRAG_STOKES = 1, DRAG_EPSTEIN = 2 };
 
@@ -225,6 +225,22 @@ static double shape_overlap(const shape_ctx *c, double lo, double hi) {
  * shape_curv). */
 void orc_weights_axis(const orc_box *b, int d, int i, double xi_p, double w[3]) {
   double fl = face(b, d, i), fh = face(b, d, i + 1);
+  if (b->shape[d] == SH_VOL) {
+    /* Volume weighting of the cylindrical radius (Eq. CIC_vol): linear
+     * interpolation in R^2 between the two cell centres around R_p. */
+    double c = 0.5 * (fl + fh);
+    w[0] = w[1] = w[2] = 0.0;
+    if (xi_p < c) {
+      double cl = 0.5 * (face(b, d, i - 1) + fl);
+      w[0] = (c * c - xi_p * xi_p) / (c * c - cl * cl);
+      w[1] = 1.0 - w[0];
+    } else {
+      double ch = 0.5 * (fh + face(b, d, i + 2));
+      w[2] = (xi_p * xi_p - c * c) / (ch * ch - c * c);
+      w[1] = 1.0 - w[2];
+    }
+    return;
+  }
   shape_ctx c = {b->geom, d, b->shape[d], xi_p, fh - fl};
   double big = 4.0 * (fh - fl);
   double norm = shape_overlap(&c, xi_p - big, xi_p + big);

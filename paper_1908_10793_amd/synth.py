@@ -266,8 +266,9 @@ def rigid_disk(n_r=50, ratio=4, rb=0.5, re=5.5, nphi=4, nz=2, eps=1.0, shape="ts
     zero = np.zeros(gs, dtype=dt_np)
     vol = np.pi * (re ** 2 - rb ** 2) * 1.0
     m = eps * 1.0 * vol / npart
+    shp = (shape,) * 3 if isinstance(shape, str) else tuple(shape)   # a name or one per axis
     box = dict(geom="cyl", ndim=3, n=n, bc_lo=("open", "periodic", "periodic"),
-               bc_hi=("open", "periodic", "periodic"), shape=(shape,) * 3, faces=[fR, fP, fZ])
+               bc_hi=("open", "periodic", "periodic"), shape=shp, faces=[fR, fP, fZ])
     return Workload("rigid_disk", dtype, [box], dict(kind="none"), "tau", cell,
                     off.astype(dt_np), np.zeros((npart, 3), dtype=dt_np),
                     [dict(rho=np.ones(gs, dtype=dt_np), vel=[zero, zero, zero])], 0.01, 1,

@@ -119,3 +119,34 @@ def test_rigid_disk_assignment_noise():
     errs = [rigid_disk_l1(r, "tsc")[0] for r in (4, 16, 64)]
     assert errs[0] > errs[1] > errs[2], errs
     assert errs[2] < 0.01, errs
+
+
+def test_volume_weighting_interpolates_the_volume_coordinate():
+    """Eq. CIC_vol: the two weights interpolate R^2 (and constants) exactly
+    between the cell centres around the particle, are non-negative, and put
+    everything on the host at its centre."""
+    R = 0.5 * np.geomspace(1.0, 3.0, 13)
+    box = O.Box("cyl", (12, 4, 2), ("open", "periodic", "periodic"),
+                ("open", "periodic", "periodic"), ("vol", "tsc", "tsc"),
+                [R, np.linspace(0, 2 * np.pi, 5), np.linspace(-0.1, 0.1, 3)])
+    c = 0.5 * (R[1:] + R[:-1])
+    cg = np.concatenate([[R[0] - 0.5 * (R[1] - R[0])], c, [R[-1] + 0.5 * (R[-1] - R[-2])]])
+    for _ in range(200):
+        i = int(RNG.integers(0, 12))
+        xp = RNG.uniform(R[i], R[i + 1])
+        w = O.weights_axis(box, 0, i, xp)
+        assert np.all(w >= -1e-15)
+        assert abs(w.sum() - 1.0) < 1e-14
+        nodes = cg[i:i + 3]            # centres of cells i-1, i, i+1 (ghosts included)
+        assert abs((w * nodes ** 2).sum() - xp ** 2) < 1e-13 * xp ** 2
+        assert w[0] == 0.0 or w[2] == 0.0
+    w = O.weights_axis(box, 0, 5, c[5])
+    np.testing.assert_allclose(w, [0.0, 1.0, 0.0], atol=1e-15)
+
+
+def test_rigid_disk_volume_weighting_is_noisier_than_tsc():
+    """Fig. distribution: volume weighting (like CIC, two-zone support)
+    leaves more assignment noise than TSC at N_p/N_R = 4."""
+    vol = rigid_disk_l1(4, ("vol", "tsc", "tsc"))[0]
+    tsc = rigid_disk_l1(4, "tsc")[0]
+    assert vol > 2 * tsc, (vol, tsc)
