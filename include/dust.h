@@ -62,7 +62,7 @@ typedef enum {
 } dust_status_t;
 
 enum { DUST_CART = 0, DUST_CYL = 1, DUST_SPH = 2 };          /* Sec. 2      */
-enum { DUST_CIC = 0, DUST_TSC = 1 };                          /* Eq. b0, b1  */
+enum { DUST_CIC = 0, DUST_TSC = 1, DUST_VOL = 2 };  /* Eq. b0, b1; Eq. CIC_vol */
 enum { DUST_F32 = 0, DUST_F64 = 1 };                          /* storage     */
 enum { DUST_ARITH_F64 = 0, DUST_ARITH_F32 = 1 };              /* push math   */
 enum { DUST_BC_PERIODIC = 0, DUST_BC_SHEAR = 1, DUST_BC_OPEN = 2 };
@@ -104,7 +104,10 @@ enum {
  * face coordinates of axis d (HOST memory, copied); theta and phi in
  * radians.  bc: DUST_BC_SHEAR only on axis 0 of a 3-D Cartesian shearing
  * box (both sides), the two sides of an axis must both be periodic or both
- * non-periodic.  shape: DUST_CIC (b_0) or DUST_TSC (b_1) per axis. */
+ * non-periodic.  shape: DUST_CIC (b_0) or DUST_TSC (b_1) per axis;
+ * DUST_VOL, the traditional volume weighting of Eq. CIC_vol (linear in R^2
+ * between the two cell centres around the particle), on the radial axis of
+ * a cylindrical box only (the comparison scheme of Sec. 3.4). */
 typedef struct {
   int32_t geom, ndim;
   int32_t n[3];

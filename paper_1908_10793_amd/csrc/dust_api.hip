@@ -140,8 +140,10 @@ dust_status_t build_box(Ctx* c, const dust_box_t& in, int ib, int64_t cell_base,
       if (!std::isfinite(f[k])) return fail(DUST_EINVAL, "box %d axis %d: face %d not finite", ib, d, k);
     for (int k = 0; k < n; ++k)
       if (!(f[k + 1] > f[k])) return fail(DUST_EINVAL, "box %d axis %d: faces not increasing", ib, d);
-    if (in.shape[d] != DUST_CIC && in.shape[d] != DUST_TSC)
+    if (in.shape[d] != DUST_CIC && in.shape[d] != DUST_TSC && in.shape[d] != DUST_VOL)
       return fail(DUST_EINVAL, "box %d axis %d: unknown shape %d", ib, d, in.shape[d]);
+    if (in.shape[d] == DUST_VOL && !(in.geom == DUST_CYL && d == 0))
+      return fail(DUST_EUNSUPPORTED, "box %d axis %d: volume weighting is for the cylindrical radius", ib, d);
     for (int s = 0; s < 2; ++s) {
       int bc = s ? in.bc_hi[d] : in.bc_lo[d];
       if (bc < DUST_BC_PERIODIC || bc > DUST_BC_OPEN)

@@ -121,7 +121,20 @@ __device__ __forceinline__ void axis_weights(const Axis& ax, int i, A delta, A w
   } else if constexpr (KIND == AX_CYL_R) {
     // Eq. CIC_cylindrical / TSC_cylindrical, nu = R_i / Delta R_i
     A nu = cell_centre<A, U>(ax, i) / cell_width<A, U>(ax, i);
-    if (ax.shape == SHAPE_CIC) {
+    if (ax.shape == SHAPE_VOL) {
+      // Eq. CIC_vol: linear in R^2 between the two cell centres around R_p,
+      // in factored form (R_c^2 - R_p^2 = (R_c - R_p)(R_c + R_p))
+      const A c = cell_centre<A, U>(ax, i), dr = delta * cell_width<A, U>(ax, i), rp = c + dr;
+      if (delta < A(0)) {
+        const A cl = cell_centre<A, U>(ax, i - 1);
+        w[0] = (-dr) * (c + rp) / ((c - cl) * (c + cl));
+        w[2] = A(0);
+      } else {
+        const A ch = cell_centre<A, U>(ax, i + 1);
+        w[2] = dr * (rp + c) / ((ch - c) * (ch + c));
+        w[0] = A(0);
+      }
+    } else if (ax.shape == SHAPE_CIC) {
       A den = A(2) * (delta + nu);
       w[0] = delta < A(0) ? (delta + A(2) * nu - A(1)) / den * (-delta) : A(0);
       w[2] = delta > A(0) ? (delta + A(2) * nu + A(1)) / den * delta : A(0);

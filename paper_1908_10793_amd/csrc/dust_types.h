@@ -9,7 +9,7 @@
 namespace dust {
 
 enum { GEOM_CART = DUST_CART, GEOM_CYL = DUST_CYL, GEOM_SPH = DUST_SPH };
-enum { SHAPE_CIC = DUST_CIC, SHAPE_TSC = DUST_TSC };
+enum { SHAPE_CIC = DUST_CIC, SHAPE_TSC = DUST_TSC, SHAPE_VOL = DUST_VOL };
 enum { BC_PERIODIC = DUST_BC_PERIODIC, BC_SHEAR = DUST_BC_SHEAR, BC_OPEN = DUST_BC_OPEN };
 enum { FORCE_NONE = DUST_FORCE_NONE, FORCE_SHEARBOX = DUST_FORCE_SHEARBOX,
        FORCE_POINTMASS = DUST_FORCE_POINTMASS, FORCE_CONST = DUST_FORCE_CONST,

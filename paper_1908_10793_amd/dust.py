@@ -21,7 +21,7 @@ F32, F64 = 0, 1
 ARITH_F64, ARITH_F32 = 0, 1
 BC = {"periodic": 0, "shear": 1, "open": 2}
 GEOM = {"cart": CART, "cyl": CYL, "sph": SPH}
-SHAPE = {"cic": CIC, "tsc": TSC}
+SHAPE = {"cic": CIC, "tsc": TSC, "vol": 2}   # vol: Eq. CIC_vol, cylindrical radius only
 FORCE = {"none": 0, "shearbox": 1, "pointmass": 2, "const": 3, "shearbox_fargo": 4}
 DRAG = {"tau": 0, "stokes": 1, "species": 2, "epstein": 3}
 PHASE_DRIFT1, PHASE_KICK, PHASE_DRIFT2 = 1, 2, 4
