@@ -1048,15 +1048,21 @@ __global__ void __launch_bounds__(256)
     mom[d] = d < nc ? A(p.mom[d][i]) : A(0);
   }
   uint32_t k = nbins;
-  if (c >= 0 && c < (int64_t)nbins) {
-    const int b = find_box(boxes, nbox, c);
-    const Box& B = boxes[b];
+  auto key_in = [&](const Box& B) {
     int idx[3];
     unravel(B, c - B.cell_base, idx);
     const A h = A(0.5) * dt;
     int here[3] = {idx[0], idx[1], idx[2]};
-    k = drift_any<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)
-            ? tile_key_idx(B, idx, ts) : tile_key_idx(B, here, ts);
+    return drift_any<A, GEOM, NDIM, U>(B, f, true, h, *tdev + double(h), idx, off, mom)
+               ? tile_key_idx(B, idx, ts) : tile_key_idx(B, here, ts);
+  };
+  if (c >= 0 && c < (int64_t)nbins) {
+    // one box (the common case): its descriptor is uniform, read with
+    // scalar loads; several boxes: the particle's box per lane
+    if (nbox == 1)
+      k = key_in(boxes[0]);
+    else
+      k = key_in(boxes[find_box(boxes, nbox, c)]);
   }
   key[i] = k;
 }

@@ -445,14 +445,8 @@ __device__ __forceinline__ void ds_body(const PView<TS>& p, const Box* boxes, in
   {
     int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
     int blo = 0x7fffffff, bhi = -1;
-    for (int j = 0; j < DS_PPT; ++j) {
-      int64_t i = base + 64 * j;
-      if (i >= p.n) break;
-      int64_t c = p.cell[i];
-      if (c < 0) continue;
-      int b = find_box(boxes, nbox, c);
-      const Box& B = boxes[b];
-      if (c >= B.cell_base + B.ncell) continue;
+    auto add = [&](const Box& B, int b, int64_t c) {
+      if (c >= B.cell_base + B.ncell) return;
       int idx[3];
       unravel(B, c - B.cell_base, idx);
 #pragma unroll
@@ -462,6 +456,19 @@ __device__ __forceinline__ void ds_body(const PView<TS>& p, const Box* boxes, in
       }
       blo = b < blo ? b : blo;
       bhi = b > bhi ? b : bhi;
+    };
+    for (int j = 0; j < DS_PPT; ++j) {
+      int64_t i = base + 64 * j;
+      if (i >= p.n) break;
+      int64_t c = p.cell[i];
+      if (c < 0) continue;
+      // one box: a uniform descriptor (scalar loads)
+      if (nbox == 1)
+        add(boxes[0], 0, c);
+      else {
+        const int b = find_box(boxes, nbox, c);
+        add(boxes[b], b, c);
+      }
     }
     if (bhi >= 0) {
 #pragma unroll
