@@ -120,10 +120,9 @@ def test_mass_density_removed_empty_and_errors():
 
 def test_mass_density_full_size_sampled_cells():
     """128^3 shearing box, 2^24 particles (FP32): 24 sampled cells (corners,
-    faces, interior) against the oracle over every particle whose host cell
-    lies within one cell of the sample (the x faces are periodic for the
-    density: the deposit folds by position, so a periodic distance is
-    exact before the fold)."""
+    faces, interior) of the unfolded density against the oracle over every
+    particle whose host cell lies within one cell of the sample, without
+    wrapping (ghosts are cells of their own until folded)."""
     dust = _dust()
     w = synth.shearing_box()
     n = w.boxes[0]["n"]
@@ -155,3 +154,29 @@ def test_mass_density_full_size_sampled_cells():
         worst = max(worst, abs(got - want) / max(abs(want), 1e-300))
     print(f"[mass] 128^3 sampled cells: worst {worst:.2e}", flush=True)
     assert worst <= TOL["f32"]
+
+
+def test_mass_density_folded_with_the_deposit_fold():
+    """The density's ghost shares folded onto their periodic partners by
+    dust_fold_ghosts (the density in the first deposit channel, the others
+    zero) match the oracle's fold."""
+    dust = _dust()
+    w = _workload("batched", "f64")
+    ctx = dust.context_for(w)
+    P, F = dust.upload(w, ctx)
+    for d in F["dep"]:
+        d.zero_()
+    ctx.deposit_mass(P, F["dep"][0])
+    fr = dust.forces_for(w, 0.0)
+    ctx.fold_ghosts(F, fr, 0.0)
+    st = download(ctx, P, F, w)
+    run = OracleRun(workload_from_state(w, st, 0.0))
+    for b, box in enumerate(run.boxes):
+        ref = np.zeros(box.ghosted_shape)
+        O.deposit_mass(box, run.x[b], run.mass[b], run.active[b], ref)
+        fo = O.Fields(box, np.ones(box.ghosted_shape), [np.zeros(box.ghosted_shape)] * 3,
+                      dep=[ref, np.zeros_like(ref), np.zeros_like(ref), np.zeros_like(ref)])
+        O.fold_ghosts(box, run.forces, 0.0, fo)
+        got = st["dep"][b][0].ravel()
+        err = np.abs(got - fo.dep[0].ravel()).max() / np.abs(fo.dep[0]).max()
+        assert err <= TOL["f64"], (b, err)
