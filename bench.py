@@ -322,6 +322,23 @@ def main():
                     "achieved": round(md_bytes / md_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(md_bytes / md_s / 1e9 / HBM_PEAK_GBS, 4)}
     del rho_d
+    # measured device-to-device copy bandwidth (read + write bytes), the
+    # practical ceiling the fused kernel's rate is also compared with
+    nel = 256 << 20                                   # 1 GiB of float32
+    src = torch.ones(nel, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * 4 * nel * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    if roof is not None:
+        roof["copy_gbs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     out = {
         "metric": "particle-steps/s (gather+exp-midpoint push+deposit)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
