@@ -791,9 +791,11 @@ template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
     sc[1] = x0;
     if (B.geom == GEOM_SPH) sc[2] = x0 * sin(cell_centre<double, false>(B.ax[1], j));
   }
-  double rho = double(fl.rho[id]);
-  for (int c = 0; c < nc; ++c)
-    fl.vel[c][id] = TS(double(fl.vel[c][id]) + double(fl.dep[c][id]) / (rho * sc[c]));
+  const double irho = 1.0 / double(fl.rho[id]);   // one division per cell
+  for (int c = 0; c < nc; ++c) {
+    const double q = double(fl.dep[c][id]) * irho;
+    fl.vel[c][id] = TS(double(fl.vel[c][id]) + (c == 0 ? q : q / sc[c]));
+  }
 }
 
 // FP64 sums of dV D over every stored cell of one box: a grid-stride loop,
