@@ -215,7 +215,7 @@ def main():
                            args.calib_copy_mb)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
