@@ -720,38 +720,30 @@ __global__ void __launch_bounds__(REDUCE_THREADS)
     k_reduce_fused_partials(const double* __restrict__ part, int n, DiagDev* dg, int sums,
                             uint32_t* defer_count) {
   constexpr int NW = REDUCE_THREADS / 64;
+  static_assert(REDUCE_THREADS % PART_WORDS == 0 && 64 % PART_WORDS == 0, "word per lane");
   __shared__ double wred[NW][PART_WORDS];
   __shared__ double red[1][PART_WORDS];
-  double acc[PART_WORDS];
-  for (int k = 0; k < PART_WORDS; ++k) acc[k] = 0.0;
-  // slots b, b + REDUCE_THREADS, ... in order; four slots' loads in flight
-  int b = threadIdx.x;
-  for (; b + 3 * REDUCE_THREADS < n; b += 4 * REDUCE_THREADS) {
-    double v[4][PART_WORDS];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int k = 0; k < PART_WORDS; ++k) v[u][k] = part[(size_t)(b + u * REDUCE_THREADS) * PART_WORDS + k];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int k = 0; k < PART_WORDS; ++k) acc[k] = k == 5 ? fmax(acc[k], v[u][k]) : acc[k] + v[u][k];
+  // the partials read as one flat array (coalesced): every element a thread
+  // reads is word k = threadIdx.x % PART_WORDS of some slot; fixed order
+  const int k = threadIdx.x % PART_WORDS;
+  const bool is_max = k == 5;
+  const int64_t total = (int64_t)n * PART_WORDS;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int64_t e = threadIdx.x; e < total; e += REDUCE_THREADS) {
+    const double v = part[e];
+    acc = is_max ? fmax(acc, v) : acc + v;
   }
-  for (; b < n; b += REDUCE_THREADS)
-    for (int k = 0; k < PART_WORDS; ++k) {
-      const double v = part[(size_t)b * PART_WORDS + k];
-      acc[k] = k == 5 ? fmax(acc[k], v) : acc[k] + v;
-    }
-  // fixed-pattern wave reductions, then the waves in order
-#pragma unroll
-  for (int k = 0; k < PART_WORDS; ++k) acc[k] = k == 5 ? wave_max(acc[k]) : wave_sum(acc[k]);
-  if ((threadIdx.x & 63) == 0)
-    for (int k = 0; k < PART_WORDS; ++k) wred[threadIdx.x >> 6][k] = acc[k];
+  // lanes of the wave with the same word, in a fixed butterfly
+  for (int off = PART_WORDS; off < 64; off <<= 1) {
+    const double o = __shfl_xor(acc, off);
+    acc = is_max ? fmax(acc, o) : acc + o;
+  }
+  if ((threadIdx.x & 63) < PART_WORDS) wred[threadIdx.x >> 6][k] = acc;
   __syncthreads();
   if (threadIdx.x < PART_WORDS) {
-    const int k = threadIdx.x;
     double v = wred[0][k];
-    for (int w = 1; w < NW; ++w) v = k == 5 ? fmax(v, wred[w][k]) : v + wred[w][k];
+    for (int w = 1; w < NW; ++w) v = is_max ? fmax(v, wred[w][k]) : v + wred[w][k];
     red[0][k] = v;
   }
   __syncthreads();
