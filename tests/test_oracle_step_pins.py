@@ -1,0 +1,369 @@
+"""Pins of the oracle's impulse, shear-periodic boundary and feedback (not GPU).
+
+Each test checks a part of one oracle step against something that the
+physics fixes independently of the oracle's own formulas:
+
+* the drag impulse of Eq. dust_feedback_final subtracts the non-drag
+  acceleration times the full step dt (reading A9): in the terminal-velocity
+  state (Delta p = 0) the gas must receive exactly m g dt per particle, and
+  without drag (tau = inf) the impulse must vanish to round-off in every
+  geometry;
+* the shear-periodic boundary of Sec. 2.1: the map of a particle across the
+  x faces is the symmetry of the shearing-sheet equations (a shift of the
+  radial neighbour box by q Omega L_x t in y and a boost of q Omega L_x in
+  v_y), checked against a particle pushed through the unbounded sheet; the
+  ghost fill reproduces sheared fields; the energy fold keeps the energy
+  measured relative to the local shear flow;
+* the feedback branch (v_g += D / rho): the gas momentum gained equals the
+  momentum the particles lost.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+RNG = np.random.default_rng(20190829)
+
+
+def _periodic_box(n=(6, 5, 4), shape="tsc", lo=(0.0, 0.0, 0.0), L=(1.0, 1.0, 1.0)):
+    faces = [np.linspace(lo[d], lo[d] + L[d], n[d] + 1) for d in range(3)]
+    return O.Box("cart", n, ("periodic",) * 3, ("periodic",) * 3, (shape,) * 3, faces)
+
+
+def _shear_box(n=(8, 32, 4), L=(2.0, 2.0, 1.0)):
+    faces = [np.linspace(-L[0] / 2, L[0] / 2, n[0] + 1), np.linspace(-L[1] / 2, L[1] / 2, n[1] + 1),
+             np.linspace(-L[2] / 2, L[2] / 2, n[2] + 1)]
+    return O.Box("cart", n, ("shear", "periodic", "periodic"), ("shear", "periodic", "periodic"),
+                 ("tsc",) * 3, faces)
+
+
+def _inside(box, N):
+    x = np.zeros((N, 3))
+    for d in range(box.ndim):
+        f = box.faces[d]
+        x[:, d] = RNG.uniform(f[0], f[-1], N)
+    return x
+
+
+def _volumes(box):
+    """Cell volumes of every stored cell (ghosts have the width of their
+    neighbour), shape of a ghosted field."""
+    gs = box.ghosted_shape
+    v = np.zeros(gs)
+    n = list(box.n) + [1] * (3 - len(box.n))
+    g2 = 1 if box.ndim > 2 else 0
+    for k in range(-g2, n[2] + g2):
+        for j in range(-1, n[1] + 1):
+            for i in range(-1, n[0] + 1):
+                v[k + g2, j + 1, i + 1] = O.cell_volume(box, i, j, k)
+    return v
+
+
+# ---------------------------------------------------------------- impulse
+
+def test_terminal_state_gives_the_gas_m_g_dt():
+    """tau << dt, constant g, uniform gas: a particle starting at the
+    terminal velocity v_g + tau g stays there (Delta p = 0), and its drag
+    impulse J = m (Delta p - dt g) hands the gas exactly m g dt (reading A9;
+    a factor h1 = tau (1 - e^{-h}) instead of dt would give m tau g)."""
+    box = _periodic_box()
+    gs = box.ghosted_shape
+    N = 40
+    tau, dt = 1e-4, 0.01
+    g = np.array([0.3, -1.0, 0.45])
+    vg = np.array([0.02, -0.01, 0.005])
+    F = O.Forces(kind="const", g=tuple(g))
+    x = _inside(box, N)
+    p = np.tile(vg + tau * g, (N, 1))
+    p0 = p.copy()
+    mass = RNG.uniform(0.5, 2.0, N)
+    fields = O.Fields(box, np.ones(gs), [np.full(gs, v) for v in vg])
+    d = O.step(box, F, "tau", x, p, np.full(N, tau), mass, np.ones(N, np.int32), fields, dt, 0.0)
+    np.testing.assert_allclose(p, p0, rtol=0, atol=1e-15)
+    dV = _volumes(box)
+    got = np.array([(dV * fields.dep[c]).sum() for c in range(3)])
+    want = mass.sum() * g * dt
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+    np.testing.assert_allclose(-d.p_part, want, rtol=1e-12)
+    # with h1 in place of dt the gas would receive m tau g: 100 times less
+    assert np.abs(got - mass.sum() * g * tau).min() > 0.5 * np.abs(want).min()
+
+
+def _zero_drag_case(kind):
+    if kind in ("shearbox", "shearbox_fargo"):
+        box = _shear_box()
+        F = O.Forces(kind=kind, Omega=1.0, q=1.5, vertical_gravity=True)
+        N = 30
+        x = _inside(box, N)
+        p = RNG.uniform(-0.3, 0.3, (N, 3))
+        if kind == "shearbox":
+            p[:, 1] -= 1.5 * x[:, 0]
+        return box, F, x, p
+    if kind == "const":
+        box = _periodic_box()
+        F = O.Forces(kind="const", g=(0.1, -0.7, 0.3))
+        N = 30
+        return box, F, _inside(box, N), RNG.uniform(-0.3, 0.3, (N, 3))
+    if kind == "cyl":
+        fR = 0.5 * 2.0 ** (np.arange(9) / 8)
+        box = O.Box("cyl", (8, 16, 4), ("open", "periodic", "periodic"),
+                    ("open", "periodic", "periodic"), ("tsc",) * 3,
+                    [fR, np.linspace(0, 2 * np.pi, 17), np.linspace(-0.1, 0.1, 5)])
+        N = 30
+        x = _inside(box, N)
+        x[:, 0] = RNG.uniform(0.6, 0.9, N)
+        p = np.zeros((N, 3))
+        p[:, 0] = RNG.uniform(-0.05, 0.05, N)
+        p[:, 1] = np.sqrt(x[:, 0]) * RNG.uniform(0.9, 1.1, N)
+        p[:, 2] = RNG.uniform(-0.05, 0.05, N)
+        return box, O.Forces(kind="pointmass", GM=1.0), x, p
+    box = O.Box("sph", (8, 8, 16), ("open", "open", "periodic"), ("open", "open", "periodic"),
+                ("tsc",) * 3, [np.linspace(0.8, 1.6, 9), np.linspace(np.pi / 2 - 0.3, np.pi / 2 + 0.3, 9),
+                               np.linspace(0, 2 * np.pi, 17)])
+    N = 30
+    x = _inside(box, N)
+    x[:, 0] = RNG.uniform(1.0, 1.4, N)
+    x[:, 1] = RNG.uniform(np.pi / 2 - 0.15, np.pi / 2 + 0.15, N)
+    p = np.zeros((N, 3))
+    p[:, 0] = RNG.uniform(-0.05, 0.05, N)
+    p[:, 1] = RNG.uniform(-0.02, 0.02, N)
+    p[:, 2] = np.sqrt(x[:, 0]) * np.sin(x[:, 1]) * RNG.uniform(0.9, 1.1, N)
+    return box, O.Forces(kind="pointmass", GM=1.0), x, p
+
+
+@pytest.mark.parametrize("kind", ["shearbox", "shearbox_fargo", "const", "cyl", "sph"])
+def test_no_drag_no_impulse(kind):
+    """tau = inf: the kick changes the momentum by dt a with a the non-drag
+    acceleration as the kick evaluates it (midpoint Coriolis terms, averaged
+    l^2), so J = m (Delta p - dt a) must vanish to round-off: nothing is
+    deposited while the particles do move."""
+    box, F, x, p = _zero_drag_case(kind)
+    N = x.shape[0]
+    gs = box.ghosted_shape
+    nc = 3
+    p0 = p.copy()
+    fields = O.Fields(box, np.ones(gs), [RNG.uniform(-1, 1, gs) for _ in range(nc)])
+    mass = np.ones(N)
+    d = O.step(box, F, "tau", x, p, np.full(N, np.inf), mass, np.ones(N, np.int32), fields, 0.02, 0.3)
+    moved = np.abs(p - p0).max()
+    assert moved > 1e-4
+    dVmin = _volumes(box).min()
+    scale = moved * mass.max() / dVmin
+    for c in range(4):
+        assert np.abs(fields.dep[c]).max() <= 1e-12 * scale, (c, np.abs(fields.dep[c]).max(), scale)
+    assert np.abs(d.p_part).max() <= 1e-13 * moved * N
+
+
+# ---------------------------------------------------------------- shear-periodic boundary
+
+def _sheet_map(x, p, L, u, t):
+    """The radial neighbour box of the shearing sheet seen from the central
+    one at time t: (x, y, v_y) -> (x + L, y - u t, v_y - u), u = q Omega L."""
+    x2, p2 = x.copy(), p.copy()
+    x2[0] += L
+    x2[1] -= u * t
+    p2[1] -= u
+    return x2, p2
+
+
+def test_sheet_map_is_a_symmetry_of_the_shearing_sheet():
+    """The shearing-sheet equations with the background gas v_g = -q Omega x
+    + w are invariant under (x, y, v_y) -> (x + L, y - q Omega L t, v_y -
+    q Omega L): pushing a transformed particle gives the transformed push.
+    This fixes the direction of the y shift and of the boost that the
+    shear-periodic boundary must use (Sec. 2.1)."""
+    Om, q, L = 1.3, 1.5, 2.0
+    u = q * Om * L
+    w = np.array([0.01, -0.02, 0.003])
+    F = O.Forces(kind="shearbox", Omega=Om, q=q, vertical_gravity=True)
+    gas = lambda xp: np.array([w[0], -q * Om * xp[0] + w[1], w[2]])
+    for tau in (np.inf, 0.05, 2.0):
+        for _ in range(5):
+            t = RNG.uniform(0.0, 3.0)
+            dt = 0.05
+            x = RNG.uniform(-1, 1, 3)
+            p = RNG.uniform(-0.5, 0.5, 3)
+            xa, pa = x.copy(), p.copy()
+            O.push_one("cart", F, "tau", tau, dt, xa, pa, gas=gas)
+            xb, pb = _sheet_map(x, p, L, u, t)
+            O.push_one("cart", F, "tau", tau, dt, xb, pb, gas=gas)
+            xm, pm = _sheet_map(xa, pa, L, u, t + dt)
+            np.testing.assert_allclose(xb, xm, rtol=0, atol=1e-13)
+            np.testing.assert_allclose(pb, pm, rtol=0, atol=1e-13)
+            # the opposite shift is not a symmetry
+            xc, pc = _sheet_map(x, p, L, -u, t)
+            O.push_one("cart", F, "tau", tau, dt, xc, pc, gas=gas)
+            xm2, _ = _sheet_map(xa, pa, L, -u, t + dt)
+            assert abs(xc[1] - xm2[1]) > 1e-6 or abs(pc[1] - pm[1]) > 1e-6
+
+
+@pytest.mark.parametrize("tau", [np.inf, 0.05])
+@pytest.mark.parametrize("side", [1, -1])
+def test_particle_across_the_shear_face_is_the_sheet_image(tau, side):
+    """A particle stepped by the oracle across an x face of the shearing box
+    equals the same particle pushed through the unbounded sheet, mapped back
+    into the box with the sheet symmetry above.  The gas is the exact shear
+    flow plus a constant, which the ghost fill (with its boost) and the TSC
+    weights reproduce exactly, so the drag case pins the ghost boost too."""
+    Om, q = 1.0, 1.5
+    box = _shear_box()
+    L, Ly = 2.0, 2.0
+    u = q * Om * L
+    gs = box.ghosted_shape
+    w = np.array([0.01, -0.02, 0.003])
+    F = O.Forces(kind="shearbox", Omega=Om, q=q)
+    xc = -L / 2 + (np.arange(-1, box.n[0] + 1) + 0.5) * (L / box.n[0])
+    vy = np.broadcast_to(-q * Om * xc[None, None, :] + w[1], gs).copy()
+    t, dt = 0.37, 0.1
+    for trial in range(6):
+        x = np.zeros((1, 3))
+        dx = L / box.n[0]
+        x[0, 0] = side * (L / 2 - RNG.uniform(0.05, 0.3) * dx)
+        x[0, 1] = RNG.uniform(-1, 1)
+        x[0, 2] = RNG.uniform(-0.5, 0.5)
+        p = np.zeros((1, 3))
+        p[0, 0] = side * RNG.uniform(0.8, 1.5) * dx / dt
+        p[0, 1] = -q * Om * x[0, 0] + RNG.uniform(-0.1, 0.1)
+        p[0, 2] = RNG.uniform(-0.1, 0.1)
+        xf, pf = x[0].copy(), p[0].copy()
+        gas = lambda xp: np.array([w[0], -q * Om * xp[0] + w[1], w[2]])
+        O.push_one("cart", F, "tau", tau, dt, xf, pf, gas=gas)
+        assert side * xf[0] > L / 2, "the free particle must leave the box"
+        fields = O.Fields(box, np.ones(gs), [np.full(gs, w[0]), vy.copy(), np.full(gs, w[2])])
+        O.step(box, F, "tau", x, p, np.array([tau]), np.array([1.0]), np.ones(1, np.int32), fields,
+               dt, t)
+        want_x, want_p = _sheet_map(xf, pf, -side * L, -side * u, t + dt)
+        want_x[1] = (want_x[1] + Ly / 2) % Ly - Ly / 2
+        np.testing.assert_allclose(x[0, [0, 2]], want_x[[0, 2]], rtol=0, atol=1e-12)
+        dy = (x[0, 1] - want_x[1] + Ly / 2) % Ly - Ly / 2
+        assert abs(dy) < 1e-12, (x[0], want_x)
+        np.testing.assert_allclose(p[0], want_p, rtol=0, atol=1e-12)
+
+
+def test_ghost_fill_reproduces_sheared_fields():
+    """Fields that are periodic in the shearing sheet's sense,
+    f(x + L_x, y) = f(x, y + q Omega L_x t), are reproduced at the x-ghost
+    centres up to the error of the linear interpolation in y; the shear
+    flow -q Omega x of v_y is reproduced exactly (boost included)."""
+    Om, q = 1.0, 1.5
+    n = (8, 64, 4)
+    box = _shear_box(n=n)
+    L, Ly = 2.0, 2.0
+    F = O.Forces(kind="shearbox", Omega=Om, q=q)
+    gs = box.ghosted_shape
+    dx = L / n[0]
+    xc = -L / 2 + (np.arange(-1, n[0] + 1) + 0.5) * dx
+    yc = -Ly / 2 + (np.arange(-1, n[1] + 1) + 0.5) * (Ly / n[1])
+    ky = 2 * np.pi / Ly
+    for t in (0.0, 0.13, 0.71, 2.9):
+        wave = np.cos(ky * (yc[None, :, None] + q * Om * t * xc[None, None, :])) * np.ones(gs)
+        shear = -q * Om * xc[None, None, :] * np.ones(gs)
+        rho = np.zeros(gs)
+        vy = np.zeros(gs)
+        act = (slice(1, -1), slice(1, -1), slice(1, -1))
+        rho[act] = wave[act]
+        vy[act] = shear[act]
+        f = O.Fields(box, rho, [np.zeros(gs), vy, np.zeros(gs)])
+        O.fill_ghosts(box, F, t, f)
+        for i in (0, -1):
+            sl = (slice(1, -1), slice(1, -1), i)
+            err = np.abs(f.rho[sl] - wave[sl]).max()
+            assert err < 1.5 * (ky * Ly / n[1]) ** 2 / 8, (t, i, err)
+            np.testing.assert_allclose(f.vel[1][sl], shear[sl], rtol=0, atol=1e-13)
+        if t > 0:
+            # the shift taken in the opposite direction would give the wave
+            # with a phase error of 2 ky q Omega L_x t, far outside the bar
+            sl = (slice(1, -1), slice(1, -1), 0)
+            wrong = np.cos(ky * (yc[None, 1:-1] + q * Om * t * (xc[0] + 2 * L))) * np.ones((n[2], n[1]))
+            assert np.abs(f.rho[sl] - wrong).max() > 0.3
+
+
+@pytest.mark.parametrize("kind", ["shearbox", "shearbox_fargo"])
+def test_fold_keeps_energy_relative_to_the_shear_flow(kind):
+    """The energy exchanged with the gas, measured relative to the local
+    shear flow, E - v_sh(x) D_y with v_sh = -q Omega x (the peculiar energy,
+    invariant under the sheet symmetry), summed with the cell volumes over
+    every stored cell, is unchanged by the fold (reading A10: a deposit that
+    crosses an x face gains +/- q Omega L_x D_y in the energy channel).  With
+    orbital advection the velocities are already residuals: plain E is
+    unchanged, and the momentum channels always are."""
+    Om, q = 1.0, 1.5
+    n = (6, 10, 4)
+    box = _shear_box(n=n)
+    L = 2.0
+    gs = box.ghosted_shape
+    F = O.Forces(kind=kind, Omega=Om, q=q)
+    dV = _volumes(box)
+    xc = -L / 2 + (np.arange(-1, n[0] + 1) + 0.5) * (L / n[0])
+    vsh = (-q * Om * xc if kind == "shearbox" else 0.0 * xc)[None, None, :] * np.ones(gs)
+    act = (slice(1, -1), slice(1, -1), slice(1, -1))
+    for t in (0.0, 0.37, 1.9):
+        dep = [RNG.standard_normal(gs) for _ in range(4)]
+        before = (dV * (dep[3] - vsh * dep[1])).sum()
+        mom_before = [(dV * dep[c]).sum() for c in range(3)]
+        f = O.Fields(box, np.ones(gs), [np.zeros(gs)] * 3, dep=[a.copy() for a in dep])
+        O.fold_ghosts(box, F, t, f)
+        after = (dV[act] * (f.dep[3][act] - vsh[act] * f.dep[1][act])).sum()
+        assert abs(after - before) < 1e-12 * (abs(before) + np.abs(dep[3]).sum() * dV.max())
+        for c in range(3):
+            assert abs((dV[act] * f.dep[c][act]).sum() - mom_before[c]) < 1e-12 * np.abs(dep[c]).sum()
+        if kind == "shearbox":
+            # the plain energy is not conserved across the faces: the boost does work
+            plain_before = (dV * dep[3]).sum()
+            plain_after = (dV[act] * f.dep[3][act]).sum()
+            assert abs(plain_after - plain_before) > 1e-3 * abs(plain_before) + 1e-6
+
+
+# ---------------------------------------------------------------- feedback
+
+@pytest.mark.parametrize("case", ["periodic", "shearbox", "cyl"])
+def test_feedback_hands_the_gas_the_particle_momentum(case):
+    """With feedback (v_g += D / (rho s)), the gas momentum gained over the
+    active cells, sum rho dV s dv_g in canonical components (s = 1 or the
+    cell-centre radius for l_phi), plus what stays in open-boundary ghosts,
+    equals minus the particles' drag impulse sum (Sec. 3.1, corrector with
+    the deposited impulse density): momentum and angular momentum are
+    conserved."""
+    if case == "periodic":
+        box = _periodic_box()
+        F = O.Forces(kind="const", g=(0.0, 0.0, -0.3))
+    elif case == "shearbox":
+        box = _shear_box(n=(6, 8, 4))
+        F = O.Forces(kind="shearbox", Omega=1.0, q=1.5)
+    else:
+        box, F, _, _ = _zero_drag_case("cyl")
+    gs = box.ghosted_shape
+    N = 60
+    x = _inside(box, N)
+    if case == "cyl":
+        x[:, 0] = RNG.uniform(0.6, 0.9, N)
+    p = RNG.uniform(-0.2, 0.2, (N, 3))
+    rho = RNG.uniform(0.5, 2.0, gs)
+    vel = [RNG.uniform(-0.2, 0.2, gs) for _ in range(3)]
+    if case == "cyl":
+        p[:, 1] += np.sqrt(x[:, 0])
+    fields = O.Fields(box, rho.copy(), [v.copy() for v in vel])
+    O.fill_ghosts(box, F, 0.05, fields)
+    vel0 = [v.copy() for v in fields.vel]
+    d = O.step(box, F, "tau", x, p, RNG.uniform(0.02, 0.5, N), RNG.uniform(0.5, 2.0, N),
+               np.ones(N, np.int32), fields, 0.1, 0.0, apply_feedback=True)
+    dV = _volumes(box)
+    act = (slice(1, -1), slice(1, -1), slice(1, -1))
+    s = np.ones(gs)
+    if case == "cyl":
+        fR = box.faces[0]
+        Rc = 0.5 * (fR[:-1] + fR[1:])
+        s[act] = Rc[None, None, :] * np.ones((box.n[2], box.n[1], box.n[0]))
+    ghost = np.ones(gs, bool)
+    ghost[act] = False
+    for c in range(3):
+        sc = s if c == 1 else np.ones(gs)
+        gained = (fields.rho[act] * dV[act] * sc[act] * (fields.vel[c][act] - vel0[c][act])).sum()
+        kept = (dV[ghost] * fields.dep[c][ghost]).sum()
+        scale = d.sum_abs_j
+        assert abs(gained + kept + d.p_part[c]) <= 1e-12 * scale, (c, gained, kept, d.p_part[c])
+        if case != "cyl":
+            assert kept == 0.0
+    assert np.abs(d.p_part).max() > 1e-6
