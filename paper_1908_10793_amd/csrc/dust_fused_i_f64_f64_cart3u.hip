@@ -1,0 +1,8 @@
+// Instantiations of the fused tile step: double storage, double arithmetic (uniform 3-D Cartesian boxes).
+#include "dust_fused_kern.h"
+
+namespace dust {
+
+DUST_FUSED_G_DECL(, double, double, GEOM_CART, 3, true)
+
+}  // namespace dust

@@ -82,9 +82,79 @@ def _global_positions(box, cell_local, off):
     return x
 
 
-def compare_step(w, st_in, st_out, run: OracleRun, dtype: str, fields_too=True, label=""):
+def oracle_diag(run: OracleRun, steps=1):
+    """The oracle's FP64 diagnostics of its last `steps` steps, summed over
+    boxes (maxima for the displacement bound), with the scale of the
+    energy sums: the largest physical particle speed times sum |J| over the
+    smallest canonical factor (a bound of sum |e_p|)."""
+    out = dict(p_part=np.zeros(3), p_grid=np.zeros(3), e_part=0.0, e_grid=0.0, sum_abs_j=0.0,
+               max_cells_per_step=0.0, n_removed=0)
+    for ds in run.diags[-steps:]:
+        for d in ds:
+            out["p_part"] = out["p_part"] + d.p_part
+            out["p_grid"] = out["p_grid"] + d.p_grid
+            out["e_part"] += d.e_part
+            out["e_grid"] += d.e_grid
+            out["sum_abs_j"] += d.sum_abs_j
+            out["max_cells_per_step"] = max(out["max_cells_per_step"], d.max_cells_per_step)
+    out["n_removed"] = int(sum(int((a == 0).sum()) for a in run.active))
+    vmax, scmin = 0.0, 1.0
+    for b, box in enumerate(run.boxes):
+        a = run.active[b].astype(bool)
+        if not a.any():
+            continue
+        x, p = run.x[b][a], run.p[b][a]
+        sc = np.ones_like(p)
+        if box.geom == "cyl":
+            sc[:, 1] = x[:, 0]
+        elif box.geom == "sph":
+            sc[:, 1] = x[:, 0]
+            sc[:, 2] = x[:, 0] * np.abs(np.sin(x[:, 1]))
+        vmax = max(vmax, float(np.abs(p / sc).max()))
+        scmin = min(scmin, float(sc.min()))
+    out["e_scale"] = vmax * out["sum_abs_j"] / scmin
+    return out
+
+
+def compare_diag(diag: dict, run: OracleRun, dtype: str, label="", steps=1, base: dict | None = None,
+                 with_max=True):
+    """Compare the GPU's FP64 diagnostics (ctx.status(), accumulated over the
+    same steps; minus `base` when given, the diagnostics of a prefix of
+    steps) with the oracle's: momentum and energy sums of the particles and
+    of the grid normwise against sum |J| (energy: against its bound
+    e_scale), the dust time-step bound (Eq. particles_dt) relative, the
+    removal count exactly.  Returns the worst normwise errors."""
+    tol = TOL[dtype]
+    o = oracle_diag(run, steps)
+    g = {k: (np.asarray(diag[k], dtype=np.float64) if k in ("p_part", "p_grid") else diag[k])
+         for k in ("p_part", "p_grid", "e_part", "e_grid", "sum_abs_j", "max_cells_per_step",
+                   "n_removed")}
+    if base is not None:
+        for k in ("p_part", "p_grid", "e_part", "e_grid", "sum_abs_j", "n_removed"):
+            bv = np.asarray(base[k], dtype=np.float64) if k in ("p_part", "p_grid") else base[k]
+            g[k] = g[k] - bv
+    js = max(o["sum_abs_j"], 1e-300)
+    es = max(o["e_scale"], 1e-300)
+    rep = {"p_part": float(np.abs(g["p_part"] - o["p_part"]).max() / js),
+           "p_grid": float(np.abs(g["p_grid"] - o["p_grid"]).max() / js),
+           "sum_abs_j": abs(g["sum_abs_j"] - o["sum_abs_j"]) / js,
+           "e_part": abs(g["e_part"] - o["e_part"]) / es,
+           "e_grid": abs(g["e_grid"] - o["e_grid"]) / es}
+    if with_max:
+        rep["max_cells"] = abs(g["max_cells_per_step"] - o["max_cells_per_step"]) / max(
+            o["max_cells_per_step"], 1e-300)
+    for k, v in rep.items():
+        assert v <= tol, (label, "diag", k, v, g, o)
+    assert int(g["n_removed"]) == o["n_removed"], (label, "n_removed", g["n_removed"], o["n_removed"])
+    rep["n_removed"] = o["n_removed"]
+    return rep
+
+
+def compare_step(w, st_in, st_out, run: OracleRun, dtype: str, fields_too=True, label="", diag=None):
     """Compare the GPU state after one step (st_out) with the oracle run
-    started from st_in.  Returns a dict of the worst errors; asserts the bar."""
+    started from st_in.  Returns a dict of the worst errors; asserts the bar.
+    diag: the GPU's diagnostics of that step (ctx.status()), compared with
+    the oracle's when given."""
     tol = TOL[dtype]
     report = {"label": label}
     bases, _ = w.cell_bases()
@@ -177,4 +247,6 @@ def compare_step(w, st_in, st_out, run: OracleRun, dtype: str, fields_too=True, 
                     worst_f = max(worst_f, e)
                     assert e <= tol, (label, "vel", b, c, e)
         report["fields"] = worst_f
+    if diag is not None:
+        report["diag"] = compare_diag(diag, run, dtype, label=label)
     return report

@@ -69,7 +69,7 @@ def _run(name, fused, nsteps=3, arith=None, tile=None, integrator=None):
         wi = workload_from_state(w, st_in, t)
         run = OracleRun(wi)
         run.step(1)
-        rep = compare_step(wi, st_in, st_out, run, w.dtype, label=f"{name} step {s}")
+        rep = compare_step(wi, st_in, st_out, run, w.dtype, label=f"{name} step {s}", diag=diag)
         # FP64 conservation on the device: sum_p J + sum_i dV D = 0
         scale = max(diag["sum_abs_j"], 1e-300)
         res = np.abs(np.array(diag["p_part"]) + np.array(diag["p_grid"])).max() / scale

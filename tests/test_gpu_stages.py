@@ -9,7 +9,7 @@ import oracle as O
 from oracle.run import OracleRun, make_box, make_forces
 from paper_1908_10793_amd import synth
 
-from gpu_common import TOL, compare_step, download, workload_from_state
+from gpu_common import TOL, compare_diag, compare_step, download, workload_from_state
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -277,6 +277,17 @@ def _small(name):
         return synth.shearing_box(n=(16, 16, 8), dt=0.05)
     if name == "shearing_box_fargo":
         return synth.shearing_box(n=(16, 16, 8), dt=0.05, fargo=True)
+    if name == "spherical_disk":
+        return synth.spherical_disk(n=(16, 12, 20), ppc=2, dt=0.05)
+    if name in ("batched_boxes", "cart2d_f64"):
+        # particles given random velocities of up to about a cell per step,
+        # so that stale bins and the deferred kernel are exercised
+        w = (synth.batched_boxes(sizes=(6, 10, 13), max_per_species=4, dt=0.05)
+             if name == "batched_boxes" else synth.cart2d_periodic(n=(24, 20), ppc=4, dt=0.05))
+        r = np.random.default_rng(7)
+        nd = w.boxes[0]["ndim"]
+        w.mom[:, :nd] = r.uniform(-1.0, 1.0, (w.n, nd)).astype(w.mom.dtype)
+        return w
     return synth.cylindrical_disk(n=(16, 12, 8), npart=3000, dt=0.05)
 
 
@@ -294,9 +305,10 @@ SCHEDULES = [
 ]
 
 
-@pytest.mark.parametrize("name", ["shearing_box", "shearing_box_fargo", "cylindrical_disk"])
+@pytest.mark.parametrize("name", ["shearing_box", "shearing_box_fargo", "cylindrical_disk",
+                                  "spherical_disk", "batched_boxes", "cart2d_f64"])
 @pytest.mark.parametrize("nsteps,rebin_every", SCHEDULES)
-def test_multi_step_schedules_match_oracle(name, nsteps, rebin_every):
+def test_multi_step_schedules_match_oracle(name, nsteps, rebin_every, feedback=False):
     """The last step of a call of nsteps fused steps with
     DUST_STEP_REBIN_EVERY(k), whatever its kind (rebinning, stale bins in
     place or written across buffers; stale steps process particles away from
@@ -304,17 +316,25 @@ def test_multi_step_schedules_match_oracle(name, nsteps, rebin_every):
     kernel for stencils outside the tile window), against the oracle started
     from the state after nsteps-1 steps of a call with the same interval.
     Without feedback the gas does not change, so those first nsteps-1 steps
-    are the same computation in both calls."""
+    are the same computation in both calls (with feedback, the same up to
+    the order of the FP32 deposit atomics).  The diagnostics of the last step
+    (those of the second call minus those of the first) are compared too,
+    removals through open faces included."""
     dust = _dust()
-    w = dataclasses.replace(_small(name), apply_feedback=False)
+    w = dataclasses.replace(_small(name), apply_feedback=feedback)
+    print(f"[schedule] {name} {nsteps}x k={rebin_every} feedback={feedback} n={w.n}", flush=True)
     ctx = dust.context_for(w)
     flags = dust.STEP_FUSED | dust.STEP_DIAG | dust.STEP_REBIN_EVERY(rebin_every)
+    if feedback:
+        flags |= dust.STEP_APPLY_FEEDBACK
     P0, F0 = dust.upload(w, ctx)
     ctx.step(P0, F0, w.dt, dust.forces_for(w), nsteps - 1, flags)
     st_a = download(ctx, P0, F0, w)
+    d_a = ctx.status()
     P, F = dust.upload(w, ctx)
     ctx.step(P, F, w.dt, dust.forces_for(w), nsteps, flags)
     st_b = download(ctx, P, F, w)
+    d_b = ctx.status()
     # every array comes back to the caller: attributes by id unchanged
     order = np.argsort(st_b["id"])
     order0 = np.argsort(st_a["id"])
@@ -324,8 +344,19 @@ def test_multi_step_schedules_match_oracle(name, nsteps, rebin_every):
     assert np.array_equal(np.sort(st_b["id"]), np.arange(len(st_b["id"])))
     run = OracleRun(workload_from_state(w, st_a, w.t0 + (nsteps - 1) * w.dt))
     run.step(1)
-    rep = compare_step(w, st_a, st_b, run, "f32", label=f"{name} {nsteps}x k={rebin_every}")
-    print("[schedule]", rep, ctx.status()["n_fallback"], flush=True)
+    label = f"{name} {nsteps}x k={rebin_every}"
+    rep = compare_step(w, st_a, st_b, run, w.dtype, label=label)
+    rep["diag"] = compare_diag(d_b, run, w.dtype, label=label, base=d_a, with_max=False)
+    print("[schedule]", rep, d_b["n_fallback"], flush=True)
+
+
+@pytest.mark.parametrize("name", ["shearing_box", "cylindrical_disk", "batched_boxes"])
+@pytest.mark.parametrize("nsteps,rebin_every", [(3, 3), (4, 2)])
+def test_multi_step_schedules_with_feedback_match_oracle(name, nsteps, rebin_every):
+    """As above with feedback on, so that deposits made from stale bins
+    (register sums, LDS planes, the deferred kernel) feed the gas that the
+    next steps gather."""
+    test_multi_step_schedules_match_oracle(name, nsteps, rebin_every, feedback=True)
 
 
 # ------------------------------------------------------------------ autotuner
