@@ -36,11 +36,12 @@ STEP_FILL_GHOSTS = 2
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with plain -O2 (no fast-math) into liboracle.so."""
+    """Compile the oracle with plain -O2 (no fast-math) into liboracle.so
+    (with OpenMP for the threaded timing variant orc_step_threads)."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+            ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -119,6 +120,8 @@ def _declare(L):
                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
                            ctypes.POINTER(_Diag)]
     L.orc_step.restype = ctypes.c_int
+    L.orc_step_threads.argtypes = L.orc_step.argtypes
+    L.orc_step_threads.restype = ctypes.c_int
     L.orc_drag_source.argtypes = [ctypes.POINTER(_Box), ctypes.POINTER(_Forces), ctypes.c_int,
                                   ctypes.POINTER(_Particles), ctypes.POINTER(_Fields),
                                   ctypes.c_double]
@@ -384,14 +387,18 @@ class Diag:
     sum_abs_j: float
     max_cells_per_step: float
     n_inactive: int
+    threads: int = 1
 
 
 def step(box: Box, forces: Forces, drag_mode: str, x, p, drag, mass, active,
          fields: Fields, dt: float, t: float, apply_feedback: bool = False,
-         fill_ghosts: bool = True) -> Diag:
+         fill_ghosts: bool = True, threads: bool = False) -> Diag:
     """One step of the hot path for the particles of one box, in place:
     x (N,3), p (N,3) FP64, drag (tau or St) and mass (N,), active (N,) int32;
-    fields' velocities are updated if apply_feedback, deposits overwritten."""
+    fields' velocities are updated if apply_feedback, deposits overwritten.
+    threads: the OpenMP variant (particle ranges per host thread, private
+    deposit arrays added in thread order), for timing on every core; the
+    thread count is in the returned Diag's `threads`."""
     for a in (x, p):
         assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape[1] == 3
     n = x.shape[0]
@@ -411,13 +418,16 @@ def step(box: Box, forces: Forces, drag_mode: str, x, p, drag, mass, active,
     dg = _Diag()
     flags = (STEP_APPLY_FEEDBACK if apply_feedback else 0) | (STEP_FILL_GHOSTS if fill_ghosts else 0)
     fc = fields.c()
-    lib().orc_step(ctypes.byref(box.c()), ctypes.byref(forces.c()), DRAG[drag_mode],
-                   ctypes.byref(P), ctypes.byref(fc), dt, t, flags, ctypes.byref(dg))
+    fn = lib().orc_step_threads if threads else lib().orc_step
+    nt = fn(ctypes.byref(box.c()), ctypes.byref(forces.c()), DRAG[drag_mode],
+            ctypes.byref(P), ctypes.byref(fc), dt, t, flags, ctypes.byref(dg))
+    if nt < 0:
+        raise MemoryError("oracle: private deposit arrays")
     for d in range(3):
         x[:, d] = xs[d]
         p[:, d] = ps[d]
     return Diag(np.array(dg.p_part[:]), np.array(dg.p_grid[:]), dg.e_part, dg.e_grid,
-                dg.sum_abs_j, dg.max_cells_per_step, dg.n_inactive)
+                dg.sum_abs_j, dg.max_cells_per_step, dg.n_inactive, nt if threads else 1)
 
 
 def drag_source(box: Box, forces: Forces, drag_mode: str, x, p, drag, mass, active,

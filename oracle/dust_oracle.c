@@ -19,6 +19,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.14159265358979323846
 
@@ -836,16 +839,15 @@ static void deposit(const orc_box *b, orc_fields *fl, const stencil *s, const do
 
 enum { STEP_APPLY_FEEDBACK = 1, STEP_FILL_GHOSTS = 2 };
 
-int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles *P,
-             orc_fields *fl, double dt, double t, int flags, orc_diag *dg) {
+/* The particle part of one step for particles [i0, i1): drift, gather,
+ * kick, deposit into fl->dep (which the caller has cleared), drift; the
+ * particle sums go to dg. */
+static void step_particles(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles *P,
+                           orc_fields *fl, double dt, double t, int64_t i0, int64_t i1,
+                           orc_diag *dg) {
   int nc = b->geom == G_CART ? b->ndim : 3;
-  int64_t ng = n_ghosted(b);
   double h = 0.5 * dt, th = t + h;
-  memset(dg, 0, sizeof(*dg));
-  for (int m = 0; m <= nc; ++m) memset(fl->dep[m], 0, sizeof(double) * ng);
-  if (flags & STEP_FILL_GHOSTS) orc_fill_ghosts(b, f, th, fl);
-
-  for (int64_t ip = 0; ip < P->n; ++ip) {
+  for (int64_t ip = i0; ip < i1; ++ip) {
     if (!P->active[ip]) continue;
     double x[3], p[3], p0[3];
     for (int d = 0; d < 3; ++d) { x[d] = P->x[d][ip]; p[d] = P->p[d][ip]; }
@@ -893,7 +895,77 @@ int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles
     if (!wrap_particle(b, f, t + dt, x, p)) P->active[ip] = 0;
     for (int d = 0; d < 3; ++d) { P->x[d][ip] = x[d]; P->p[d][ip] = p[d]; }
   }
+}
 
+/* Grid part of one step after the particles: FP64 conservation sums over
+ * every stored cell (before folding), fold, feedback, inactive count. */
+static void step_grid(const orc_box *b, const orc_forces *f, orc_particles *P, orc_fields *fl,
+                      double dt, double t, int flags, orc_diag *dg);
+
+/* One step; particles in index order on one thread. */
+int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles *P,
+             orc_fields *fl, double dt, double t, int flags, orc_diag *dg) {
+  int nc = b->geom == G_CART ? b->ndim : 3;
+  int64_t ng = n_ghosted(b);
+  memset(dg, 0, sizeof(*dg));
+  for (int m = 0; m <= nc; ++m) memset(fl->dep[m], 0, sizeof(double) * ng);
+  if (flags & STEP_FILL_GHOSTS) orc_fill_ghosts(b, f, t + 0.5 * dt, fl);
+  step_particles(b, f, drag_mode, P, fl, dt, t, 0, P->n, dg);
+  step_grid(b, f, P, fl, dt, t, flags, dg);
+  return 0;
+}
+
+/* The same step on several host threads (OpenMP): thread k of T takes the
+ * particles [n k / T, n (k+1) / T) and deposits into a private copy of the
+ * deposit arrays; the copies and the particle sums are then added in
+ * thread order.  Used to time the reference on every host core; the serial
+ * orc_step is the reference of the tests.  Returns the thread count. */
+int orc_step_threads(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles *P,
+                     orc_fields *fl, double dt, double t, int flags, orc_diag *dg) {
+  int nc = b->geom == G_CART ? b->ndim : 3;
+  int64_t ng = n_ghosted(b);
+  memset(dg, 0, sizeof(*dg));
+  for (int m = 0; m <= nc; ++m) memset(fl->dep[m], 0, sizeof(double) * ng);
+  if (flags & STEP_FILL_GHOSTS) orc_fill_ghosts(b, f, t + 0.5 * dt, fl);
+  int nt = 1;
+#ifdef _OPENMP
+  nt = omp_get_max_threads();
+#endif
+  double *priv = (double *)calloc((size_t)nt * (nc + 1) * ng, sizeof(double));
+  orc_diag *pd = (orc_diag *)calloc((size_t)nt, sizeof(orc_diag));
+  if (!priv || !pd) { free(priv); free(pd); return -1; }
+#pragma omp parallel num_threads(nt)
+  {
+    int k = 0;
+#ifdef _OPENMP
+    k = omp_get_thread_num();
+#endif
+    orc_fields mine = *fl;
+    for (int m = 0; m <= nc; ++m) mine.dep[m] = priv + ((size_t)k * (nc + 1) + m) * ng;
+    int64_t i0 = P->n * k / nt, i1 = P->n * (k + 1) / nt;
+    step_particles(b, f, drag_mode, P, &mine, dt, t, i0, i1, &pd[k]);
+  }
+  for (int k = 0; k < nt; ++k) {
+    for (int m = 0; m <= nc; ++m) {
+      const double *src = priv + ((size_t)k * (nc + 1) + m) * ng;
+      for (int64_t i = 0; i < ng; ++i) fl->dep[m][i] += src[i];
+    }
+    for (int c = 0; c < 3; ++c) dg->p_part[c] += pd[k].p_part[c];
+    dg->e_part += pd[k].e_part;
+    dg->sum_abs_j += pd[k].sum_abs_j;
+    if (pd[k].max_cells_per_step > dg->max_cells_per_step)
+      dg->max_cells_per_step = pd[k].max_cells_per_step;
+  }
+  free(priv);
+  free(pd);
+  step_grid(b, f, P, fl, dt, t, flags, dg);
+  return nt;
+}
+
+static void step_grid(const orc_box *b, const orc_forces *f, orc_particles *P, orc_fields *fl,
+                      double dt, double t, int flags, orc_diag *dg) {
+  int nc = b->geom == G_CART ? b->ndim : 3;
+  double th = t + 0.5 * dt;
   /* conservation sums over every stored cell, before folding */
   int n0 = b->n[0], n1 = b->n[1], n2 = b->ndim > 2 ? b->n[2] : 1;
   int g2 = b->ndim > 2 ? 1 : 0;
@@ -922,7 +994,6 @@ int orc_step(const orc_box *b, const orc_forces *f, int drag_mode, orc_particles
         }
   }
   for (int64_t ip = 0; ip < P->n; ++ip) dg->n_inactive += P->active[ip] ? 0 : 1;
-  return 0;
 }
 
 /* ------------------------------------------------------------------ */

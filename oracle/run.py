@@ -97,19 +97,22 @@ class OracleRun:
             self.mass.append(mass)
             self.active.append(np.ones(len(sel), dtype=np.int32))
             g = w.gas[b]
-            self.fields.append(Fields(box, np.asarray(g["rho"], dtype=np.float64),
-                                      [np.asarray(v, dtype=np.float64) for v in g["vel"]]))
+            # copies: the step updates the gas in place (feedback)
+            self.fields.append(Fields(box, np.array(g["rho"], dtype=np.float64),
+                                      [np.array(v, dtype=np.float64) for v in g["vel"]]))
         self.t = float(w.t0)
         self.diags = []
 
-    def step(self, nsteps: int = 1, apply_feedback: bool | None = None):
+    def step(self, nsteps: int = 1, apply_feedback: bool | None = None, threads: bool = False):
+        """nsteps steps of every box (threads: the OpenMP variant of the
+        step, for timing on every host core)."""
         fb = self.w.apply_feedback if apply_feedback is None else apply_feedback
         for _ in range(nsteps):
             ds = []
             for b, box in enumerate(self.boxes):
                 ds.append(step(box, self.forces, self.mode[b], self.x[b], self.p[b],
                                self.drag[b], self.mass[b], self.active[b], self.fields[b],
-                               self.w.dt, self.t, apply_feedback=fb))
+                               self.w.dt, self.t, apply_feedback=fb, threads=threads))
             self.diags.append(ds)
             self.t += self.w.dt
 

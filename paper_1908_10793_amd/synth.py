@@ -90,6 +90,12 @@ def _ghosted_centres(faces):
     return 0.5 * (ext[:-1] + ext[1:])
 
 
+def _offsets(r: np.random.Generator, size, dt_np):
+    """Offsets uniform in [-1/2, 1/2), drawn in the storage precision (a
+    double rounded to single precision could reach +1/2)."""
+    return r.random(size, dtype=dt_np) - dt_np(0.5)
+
+
 def _active_centres(faces):
     f = np.asarray(faces, dtype=np.float64)
     return 0.5 * (f[:-1] + f[1:])
@@ -107,7 +113,7 @@ def cart2d_periodic(n=(64, 64), ppc=16, tau=0.1, dt=0.01, nsteps=10, dtype="f64"
     dt_np = np.float64 if dtype == "f64" else np.float32
     cell = r.integers(0, ncell, size=N).astype(np.int32)
     off = np.zeros((N, 3), dtype=dt_np)
-    off[:, :2] = r.uniform(-0.5, 0.5, size=(N, 2)).astype(dt_np)
+    off[:, :2] = _offsets(r, (N, 2), dt_np)
     mom = np.zeros((N, 3), dtype=dt_np)
     gs = _ghost_shape(n, 2)
     rho = np.ones(gs)
@@ -206,7 +212,7 @@ def cylindrical_disk(n=(256, 512, 64), npart=2 ** 25, Rin=0.4, Rout=2.5, zh=0.15
     ci = r.choice(n[0], size=npart, p=wR / wR.sum())
     cj = r.integers(0, n[1], size=npart)
     ck = r.integers(0, n[2], size=npart)
-    off = r.uniform(-0.5, 0.5, size=(npart, 3)).astype(dt_np)
+    off = _offsets(r, (npart, 3), dt_np)
     cell = (ci + n[0] * (cj + n[1] * ck)).astype(np.int32)
     Rp = 0.5 * (fR[ci] + fR[ci + 1]) + off[:, 0].astype(np.float64) * wR[ci]
     zp = 0.5 * (fZ[ck] + fZ[ck + 1]) + off[:, 2].astype(np.float64) * (fZ[1] - fZ[0])
@@ -291,7 +297,7 @@ def spherical_disk(n=(256, 128, 512), ppc=4, rin=0.5, rout=5.0, dth=0.3,
     ncell = n[0] * n[1] * n[2]
     N = ncell * ppc
     cell = r.integers(0, ncell, size=N).astype(np.int32)
-    off = r.uniform(-0.5, 0.5, size=(N, 3)).astype(dt_np)
+    off = _offsets(r, (N, 3), dt_np)
     ci = cell % n[0]
     cj = (cell // n[0]) % n[1]
     rp = _active_centres(fr)[ci] + off[:, 0].astype(np.float64) * (fr[1] - fr[0])
@@ -330,24 +336,48 @@ def batched_boxes(sizes=(32, 48, 64, 80, 96, 128, 160, 192), max_per_species=32,
     """Independent periodic unit cubes of uneven sizes; in every cell each
     species has U{1..max} particles at uniform random offsets, at rest; gas
     rho = 1 + 1e-3 N(0,1), v ~ U(-0.01, 0.01).  Species masses are those of
-    eps_species per species at the mean count in a 64^3 box."""
-    r = rng(seed)
+    eps_species per species at the mean count in a 64^3 box.
+
+    Every box draws from its own stream (spawned from the seed), so a box's
+    inputs do not depend on the other boxes: a subset of boxes generated
+    alone (same sizes list, ``boxes=``) holds the same particles and gas as
+    in the whole batch.  Offsets are drawn in the storage precision, so they
+    lie in [-1/2, 1/2) exactly.  Arrays are allocated once at their full size
+    (about 29 bytes per particle in FP32 for the 8-box batch of ~1e9
+    particles)."""
+    streams = np.random.SeedSequence(SEED0 + seed).spawn(len(sizes))
     dt_np = np.float64 if dtype == "f64" else np.float32
     ns = len(species_tau)
-    boxes, gas, cells, specs = [], [], [], []
-    base = 0
+    ncells = [nb ** 3 for nb in sizes]
+    bases = np.concatenate([[0], np.cumsum(ncells)]).astype(np.int64)
+    # counts first (one draw per box stream), then every array at its size
+    gens, counts = [], []
+    for b in range(len(sizes)):
+        r = np.random.Generator(np.random.PCG64(streams[b]))
+        gens.append(r)
+        counts.append(r.integers(1, max_per_species + 1, size=ncells[b] * ns, dtype=np.int32))
+    nper = [int(c.sum(dtype=np.int64)) for c in counts]
+    N = int(sum(nper))
+    cell = np.empty(N, dtype=np.int32)
+    species = np.empty(N, dtype=np.uint8)
+    off = np.empty((N, 3), dtype=dt_np)
+    boxes, gas = [], []
+    at = 0
     for b, nb in enumerate(sizes):
+        r = gens[b]
         n = (nb, nb, nb)
-        ncell = nb ** 3
         faces = [_uniform_faces(0.0, 1.0, nb) for _ in range(3)]
         boxes.append(dict(geom="cart", ndim=3, n=n, bc_lo=("periodic",) * 3,
                           bc_hi=("periodic",) * 3, shape=(shape,) * 3, faces=faces))
-        cnt = r.integers(1, max_per_species + 1, size=(ncell, ns))
-        c = np.repeat(np.repeat(np.arange(ncell), ns), cnt.ravel())
-        s = np.repeat(np.tile(np.arange(ns), ncell), cnt.ravel())
-        cells.append((c + base).astype(np.int32))
-        specs.append(s.astype(np.uint8))
-        base += ncell
+        k = np.repeat(np.arange(ncells[b] * ns, dtype=np.int32), counts[b])
+        sl = slice(at, at + nper[b])
+        np.floor_divide(k, ns, out=cell[sl])
+        cell[sl] += np.int32(bases[b])
+        species[sl] = k % ns
+        del k
+        off[sl] = r.random((nper[b], 3), dtype=dt_np)
+        off[sl] -= dt_np(0.5)
+        at += nper[b]
         gs = _ghost_shape(n, 3)
         rho = np.ones(gs)
         rho[1:-1, 1:-1, 1:-1] = 1.0 + 1e-3 * r.standard_normal((nb, nb, nb))
@@ -357,10 +387,6 @@ def batched_boxes(sizes=(32, 48, 64, 80, 96, 128, 160, 192), max_per_species=32,
             v[1:-1, 1:-1, 1:-1] = r.uniform(-0.01, 0.01, size=(nb, nb, nb))
             vel.append(v.astype(dt_np))
         gas.append(dict(rho=rho.astype(dt_np), vel=vel))
-    cell = np.concatenate(cells)
-    species = np.concatenate(specs)
-    N = cell.shape[0]
-    off = r.uniform(-0.5, 0.5, size=(N, 3)).astype(dt_np)
     mom = np.zeros((N, 3), dtype=dt_np)
     mean_count = 0.5 * (1 + max_per_species)
     mass = [eps_species / (64 ** 3) / mean_count for _ in range(ns)]

@@ -367,3 +367,28 @@ def test_feedback_hands_the_gas_the_particle_momentum(case):
         if case != "cyl":
             assert kept == 0.0
     assert np.abs(d.p_part).max() > 1e-6
+
+
+# ---------------------------------------------------------------- threaded timing variant
+
+def test_threaded_step_equals_serial_step():
+    """The OpenMP variant of the oracle step (timing on every host core)
+    does each particle's arithmetic exactly as the serial step; only the
+    order in which the deposits are added differs."""
+    import os
+    from oracle.run import OracleRun
+    from paper_1908_10793_amd import synth
+    os.environ.setdefault("OMP_NUM_THREADS", "4")
+    w = synth.batched_boxes(sizes=(6, 5), max_per_species=3, dtype="f64")
+    a, b = OracleRun(w), OracleRun(w)
+    a.step(1)
+    b.step(1, threads=True)
+    for k in range(len(a.boxes)):
+        np.testing.assert_array_equal(a.x[k], b.x[k])
+        np.testing.assert_array_equal(a.p[k], b.p[k])
+        for c in range(4):
+            ref = a.fields[k].dep[c]
+            assert np.abs(b.fields[k].dep[c] - ref).max() <= 1e-14 * np.abs(ref).max()
+        for c in range(3):
+            np.testing.assert_allclose(b.fields[k].vel[c], a.fields[k].vel[c], rtol=0, atol=1e-15)
+    assert b.diags[-1][0].threads >= 1
