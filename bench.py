@@ -1,29 +1,42 @@
 #!/usr/bin/env python3
 """Benchmark of the dust-particle hot path on one MI355X.
 
-One step = one pass of the whole hot path over the shearing-box workload
-(3-D standard shearing box, 128^3 cells, 2^24 particles, TSC weights, FP32
-storage): binning by tile, half drift, weights, gather, exponential-midpoint
-kick, momentum + energy deposit, half drift with shear-periodic wrap, ghost
-fill and fold, feedback onto the gas, FP64 conservation sums; the loop runs
-eagerly (every launch asynchronous on one stream) so that HIP events can
-bracket each fused-kernel launch; the same loop replayed from a captured
-hipGraph is reported beside it.  Inputs are resident in HBM before the timed
-region.
+One step = one pass of the whole hot path over one batch of synthetic input:
+binning by tile (every k steps, k from the autotuner), half drift, weights,
+gather, exponential-midpoint kick, momentum + energy deposit, half drift with
+wrap, ghost fill and fold, feedback onto the gas, FP64 conservation sums.
+Inputs are resident in HBM before the timed region.
 
-Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
-(the fused tile kernel, timed with HIP events on its own stream inside the
-timed region) and the FP64 CPU oracle timed on a bounded sample; beside
-them, outside the timed step, the gas predictor's drag source on the same
-particles and gas ("drag_source") and the dust density deposit
-("mass_density").
+Workloads (--config):
+  5 (default, the headline)  8 independent periodic cubes of 32^3 .. 192^3
+      cells of width 1/64 (15,073,280 cells), 4 species (tau = 0.01, 0.1, 1, 10), U{1..32}
+      particles per cell and species (about 9.95e8 particles), TSC, FP32
+      storage and push, dt = 0.01; one launch per step covers every box; the
+      K-step loop is captured in a hipGraph and replayed.
+  2  3-D shearing box 128^3, 2^24 particles (8 per cell), TSC, FP32.
+  3  cylindrical disk 256x512x64 (log R), 2^25 particles, Stokes numbers.
+  4  spherical disk 256x128x512, 2^26 particles, stiff stopping times.
+  1  2-D periodic box 64^2, 65,536 particles, CIC, FP64.
+
+Prints one JSON line: particle-steps/s (median of 5 timed runs of the K
+steps, launched from the host), the roofline of the dominant kernel (the fused
+tile kernel, timed with HIP events recorded on the library's stream around
+every launch inside the timed runs), the same K steps replayed from a captured
+hipGraph (timing.graph), the worst error of one step against the FP64 oracle on the box the
+oracle can step (box 0 for config 5, a particle sample otherwise), the plain
+FP64 GPU step (unfused, FP64 storage and arithmetic) with its own error and the
+speed-up over it, and the oracle timed on the host cores (one thread, and
+every core with OpenMP).  With config 5 the 128^3 shearing box is reported too
+(key "config2").
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -31,23 +44,38 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (gather+exp-midpoint push+deposit)"
+WORKLOAD_NAMES = {1: "cart2d_periodic", 2: "shearing_box", 3: "cylindrical_disk",
+                  4: "spherical_disk", 5: "batched_boxes"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=5, choices=(1, 2, 3, 4, 5))
+    ap.add_argument("--reps", type=int, default=5, help="timed replays of the K steps (median)")
     ap.add_argument("--rebin-every", type=int, default=1, help="with --no-tune")
     ap.add_argument("--tile", type=str, default="8,8,4,0", help="with --no-tune")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (dust_ctx_autotune) and use --tile / --rebin-every")
-    ap.add_argument("--n", type=int, default=128, help="cells per axis")
+    ap.add_argument("--tune-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
-    ap.add_argument("--unfused", action="store_true", help="time the unfused per-phase chain")
-    ap.add_argument("--arith", choices=("f64", "f32"), default="f32",
-                    help="per-particle arithmetic of the FP32-storage path")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU step")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the side measurements (drag source, dust density, config 2)")
+    ap.add_argument("--no-check", action="store_true", help="skip the parity check against the oracle")
+    ap.add_argument("--eager", action="store_true", help="time the eager loop, not the graph")
+    ap.add_argument("--arith", choices=("f64", "f32"), default=None,
+                    help="per-particle arithmetic of the FP32-storage path (default: the "
+                         "context's, FP32 for Cartesian boxes)")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+                    help="particles the oracle steps for the CPU baseline (configs 2-4)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (the "
                          "reference kernel of the HBM byte counters)")
@@ -56,30 +84,40 @@ def parse():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
                     help="write the HBM byte summary of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) taken with --calib-copy-mb")
+    ap.add_argument("--n-particles", type=int, default=0,
+                    help="with --summarize-counters: particles of the profiled run")
     ap.add_argument("--command", type=str, default="",
                     help="the profiling command, recorded in the summary")
     return ap.parse_args()
 
 
+# ------------------------------------------------------------------ profiles
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("dust_fused.hip", "dust_device.h", "dust_particle.h"):
-        with open(os.path.join(HERE, "paper_1908_10793_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(HERE, "paper_1908_10793_amd", "csrc")
+    for f in ("dust_fused_kern.h", "dust_device.h", "dust_particle.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-COUNTER_SUMMARY = os.path.join(HERE, "profiles", "k_fused_shearing_box_128_hbm_bytes.txt")
 FUSED_KERNEL = "k_fused"
 
 
-def counter_traffic(kernel_hash: str, n_particles: int):
+def counter_summary_path(name: str) -> str:
+    return os.path.join(HERE, "profiles", f"k_fused_{name}_hbm_bytes.txt")
+
+
+def counter_traffic(name: str, kernel_hash: str, n_particles: int):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(COUNTER_SUMMARY):
+    counter summary of this workload, if it was taken on the current kernel
+    source and the same particle count."""
+    path = counter_summary_path(name)
+    if not os.path.exists(path):
         return None
     d = {}
-    with open(COUNTER_SUMMARY) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -150,22 +188,21 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
     fetch = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
     write = _counter_per_dispatch(write_dir, "WRITE_SIZE")
     copy_kib = copy_mb * 1024.0
-    # the calibration copy is the largest copy dispatch of the run
+
     def is_copy(k):
         return "copy" in k.lower() or "elementwise" in k.lower()
+    # the calibration copy is the largest copy dispatch of the run
     cf = max(max(v) for k, v in fetch.items() if is_copy(k))
     cw = max(max(v) for k, v in write.items() if is_copy(k))
     f_fetch, f_write = copy_kib / cf, copy_kib / cw
-    # mean over the fused dispatches after the first (cold) one
+
     def warm_mean(v):
         w = v[1:] if len(v) > 1 else v
         return sum(w) / len(w), len(w)
-    kf = [warm_mean(v) for k, v in fetch.items() if FUSED_KERNEL + "<" in k]
-    kw = [warm_mean(v) for k, v in write.items() if FUSED_KERNEL + "<" in k]
-    (kf, nfd), (kw, nwd) = kf[0], kw[0]
-    kf, kw = [kf], [kw]
-    fb = kf[0] * f_fetch * 1024.0
-    wb = kw[0] * f_write * 1024.0
+    (kf, nfd), = [warm_mean(v) for k, v in fetch.items() if FUSED_KERNEL + "<" in k]
+    (kw, nwd), = [warm_mean(v) for k, v in write.items() if FUSED_KERNEL + "<" in k]
+    fb = kf * f_fetch * 1024.0
+    wb = kw * f_write * 1024.0
     lines = ["# HBM bytes of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per",
              "# dispatch), each scaled by known/counted bytes of a device copy of known size",
              f"# command: {command}",
@@ -178,8 +215,8 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
              f"fetch_scale: {f_fetch:.4f}",
              f"write_scale: {f_write:.4f}",
              f"fused_dispatches_averaged: {nfd} (FETCH), {nwd} (WRITE); the first, cold one left out",
-             f"fused_fetch_kib_counted: {kf[0]:.1f}",
-             f"fused_write_kib_counted: {kw[0]:.1f}",
+             f"fused_fetch_kib_counted: {kf:.1f}",
+             f"fused_write_kib_counted: {kw:.1f}",
              f"fused_fetch_bytes: {fb:.4g}",
              f"fused_write_bytes: {wb:.4g}",
              f"hbm_bytes_per_launch: {fb + wb:.6g}"]
@@ -187,22 +224,431 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
         fh.write("\n".join(lines) + "\n")
 
 
-def cpu_baseline(w, sample: int):
-    """The FP64 oracle (serial C, one core) on the first `sample` particles of
-    the same workload, one step."""
+# ------------------------------------------------------------------ host
+
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": aff, "cpu_count": os.cpu_count(), "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+# ------------------------------------------------------------------ workloads
+
+def make_workload(cfg: int, dtype: str):
+    from paper_1908_10793_amd import synth
+    if cfg == 1:
+        return synth.cart2d_periodic(dtype="f64")
+    if cfg == 2:
+        return synth.shearing_box(dtype=dtype)
+    if cfg == 3:
+        return synth.cylindrical_disk(dtype=dtype)
+    if cfg == 4:
+        return synth.spherical_disk(dtype=dtype)
+    return synth.batched_boxes(dtype=dtype)
+
+
+def describe(cfg: int, w, arith: str) -> str:
+    if cfg == 5:
+        sz = ",".join(str(b["n"][0]) for b in w.boxes)
+        return (f"batched: {len(w.boxes)} periodic cubes of {sz} cells per side (cell width 1/64), 4 species "
+                f"(tau = 0.01, 0.1, 1, 10), U{{1..32}} particles per cell and species, "
+                f"{w.n} particles, TSC, FP32 storage, {arith.upper()} push, dt = {w.dt}, feedback on")
+    if cfg == 2:
+        return (f"shearing box 128^3, {w.n} particles (8/cell, seeded sub-lattice), TSC, FP32 storage, "
+                f"{arith.upper()} push, dt = {w.dt}, feedback on")
+    if cfg == 3:
+        return f"cylindrical disk 256x512x64 (log R), {w.n} particles, Stokes numbers, TSC, FP32 storage"
+    if cfg == 4:
+        return f"spherical disk 256x128x512, {w.n} particles, stiff stopping times, TSC, FP32 storage"
+    return f"2-D periodic box 64^2, {w.n} particles, CIC, FP64"
+
+
+def oracle_subset(w, cfg: int, sample: int):
+    """The part of w that the oracle steps for the parity check and the CPU
+    baseline: box 0 of the batch (boxes are independent), or the first
+    `sample` particles of a single box (all of them on the full grid).
+    Returns (workload, particle index array into w)."""
     import numpy as np
-    import dataclasses
-    from oracle.run import OracleRun
+    if cfg == 5:
+        bases, _ = w.cell_bases()
+        n0 = int(np.searchsorted(w.cell, bases[1], side="left"))
+        assert np.all(w.cell[:n0] < bases[1])
+        sel = np.arange(n0)
+        sub = dataclasses.replace(w, boxes=[w.boxes[0]], cell=w.cell[:n0].copy(),
+                                  off=w.off[:n0].copy(), mom=w.mom[:n0].copy(),
+                                  species=w.species[:n0].copy(), gas=[w.gas[0]])
+        return sub, sel
     sel = np.arange(min(sample, w.n))
-    ws = dataclasses.replace(w, cell=w.cell[sel], off=w.off[sel], mom=w.mom[sel],
-                             species=w.species[sel] if w.species is not None else None)
-    run = OracleRun(ws)
+    sub = dataclasses.replace(
+        w, cell=w.cell[sel], off=w.off[sel], mom=w.mom[sel],
+        species=w.species[sel] if w.species is not None else None,
+        drag=w.drag[sel] if w.drag is not None else None,
+        mass=w.mass[sel] if w.mass is not None else None)
+    return sub, sel
+
+
+def gpu_state_of(P, F, sel_ids, nstore0, full_box: bool):
+    """The GPU particles whose id is in sel_ids (sorted by id) and, for a full
+    box (box 0), its deposits and gas (first nstore0 stored cells)."""
+    import numpy as np
+    import torch
+    torch.cuda.synchronize()
+    ids = P["id"]
+    lo, hi = int(sel_ids[0]), int(sel_ids[-1])
+    m = (ids >= lo) & (ids <= hi)
+    idx = torch.nonzero(m).squeeze(1)
+    order = torch.argsort(ids[idx])
+    idx = idx[order]
+    st = {"id": ids[idx].cpu().numpy(), "cell": P["cell"][idx].cpu().numpy().astype(np.int64),
+          "off": np.stack([t[idx].cpu().numpy().astype(np.float64) for t in P["off"]], 1),
+          "mom": np.stack([t[idx].cpu().numpy().astype(np.float64) for t in P["mom"]], 1)}
+    if full_box:
+        st["dep"] = [d[:nstore0].cpu().numpy().astype(np.float64) for d in F["dep"]]
+        st["vel"] = [v[:nstore0].cpu().numpy().astype(np.float64) for v in F["vel"]]
+    return st
+
+
+def parity_errors(sub, run, st, full_box: bool, tol: float):
+    """Worst normwise errors of the GPU state after one step against the
+    oracle run from the same input (positions in host-cell widths, momenta
+    against |p| + |p_start| + max |gas momentum|, deposits and fed-back gas
+    per channel against their maxima)."""
+    import numpy as np
+    import oracle as O
+    box = run.boxes[0]
+    cell_o, off_o, p_o, act = run.particle_state(0)
+    nd = box.ndim
+    cell_g = st["cell"]
+    assert np.array_equal(act, cell_g >= 0), "removed-particle sets differ"
+    a = act
+    x_o = run.x[0][a]
+    lo = 0
+    x_g = O.to_global(box, cell_g[a] - lo, st["off"][a])
+    dx = x_g - x_o
+    idx = O.unravel(box, cell_o[a])
+    ex = 0.0
+    for d in range(nd):
+        c, wd = O.centers_widths(box, d)
+        if box.bc_lo[d] in ("periodic", "shear"):
+            L = box.faces[d][-1] - box.faces[d][0]
+            dx[:, d] = (dx[:, d] + 0.5 * L) % L - 0.5 * L
+        ex = max(ex, float(np.abs(dx[:, d] / wd[idx[d]]).max()))
+    nc = nd if box.geom == "cart" else 3
+    p0 = np.asarray(sub.mom, dtype=np.float64)[a][:, :nc]
+    gmax = max(float(np.abs(np.asarray(v)).max()) for v in sub.gas[0]["vel"][:nc])
+    sc = np.ones((a.sum(), 3))
+    if box.geom == "cyl":
+        sc[:, 1] = x_o[:, 0]
+    elif box.geom == "sph":
+        sc[:, 1] = x_o[:, 0]
+        sc[:, 2] = x_o[:, 0] * np.sin(x_o[:, 1])
+    scale = np.abs(p_o[a][:, :nc]).max(1) + np.abs(p0).max(1) + gmax * sc[:, :nc].max(1) + 1e-300
+    emom = float((np.abs(st["mom"][a][:, :nc] - p_o[a][:, :nc]).max(1) / scale).max())
+    cells_diff = int((cell_g[a] != cell_o[a]).sum())
+    out = {"pos": ex, "mom": emom, "cell_mismatch": cells_diff}
+    if full_box:
+        fo = run.fields[0]
+        edep = 0.0
+        for c in range(nc + 1):
+            ref = fo.dep[c].reshape(-1)
+            den = np.abs(ref).max()
+            if den > 0:
+                edep = max(edep, float(np.abs(st["dep"][c] - ref).max() / den))
+        evel = 0.0
+        act_sl = (slice(1, -1),) * 3
+        for c in range(nc):
+            ref = fo.vel[c].reshape(box.ghosted_shape)[act_sl]
+            got = st["vel"][c].reshape(box.ghosted_shape)[act_sl]
+            evel = max(evel, float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)))
+        out["dep"] = edep
+        out["vel"] = evel
+    out["worst"] = max(v for k, v in out.items() if k != "cell_mismatch")
+    out["tol"] = tol
+    out["pass"] = out["worst"] <= tol
+    return out
+
+
+def check_step(ctx, dust, w, cfg, P, F, flags, t, sample, time_oracle: bool):
+    """One GPU step (flags) from the current state against the FP64 oracle on
+    the subset the oracle steps.  Returns (parity dict, cpu baseline dict)."""
+    import numpy as np
+    from oracle.run import OracleRun
+    sub, sel = oracle_subset(w, cfg, sample)
+    full_box = cfg == 5 or len(sel) == w.n
+    nstore0 = int(np.prod([b + 2 for b in w.boxes[0]["n"][:w.boxes[0]["ndim"]]]))
+    ctx.step(P, F, w.dt, dust.forces_for(w, t), 1, flags)
+    st = gpu_state_of(P, F, sel, nstore0, full_box)
+    run = OracleRun(dataclasses.replace(sub, t0=t))
     t0 = time.perf_counter()
     run.step(1)
-    dt = time.perf_counter() - t0
-    return {"value": len(sel) / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 step of {len(sel)} of the {w.n} particles on the full {w.boxes[0]['n']} "
-                      f"grid (serial FP64 C oracle, {dt:.1f} s)"}
+    t_one = time.perf_counter() - t0
+    # the oracle steps the sample with the gas of the whole grid; with a
+    # particle sample the deposits cover only part of the particles
+    par = parity_errors(sub, run, st, full_box, 1e-12 if w.dtype == "f64" else 1e-5)
+    cpu = None
+    if time_oracle:
+        run_t = OracleRun(dataclasses.replace(sub, t0=t))
+        t0 = time.perf_counter()
+        run_t.step(1, threads=True)
+        t_thr = time.perf_counter() - t0
+        nthr = run_t.diags[-1][0].threads
+        what = ("box 0 (32^3, every particle)" if cfg == 5 else
+                f"the first {len(sel)} of the {w.n} particles on the full grid")
+        cpu = {"value": len(sel) / t_one, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"1 step of {what} ({len(sel)} particles, serial FP64 C oracle, "
+                         f"{t_one:.1f} s)",
+               "threads": {"value": len(sel) / t_thr, "cores": nthr,
+                           "sample": f"the same step with the OpenMP variant on {nthr} threads "
+                                     f"({t_thr:.2f} s)"},
+               **host_info()}
+    return par, cpu
+
+
+def timed_kernel(ctx, fn, K, stream):
+    """Average time of K calls of fn() (HIP events on the launch stream)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(K):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / K
+
+
+def run_config(cfg: int, args, extra: bool, K: int, W: int):
+    import numpy as np
+    import torch
+    from paper_1908_10793_amd import dust
+
+    dtype = "f64" if cfg == 1 else "f32"
+    t_gen = time.perf_counter()
+    w = make_workload(cfg, dtype)
+    log(f"config {cfg}: {w.n} particles generated in {time.perf_counter() - t_gen:.1f} s")
+    N = w.n
+    C = sum(int(np.prod(b["n"][:b["ndim"]])) for b in w.boxes)
+    ctx = dust.context_for(w)
+    arith = args.arith or ("f32" if w.boxes[0]["geom"] == "cart" else "f64")
+    if dtype == "f32":
+        ctx.set_arith(arith)
+    tx, ty, tz, slack = (int(v) for v in args.tile.split(","))
+    if cfg == 1 and args.tile == "8,8,4,0":
+        tx, ty, tz = 16, 16, 1
+    ctx.set_tile(tx, ty, tz, slack)
+    check = not args.no_check
+    P, F = dust.upload(w, ctx, with_id=check)
+    torch.cuda.synchronize()
+    log(f"uploaded ({torch.cuda.memory_allocated() / 2**30:.1f} GiB on the device)")
+    flags = dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG | dust.STEP_FUSED
+    tuned = None
+    if args.no_tune:
+        flags |= dust.STEP_REBIN_EVERY(args.rebin_every)
+        rebin = args.rebin_every
+    else:
+        t0 = time.perf_counter()
+        tuned = ctx.autotune(P, F, w.dt, dust.forces_for(w, 0.0), dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG,
+                             steps=args.tune_steps)
+        (tx, ty, tz), rebin = tuned["tile"], tuned["rebin_every"]
+        log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuned}")
+    t = 0.0
+    out = {}
+    # one step against the FP64 oracle (the first warm-up step)
+    parity, cpu = None, None
+    if check:
+        parity, cpu = check_step(ctx, dust, w, cfg, P, F, flags, t, args.cpu_sample,
+                                 time_oracle=not args.no_cpu_baseline and not extra)
+        t += w.dt
+        log(f"parity: {parity}")
+        del P["id"]
+        torch.cuda.empty_cache()
+    ctx.status()
+    nw = max(W - (1 if check else 0), 0)
+    if nw:
+        ctx.step(P, F, w.dt, dust.forces_for(w, t), nw, flags)
+        t += nw * w.dt
+    torch.cuda.synchronize()
+    ctx.status()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fl, profile: bool):
+        nonlocal t
+        times, kern = [], []
+        for r in range(max(args.reps, 1)):
+            torch.cuda.synchronize()
+            e0.record(stream)
+            ctx.step(P, F, w.dt, dust.forces_for(w, t), K, fl)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            if profile:
+                kern.extend(ctx.profile(K))
+            t += K * w.dt
+            log(f"{'graph' if fl & dust.STEP_GRAPH else 'eager'} rep {r}: {times[-1] / K:.3f} ms/step")
+        return times, kern
+
+    # timed region: K steps launched from the host, each fused-kernel launch
+    # bracketed by HIP events on the library's stream (events recorded inside
+    # a captured graph cannot be timed on this runtime)
+    ctx.set_profile(K)
+    reps, kern = timed(flags, True)
+    diag = ctx.status()
+    ctx.set_profile(0)
+    graph = None
+    if not args.eager:
+        gflags = flags | dust.STEP_GRAPH
+        ctx.step(P, F, w.dt, dust.forces_for(w, t), K, gflags)   # capture (and run)
+        t += K * w.dt
+        torch.cuda.synchronize()
+        ctx.status()
+        greps, _ = timed(gflags, False)
+        ctx.status()
+        gms = float(np.median(greps))
+        graph = {"value": N * K / (gms * 1e-3), "ms_per_step": gms / K,
+                 "reps_ms": [round(x, 3) for x in greps]}
+    ms = float(np.median(reps))
+    value = N * K / (ms * 1e-3)
+    ppc = N / C
+    real = 8 if dtype == "f64" else 4
+    state = 4 + 2 * 2 * real if cfg == 1 else 4 + 6 * real      # cell + offsets + momenta
+    per_p = 2.0 * state + (4.0 if cfg in (3, 4) else 0.0)       # read + write (+ per-particle drag)
+    per_cell = (4 + 8) * real if cfg != 1 else (3 + 6) * real    # gas rho + v read, deposit RMW
+    bytes_per_pstep = per_p + per_cell / ppc
+    roof = None
+    if kern:
+        kavg = float(np.mean(kern)) * 1e-3
+        achieved = bytes_per_pstep * N / kavg / 1e9
+        khash = source_hash()
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counter_traffic(WORKLOAD_NAMES[cfg], khash, N),
+                "kernel": FUSED_KERNEL, "kernel_avg_us": round(kavg * 1e6, 2),
+                "launches_timed": len(kern),
+                "bytes_per_particle_step": round(bytes_per_pstep, 3),
+                "algorithmic_bytes_per_launch": bytes_per_pstep * N, "kernel_source_hash": khash,
+                "step_frac": round(bytes_per_pstep * value / 1e9 / HBM_PEAK_GBS, 4)}
+    res = float(np.max(np.abs(np.array(diag["p_part"]) + np.array(diag["p_grid"])))) / max(
+        diag["sum_abs_j"], 1e-300)
+    out.update({
+        "value": value, "ms_per_step": ms / K,
+        "config": {"workload": describe(cfg, w, arith), "n_particles": N, "active_cells": C,
+                   "boxes": [list(b["n"][:b["ndim"]]) for b in w.boxes],
+                   "tile": [tx, ty, tz], "rebin_every": rebin, "autotuned": tuned,
+                   "timed_loop": "eager (graph replay under timing.graph)", "steps_per_call": K,
+                   "storage": dtype,
+                   "push_arith": arith if dtype == "f32" else "f64",
+                   "deposit_accum": "per-cell register sums, FP64 LDS tile window, HBM atomics"},
+        "roofline": roof,
+        "timing": {"reps_ms": [round(x, 3) for x in reps], "median_ms": ms,
+                   "min_ms": float(np.min(reps)), "graph": graph},
+        "parity": parity,
+        "diag": {"momentum_residual": res, "max_cells_per_step": diag["max_cells_per_step"],
+                 "n_fallback": diag["n_fallback"], "flags": diag["flag_names"], "steps": diag["steps"]},
+    })
+    if cpu:
+        out["cpu_baseline"] = cpu
+    if not args.no_extra and not extra:
+        Kx = max(1, min(K, 10))
+        fr = dust.forces_for(w, t)
+        ds_s = timed_kernel(ctx, lambda: ctx.drag_source(P, F, w.dt, fr), Kx, stream)
+        sp = 1.0 if "species" in P else 0.0
+        ds_bytes = (4 + 6 * real + sp + (4 * real if w.drag is not None else 0) +
+                    (4 + 3) * real / ppc) * N
+        out["drag_source"] = {"kernel": "k_drag_source", "us_per_launch": round(ds_s * 1e6, 2),
+                              "algorithmic_bytes_per_launch": ds_bytes,
+                              "achieved": round(ds_bytes / ds_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(ds_bytes / ds_s / 1e9 / HBM_PEAK_GBS, 4)}
+        rho_d = torch.zeros_like(F["rho"])
+        md_s = timed_kernel(ctx, lambda: ctx.deposit_mass(P, rho_d), Kx, stream)
+        md_bytes = (4 + 3 * real + sp + 2 * real / ppc) * N
+        out["mass_density"] = {"kernel": "k_mass_density", "us_per_launch": round(md_s * 1e6, 2),
+                               "algorithmic_bytes_per_launch": md_bytes,
+                               "achieved": round(md_bytes / md_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(md_bytes / md_s / 1e9 / HBM_PEAK_GBS, 4)}
+        del rho_d
+        log(f"drag source {ds_s * 1e3:.2f} ms, dust density {md_s * 1e3:.2f} ms")
+    ctx.close()
+    del P, F, ctx
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if dtype == "f32" and not args.no_fp64 and not extra:
+        out["fp64_plain"] = fp64_plain(w, cfg, args, K)
+        if out["fp64_plain"]:
+            out["fp64_plain"]["speedup_of_fp32_fused"] = round(
+                out["fp64_plain"]["ms_per_step"] / (ms / K), 2)
+    return out, w
+
+
+def fp64_plain(w, cfg, args, K):
+    """The plain FP64 GPU step: FP64 storage and arithmetic, the unfused
+    per-phase chain (drift, gather, kick, deposit, drift, one thread per
+    particle, HBM atomics), on the same inputs widened exactly; one step
+    checked against the oracle at the FP64 bar, then a few steps timed."""
+    import torch
+    from paper_1908_10793_amd import dust
+    w64 = dataclasses.replace(w, dtype="f64")
+    ctx = dust.context_for(w64)
+    check = not args.no_check
+    P, F = dust.upload(w64, ctx, with_id=check)
+    flags = dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
+    t = 0.0
+    par = None
+    if check:
+        par, _ = check_step(ctx, dust, w64, cfg, P, F, flags, t, args.cpu_sample, time_oracle=False)
+        t += w.dt
+        log(f"fp64 plain parity: {par}")
+        del P["id"]
+        torch.cuda.empty_cache()
+    K64 = max(1, min(K, 3))
+    ctx.step(P, F, w.dt, dust.forces_for(w, t), 1, flags)
+    t += w.dt
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.step(P, F, w.dt, dust.forces_for(w, t), K64, flags)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K64
+    log(f"fp64 plain: {ms:.2f} ms/step")
+    ctx.close()
+    del P, F, ctx
+    torch.cuda.empty_cache()
+    return {"value": w.n / (ms * 1e-3), "ms_per_step": ms, "steps_timed": K64,
+            "what": "unfused per-phase chain, FP64 storage and arithmetic, same inputs",
+            "parity": par}
+
+
+def copy_bandwidth():
+    """Measured device-to-device copy bandwidth (read + write bytes)."""
+    import torch
+    nel = 256 << 20
+    src = torch.ones(nel, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2.0 * 4 * nel * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def main():
@@ -211,155 +657,33 @@ def main():
         summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
         return
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters, args.command, 8 * args.n ** 3,
+        summarize_counters(*args.summarize_counters, args.command, args.n_particles,
                            args.calib_copy_mb)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
     import torch
-    from paper_1908_10793_amd import dust, synth
-
-    n = args.n
-    w = synth.shearing_box(n=(n, n, n), dtype="f32")
-    N = w.n
-    ctx = dust.context_for(w)
-    tx, ty, tz, slack = (int(v) for v in args.tile.split(","))
-    ctx.set_tile(tx, ty, tz, slack)
-    ctx.set_arith(args.arith)
-    P, F = dust.upload(w, ctx, with_id=False)
-    flags = dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
-    tuned = None
-    if args.unfused:
-        pass
-    elif args.no_tune:
-        flags |= dust.STEP_FUSED | dust.STEP_REBIN_EVERY(args.rebin_every)
-    else:
-        # tile shape and rebinning interval from the autotuner (on copies)
-        tuned = ctx.autotune(P, F, w.dt, dust.forces_for(w, 0.0), flags, steps=12)
-        (tx, ty, tz), rebin = tuned["tile"], tuned["rebin_every"]
-        args.rebin_every = rebin
-        flags |= dust.STEP_FUSED           # interval from the context
+    assert torch.cuda.is_available(), "the benchmark needs a GPU"
     K, W = args.steps, args.warmup
-    t = 0.0
-    torch.cuda.synchronize()
-    # warm-up
-    if W > 0:
-        ctx.step(P, F, w.dt, dust.forces_for(w, t), W, flags)
-        t += W * w.dt
-    torch.cuda.synchronize()
-    ctx.status()
-    ctx.set_profile(K)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    ctx.step(P, F, w.dt, dust.forces_for(w, t), K, flags)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    t += K * w.dt
-    kern = ctx.profile(K) if not args.unfused else []
-    diag = ctx.status()
-    value = N * K / (ms * 1e-3)
-    ppc = N / (n ** 3)
-    bytes_per_pstep = 56.0 + 48.0 / ppc          # algorithmic bytes per particle-step
-    roof = None
-    if kern:
-        kavg = float(np.mean(kern)) * 1e-3
-        achieved = bytes_per_pstep * N / kavg / 1e9
-        khash = source_hash()
-        traffic = counter_traffic(khash, N)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_fused", "kernel_avg_us": round(kavg * 1e6, 2),
-                "algorithmic_bytes_per_launch": bytes_per_pstep * N, "kernel_source_hash": khash}
-    res = float(np.max(np.abs(np.array(diag["p_part"]) + np.array(diag["p_grid"])))) / max(
-        diag["sum_abs_j"], 1e-300)
-    # the same loop replayed from a captured hipGraph (not the headline)
-    ctx.set_profile(0)
-    gflags = flags | dust.STEP_GRAPH
-    ctx.step(P, F, w.dt, dust.forces_for(w, t), K, gflags)   # capture
-    t += K * w.dt
-    torch.cuda.synchronize()
-    e0.record(stream)
-    ctx.step(P, F, w.dt, dust.forces_for(w, t), K, gflags)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    graph_value = N * K / (e0.elapsed_time(e1) * 1e-3)
-    t += K * w.dt
-    ctx.status()
-    # the gas predictor's drag source (Eq. f_D) on the same particles and gas,
-    # reported beside the step (not part of it): one launch per call
-    fr = dust.forces_for(w, t)
-    ctx.drag_source(P, F, w.dt, fr)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(K):
-        ctx.drag_source(P, F, w.dt, fr)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ds_s = e0.elapsed_time(e1) * 1e-3 / K
-    ds_bytes = (28.0 + 1.0 + 36.0 / ppc) * N       # state + species + gas read / deposit RMW
-    drag_source = {"kernel": "k_drag_source", "us_per_launch": round(ds_s * 1e6, 2),
-                   "algorithmic_bytes_per_launch": ds_bytes,
-                   "achieved": round(ds_bytes / ds_s / 1e9, 1), "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": round(ds_bytes / ds_s / 1e9 / HBM_PEAK_GBS, 4)}
-    # the dust density deposit on the same particles (beside the step)
-    rho_d = torch.zeros_like(F["rho"])
-    ctx.deposit_mass(P, rho_d)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(K):
-        ctx.deposit_mass(P, rho_d)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    md_s = e0.elapsed_time(e1) * 1e-3 / K
-    md_bytes = (16.0 + 1.0 + 8.0 / ppc) * N          # cell + offsets + species, density RMW
-    mass_density = {"kernel": "k_mass_density", "us_per_launch": round(md_s * 1e6, 2),
-                    "algorithmic_bytes_per_launch": md_bytes,
-                    "achieved": round(md_bytes / md_s / 1e9, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(md_bytes / md_s / 1e9 / HBM_PEAK_GBS, 4)}
-    del rho_d
-    # measured device-to-device copy bandwidth (read + write bytes), the
-    # practical ceiling the fused kernel's rate is also compared with
-    nel = 256 << 20                                   # 1 GiB of float32
-    src = torch.ones(nel, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2.0 * 4 * nel * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    if roof is not None:
-        roof["copy_gbs"] = round(copy_gbs, 1)
-        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
-    out = {
-        "metric": "particle-steps/s (gather+exp-midpoint push+deposit)",
-        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.arith, "data": "synthetic",
-        "config": {"workload": f"shearing_box {n}^3 standard shearing box, {N} particles "
-                               f"(8/cell, seeded sub-lattice), TSC, FP32 storage, {args.arith.upper()} push "
-                               f"arithmetic, dt=0.005, feedback on",
-                   "n_particles": N, "grid": [n, n, n], "tile": [tx, ty, tz], "slack": slack,
-                   "rebin_every": args.rebin_every, "autotuned": tuned,
-                   "fused": not args.unfused, "graph": False,
-                   "storage": "f32", "push_arith": args.arith,
-                   "deposit_accum": "f32 registers per cell, f64 LDS tile window, f32 HBM atomics"},
-        "roofline": roof,
-        "graph_value": graph_value,
-        "drag_source": drag_source,
-        "mass_density": mass_density,
-        "diag": {"momentum_residual": res, "max_cells_per_step": diag["max_cells_per_step"],
-                 "n_fallback": diag["n_fallback"], "flags": diag["flag_names"],
-                 "steps": diag["steps"]},
-    }
+    res, w = run_config(args.config, args, extra=False, K=K, W=W)
+    del w
+    copy_gbs = copy_bandwidth()
+    if res.get("roofline"):
+        res["roofline"]["copy_gbs"] = round(copy_gbs, 1)
+        res["roofline"]["frac_of_copy"] = round(res["roofline"]["achieved"] / copy_gbs, 4)
+    out = {"metric": METRIC, "value": res["value"], "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": K, "warmup": W, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": res["config"]["push_arith"], "data": "synthetic"}
+    out.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step")})
+    if args.config == 5 and not args.no_extra:
+        r2, w2 = run_config(2, args, extra=True, K=min(K, 20), W=W)
+        del w2
+        out["config2"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"],
+                          "workload": r2["config"]["workload"], "tile": r2["config"]["tile"],
+                          "rebin_every": r2["config"]["rebin_every"], "roofline": r2["roofline"],
+                          "parity": r2["parity"], "diag": r2["diag"]}
     if args.calib_copy_mb > 0:
         nel = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -368,8 +692,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "dust_fused.h"
@@ -491,23 +492,44 @@ enum StepMove {
   STEP_MOVE,       // stale bins, written to y slot for slot
 };
 
+// Whether a fused step runs the FP32 uniform-Cartesian tile kernel
+// (dust_cart3.hip): 3-D Cartesian boxes with uniform axes, FP32 storage and
+// arithmetic, forces none, constant or standard shearing box, fewer than 2^31
+// particles (32-bit slot numbers).
+bool use_c3(const Ctx* c, bool f32, const Forces& F, int64_t n) {
+  return f32 && c->geom == GEOM_CART && c->ndim == 3 && c->unif &&
+         (F.kind == FORCE_NONE || F.kind == FORCE_CONST || F.kind == FORCE_SHEARBOX) && n < (int64_t(1) << 31);
+}
+
 template <typename TS, typename A>
 dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const FView<TS>& fv,
                          const Forces& F, double dt, int flags, StepMove mv, hipStream_t st) {
   int nc = ctx_nc(c);
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
+  constexpr bool f32 = std::is_same<TS, float>::value && std::is_same<A, float>::value;
+  const bool c3 = use_c3(c, f32, F, x.n);
   // Rebinning: keys of the cells the particles kick in, a stable sort, and the
   // source index of every slot in the fused kernel's order, through which
   // the fused kernel reads x while writing y in binned order (the particles
   // without a cell are copied across).
   const uint32_t* src_index = nullptr;
   if (mv == STEP_REBIN) {
-    launch_halfstep_keys<TS, A>(x, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, dt, c->tdev,
-                                c->n_active, c->tile, c->bin.key[0], st);
+    if constexpr (f32) {
+      if (c3)
+        launch_c3_keys(x, c->boxes_d, c->nbox, dt, c->n_active, c->tile, c->bin.key[0], st);
+    }
+    if (!c3)
+      launch_halfstep_keys<TS, A>(x, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, dt, c->tdev,
+                                  c->n_active, c->tile, c->bin.key[0], st);
     c->bin_cur = launch_bin(x.cell, x.n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_TILE, c->tile,
                             c->bin, nullptr, c->bin_start, true, st);
     uint32_t* lm = c->bin.val[1 - c->bin_cur];   // free once the sort is done
-    launch_level_perm<TS>(c->plan, x, y, c->bin.val[c->bin_cur], c->bin_start, c->n_active, lm, st);
+    if (c3) {
+      launch_c3_level_perm(c->plan, c->bin.val[c->bin_cur], c->bin_start, lm, st);
+      launch_copy_tail<TS>(x, y, c->bin_start, c->n_active, st, c->bin.val[c->bin_cur]);
+    } else {
+      launch_level_perm<TS>(c->plan, x, y, c->bin.val[c->bin_cur], c->bin_start, c->n_active, lm, st);
+    }
     src_index = lm;
   } else if (mv == STEP_MOVE) {
     launch_copy_tail<TS>(x, y, c->bin_start, c->n_active, st);
@@ -519,10 +541,17 @@ dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const F
   const bool prof = c->prof_used < c->prof_max;
   hipEvent_t ev0 = prof ? c->prof_ev[2 * c->prof_used] : nullptr;
   hipEvent_t ev1 = prof ? c->prof_ev[2 * c->prof_used + 1] : nullptr;
-  launch_fused<TS, A>(c->plan, x, out, mv != STEP_IN_PLACE, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif,
-                      fv, F, c->species_d, c->drag_mode, dt, c->tdev, c->bin_start,
-                      (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr, src_index,
-                      ev0, ev1, st);
+  if constexpr (f32) {
+    if (c3)
+      launch_c3(c->plan, x, out, mv != STEP_IN_PLACE, c->boxes_d, c->nbox, fv, F, c->species_d, c->drag_mode, dt,
+                c->tdev, c->bin_start, (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr,
+                src_index, ev0, ev1, st);
+  }
+  if (!c3)
+    launch_fused<TS, A>(c->plan, x, out, mv != STEP_IN_PLACE, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif,
+                        fv, F, c->species_d, c->drag_mode, dt, c->tdev, c->bin_start,
+                        (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, c->diag, dg != nullptr, src_index,
+                        ev0, ev1, st);
   HIP_TRY(hipGetLastError());
   if (prof) ++c->prof_used;
   if (dg)
@@ -1052,7 +1081,8 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
     if ((s = ensure_bin(c, p->n)) || (s = ensure_bin_start(c)) || (s = ensure_shadow(c, p))) return s;
     if (!c->plan.ok) return fail(DUST_EUNSUPPORTED, "no fused plan for these boxes");
     if (fused_plan_reserve(c->plan, p->n) != DUST_OK) return fail(DUST_ENOMEM, "deferred-particle list");
-    if (fused_lds_bytes(c->plan, ctx_nc(c), c->prec == DUST_F64 ? 8 : 4) + FUSED_STATIC_LDS > 160 * 1024)
+    if (fused_lds_bytes(c->plan, ctx_nc(c), c->prec == DUST_F64 ? 8 : 4) + FUSED_STATIC_LDS > 160 * 1024 ||
+        c3_lds_bytes(c->plan) + FUSED_STATIC_LDS > 160 * 1024)
       return fail(DUST_EUNSUPPORTED, "fused tile window needs more than 160 KiB of LDS");
   }
   Forces F = forces_of(frc);
@@ -1138,7 +1168,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
 
 
 // Autotuner: times the fused step for every compiled tile shape and
-// rebinning intervals 1..4 on copies of the caller's particles and fields,
+// rebinning intervals 1, 2, 3, 4, 6, 8 on copies of the caller's particles and fields,
 // then keeps the fastest shape and interval in the context.
 dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust_fields_t* f,
                                 double dt, const dust_forces_t* frc, int32_t flags, int32_t steps,
@@ -1223,7 +1253,9 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
     drop_graph(c);
     if (fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack) != DUST_OK) continue;
     if (fused_lds_bytes(c->plan, ctx_nc(c), (int)rs) + FUSED_STATIC_LDS > 160 * 1024) continue;
-    for (int k = 1; k <= 4 && !s; ++k) {
+    static const int kIntervals[] = {1, 2, 3, 4, 6, 8};
+    for (int ki = 0; ki < 6 && !s; ++ki) {
+      const int k = kIntervals[ki];
       if ((s = restore())) break;
       const int32_t fl = flags | DUST_STEP_FUSED | DUST_STEP_REBIN_EVERY(k);
       if ((s = dust_step(c, &pc, &fc, dt, frc, 1, fl, st))) break;  // warm-up

@@ -30,6 +30,8 @@ struct FusedPlan {
   uint32_t* defer_count = nullptr;   // deferred particles of the current launch
   uint32_t* defer_list = nullptr;    // their (slot, source) pairs (capacity defer_cap pairs)
   size_t defer_cap = 0;
+  uint8_t* tile_map = nullptr;       // per tile, 256 tile-local cells in thread order (FP32
+                                     // Cartesian path: ranked by particle count at each rebinning)
 };
 
 // Capacity of the deferred-particle list for n particles.
@@ -73,10 +75,33 @@ void launch_level_perm(const FusedPlan& plan, const PView<TS>& src, const PView<
                        hipStream_t st);
 
 // The particles without a cell (slots from bin_start[nbins] on): dst[s] =
-// src[s] (distinct arrays).
+// src[perm[s]], or src[s] when perm is null (distinct arrays).
 template <typename TS>
 void launch_copy_tail(const PView<TS>& src, const PView<TS>& dst, const int64_t* bin_start, int64_t nbins,
-                      hipStream_t st);
+                      hipStream_t st, const uint32_t* perm = nullptr);
+
+// Adds the per-workgroup diagnostic partials of the last fused launch (tile
+// kernel and deferred kernel) to the diagnostics block, and resets the
+// deferred-particle count.
+void launch_reduce_fused(const FusedPlan& plan, DiagDev* dg, bool sums, hipStream_t st);
+
+// The fused step of uniform 3-D Cartesian boxes in FP32 storage and
+// arithmetic (dust_cart3.hip), with forces none, constant or standard
+// shearing box: the tile kernel (ev0 / ev1 around it), the deferred-particle
+// kernel and the reduction of their diagnostic partials.
+void launch_c3(const FusedPlan& plan, const PView<float>& p, const PView<float>& q, bool copy_attrs,
+               const Box* boxes_d, int nbox, const FView<float>& fl, const Forces& f, const Species* sp,
+               int drag_mode, double dt, const double* tdev, const int64_t* bin_start, const double* xg,
+               DiagDev* dg, bool sums, const uint32_t* src_index, hipEvent_t ev0, hipEvent_t ev1,
+               hipStream_t st);
+// Its rebinning: half-step tile keys with its own drift, and after the sort
+// the per-tile ranking of cells by count (plan.tile_map) with the source
+// index of every slot (lm).
+void launch_c3_keys(const PView<float>& p, const Box* boxes_d, int nbox, double dt, int64_t nbins,
+                    TileShape ts, uint32_t* key, hipStream_t st);
+void launch_c3_level_perm(const FusedPlan& plan, const uint32_t* perm, const int64_t* bin_start, uint32_t* lm,
+                          hipStream_t st);
+size_t c3_lds_bytes(const FusedPlan& plan);
 
 // dst = src, every particle array.
 template <typename TS>

@@ -72,6 +72,7 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
     return DUST_EDEVICE;
   if (hipMalloc((void**)&plan.part_d, sizeof(double) * PART_WORDS * (tiles.size() + DEFER_BLOCKS)) !=
           hipSuccess ||
+      hipMalloc((void**)&plan.tile_map, 256 * tiles.size()) != hipSuccess ||
       hipMalloc((void**)&plan.defer_count, 256) != hipSuccess)
     return DUST_ENOMEM;
   if (hipMemset(plan.defer_count, 0, 256) != hipSuccess) return DUST_EDEVICE;
@@ -84,6 +85,8 @@ void fused_plan_free(FusedPlan& plan) {
   if (plan.part_d) (void)hipFree(plan.part_d);
   if (plan.defer_count) (void)hipFree(plan.defer_count);
   if (plan.defer_list) (void)hipFree(plan.defer_list);
+  if (plan.tile_map) (void)hipFree(plan.tile_map);
+  plan.tile_map = nullptr;
   plan.tiles_d = nullptr;
   plan.part_d = nullptr;
   plan.defer_count = nullptr;
@@ -191,7 +194,12 @@ void launch_fused(const FusedPlan& plan, const PView<TS>& p, const PView<TS>& q,
   else if (geom == GEOM_CYL) DUST_G(GEOM_CYL, 3, false);
   else DUST_G(GEOM_SPH, 3, false);
 #undef DUST_G
-  hipLaunchKernelGGL(k_reduce_fused_partials, dim3(1), dim3(REDUCE_THREADS), 0, st, (const double*)part,
+  launch_reduce_fused(plan, dg, sums, st);
+}
+
+void launch_reduce_fused(const FusedPlan& plan, DiagDev* dg, bool sums, hipStream_t st) {
+  if (plan.ntiles == 0) return;
+  hipLaunchKernelGGL(k_reduce_fused_partials, dim3(1), dim3(REDUCE_THREADS), 0, st, (const double*)plan.part_d,
                      plan.ntiles + DEFER_BLOCKS, dg, (int)sums, plan.defer_count);
 }
 
@@ -236,7 +244,8 @@ __global__ void __launch_bounds__(256)
     else
       k = key_in(boxes[find_box(boxes, nbox, c)]);
   }
-  key[i] = k;
+  // a key beyond the bins would break the sort's bin starts
+  key[i] = k < nbins ? k : nbins;
 }
 
 template <typename TS, typename A>
@@ -334,11 +343,10 @@ void launch_level_perm(const FusedPlan& plan, const PView<TS>& src, const PView<
 
 template <typename TS>
 void launch_copy_tail(const PView<TS>& src, const PView<TS>& dst, const int64_t* bin_start, int64_t nbins,
-                      hipStream_t st) {
+                      hipStream_t st, const uint32_t* perm) {
   if (src.n == 0) return;
   unsigned g = (unsigned)std::min<int64_t>((src.n + 255) / 256, 512);
-  hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, src, dst, (const uint32_t*)nullptr,
-                     bin_start, nbins);
+  hipLaunchKernelGGL(k_copy_tail<TS>, dim3(g), dim3(256), 0, st, src, dst, perm, bin_start, nbins);
 }
 
 template <typename TS>
@@ -369,9 +377,9 @@ template void launch_level_perm<double>(const FusedPlan&, const PView<double>&, 
                                         const uint32_t*, const int64_t*, int64_t, uint32_t*,
                                         hipStream_t);
 template void launch_copy_tail<float>(const PView<float>&, const PView<float>&, const int64_t*, int64_t,
-                                      hipStream_t);
+                                      hipStream_t, const uint32_t*);
 template void launch_copy_tail<double>(const PView<double>&, const PView<double>&, const int64_t*,
-                                       int64_t, hipStream_t);
+                                       int64_t, hipStream_t, const uint32_t*);
 template void launch_copy_particles<float>(const PView<float>&, const PView<float>&, hipStream_t);
 template void launch_copy_particles<double>(const PView<double>&, const PView<double>&, hipStream_t);
 

@@ -19,7 +19,7 @@ Workloads (recipes in the design notes):
   cylindrical_disk   log-spaced R, Keplerian disk gas (Nelson et al. 2013
                      profile of the radial-drift test), Stokes numbers
   spherical_disk     the same disk in (r, theta, phi), stiff stopping times
-  batched_boxes      several periodic 3-D boxes, four dust species
+  batched_boxes      several periodic 3-D boxes (same cell width), four species
   rigid_disk         uniform dust density in a cylindrical grid, radii from
                      the inverse cumulative distribution (particle assignment)
 """
@@ -332,11 +332,16 @@ def spherical_disk(n=(256, 128, 512), ppc=4, rin=0.5, rout=5.0, dth=0.3,
 
 def batched_boxes(sizes=(32, 48, 64, 80, 96, 128, 160, 192), max_per_species=32,
                   species_tau=(0.01, 0.1, 1.0, 10.0), eps_species=0.25, dt=0.01,
-                  nsteps=100, dtype="f32", seed=4, shape="tsc") -> Workload:
-    """Independent periodic unit cubes of uneven sizes; in every cell each
+                  nsteps=100, dtype="f32", seed=4, shape="tsc", dx=1.0 / 64) -> Workload:
+    """Independent periodic cubes of uneven sizes n^3 with the same cell
+    width (1/64 by default, so a box spans n/64 per side); in every cell each
     species has U{1..max} particles at uniform random offsets, at rest; gas
-    rho = 1 + 1e-3 N(0,1), v ~ U(-0.01, 0.01).  Species masses are those of
-    eps_species per species at the mean count in a 64^3 box.
+    rho = 1 + 1e-3 N(0,1), v ~ U(-0.01, 0.01).  Species masses give a dust
+    to gas ratio of eps_species per species at the mean count: with one
+    species table for all boxes this holds in every box only because the
+    cells have the same volume (in unit cubes of n^3 cells the ratio would
+    grow as n^3, reaching 27 in a 192^3 box, where the explicit feedback of
+    the impulse is unstable).
 
     Every box draws from its own stream (spawned from the seed), so a box's
     inputs do not depend on the other boxes: a subset of boxes generated
@@ -366,7 +371,7 @@ def batched_boxes(sizes=(32, 48, 64, 80, 96, 128, 160, 192), max_per_species=32,
     for b, nb in enumerate(sizes):
         r = gens[b]
         n = (nb, nb, nb)
-        faces = [_uniform_faces(0.0, 1.0, nb) for _ in range(3)]
+        faces = [_uniform_faces(0.0, nb * dx, nb) for _ in range(3)]
         boxes.append(dict(geom="cart", ndim=3, n=n, bc_lo=("periodic",) * 3,
                           bc_hi=("periodic",) * 3, shape=(shape,) * 3, faces=faces))
         k = np.repeat(np.arange(ncells[b] * ns, dtype=np.int32), counts[b])
@@ -389,7 +394,7 @@ def batched_boxes(sizes=(32, 48, 64, 80, 96, 128, 160, 192), max_per_species=32,
         gas.append(dict(rho=rho.astype(dt_np), vel=vel))
     mom = np.zeros((N, 3), dtype=dt_np)
     mean_count = 0.5 * (1 + max_per_species)
-    mass = [eps_species / (64 ** 3) / mean_count for _ in range(ns)]
+    mass = [eps_species * dx ** 3 / mean_count for _ in range(ns)]
     return Workload("batched_boxes", dtype, boxes, dict(kind="none"), "species", cell, off,
                     mom, gas, dt, nsteps, species=species, species_tau=list(species_tau),
                     species_mass=mass)
