@@ -494,11 +494,14 @@ enum StepMove {
 
 // Whether a fused step runs the FP32 uniform-Cartesian tile kernel
 // (dust_cart3.hip): 3-D Cartesian boxes with uniform axes, FP32 storage and
-// arithmetic, forces none, constant or standard shearing box, fewer than 2^31
-// particles (32-bit slot numbers).
-bool use_c3(const Ctx* c, bool f32, const Forces& F, int64_t n) {
+// arithmetic, forces none, constant or standard shearing box, masses and
+// stopping times from the species table (no per-particle arrays), fewer
+// than 2^31 particles (32-bit slot numbers).
+template <typename TS>
+bool use_c3(const Ctx* c, bool f32, const Forces& F, const PView<TS>& x) {
   return f32 && c->geom == GEOM_CART && c->ndim == 3 && c->unif &&
-         (F.kind == FORCE_NONE || F.kind == FORCE_CONST || F.kind == FORCE_SHEARBOX) && n < (int64_t(1) << 31);
+         (F.kind == FORCE_NONE || F.kind == FORCE_CONST || F.kind == FORCE_SHEARBOX) &&
+         c->drag_mode == DUST_DRAG_SPECIES && !x.mass && !x.drag && x.n < (int64_t(1) << 31);
 }
 
 template <typename TS, typename A>
@@ -507,7 +510,7 @@ dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const F
   int nc = ctx_nc(c);
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
   constexpr bool f32 = std::is_same<TS, float>::value && std::is_same<A, float>::value;
-  const bool c3 = use_c3(c, f32, F, x.n);
+  const bool c3 = use_c3(c, f32, F, x);
   // Rebinning: keys of the cells the particles kick in, a stable sort, and the
   // source index of every slot in the fused kernel's order, through which
   // the fused kernel reads x while writing y in binned order (the particles

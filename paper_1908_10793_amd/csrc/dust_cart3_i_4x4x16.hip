@@ -1,0 +1,8 @@
+// Instantiation of the uniform-Cartesian FP32 tile kernel for 4x4x16 tiles.
+#include "dust_cart3_kern.h"
+
+namespace dust {
+
+DUST_C3_SHAPE_DECL(, 4, 4, 16)
+
+}  // namespace dust

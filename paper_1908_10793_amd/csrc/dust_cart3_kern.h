@@ -1,0 +1,692 @@
+// Fused tile step for uniform 3-D Cartesian boxes in FP32 storage and
+// arithmetic (gfx950): the path of the batched boxes and of the shearing box.
+// The kernel and its launchers; dust_cart3.hip holds the rebinning kernels
+// and the dispatcher, dust_cart3_i_*.hip one tile shape each.
+//
+// Same plan, binning and deferred-particle kernel as the general tile kernel
+// (dust_fused_kern.h); what differs is written for the short instruction path
+// this case allows:
+//  * the cells of a tile are assigned to threads in descending order of their
+//    particle count (ranked once per rebinning, k_c3_level_perm), so that a
+//    wave, which runs as many levels as its fullest cell, holds cells of
+//    similar counts;
+//  * the half drift is one FMA per axis with the half step over the cell
+//    width formed once per workgroup;
+//  * the gather is the plain weighted sum of the staged gas.  In the standard
+//    shearing box the window stages the gas velocity relative to the
+//    background shear, v_y + q Omega x_c (formed in FP64 at the cell centre;
+//    the x ghosts from the FP64 ghost layer), and the particle's v_y + q
+//    Omega x_p is formed from the cell-centre term split in two FP32 words:
+//    the weights reproduce linear fields exactly, so the slip keeps its
+//    accuracy where |v| is a thousand times the slip;
+//  * the particle diagnostic sums are FP32 per thread (a thread's cell),
+//    added in FP64 across the workgroup.
+// Deposits are summed in registers over the 27 cells around the thread's
+// cell (with weights shifted for a particle that moved to a neighbouring cell
+// since the rebinning; the stencil planes outside go to an FP64 LDS window
+// with atomics), then the window is added to the grid.
+#pragma once
+
+#include "dust_fused_kern.h"
+
+namespace dust {
+
+
+// Move by dxc cells along one axis of a uniform grid (offset renormalised into
+// [-1/2, 1/2)); returns the new cell index (not wrapped).
+__device__ __forceinline__ int c3_move(int i, float& off, float v, float hinv) {
+  float dn = fmaf(v, hinv, off);
+  if (dn >= 0.5f || dn < -0.5f) {
+    const float k = floorf(dn + 0.5f);
+    dn -= k;
+    i += (int)k;
+    if (dn >= 0.5f) {
+      dn -= 1.0f;
+      ++i;
+    } else if (dn < -0.5f) {
+      dn += 1.0f;
+      --i;
+    }
+  }
+  off = dn;
+  return i;
+}
+
+// Cell coordinates of a local cell id (FP64 reciprocal with one correction).
+__device__ __forceinline__ void c3_unravel(int l, int n0, int n1, double inv0, double inv1, int idx[3]) {
+  const int r = div_small(l, n0, inv0);
+  idx[0] = l - r * n0;
+  const int k = div_small(r, n1, inv1);
+  idx[1] = r - k * n1;
+  idx[2] = k;
+}
+
+// Uniform constants of the workgroup's box.
+struct C3Box {
+  int n[3];
+  float hinv[3];        // (dt/2) / cell width
+  float dtinv[3];       // dt / cell width (displacement diagnostic)
+  bool per[3];          // periodic axis
+  bool shear;           // shear-periodic x
+  bool tsc[3];
+  int cell_base, ncell;
+};
+
+__device__ __forceinline__ C3Box c3_box(const Box& B, float dt) {
+  C3Box c;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c.n[d] = B.ax[d].n;
+    c.hinv[d] = float(0.5 * double(dt) * B.ax[d].inv_d);
+    c.dtinv[d] = float(double(dt) * B.ax[d].inv_d);
+    c.per[d] = B.ax[d].bc_lo == BC_PERIODIC && B.ax[d].bc_hi == BC_PERIODIC;
+    c.tsc[d] = B.ax[d].shape == SHAPE_TSC;
+  }
+  c.shear = B.ax[0].bc_lo == BC_SHEAR;
+  c.cell_base = (int)B.cell_base;
+  c.ncell = (int)B.ncell;
+  return c;
+}
+
+// Weights of cells i-1, i, i+1 of one axis (b-spline overlaps, Eq. b0 / b1),
+// middle weight 1 - w0 - w2.
+__device__ __forceinline__ void c3_weights(bool tsc, float d, float w[3]) {
+  if (tsc) {
+    const float m = 0.5f - d, p = 0.5f + d;
+    w[0] = 0.5f * m * m;
+    w[2] = 0.5f * p * p;
+  } else {
+    w[0] = d < 0.0f ? -d : 0.0f;
+    w[2] = d > 0.0f ? d : 0.0f;
+  }
+  w[1] = 1.0f - w[0] - w[2];
+}
+
+// Wrap a cell index along a periodic axis: one box length (the normal case),
+// else by the remainder (a particle that moved further, whatever its speed,
+// still gets a cell of the box).
+__device__ __forceinline__ int c3_wrap(int i, int n) {
+  i = i < 0 ? i + n : (i >= n ? i - n : i);
+  if (i < 0 || i >= n) {
+    i %= n;
+    if (i < 0) i += n;
+  }
+  return i;
+}
+
+// The wave layout of a tile's particles: thread t owns the tile-local cell
+// lc (the cell of rank t by descending particle count, -1 if none); wave w's
+// particles follow those of waves 0..w-1 from the tile's first slot on,
+// level-major inside the wave.  Returns this thread's WaveLevels; ps: the
+// first sorted slot of its cell.
+__device__ __forceinline__ WaveLevels c3_layout(const TileDesc& td, int lc,
+                                                const int64_t* __restrict__ bin_start, int64_t& ps) {
+  __shared__ uint32_t wtot[FUSED_THREADS / 64];
+  const int t = threadIdx.x;
+  int cnt = 0;
+  ps = 0;
+  if (lc >= 0) {
+    ps = bin_start[td.key0 + lc];
+    cnt = (int)(bin_start[td.key0 + lc + 1] - ps);
+  }
+  const uint32_t tot = (uint32_t)wave_sum(cnt);
+  if ((t & 63) == 0) wtot[t >> 6] = tot;
+  __syncthreads();
+  uint32_t base = (uint32_t)bin_start[td.key0];
+  for (int w = 0; w < (t >> 6); ++w) base += wtot[w];
+  WaveLevels wl;
+  wl.cnt = cnt;
+  wl.nlev = wave_max(cnt);
+  wl.base = base;
+  return wl;
+}
+
+// Element i (a slot number) of a particle array, with 64-bit index arithmetic.
+template <typename T> __device__ __forceinline__ const T& at32(const T* base, uint32_t i) {
+  return base[(uint64_t)i];
+}
+template <typename T> __device__ __forceinline__ T& at32(T* base, uint32_t i) { return base[(uint64_t)i]; }
+
+// Stored state of a particle and its species (masses and stopping times
+// come from the species table on this path).
+struct C3Raw {
+  int32_t cell, species;
+  float off[3], mom[3];
+};
+
+__device__ __forceinline__ void c3_load(const PView<float>& p, uint32_t i, C3Raw& r) {
+  r.cell = at32(p.cell, i);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    r.off[d] = at32(p.off[d], i);
+    r.mom[d] = at32(p.mom[d], i);
+  }
+  r.species = p.species ? (int32_t)at32(p.species, i) : 0;
+}
+
+// The fused step.  SB: standard shearing-box forces (else none or a constant
+// acceleration).  REBIN: the step after a rebinning (particles read through
+// src_index, attributes copied, input checks); else COPY: stale bins written
+// to another buffer slot for slot (attributes copied), or in place.  Masses
+// and stopping times come from the species table.
+template <int TX, int TY, int TZ, bool SB, bool REBIN, bool COPY>
+__global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+    k_c3(const TileDesc* __restrict__ tiles, const uint8_t* __restrict__ tmap, PView<float> p,
+         PView<float> dst, int copy_attrs, const Box* __restrict__ boxes, FView<float> fl, Forces f,
+         const Species* __restrict__ sp, int drag_mode, float dt, const double* __restrict__ tdev,
+         const int64_t* __restrict__ bin_start, const double* __restrict__ xg, DiagDev* dg,
+         double* __restrict__ part, int sums, uint32_t* __restrict__ defer_list,
+         uint32_t* __restrict__ defer_count, const uint32_t* __restrict__ src_index) {
+  constexpr int H = FUSED_HALO;
+  constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RZ = TZ + 2 * H;
+  constexpr int RC = RX * RY * RZ;
+  extern __shared__ double smem[];
+  double* dep = smem;                                                  // 4 * RC (FP64)
+  float4* gas = reinterpret_cast<float4*>(smem + 4 * RC);              // RC
+  __shared__ float sp_c[DUST_MAX_SPECIES], sp_psi[DUST_MAX_SPECIES], sp_m[DUST_MAX_SPECIES];
+  __shared__ float2 xres[RX];   // SB: q Omega x_c of the window's x columns, as hi + lo
+  const TileDesc td = tiles[blockIdx.x];
+  const Box& B = boxes[td.box];
+  const C3Box cb = c3_box(B, dt);
+  const int ox = td.i0 - H, oy = td.j0 - H, oz = td.k0 - H;
+  if (threadIdx.x < sp->n) {
+    float c, psi;
+    propagator<float>(dt * float(sp->inv_tau[threadIdx.x]), c, psi);
+    sp_c[threadIdx.x] = c;
+    sp_psi[threadIdx.x] = psi;
+    sp_m[threadIdx.x] = float(sp->mass[threadIdx.x]);
+  }
+  const double qO = SB ? f.q * f.Omega : 0.0;
+  const double x_lo = B.ax[0].lo, dx0 = B.ax[0].d;
+  if (SB && threadIdx.x < RX) {
+    const double v = qO * (x_lo + (double(ox + (int)threadIdx.x) + 0.5) * dx0);
+    const float hi = float(v);
+    xres[threadIdx.x] = make_float2(hi, float(v - double(hi)));
+  }
+  const double t0 = *tdev;
+  const int n0 = cb.n[0], n1 = cb.n[1], n2 = cb.n[2];
+  // stage the gas window (periodic images beyond the box), clear the deposit window
+  for (int r = threadIdx.x; r < RC; r += FUSED_THREADS) {
+    const int a = r % RX, bq = (r / RX) % RY, cq = r / (RX * RY);
+    int i = ox + a, j = oy + bq, k = oz + cq;
+    if (cb.per[0]) i = wrap_index(i, n0);
+    if (cb.per[1]) j = wrap_index(j, n1);
+    if (cb.per[2]) k = wrap_index(k, n2);
+    const bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && k >= -1 && k <= n2;
+    float gv[3] = {0.0f, 0.0f, 0.0f};
+    if (in) {
+      if (SB) {
+        // velocity relative to the background shear, formed in FP64
+        const double xc = x_lo + (double(i) + 0.5) * dx0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double v = gas_comp(B, fl, xg, m, i, j, k);
+          gv[m] = float(m == 1 ? v + qO * xc : v);
+        }
+      } else {
+        const int64_t id = stored_index(B, i, j, k);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) gv[m] = fl.vel[m][id];
+      }
+    }
+    gas[r] = make_float4(gv[0], gv[1], gv[2], 0.0f);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dep[m * RC + r] = 0.0;
+  }
+  __syncthreads();
+
+  // this thread's cell (ranked by particle count) and the wave's slot layout
+  const int lc = (int)threadIdx.x < td.ex * td.ey * td.ez ? (int)tmap[(size_t)blockIdx.x * 256 + threadIdx.x]
+                                                         : -1;
+  int64_t ps;
+  const WaveLevels wl = c3_layout(td, lc, bin_start, ps);
+  const bool own = lc >= 0;
+  const int lx = own ? lc % td.ex : 0, ly = own ? (lc / td.ex) % td.ey : 0,
+            lz = own ? lc / (td.ex * td.ey) : 0;
+  const int mycell[3] = {td.i0 + lx, td.j0 + ly, td.k0 + lz};
+  const int mybase = (lx + H) + RX * ((ly + H) + RY * (lz + H));
+  const int32_t mycid = cb.cell_base + mycell[0] + n0 * (mycell[1] + n1 * mycell[2]);
+
+  float acc[27][4];
+#pragma unroll
+  for (int o = 0; o < 27; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[o][k] = 0.0f;
+  // FP32 diagnostic sums of this thread's particles (impulse, energy, |impulse|,
+  // largest displacement), added in FP64 across the workgroup at the end
+  float s_j0 = 0.0f, s_j1 = 0.0f, s_j2 = 0.0f, s_e = 0.0f, s_abs = 0.0f, s_cells = 0.0f;
+  const float Om = float(f.Omega);
+  const float qOdx = float(qO * dx0);
+  const float g0c = float(f.g[0]), g1c = float(f.g[1]), g2c = float(f.g[2]);
+  const bool cg = !SB && f.kind == FORCE_CONST;
+  const float gz_c = SB && f.vertical_gravity ? -Om * Om : 0.0f;
+  const float z_lo = float(B.ax[2].lo), dz = float(B.ax[2].d);
+
+  uint32_t lvl = wl.base;
+  uint32_t slot = level_slot(wl, 0, lvl);
+  uint32_t slot_b = level_slot(wl, 1, lvl);
+  C3Raw nxt;
+  uint32_t nxt_si = slot, si_b = slot_b;
+  if (wl.cnt > 0) {
+    if constexpr (REBIN) nxt_si = at32(src_index, slot);
+    c3_load(p, nxt_si, nxt);
+  }
+  if (REBIN && wl.cnt > 1) si_b = at32(src_index, slot_b);
+  for (int j = 0; j < wl.nlev; ++j) {
+    const bool has = wl.cnt > j;
+    const uint32_t i = slot;
+    const uint32_t si = nxt_si;
+    const C3Raw cur = nxt;
+    // the id (copied on rebinning steps) is loaded before the next particle,
+    // so that waiting for it does not wait for the prefetch
+    const int32_t pid = COPY && has && p.id ? at32(p.id, si) : 0;
+    slot = slot_b;
+    nxt_si = si_b;
+    slot_b = level_slot(wl, j + 2, lvl);
+    if (wl.cnt > j + 1) c3_load(p, nxt_si, nxt);
+    if constexpr (REBIN) {
+      si_b = slot_b;
+      if (wl.cnt > j + 2) si_b = at32(src_index, slot_b);
+    } else {
+      si_b = slot_b;
+    }
+
+    int idx[3] = {mycell[0], mycell[1], mycell[2]};
+    const int32_t cid = has ? cur.cell : -1;
+    bool live = cid >= cb.cell_base && cid < cb.cell_base + cb.ncell;
+    bool deferred = false;
+    if constexpr (REBIN) {
+      // inputs from the caller (every call starts with a rebinning): cell ids
+      // and offsets are checked here; later steps write them in range
+      if (cid >= 0 && !live) flag(dg, DUST_FLAG_BAD_CELL);
+      bool bad = false;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) bad |= live && !(cur.off[d] >= -0.5f && cur.off[d] < 0.5f);
+      if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+    }
+    if constexpr (COPY) {
+      if (has && !live) {
+        // a particle without a cell is carried unchanged
+        at32(dst.cell, i) = cid;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          at32(dst.off[d], i) = cur.off[d];
+          at32(dst.mom[d], i) = cur.mom[d];
+        }
+      }
+    }
+    float off[3] = {cur.off[0], cur.off[1], cur.off[2]}, mom[3] = {cur.mom[0], cur.mom[1], cur.mom[2]};
+    if (live) {
+      if (cid != mycid) c3_unravel(cid - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx);
+      // half drift to x^{n+1/2} (periodic images, open faces remove, a
+      // shear-periodic x face defers)
+      bool removed = false;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        idx[d] = c3_move(idx[d], off[d], mom[d], cb.hinv[d]);
+        if (idx[d] < 0 || idx[d] >= cb.n[d]) {
+          if (cb.per[d]) idx[d] = c3_wrap(idx[d], cb.n[d]);
+          else if (d == 0 && cb.shear) deferred = true;
+          else removed = true;
+        }
+      }
+      if (removed) {
+        // left through an open face: no cell from now on (it keeps the
+        // offsets and momenta it had when it left)
+        at32(dst.cell, i) = -1;
+        if (COPY) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            at32(dst.off[d], i) = off[d];
+            at32(dst.mom[d], i) = mom[d];
+          }
+        }
+        if (dg) {
+          atomicAdd(&dg->n_removed, 1ull);
+          atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
+        }
+        live = false;
+      }
+    }
+    int la = lx + H, lb = ly + H, lcz = lz + H;
+    if (live && !deferred) {
+      la = win_coord(idx[0], ox, n0, RX, cb.per[0]);
+      lb = win_coord(idx[1], oy, n1, RY, cb.per[1]);
+      lcz = win_coord(idx[2], oz, n2, RZ, cb.per[2]);
+      deferred = !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 && lcz >= 1 && lcz <= RZ - 2);
+    }
+    deferred = deferred && live;
+    {
+      const uint64_t dm = __ballot(deferred);
+      if (dm) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)dm) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(defer_count, (uint32_t)__popcll(dm));
+        base = __shfl(base, leader, 64);
+        if (deferred) {
+          defer_list[2 * (base + lanes_below(dm))] = i;
+          defer_list[2 * (base + lanes_below(dm)) + 1] = si;
+        }
+      }
+    }
+    if (deferred) live = false;
+    if (!live) {
+      // a dummy at the centre of this thread's cell, with zero deposits (a
+      // divergent skip would keep two copies of the register sums)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) off[d] = 0.0f;
+      la = lx + H;
+      lb = ly + H;
+      lcz = lz + H;
+    }
+    // weights at x^{n+1/2}
+    float w[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c3_weights(cb.tsc[d], off[d], w[d]);
+    const int sx = la - (lx + H), sy = lb - (ly + H), sz = lcz - (lz + H);
+    const bool near = sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1 && sz >= -1 && sz <= 1;
+    // gather (Eq. Delta_vp), one z-plane of the stencil per iteration of a
+    // loop that is not unrolled (straight-line code would let the compiler
+    // issue all 27 LDS reads first, 81 registers); the nine reads of a plane
+    // are issued together
+    float v[3] = {0.0f, 0.0f, 0.0f};
+    {
+      int r0 = la + RX * (lb - 1 + RY * (lcz - 1));
+#pragma unroll 1
+      for (int c = 0; c < 3; ++c, r0 += RX * RY) {
+        const float wz = c == 0 ? w[2][0] : c == 1 ? w[2][1] : w[2][2];
+        float4 g[9];
+#pragma unroll
+        for (int q9 = 0; q9 < 9; ++q9) g[q9] = gas[r0 + RX * (q9 / 3) + (q9 % 3) - 1];
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          const float4 g0 = g[3 * bb], g1 = g[3 * bb + 1], g2 = g[3 * bb + 2];
+          const float ux = w[0][0] * g0.x + w[0][1] * g1.x + w[0][2] * g2.x;
+          const float uy = w[0][0] * g0.y + w[0][1] * g1.y + w[0][2] * g2.y;
+          const float uz = w[0][0] * g0.z + w[0][1] * g1.z + w[0][2] * g2.z;
+          const float wbc = w[1][bb] * wz;
+          v[0] += wbc * ux;
+          v[1] += wbc * uy;
+          v[2] += wbc * uz;
+        }
+      }
+    }
+    // kick (Eq. exp_midpoint; App. B.1 Eq. standard_SB_exp_midpoint)
+    int spc = live ? cur.species : 0;
+    if (spc >= sp->n) {
+      flag(dg, DUST_FLAG_BAD_CELL);
+      spc = 0;
+    }
+    const float m = sp_m[spc], c = sp_c[spc], psi = sp_psi[spc];
+    const float h1 = dt + dt * psi;
+    const float dtp = dt * psi;
+    float dp[3], jj[3];
+    if constexpr (SB) {
+      // y relative to the background shear: v_y + q Omega x at x^{n+1/2}
+      const float2 xr = xres[la];
+      const float uy = (mom[1] + xr.x) + fmaf(qOdx, off[0], xr.y);
+      const float s0 = v[0] - mom[0], s1 = v[1] - uy, s2 = v[2] - mom[2];
+      const float gz = gz_c * (z_lo + (float(idx[2]) + 0.5f + off[2]) * dz);
+      const float an0 = 2.0f * Om * uy, an1 = -2.0f * Om * mom[0];
+      const float r0 = c * s0 + h1 * an0, r1 = c * s1 + h1 * an1;
+      const float W = Om * h1, den = 1.0f / (1.0f + W * W);
+      dp[0] = (r0 + W * r1) * den;
+      dp[1] = (r1 - W * r0) * den;
+      dp[2] = c * s2 + h1 * gz;
+      const float a0 = an0 + Om * dp[1], a1 = an1 - Om * dp[0];
+      jj[0] = c * s0 + dtp * a0;
+      jj[1] = c * s1 + dtp * a1;
+      jj[2] = c * s2 + dtp * gz;
+    } else {
+      const float gk[3] = {cg ? g0c : 0.0f, cg ? g1c : 0.0f, cg ? g2c : 0.0f};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float sk = v[k] - mom[k];
+        dp[k] = c * sk + h1 * gk[k];
+        jj[k] = c * sk + dtp * gk[k];
+      }
+    }
+    float qd[4];
+    float e = 0.0f, cells = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float vbar = mom[k] + 0.5f * dp[k];
+      e += vbar * jj[k];
+      qd[k] = live ? -m * jj[k] : 0.0f;   // deposits carry the minus sign of Eq. dust_feedback_final
+      cells = fmaxf(cells, fabsf(vbar) * cb.dtinv[k]);
+      mom[k] += dp[k];
+    }
+    qd[3] = live ? -m * e : 0.0f;
+    s_cells = live ? fmaxf(s_cells, cells) : s_cells;
+    s_j0 -= qd[0];
+    s_j1 -= qd[1];
+    s_j2 -= qd[2];
+    s_e -= qd[3];
+    s_abs += fabsf(qd[0]) + fabsf(qd[1]) + fabsf(qd[2]);
+    // deposit (same weights and cells as the gather): register sums over the
+    // 27 cells around the thread's cell, the rest through the FP64 window
+    {
+      const int base = la + RX * (lb + RY * lcz);
+      auto lds_add = [&](int a, int bb, int cc, float wt) {
+        const int r0 = base + a + RX * (bb + RY * cc);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicAdd(&dep[k * RC + r0], double(wt * qd[k]));
+      };
+      if (live && !near) {
+#pragma unroll
+        for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+          for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) lds_add(a, bb, cc, w[0][a + 1] * w[1][bb + 1] * w[2][cc + 1]);
+      }
+      if (live && near && (sx | sy | sz)) {
+        // stencil planes outside the thread's 27 cells: row sy, column sx
+        // (rows other than sy), layer sz (the cells in neither)
+        if (sy != 0) {
+          const float wy = sy > 0 ? w[1][2] : w[1][0];
+#pragma unroll
+          for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) lds_add(a, sy, cc, w[0][a + 1] * wy * w[2][cc + 1]);
+        }
+        if (sx != 0) {
+          const float wx = sx > 0 ? w[0][2] : w[0][0];
+#pragma unroll
+          for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+            for (int bb = -1; bb <= 1; ++bb)
+              if (sy == 0 || bb != sy) lds_add(sx, bb, cc, wx * w[1][bb + 1] * w[2][cc + 1]);
+        }
+        if (sz != 0) {
+          const float wz = sz > 0 ? w[2][2] : w[2][0];
+#pragma unroll
+          for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a)
+              if ((sy == 0 || bb != sy) && (sx == 0 || a != sx))
+                lds_add(a, bb, sz, w[0][a + 1] * w[1][bb + 1] * wz);
+        }
+      }
+    }
+    {
+      // weights shifted to this thread's cell (zero where the stencil leaves
+      // its 27 cells)
+      const int sd[3] = {sx, sy, sz};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float w0 = w[d][0], w1 = w[d][1], w2 = w[d][2];
+        w[d][0] = sd[d] == 0 ? w0 : sd[d] < 0 ? w1 : 0.0f;
+        w[d][1] = sd[d] == 0 ? w1 : sd[d] < 0 ? w2 : w0;
+        w[d][2] = sd[d] == 0 ? w2 : sd[d] < 0 ? 0.0f : w1;
+      }
+      float qf[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qf[k] = live && near ? qd[k] : 0.0f;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          const float wbc = w[1][bb] * w[2][cc];
+          float qb[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) qb[k] = wbc * qf[k];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int oo = a + 3 * (bb + 3 * cc);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[oo][k] = fmaf(w[0][a], qb[k], acc[oo][k]);
+          }
+        }
+    }
+    // second half drift to x^{n+1}
+    if (live) {
+      bool alive = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) idx[d] = c3_move(idx[d], off[d], mom[d], cb.hinv[d]);
+      if (cb.shear && (idx[0] < 0 || idx[0] >= n0)) shear_image<float, false>(B, f, t0 + double(dt), idx, off, mom);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (idx[d] < 0 || idx[d] >= cb.n[d]) {
+          if (cb.per[d] || (d == 0 && cb.shear)) idx[d] = c3_wrap(idx[d], cb.n[d]);
+          else alive = false;
+        }
+      at32(dst.cell, i) = alive ? cb.cell_base + idx[0] + n0 * (idx[1] + n1 * idx[2]) : -1;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        at32(dst.off[d], i) = off[d];
+        at32(dst.mom[d], i) = mom[d];
+      }
+      if (!alive && dg) {
+        atomicAdd(&dg->n_removed, 1ull);
+        atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
+      }
+    }
+    if constexpr (COPY) {
+      if (has && !deferred) {
+        if (p.species) at32(dst.species, i) = (uint8_t)cur.species;
+        if (p.id) at32(dst.id, i) = pid;
+      }
+    }
+  }
+
+  // register sums of my cell's stencil -> deposit window
+  if (own) {
+#pragma unroll
+    for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+      for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+          const int oo = (a + 1) + 3 * ((bb + 1) + 3 * (cc + 1));
+          const int r0 = mybase + a + RX * (bb + RY * cc);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (acc[oo][k] != 0.0f) atomicAdd(&dep[k * RC + r0], double(acc[oo][k]));
+        }
+  }
+  __syncthreads();
+  // the deposit window to the grid (periodic images to their cells; uniform
+  // cell volume)
+  const double iv = inv_volume(B, 0, 0, 0);
+  for (int r = threadIdx.x; r < RC; r += FUSED_THREADS) {
+    const int a = r % RX, bq = (r / RX) % RY, cq = r / (RX * RY);
+    int i = ox + a, j = oy + bq, k = oz + cq;
+    if (cb.per[0]) i = wrap_index(i, n0);
+    if (cb.per[1]) j = wrap_index(j, n1);
+    if (cb.per[2]) k = wrap_index(k, n2);
+    const bool in = i >= -1 && i <= n0 && j >= -1 && j <= n1 && k >= -1 && k <= n2;
+    if (!in) continue;
+    const int64_t id = stored_index(B, i, j, k);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double x = dep[m * RC + r];
+      if (x != 0.0) unsafeAtomicAdd(&fl.dep[m][id], float(x * iv));
+    }
+  }
+  // diagnostics: the workgroup's FP64 sums to its own slot of `part`
+  if (dg) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double s[6] = {double(s_j0), double(s_j1), double(s_j2), double(s_e), double(s_abs), double(s_cells)};
+    if (sums) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s[k] = wave_sum(s[k]);
+      s[5] = wave_max(s[5]);
+    }
+    __shared__ double red[FUSED_THREADS / 64][PART_WORDS];
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) red[wave][k] = s[k];
+      red[wave][6] = 0.0;
+      red[wave][7] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < PART_WORDS) {
+      const int k = threadIdx.x;
+      double vv = red[0][k];
+      for (int w2 = 1; w2 < FUSED_THREADS / 64; ++w2) vv = k == 5 ? fmax(vv, red[w2][k]) : vv + red[w2][k];
+      part[(size_t)blockIdx.x * PART_WORDS + k] = sums || k >= 6 ? vv : 0.0;
+    }
+  }
+}
+
+template <int TX, int TY, int TZ, bool SB, bool REBIN, bool COPY>
+void launch_c3_t(const FusedPlan& plan, const PView<float>& p, const PView<float>& q, const Box* boxes_d,
+                 const FView<float>& fl, const Forces& f, const Species* sp, int drag_mode, double dt,
+                 const double* tdev, const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
+                 const uint32_t* src_index, hipStream_t st) {
+  const size_t lds = c3_lds_bytes(plan);
+  auto kern = k_c3<TX, TY, TZ, SB, REBIN, COPY>;
+  if (lds > 64 * 1024) {
+    static bool raised = false;
+    if (!raised) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL(kern, dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, plan.tiles_d, plan.tile_map, p, q,
+                     COPY ? 1 : 0, boxes_d, fl, f, sp, drag_mode, float(dt), tdev, bin_start, xg, dg,
+                     plan.part_d, (int)sums, plan.defer_list, plan.defer_count, src_index);
+}
+
+// The tile kernel of one tile shape: forces (standard shearing box or not)
+// and the kind of step (after a rebinning through src_index; stale bins
+// written across with copy_attrs; stale bins in place).
+template <int TX, int TY, int TZ>
+void launch_c3_shape(const FusedPlan& plan, const PView<float>& p, const PView<float>& q, bool copy_attrs,
+                     const Box* boxes_d, const FView<float>& fl, const Forces& f, const Species* sp,
+                     int drag_mode, double dt, const double* tdev, const int64_t* bin_start, const double* xg,
+                     DiagDev* dg, bool sums, const uint32_t* src_index, hipStream_t st) {
+#define DUST_C3M(SBV, RB, CP)                                                                               \
+  launch_c3_t<TX, TY, TZ, SBV, RB, CP>(plan, p, q, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start, xg,  \
+                                       dg, sums, src_index, st)
+  const bool sb = f.kind == FORCE_SHEARBOX;
+  if (src_index) {
+    if (sb) DUST_C3M(true, true, true);
+    else DUST_C3M(false, true, true);
+  } else if (copy_attrs) {
+    if (sb) DUST_C3M(true, false, true);
+    else DUST_C3M(false, false, true);
+  } else {
+    if (sb) DUST_C3M(true, false, false);
+    else DUST_C3M(false, false, false);
+  }
+#undef DUST_C3M
+}
+
+#define DUST_C3_SHAPE_DECL(PREFIX, TX, TY, TZ)                                                              \
+  PREFIX template void launch_c3_shape<TX, TY, TZ>(                                                         \
+      const FusedPlan&, const PView<float>&, const PView<float>&, bool, const Box*, const FView<float>&,     \
+      const Forces&, const Species*, int, double, const double*, const int64_t*, const double*, DiagDev*,   \
+      bool, const uint32_t*, hipStream_t);
+#define DUST_C3_SHAPES(PREFIX)                                                                              \
+  DUST_C3_SHAPE_DECL(PREFIX, 8, 8, 4)                                                                       \
+  DUST_C3_SHAPE_DECL(PREFIX, 16, 4, 4)                                                                      \
+  DUST_C3_SHAPE_DECL(PREFIX, 4, 16, 4)                                                                      \
+  DUST_C3_SHAPE_DECL(PREFIX, 4, 4, 16)                                                                      \
+  DUST_C3_SHAPE_DECL(PREFIX, 8, 4, 8)                                                                       \
+  DUST_C3_SHAPE_DECL(PREFIX, 4, 8, 8)
+
+}  // namespace dust
