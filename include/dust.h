@@ -265,6 +265,22 @@ const char *dust_last_error(void);
 dust_status_t dust_bin(void *ctx, dust_particles_t *p, int32_t key_mode, int32_t *perm_out,
                        int64_t *bin_start_out, int apply_permutation, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dust_bin
+ * with the same arguments and results (bit for bit), whose sort workspace
+ * (keys, values, digit histograms, scan sums, permutation staging) lies in a
+ * fixed device array of the library instead of the context's workspace.
+ * Calls no hipMalloc, hipFree or other allocating routine.  At most
+ * DUST_BIN_NOALLOC_MAX particles (else DUST_ESHAPE, nothing launched).  The
+ * array (25 MiB) exists once per GPU until the process ends; its address is
+ * taken when the first context on that GPU is created.  All calls on one GPU
+ * share it and it keeps the last call's contents: calls that overlap on one
+ * GPU (other streams, threads or contexts) race, and the caller must order
+ * them. */
+#define DUST_BIN_NOALLOC_MAX (1 << 20)
+dust_status_t dust_bin_noalloc(void *ctx, dust_particles_t *p, int32_t key_mode, int32_t *perm_out,
+                               int64_t *bin_start_out, int apply_permutation, void *stream);
+
 /* Fill the ghosts of periodic and shear-periodic axes of rho and vel at time
  * t (shear offset q Omega L_x t, linear in y between the two nearest cells;
  * v_y of a shear image shifted by -/+ q Omega L_x).  Open-axis ghosts are

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -412,12 +413,11 @@ dust_status_t ensure_bin_start(Ctx* c) {
   return DUST_OK;
 }
 
-// Apply perm (sorted slot -> input index, in bin.val[0]) to every particle array.
-dust_status_t apply_perm(Ctx* c, dust_particles_t* p, hipStream_t st) {
+// Apply perm (sorted slot -> input index) to every particle array, staging
+// each through tmp (8 bytes per particle).
+dust_status_t apply_perm(Ctx* c, dust_particles_t* p, const uint32_t* perm, void* tmp, hipStream_t st) {
   int64_t n = p->n;
   int rs = (int)real_size(c);
-  const uint32_t* perm = c->bin.val[c->bin_cur];
-  void* tmp = c->bin.gather_tmp;
   auto one = [&](void* a, int bytes) -> dust_status_t {
     if (!a) return DUST_OK;
     launch_permute(a, tmp, perm, n, bytes, st);
@@ -435,6 +435,63 @@ dust_status_t apply_perm(Ctx* c, dust_particles_t* p, hipStream_t st) {
   if ((s = one(p->species, 1))) return s;
   if ((s = one(p->id, 4))) return s;
   return DUST_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free sort workspace
+
+// Fixed device workspace of dust_bin_noalloc: two key and two value arrays,
+// the digit histograms, the scan's block sums and the staging array of the
+// permutation, for up to DUST_BIN_NOALLOC_MAX particles (about 24.3 MiB of
+// the 25 MiB).  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code uses the address taken with hipGetSymbolAddress on
+// that device (g_scratch_ptr), never the array's name.
+constexpr size_t kScratchBytes = (size_t)25 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Takes the address of the current device's copy of the array, once per
+// device (called by dust_ctx_create with `device` current).
+dust_status_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(DUST_EUNSUPPORTED, "device %d: at most %d devices", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DUST_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(DUST_EDEVICE, "address of the sort scratch array on device %d: %s", device, hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return DUST_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+// The sort workspace for n particles carved from a scratch array at base;
+// false if it would not fit.
+bool scratch_work(void* base, int64_t n, BinWork& w) {
+  const int64_t nn = std::max<int64_t>(n, 1);
+  const size_t hist = (size_t)256 * bin_blocks(nn);
+  const size_t scan = bin_scan_tmp_words((int64_t)hist);
+  auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bytes = 4 * rup((size_t)nn * 4) + rup(hist * 4) + rup(scan * 4) + rup((size_t)nn * 8);
+  if (bytes > kScratchBytes) return false;
+  char* q = (char*)base;
+  auto take = [&](size_t b) { char* r = q; q += rup(b); return r; };
+  w.key[0] = (uint32_t*)take((size_t)nn * 4);
+  w.key[1] = (uint32_t*)take((size_t)nn * 4);
+  w.val[0] = (uint32_t*)take((size_t)nn * 4);
+  w.val[1] = (uint32_t*)take((size_t)nn * 4);
+  w.hist = (uint32_t*)take(hist * 4);
+  w.scan_tmp = (uint32_t*)take(scan * 4);
+  w.gather_tmp = take((size_t)nn * 8);
+  w.cap_n = (size_t)nn;
+  return true;
 }
 
 // ------------------------------------------------------------------ typed drivers
@@ -638,6 +695,10 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(DUST_EINVAL, "device %d of %d", device, ndev);
   HIP_TRY(hipSetDevice(device));
+  {
+    const dust_status_t s = scratch_setup(device);
+    if (s) return s;
+  }
   Ctx* c = new Ctx();
   c->device = device;
   c->prec = prec;
@@ -861,7 +922,37 @@ dust_status_t dust_bin(void* ctx, dust_particles_t* p, int32_t key_mode, int32_t
   c->last_stream = st;
   c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, key_mode, c->tile,
                           c->bin, perm_out, bin_start_out, false, st);
-  if (apply_permutation && p->n > 0) return apply_perm(c, p, st);
+  if (apply_permutation && p->n > 0) return apply_perm(c, p, c->bin.val[c->bin_cur], c->bin.gather_tmp, st);
+  HIP_TRY(hipGetLastError());
+  return DUST_OK;
+}
+
+dust_status_t dust_bin_noalloc(void* ctx, dust_particles_t* p, int32_t key_mode, int32_t* perm_out,
+                               int64_t* bin_start_out, int apply_permutation, void* stream) {
+  g_err.clear();
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  Ctx* c = (Ctx*)ctx;
+  if (key_mode != DUST_BIN_CELL && key_mode != DUST_BIN_TILE) return fail(DUST_EINVAL, "unknown key mode");
+  if (!p) return fail(DUST_EINVAL, "particles is NULL");
+  if (p->n < 0 || p->n > DUST_BIN_NOALLOC_MAX)
+    return fail(DUST_ESHAPE, "dust_bin_noalloc: %lld particles, at most %d", (long long)p->n,
+                DUST_BIN_NOALLOC_MAX);
+  if (p->n > 0 && !p->cell) return fail(DUST_EINVAL, "particles.cell is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  void* base = scratch_of(c->device);
+  if (!base) return fail(DUST_EDEVICE, "no scratch array address for device %d", c->device);
+  BinWork w;
+  if (!scratch_work(base, p->n, w)) return fail(DUST_ESHAPE, "sort workspace exceeds the scratch array");
+  c->last_stream = st;
+  // every workspace word the sort reads is written before in the same call
+  // (keys, histograms, scans), so nothing is cleared
+  const int cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, key_mode, c->tile, w,
+                             perm_out, bin_start_out, false, st);
+  if (apply_permutation && p->n > 0) {
+    dust_status_t s = apply_perm(c, p, w.val[cur], w.gather_tmp, st);
+    if (s) return s;
+  }
   HIP_TRY(hipGetLastError());
   return DUST_OK;
 }

@@ -26,6 +26,7 @@ FORCE = {"none": 0, "shearbox": 1, "pointmass": 2, "const": 3, "shearbox_fargo":
 DRAG = {"tau": 0, "stokes": 1, "species": 2, "epstein": 3}
 PHASE_DRIFT1, PHASE_KICK, PHASE_DRIFT2 = 1, 2, 4
 BIN_CELL, BIN_TILE = 0, 1
+BIN_NOALLOC_MAX = 1 << 20   # particles of one dust_bin_noalloc call
 STEP_APPLY_FEEDBACK, STEP_FUSED, STEP_DIAG, STEP_GRAPH, STEP_NO_FILL = 1, 2, 4, 8, 16
 FLAG_NAMES = {1: "nonfinite", 2: "offset_range", 4: "cfl", 8: "left_open", 16: "tile_overflow",
               32: "bad_cell"}
@@ -75,7 +76,7 @@ class dust_diag_t(ctypes.Structure):
 
 
 EXPORTS = ["dust_ctx_create", "dust_ctx_destroy", "dust_ctx_set_arith", "dust_ctx_set_tile",
-           "dust_ctx_grid_size", "dust_ctx_status", "dust_last_error", "dust_bin",
+           "dust_ctx_grid_size", "dust_ctx_status", "dust_last_error", "dust_bin", "dust_bin_noalloc",
            "dust_fill_ghosts", "dust_gather", "dust_push_expmid", "dust_deposit",
            "dust_fold_ghosts", "dust_apply_feedback", "dust_step", "dust_ctx_set_profile",
            "dust_ctx_profile", "dust_ctx_autotune", "dust_drag_source",
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     L.dust_ctx_profile.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), i32,
                                    ctypes.POINTER(ctypes.c_int32)]
     L.dust_bin.argtypes = [_vp, ctypes.POINTER(dust_particles_t), i32, _vp, _vp, ctypes.c_int, _vp]
+    L.dust_bin_noalloc.argtypes = L.dust_bin.argtypes
     L.dust_fill_ghosts.argtypes = [_vp, ctypes.POINTER(dust_fields_t),
                                    ctypes.POINTER(dust_forces_t), ctypes.c_double, _vp]
     L.dust_fold_ghosts.argtypes = L.dust_fill_ghosts.argtypes
@@ -316,6 +318,17 @@ class Context:
                                        _ptr(perm, torch.int32, "perm"),
                                        _ptr(bin_start, torch.int64, "bin_start"), int(apply),
                                        _stream(stream)))
+
+    def bin_noalloc(self, P, key_mode="cell", perm=None, bin_start=None, apply=False, stream=None):
+        """bin() through the allocation-free entry point (at most
+        BIN_NOALLOC_MAX particles)."""
+        import torch
+        pt = self.particles_t(P)
+        _check(load_library().dust_bin_noalloc(self.handle, ctypes.byref(pt),
+                                               BIN_TILE if key_mode == "tile" else BIN_CELL,
+                                               _ptr(perm, torch.int32, "perm"),
+                                               _ptr(bin_start, torch.int64, "bin_start"), int(apply),
+                                               _stream(stream)))
 
     def fill_ghosts(self, F, forces: dust_forces_t, t: float, stream=None):
         f = self.fields_t(F)
