@@ -186,6 +186,21 @@ def _counter_per_dispatch(run_dir: str, counter: str):
     return out
 
 
+def _last_copy(run_dir: str, counter: str, is_copy):
+    """The counter's value for the last copy dispatch of a run."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(_rocpd(run_dir))
+    per = collections.defaultdict(float)
+    names = {}
+    for di, name, val in con.execute(
+            "select dispatch_id, kernel_name, value from counters_collection where counter_name = ?",
+            (counter,)):
+        per[di] += val
+        names[di] = _short(name)
+    return per[max(di for di in per if is_copy(names[di]))]
+
+
 def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
                        n_particles: int, copy_mb: int):
     """HBM bytes per launch of the fused kernel: FETCH_SIZE and WRITE_SIZE (KiB
@@ -197,9 +212,9 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str,
 
     def is_copy(k):
         return "copy" in k.lower() or "elementwise" in k.lower()
-    # the calibration copy is the largest copy dispatch of the run
-    cf = max(max(v) for k, v in fetch.items() if is_copy(k))
-    cw = max(max(v) for k, v in write.items() if is_copy(k))
+    # the calibration copy is the run's last copy dispatch (made at its end)
+    cf = _last_copy(fetch_dir, "FETCH_SIZE", is_copy)
+    cw = _last_copy(write_dir, "WRITE_SIZE", is_copy)
     f_fetch, f_write = copy_kib / cf, copy_kib / cw
 
     def warm_mean(v):

@@ -8,28 +8,54 @@ namespace dust {
 
 DUST_C3_SHAPES(extern)
 
-// Rebinning: rank the cells of every tile by particle count (descending,
-// ties by tile-local index) into tmap, and write lm[slot] = perm[ps + j], the
-// source of every slot of the level-major layout that c3_layout describes.
+// Rebinning: order the cells of every tile for the tile kernel's threads
+// into tmap, and write lm[slot] = perm[ps + j], the source of every slot of
+// the level-major layout that c3_layout describes.
+//
+// A wave runs as many levels as its fullest cell, so its cells should have
+// similar counts; and its 64 lanes read the gas window at their cells'
+// stencils, where lanes whose float4 fall in the same LDS bank group
+// (window index mod 16) serialise.  The cells are therefore ranked by count
+// (descending, ties by tile-local index) within each bank group, and ordered
+// by (rank, group): a wave of a full tile takes 4 ranks of every group, and
+// every 16 consecutive lanes hold one cell of each group.  (rx, ry: x and y
+// extents of the tile kernel's gas window.)
 __global__ void __launch_bounds__(256)
     k_c3_level_perm(const TileDesc* __restrict__ tiles, const uint32_t* __restrict__ perm,
                     const int64_t* __restrict__ bin_start, uint8_t* __restrict__ tmap,
-                    uint32_t* __restrict__ lm) {
+                    uint32_t* __restrict__ lm, int rx, int ry) {
   __shared__ int cnt_s[256];
+  __shared__ int grp_s[256];
+  __shared__ int gsize[16];
   __shared__ uint8_t map_s[256];
   const TileDesc td = tiles[blockIdx.x];
   const int nct = td.ex * td.ey * td.ez;
   const int t = threadIdx.x;
   const int c = t < nct ? (int)(bin_start[td.key0 + t + 1] - bin_start[td.key0 + t]) : -1;
+  int g = -1;
+  if (t < nct) {
+    const int lx = t % td.ex, ly = (t / td.ex) % td.ey, lz = t / (td.ex * td.ey);
+    g = ((lx + FUSED_HALO) + rx * ((ly + FUSED_HALO) + ry * (lz + FUSED_HALO))) & 15;
+  }
   cnt_s[t] = c;
+  grp_s[t] = g;
+  if (t < 16) gsize[t] = 0;
+  __syncthreads();
+  if (t < nct) atomicAdd(&gsize[g], 1);
   __syncthreads();
   if (t < nct) {
     int rank = 0;
     for (int u = 0; u < nct; ++u) {
       const int cu = cnt_s[u];
-      rank += (cu > c || (cu == c && u < t)) ? 1 : 0;
+      rank += (grp_s[u] == g && (cu > c || (cu == c && u < t))) ? 1 : 0;
     }
-    map_s[rank] = (uint8_t)t;
+    // position in (rank, group) order
+    int pos = 0;
+    for (int k = 0; k < 16; ++k) {
+      const int sz = gsize[k];
+      pos += min(sz, rank) + ((k < g && sz > rank) ? 1 : 0);
+    }
+    map_s[pos] = (uint8_t)t;
   }
   __syncthreads();
   const int lc = t < nct ? (int)map_s[t] : -1;
@@ -121,7 +147,7 @@ void launch_c3_level_perm(const FusedPlan& plan, const uint32_t* perm, const int
                           uint32_t* lm, hipStream_t st) {
   if (plan.ntiles > 0)
     hipLaunchKernelGGL(k_c3_level_perm, dim3(plan.ntiles), dim3(256), 0, st, plan.tiles_d, perm, bin_start,
-                       plan.tile_map, lm);
+                       plan.tile_map, lm, plan.tile.t[0] + 2 * FUSED_HALO, plan.tile.t[1] + 2 * FUSED_HALO);
 }
 
 }  // namespace dust

@@ -150,18 +150,26 @@ template <typename T> __device__ __forceinline__ T& at32(T* base, uint32_t i) { 
 // Stored state of a particle and its species (masses and stopping times
 // come from the species table on this path).
 struct C3Raw {
-  int32_t cell, species;
+  int32_t cell, species, id;
   float off[3], mom[3];
 };
 
+// ID: also the id (when the attributes are copied to another buffer).
+template <bool ID>
 __device__ __forceinline__ void c3_load(const PView<float>& p, uint32_t i, C3Raw& r) {
   r.cell = at32(p.cell, i);
+  // the id and species arrays may be absent: the loads then read an element
+  // of the cell array, and the value is ignored where it is used (a load on
+  // a select rather than on a branch, and no wait right after it)
+  if constexpr (ID) r.id = at32(p.id ? p.id : p.cell, p.id ? i : 0u);
+  else r.id = 0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     r.off[d] = at32(p.off[d], i);
     r.mom[d] = at32(p.mom[d], i);
   }
-  r.species = p.species ? (int32_t)at32(p.species, i) : 0;
+  r.species = (int32_t)at32(p.species ? p.species : reinterpret_cast<const uint8_t*>(p.cell),
+                            p.species ? i : 0u);
 }
 
 // The fused step.  SB: standard shearing-box forces (else none or a constant
@@ -262,33 +270,71 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   const float gz_c = SB && f.vertical_gravity ? -Om * Om : 0.0f;
   const float z_lo = float(B.ax[2].lo), dz = float(B.ax[2].d);
 
+  // The results of a particle are stored at the top of the next iteration,
+  // before the next prefetch: on this target one counter tracks both loads
+  // and stores, so waiting for prefetched data also waits for every store
+  // issued before that wait; stores issued at the end of an iteration would
+  // put a full write round trip on every iteration, while stores issued at
+  // its top have had the whole iteration to complete by the next wait.
+  bool pend = false, pend_attr = false;
+  uint32_t pend_i = 0;
+  int32_t pend_cell = 0, pend_sp = 0, pend_id = 0;
+  float pend_off[3] = {0.0f, 0.0f, 0.0f}, pend_mom[3] = {0.0f, 0.0f, 0.0f};
+  auto store_pending = [&]() {
+    if (pend) {
+      at32(dst.cell, pend_i) = pend_cell;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        at32(dst.off[d], pend_i) = pend_off[d];
+        at32(dst.mom[d], pend_i) = pend_mom[d];
+      }
+    }
+    if constexpr (COPY) {
+      if (pend_attr) {
+        if (p.species) at32(dst.species, pend_i) = (uint8_t)pend_sp;
+        if (p.id) at32(dst.id, pend_i) = pend_id;
+      }
+    }
+    pend = false;
+    pend_attr = false;
+  };
+
   uint32_t lvl = wl.base;
   uint32_t slot = level_slot(wl, 0, lvl);
   uint32_t slot_b = level_slot(wl, 1, lvl);
+  // a lane without a particle at a level loads the wave's first particle (a
+  // slot of the wave whenever the wave has particles): the loads of a level
+  // are then issued in every lane, with no old value to keep across them
+  auto valid = [&](int j, uint32_t sl) { return wl.cnt > j ? sl : wl.base; };
   C3Raw nxt;
-  uint32_t nxt_si = slot, si_b = slot_b;
-  if (wl.cnt > 0) {
-    if constexpr (REBIN) nxt_si = at32(src_index, slot);
-    c3_load(p, nxt_si, nxt);
+  uint32_t nxt_si = valid(0, slot), si_b = valid(1, slot_b);
+  if (wl.nlev > 0) {
+    if constexpr (REBIN) {
+      nxt_si = at32(src_index, nxt_si);
+      si_b = at32(src_index, si_b);
+    }
+    c3_load<COPY>(p, nxt_si, nxt);
+    // wait for the first particle here (once per thread): otherwise the wait
+    // analysis at the loop head, which merges this entry with the back edge,
+    // keeps these loads pending there and waits, behind every store of the
+    // previous iteration, before the registers are reused
+    asm volatile("" ::"v"(nxt.cell), "v"(nxt.species), "v"(nxt.id), "v"(nxt.off[0]), "v"(nxt.off[1]),
+                 "v"(nxt.off[2]), "v"(nxt.mom[0]), "v"(nxt.mom[1]), "v"(nxt.mom[2]), "v"(si_b));
   }
-  if (REBIN && wl.cnt > 1) si_b = at32(src_index, slot_b);
-  for (int j = 0; j < wl.nlev; ++j) {
+  const int nlev = __builtin_amdgcn_readfirstlane(wl.nlev);   // the same in every lane
+  for (int j = 0; j < nlev; ++j) {
     const bool has = wl.cnt > j;
     const uint32_t i = slot;
     const uint32_t si = nxt_si;
     const C3Raw cur = nxt;
-    // the id (copied on rebinning steps) is loaded before the next particle,
-    // so that waiting for it does not wait for the prefetch
-    const int32_t pid = COPY && has && p.id ? at32(p.id, si) : 0;
+    store_pending();
     slot = slot_b;
     nxt_si = si_b;
     slot_b = level_slot(wl, j + 2, lvl);
-    if (wl.cnt > j + 1) c3_load(p, nxt_si, nxt);
+    if (j + 1 < nlev) c3_load<COPY>(p, nxt_si, nxt);
+    si_b = valid(j + 2, slot_b);
     if constexpr (REBIN) {
-      si_b = slot_b;
-      if (wl.cnt > j + 2) si_b = at32(src_index, slot_b);
-    } else {
-      si_b = slot_b;
+      if (j + 2 < nlev) si_b = at32(src_index, si_b);
     }
 
     int idx[3] = {mycell[0], mycell[1], mycell[2]};
@@ -413,7 +459,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       }
     }
     // kick (Eq. exp_midpoint; App. B.1 Eq. standard_SB_exp_midpoint)
-    int spc = live ? cur.species : 0;
+    int spc = live && p.species ? cur.species : 0;
     if (spc >= sp->n) {
       flag(dg, DUST_FLAG_BAD_CELL);
       spc = 0;
@@ -552,24 +598,28 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
           if (cb.per[d] || (d == 0 && cb.shear)) idx[d] = c3_wrap(idx[d], cb.n[d]);
           else alive = false;
         }
-      at32(dst.cell, i) = alive ? cb.cell_base + idx[0] + n0 * (idx[1] + n1 * idx[2]) : -1;
+      pend = true;
+      pend_cell = alive ? cb.cell_base + idx[0] + n0 * (idx[1] + n1 * idx[2]) : -1;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        at32(dst.off[d], i) = off[d];
-        at32(dst.mom[d], i) = mom[d];
+        pend_off[d] = off[d];
+        pend_mom[d] = mom[d];
       }
       if (!alive && dg) {
         atomicAdd(&dg->n_removed, 1ull);
         atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
       }
     }
+    pend_i = i;
     if constexpr (COPY) {
       if (has && !deferred) {
-        if (p.species) at32(dst.species, i) = (uint8_t)cur.species;
-        if (p.id) at32(dst.id, i) = pid;
+        pend_attr = true;
+        pend_sp = cur.species;
+        pend_id = cur.id;
       }
     }
   }
+  store_pending();
 
   // register sums of my cell's stencil -> deposit window
   if (own) {
