@@ -567,22 +567,25 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
         w[d][1] = sd[d] == 0 ? w1 : sd[d] < 0 ? w2 : w0;
         w[d][2] = sd[d] == 0 ? w2 : sd[d] < 0 ? 0.0f : w1;
       }
-      float qf[4];
+      // the x weight times the deposit (12 products), then one FMA per cell
+      // and channel with the y-z weight
+      float qf[4], wq[3][4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) qf[k] = live && near ? qd[k] : 0.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wq[a][k] = w[0][a] * qf[k];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb) {
           const float wbc = w[1][bb] * w[2][cc];
-          float qb[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) qb[k] = wbc * qf[k];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const int oo = a + 3 * (bb + 3 * cc);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc[oo][k] = fmaf(w[0][a], qb[k], acc[oo][k]);
+            for (int k = 0; k < 4; ++k) acc[oo][k] = fmaf(wbc, wq[a][k], acc[oo][k]);
           }
         }
     }
