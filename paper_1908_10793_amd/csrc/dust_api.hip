@@ -198,6 +198,17 @@ dust_status_t build_box(Ctx* c, const dust_box_t& in, int ib, int64_t cell_base,
     if (st) return st;
     st = upload_table(c, iv, &ax.ivol);
     if (st) return st;
+    ax.trig = nullptr;
+    if (ax.kind == AX_THETA) {
+      std::vector<double> tg(2 * (n + 2));
+      for (int k = -1; k <= n; ++k) {
+        const double th = 0.5 * (ff[k + 1] + ff[k + 2]);
+        tg[2 * (k + 1)] = std::sin(th);
+        tg[2 * (k + 1) + 1] = std::cos(th);
+      }
+      st = upload_table(c, tg, &ax.trig);
+      if (st) return st;
+    }
     ncell *= n;
   }
   if (B.ax[0].bc_lo == DUST_BC_SHEAR) {

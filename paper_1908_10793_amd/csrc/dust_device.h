@@ -417,6 +417,77 @@ __device__ __forceinline__ void where(const Box& b, const int idx[3], const A of
   }
 }
 
+// Slip form of the gather in curvilinear boxes.  The slip of a canonical
+// component m >= 1 (an angular momentum, l = sc u with u the physical
+// velocity) is sc * sum_i W_i (v_i - u), and its relative accuracy is that
+// of u and sc.  In FP32 a particle close to co-rotation has a slip a
+// thousand times below u, where one FP32 word for u or sc (6e-8 relative)
+// would leave 6e-5 in the slip; so in FP32 both are carried as unevaluated
+// pairs hi + lo: sc from its FP64 cell-centre value (split in two words)
+// plus the offset term, and u = l / sc with its remainder formed by an FMA.
+// up: the hi part of u, which the gather subtracts from every v_i (those
+// differences are exact for close values); ulo, shi, slo: what
+// slip_canonical needs.  In FP64, and for Cartesian or radial components,
+// u = p / sc with ulo = slo = 0.
+template <typename A> struct SlipScale {
+  A up[3], ulo[3], shi[3], slo[3];
+};
+
+template <typename A, int GEOM, int NDIM, bool U>
+__device__ __forceinline__ void slip_scale(const Box& b, const int idx[3], const A off[3], const A mom[3],
+                                           const Where<A>& wh, SlipScale<A>& q) {
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    q.up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
+    q.ulo[m] = A(0);
+    q.shi[m] = wh.sc[m];
+    q.slo[m] = A(0);
+  }
+  if constexpr (GEOM != GEOM_CART && sizeof(A) == 4) {
+    // radius: FP64 cell centre split in two words, plus the offset term
+    const double rc = cell_centre<double, U>(b.ax[0], idx[0]);
+    const float rh = float(rc);
+    const float rl = float(rc - double(rh)) + off[0] * cell_width<float, U>(b.ax[0], idx[0]);
+    q.shi[1] = rh;
+    q.slo[1] = rl;
+    if constexpr (GEOM == GEOM_SPH) {
+      // sin(theta_c + d) = S + (S (cos d - 1) + C sin d), S and C from the
+      // FP64 table of cell centres, d = offset * width below a cell width
+      const double* tg = b.ax[1].trig + 2 * (idx[1] + 1);
+      const double S = tg[0], C = tg[1];
+      const float d = off[1] * cell_width<float, U>(b.ax[1], idx[1]);
+      const float d2 = d * d;
+      const float sd = d * (1.0f - d2 * (1.0f / 6.0f));
+      const float cm1 = -0.5f * d2 * (1.0f - d2 * (1.0f / 12.0f));
+      const float sh = float(S);
+      const float sl = float(S - double(sh)) + (sh * cm1 + float(C) * sd);
+      // (rh + rl)(sh + sl): the product of the high words and its exact
+      // rounding error, plus the other three products (the low words are
+      // up to a few percent of the high ones: none is negligible)
+      const float p = rh * sh;
+      q.shi[2] = p;
+      q.slo[2] = fmaf(rh, sh, -p) + (rh * sl + rl * (sh + sl));
+    }
+#pragma unroll
+    for (int m = 1; m < 3; ++m) {
+      if (GEOM == GEOM_CYL && m == 2) continue;   // v_z: Cartesian
+      const float S = q.shi[m] + q.slo[m];
+      const float u = mom[m] / S;
+      const float e = fmaf(-u, q.shi[m], mom[m]) - u * q.slo[m];   // mom - u (hi + lo)
+      q.up[m] = u;
+      q.ulo[m] = e / S;
+    }
+  }
+}
+
+// Canonical slip from the gathered sum_i W_i (v_i - up) of component m.
+template <typename A, int GEOM>
+__device__ __forceinline__ A slip_canonical(const SlipScale<A>& q, int m, A v) {
+  if (GEOM == GEOM_CART || m == 0) return v;
+  const A s = v - q.ulo[m];
+  return fma(s, q.shi[m], s * q.slo[m]);
+}
+
 // Result of one kick: momentum increments, drag impulse per unit mass
 // J/m = c s + dt psi a (s = p_g - p, the slip; a = the non-drag part of G as
 // evaluated in the kick), and the energy e/m = v_bar . (J/m) (physical).

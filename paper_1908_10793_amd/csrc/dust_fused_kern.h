@@ -138,17 +138,18 @@ __device__ __forceinline__ void load_raw(const PView<TS>& p, int64_t i, Raw<TS>&
 
 // Register budget: the FP32 kernel needs about 250 VGPRs (108 of them the
 // register sums); the compiler keeps the standard-form shapes but one under
-// 256 (2 waves/SIMD) by itself, and 4x4x16 and the orbital-advection
-// kernels with an explicit target (an explicit target where it is not
-// needed costs time: about 25 us of 900).
-template <typename A, typename TS, int TX, int TY, bool FG>
+// 256 (2 waves/SIMD) by itself, and 4x4x16, the orbital-advection and the
+// curvilinear kernels (whose slip form carries two-word scale factors) with
+// an explicit target (an explicit target where it is not needed costs time:
+// about 25 us of 900).
+template <typename A, typename TS, int GEOM, int TX, int TY, bool FG>
 constexpr int fused_waves_target() {
-  return sizeof(A) == 4 && sizeof(TS) == 4 && (FG || TX * TY <= 16) ? 2 : 1;
+  return sizeof(A) == 4 && sizeof(TS) == 4 && (FG || TX * TY <= 16 || GEOM != GEOM_CART) ? 2 : 1;
 }
 
 template <typename TS, typename A, int GEOM, int NDIM, bool U, int TX, int TY, int TZ, bool FG>
 __global__ void __launch_bounds__(FUSED_THREADS)
-    __attribute__((amdgpu_waves_per_eu(fused_waves_target<A, TS, TX, TY, FG>())))
+    __attribute__((amdgpu_waves_per_eu(fused_waves_target<A, TS, GEOM, TX, TY, FG>())))
     k_fused(const TileDesc* __restrict__ tiles, PView<TS> p, PView<TS> dst, int copy_attrs,
             const Box* __restrict__ boxes, FView<TS> fl, Forces f, const Species* __restrict__ sp,
             int drag_mode, A dt, const double* __restrict__ tdev,
@@ -364,9 +365,9 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // shearing box's background shear).
     Where<A> wh;
     where<A, GEOM, NDIM, U>(B, idx, off, wh);
-    A up[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
+    SlipScale<A> ss;
+    slip_scale<A, GEOM, NDIM, U>(B, idx, off, mom, wh, ss);
+    const A* up = ss.up;
     A v[3] = {A(0), A(0), A(0)};
     // (always true here; kept as a branch, which bounds how far the compiler
     // hoists the window reads and so the register use)
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // kick
     A sl[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
+    for (int m = 0; m < 3; ++m) sl[m] = m < nc ? slip_canonical<A, GEOM>(ss, m, v[m]) : A(0);
     int spc = live ? cur.species : 0;
     if (spc >= sp->n) {
       flag(dg, DUST_FLAG_BAD_CELL);
@@ -657,9 +658,9 @@ __global__ void __launch_bounds__(256)
       stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
       Where<A> wh;
       where<A, GEOM, NDIM, U>(B, idx, off, wh);
-      A up[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) up[m] = GEOM == GEOM_CART || m == 0 ? mom[m] : mom[m] / wh.sc[m];
+      SlipScale<A> ss;
+      slip_scale<A, GEOM, NDIM, U>(B, idx, off, mom, wh, ss);
+      const A* up = ss.up;
       A v[3] = {A(0), A(0), A(0)};
       // The stencil's field values are loaded unconditionally, so that the
       // loads issue together; x ghosts of a shear-periodic box then take the
@@ -692,7 +693,7 @@ __global__ void __launch_bounds__(256)
         }
       A sl[3];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) sl[m] = m < nc ? (GEOM == GEOM_CART || m == 0 ? v[m] : v[m] * wh.sc[m]) : A(0);
+      for (int m = 0; m < 3; ++m) sl[m] = m < nc ? slip_canonical<A, GEOM>(ss, m, v[m]) : A(0);
       int spc = p.species ? p.species[si] : 0;
       if (spc >= sp->n) spc = 0;
       const A m = p.mass ? A(p.mass[si]) : A(sp->mass[spc]);

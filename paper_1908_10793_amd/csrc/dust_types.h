@@ -27,6 +27,8 @@ struct Axis {
   double inv_n;                 // 1/n (index arithmetic)
   const double *faces;          // device: face k at faces[k+1], k = -1 .. n+1
   const double *ivol;           // device: inverse volume factor of cell k at ivol[k+1]
+  const double *trig;           // device, polar axis only: sin, cos of the centre of cell k
+                                // at trig[2(k+1)], trig[2(k+1)+1]; else null
 };
 
 struct Box {
