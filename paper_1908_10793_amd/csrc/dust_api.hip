@@ -82,6 +82,12 @@ struct Ctx {
   TileShape tile{{8, 8, 4}};
   int slack = 0;
   int rebin_default = 1;          // rebinning interval when the step flags give none
+  // the binned layout that the last fused FP32 uniform-Cartesian run left in
+  // the caller's arrays (bin_start and the plan's tile_map describe it);
+  // dust_drag_source and dust_deposit_mass use it for those arrays
+  bool lay_valid = false;
+  int64_t lay_n = 0;
+  const void* lay_cell = nullptr;
   FusedPlan plan{};
   // fused-kernel timing
   std::vector<hipEvent_t> prof_ev;  // 2 per launch
@@ -572,6 +578,12 @@ bool use_c3(const Ctx* c, bool f32, const Forces& F, const PView<TS>& x) {
          c->drag_mode == DUST_DRAG_SPECIES && !x.mass && !x.drag && x.n < (int64_t(1) << 31);
 }
 
+// Whether the particles are the arrays the last fused FP32 uniform-Cartesian
+// run left in their binned layout (same count and cell array).
+bool on_layout(const Ctx* c, const PView<float>& p) {
+  return c->lay_valid && p.n == c->lay_n && (const void*)p.cell == c->lay_cell;
+}
+
 template <typename TS, typename A>
 dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const FView<TS>& fv,
                          const Forces& F, double dt, int flags, StepMove mv, hipStream_t st) {
@@ -670,6 +682,10 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
     launch_advance_time(c->tdev, dt, (flags & DUST_STEP_DIAG) ? c->diag : nullptr, st);
   }
   if (in_shadow) launch_copy_particles<TS>(sh, pv, st);
+  constexpr bool f32 = std::is_same<TS, float>::value && std::is_same<A, float>::value;
+  c->lay_valid = use_c3(c, f32, F, pv);
+  c->lay_n = pv.n;
+  c->lay_cell = pv.cell;
   return DUST_OK;
 }
 
@@ -837,6 +853,7 @@ dust_status_t dust_ctx_set_tile(void* ctx, int32_t tx, int32_t ty, int32_t tz, i
   }
   if (slack < 0 || slack > 4) return fail(DUST_EINVAL, "slack %d out of 0..4", slack);
   drop_graph(c);
+  c->lay_valid = false;
   dust_status_t s = fused_plan_init(c->plan, c->boxes.data(), c->nbox, want, slack);
   if (s) {
     // keep the previous shape (and a valid plan)
@@ -931,6 +948,7 @@ dust_status_t dust_bin(void* ctx, dust_particles_t* p, int32_t key_mode, int32_t
   dust_status_t s = ensure_bin(c, p->n);
   if (s) return s;
   c->last_stream = st;
+  if (apply_permutation) c->lay_valid = false;
   c->bin_cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, key_mode, c->tile,
                           c->bin, perm_out, bin_start_out, false, st);
   if (apply_permutation && p->n > 0) return apply_perm(c, p, c->bin.val[c->bin_cur], c->bin.gather_tmp, st);
@@ -956,6 +974,7 @@ dust_status_t dust_bin_noalloc(void* ctx, dust_particles_t* p, int32_t key_mode,
   BinWork w;
   if (!scratch_work(base, p->n, w)) return fail(DUST_ESHAPE, "sort workspace exceeds the scratch array");
   c->last_stream = st;
+  if (apply_permutation) c->lay_valid = false;
   // every workspace word the sort reads is written before in the same call
   // (keys, histograms, scans), so nothing is cleared
   const int cur = launch_bin(p->cell, p->n, c->boxes_d, c->nbox, c->n_active, key_mode, c->tile, w,
@@ -1115,6 +1134,17 @@ dust_status_t dust_drag_source(void* ctx, const dust_particles_t* p, dust_fields
   return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
     using TS = decltype(ts);
     using A = decltype(ta);
+    if constexpr (std::is_same<TS, float>::value && std::is_same<A, float>::value) {
+      const PView<float> pv = pview<float>(p);
+      if (on_layout(c, pv) && use_c3(c, true, F, pv)) {
+        const FView<float> fv = fview<float>(f);
+        float* const out[3] = {fv.dep[0], fv.dep[1], fv.dep[2]};
+        launch_c3_aux(c->plan, pv, c->boxes_d, c->nbox, fv, out, false, F, c->species_d, dt, c->bin_start,
+                      c->n_active, c->diag, st);
+        HIP_TRY(hipGetLastError());
+        return DUST_OK;
+      }
+    }
     launch_drag_source<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), F,
                               c->species_d, c->drag_mode, dt, c->diag, st);
     HIP_TRY(hipGetLastError());
@@ -1137,6 +1167,17 @@ dust_status_t dust_deposit_mass(void* ctx, const dust_particles_t* p, void* rho_
   return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
     using TS = decltype(ts);
     using A = decltype(ta);
+    if constexpr (std::is_same<TS, float>::value && std::is_same<A, float>::value) {
+      const PView<float> pv = pview<float>(p);
+      const Forces none{};
+      if (on_layout(c, pv) && use_c3(c, true, none, pv)) {
+        float* const out[3] = {(float*)rho_d, nullptr, nullptr};
+        launch_c3_aux(c->plan, pv, c->boxes_d, c->nbox, FView<float>{}, out, true, none, c->species_d, 1.0,
+                      c->bin_start, c->n_active, c->diag, st);
+        HIP_TRY(hipGetLastError());
+        return DUST_OK;
+      }
+    }
     launch_mass_density<TS, A>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, (TS*)rho_d,
                                c->species_d, c->diag, st);
     HIP_TRY(hipGetLastError());
@@ -1390,6 +1431,7 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
   c->prof_max = prof_max;
   c->tile = s ? keep_tile : best_tile;
   drop_graph(c);
+  c->lay_valid = false;
   dust_status_t s2 = fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack);
   HIP_TRY(hipMemcpy(c->diag, &saved, sizeof(DiagDev), hipMemcpyHostToDevice));
   if (s) return s;

@@ -7,6 +7,7 @@
 namespace dust {
 
 DUST_C3_SHAPES(extern)
+DUST_C3_AUX_SHAPES(extern)
 
 // Rebinning: order the cells of every tile for the tile kernel's threads
 // into tmap, and write lm[slot] = perm[ps + j], the source of every slot of
@@ -134,6 +135,23 @@ void launch_c3(const FusedPlan& plan, const PView<float>& p, const PView<float>&
                      (const uint32_t*)plan.defer_list, (const uint32_t*)plan.defer_count, plan.part_d,
                      plan.ntiles, (int)sums, dg);
   launch_reduce_fused(plan, dg, sums, st);
+}
+
+void launch_c3_aux(const FusedPlan& plan, const PView<float>& p, const Box* boxes_d, int nbox,
+                   const FView<float>& fl, float* const out[3], bool mass, const Forces& f, const Species* sp,
+                   double dt, const int64_t* bin_start, int64_t nbins, DiagDev* dg, hipStream_t st) {
+  if (plan.ntiles == 0 && p.n == 0) return;
+#define DUST_C3A(TX, TY, TZ) \
+  launch_c3_aux_shape<TX, TY, TZ>(plan, p, boxes_d, nbox, fl, out, mass, f, sp, dt, bin_start, nbins, dg, st)
+  switch (plan.shape) {
+    case 0: DUST_C3A(8, 8, 4); break;
+    case 1: DUST_C3A(16, 4, 4); break;
+    case 2: DUST_C3A(4, 16, 4); break;
+    case 3: DUST_C3A(4, 4, 16); break;
+    case 4: DUST_C3A(8, 4, 8); break;
+    default: DUST_C3A(4, 8, 8); break;
+  }
+#undef DUST_C3A
 }
 
 void launch_c3_keys(const PView<float>& p, const Box* boxes_d, int nbox, double dt, int64_t nbins,

@@ -101,6 +101,12 @@ void launch_c3_keys(const PView<float>& p, const Box* boxes_d, int nbox, double 
                     TileShape ts, uint32_t* key, hipStream_t st);
 void launch_c3_level_perm(const FusedPlan& plan, const uint32_t* perm, const int64_t* bin_start, uint32_t* lm,
                           hipStream_t st);
+// Predictor drag source (mass: dust density) on the binned layout of the
+// last fused step (see k_c3_aux): out[0..2] the momentum deposit channels
+// (mass: out[0] the density array).
+void launch_c3_aux(const FusedPlan& plan, const PView<float>& p, const Box* boxes_d, int nbox,
+                   const FView<float>& fl, float* const out[3], bool mass, const Forces& f, const Species* sp,
+                   double dt, const int64_t* bin_start, int64_t nbins, DiagDev* dg, hipStream_t st);
 size_t c3_lds_bytes(const FusedPlan& plan);
 
 // dst = src, every particle array.
