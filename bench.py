@@ -649,14 +649,15 @@ def run_config(cfg: int, args, extra: bool, K: int, W: int):
         sp = 1.0 if "species" in P else 0.0
         ds_bytes = (4 + 6 * real + sp + (4 * real if w.drag is not None else 0) +
                     (4 + 3) * real / ppc) * N
-        out["drag_source"] = {"kernel": "k_drag_source", "us_per_launch": round(ds_s * 1e6, 2),
+        tiled = tile_kernel(cfg, dtype, arith) == "k_c3"   # the binned-layout kernel
+        out["drag_source"] = {"kernel": "k_c3_aux" if tiled else "k_drag_source", "us_per_launch": round(ds_s * 1e6, 2),
                               "algorithmic_bytes_per_launch": ds_bytes,
                               "achieved": round(ds_bytes / ds_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": round(ds_bytes / ds_s / 1e9 / HBM_PEAK_GBS, 4)}
         rho_d = torch.zeros_like(F["rho"])
         md_s = timed_kernel(ctx, lambda: ctx.deposit_mass(P, rho_d), Kx, stream)
         md_bytes = (4 + 3 * real + sp + 2 * real / ppc) * N
-        out["mass_density"] = {"kernel": "k_mass_density", "us_per_launch": round(md_s * 1e6, 2),
+        out["mass_density"] = {"kernel": "k_c3_aux" if tiled else "k_mass_density", "us_per_launch": round(md_s * 1e6, 2),
                                "algorithmic_bytes_per_launch": md_bytes,
                                "achieved": round(md_bytes / md_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(md_bytes / md_s / 1e9 / HBM_PEAK_GBS, 4)}

@@ -2,7 +2,7 @@
 // kernels (half-step keys with this path's drift; the ranking of each tile's
 // cells by particle count and the source index of every slot) and the
 // dispatcher over tile shapes.  The kernel is in dust_cart3_kern.h.
-#include "dust_cart3_kern.h"
+#include "dust_cart3_aux.h"
 
 namespace dust {
 
