@@ -642,7 +642,7 @@ def run_config(cfg: int, args, extra: bool, K: int, W: int):
     })
     if cpu:
         out["cpu_baseline"] = cpu
-    if not args.no_extra and not extra:
+    if not args.no_extra:
         Kx = max(1, min(K, 10))
         fr = dust.forces_for(w, t)
         ds_s = timed_kernel(ctx, lambda: ctx.drag_source(P, F, w.dt, fr), Kx, stream)
@@ -768,7 +768,8 @@ def main():
         out["config2"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"],
                           "workload": r2["config"]["workload"], "tile": r2["config"]["tile"],
                           "rebin_every": r2["config"]["rebin_every"], "roofline": r2["roofline"],
-                          "parity": r2["parity"], "diag": r2["diag"]}
+                          "parity": r2["parity"], "diag": r2["diag"],
+                          "drag_source": r2.get("drag_source"), "mass_density": r2.get("mass_density")}
     if args.calib_copy_mb > 0:
         nel = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")

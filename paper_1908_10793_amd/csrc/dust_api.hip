@@ -570,12 +570,12 @@ enum StepMove {
 // (dust_cart3.hip): 3-D Cartesian boxes with uniform axes, FP32 storage and
 // arithmetic, forces none, constant or standard shearing box, masses and
 // stopping times from the species table (no per-particle arrays), fewer
-// than 2^31 particles (32-bit slot numbers).
+// than 2^30 particles (32-bit byte offsets of 4-byte elements).
 template <typename TS>
 bool use_c3(const Ctx* c, bool f32, const Forces& F, const PView<TS>& x) {
   return f32 && c->geom == GEOM_CART && c->ndim == 3 && c->unif &&
          (F.kind == FORCE_NONE || F.kind == FORCE_CONST || F.kind == FORCE_SHEARBOX) &&
-         c->drag_mode == DUST_DRAG_SPECIES && !x.mass && !x.drag && x.n < (int64_t(1) << 31);
+         c->drag_mode == DUST_DRAG_SPECIES && !x.mass && !x.drag && x.n < (int64_t(1) << 30);
 }
 
 // Whether the particles are the arrays the last fused FP32 uniform-Cartesian

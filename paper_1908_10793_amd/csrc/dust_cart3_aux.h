@@ -30,13 +30,110 @@ __device__ __forceinline__ float aux_gas_residual(const Box& B, const FView<floa
   return float(v);
 }
 
+// One particle against global memory, in its own cell's frame (stencil
+// cells are stored cells, ghosts included): the path of particles whose
+// stencil leaves their tile's window, of particles of another box, and of
+// the slots after the binned ones.
+template <bool SB, bool MASS>
+__device__ void aux_far_particle(const PView<float>& p, int64_t i, const Box* __restrict__ boxes, int nbox,
+                                 const FView<float>& fl, float* const outs[3], const Forces& f,
+                                 const Species* __restrict__ sp, float inv_dt, DiagDev* dg) {
+  constexpr int NC = MASS ? 1 : 3;
+  const int32_t cid = p.cell[i];
+  if (cid < 0) return;
+  const int b = find_box(boxes, nbox, cid);
+  const Box& B = boxes[b];
+  if (cid >= B.cell_base + B.ncell) {
+    flag(dg, DUST_FLAG_BAD_CELL);
+    return;
+  }
+  const C3Box cb = c3_box(B, 0.0f);
+  int idx[3];
+  c3_unravel(cid - cb.cell_base, cb.n[0], cb.n[1], B.ax[0].inv_n, B.ax[1].inv_n, idx);
+  float off[3], mom[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    off[d] = p.off[d][i];
+    mom[d] = MASS ? 0.0f : p.mom[d][i];
+  }
+  int spc = p.species ? p.species[i] : 0;
+  if (spc >= sp->n) spc = 0;
+  const double it = sp->inv_tau[spc];
+  const float k = MASS ? float(sp->mass[spc])
+                       : float(sp->mass[spc] * (it < double(inv_dt) ? it : double(inv_dt)));
+  const double qO = SB ? f.q * f.Omega : 0.0;
+  float w[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) c3_weights(cb.tsc[d], off[d], w[d]);
+  float q[3] = {0.0f, 0.0f, 0.0f};
+  if constexpr (MASS) {
+    q[0] = k;
+  } else {
+    float u[3] = {mom[0], mom[1], mom[2]};
+    if (SB) u[1] = float(double(mom[1]) + qO * (B.ax[0].lo + (double(idx[0]) + 0.5 + double(off[0])) * B.ax[0].d));
+    float v[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float wt = w[0][a] * w[1][bb] * w[2][c];
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            v[m] += wt * (aux_gas_residual<SB>(B, fl, m, idx[0] + a - 1, idx[1] + bb - 1, idx[2] + c - 1, qO) - u[m]);
+        }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) q[m] = -k * v[m];
+  }
+  const float iv = float(inv_volume(B, 0, 0, 0));
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float wt = w[0][a] * w[1][bb] * w[2][c] * iv;
+        const int64_t id = stored_index(B, idx[0] + a - 1, idx[1] + bb - 1, idx[2] + c - 1);
+#pragma unroll
+        for (int m = 0; m < NC; ++m) unsafeAtomicAdd(&outs[m][id], wt * q[m]);
+      }
+}
+
+// The listed particles of k_c3_aux, then the slots after the binned ones;
+// the last workgroup to finish clears the list's count for the next launch.
+template <bool SB, bool MASS>
+__global__ void __launch_bounds__(256)
+    k_c3_aux_far(PView<float> p, const Box* __restrict__ boxes, int nbox, FView<float> fl,
+                 float* __restrict__ out0, float* __restrict__ out1, float* __restrict__ out2, Forces f,
+                 const Species* __restrict__ sp, float inv_dt, const uint32_t* __restrict__ list,
+                 uint32_t* __restrict__ count, const int64_t* __restrict__ bin_start, int64_t nbins,
+                 uint32_t* __restrict__ done, DiagDev* dg) {
+  float* const outs[3] = {out0, out1, out2};
+  const uint32_t nl = *count;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t e = t; e < nl; e += stride)
+    aux_far_particle<SB, MASS>(p, list[e], boxes, nbox, fl, outs, f, sp, inv_dt, dg);
+  for (int64_t i = bin_start[nbins] + t; i < p.n; i += stride)
+    aux_far_particle<SB, MASS>(p, i, boxes, nbox, fl, outs, f, sp, inv_dt, dg);
+  // every workgroup has read the count once it reaches here
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (atomicAdd(done, 1u) == gridDim.x - 1) {
+      *count = 0u;
+      *done = 0u;
+    }
+  }
+}
+
 template <int TX, int TY, int TZ, bool SB, bool MASS>
-__global__ void __launch_bounds__(FUSED_THREADS)
-    k_c3_aux(const TileDesc* __restrict__ tiles, int ntiles, const uint8_t* __restrict__ tmap,
-             PView<float> p, const Box* __restrict__ boxes, int nbox, FView<float> fl,
-             float* __restrict__ out0, float* __restrict__ out1, float* __restrict__ out2, Forces f,
-             const Species* __restrict__ sp, float inv_dt, const int64_t* __restrict__ bin_start,
-             int64_t nbins, DiagDev* dg) {
+__global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(MASS ? 4 : 3)))
+    k_c3_aux(const TileDesc* __restrict__ tiles, const uint8_t* __restrict__ tmap, PView<float> p,
+             const Box* __restrict__ boxes, FView<float> fl, float* __restrict__ out0,
+             float* __restrict__ out1, float* __restrict__ out2, Forces f, const Species* __restrict__ sp,
+             float inv_dt, const int64_t* __restrict__ bin_start, uint32_t* __restrict__ far_list,
+             uint32_t* __restrict__ far_count, DiagDev* dg) {
   constexpr int H = FUSED_HALO;
   constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RZ = TZ + 2 * H;
   constexpr int RC = RX * RY * RZ;
@@ -53,79 +150,6 @@ __global__ void __launch_bounds__(FUSED_THREADS)
                              : float(sp->mass[threadIdx.x] * (it < double(inv_dt) ? it : double(inv_dt)));
   }
   const double qO = SB ? f.q * f.Omega : 0.0;
-
-  // global-memory step of one particle (own cell's frame: stencil cells are
-  // stored cells, ghosts included)
-  auto far = [&](const Box& B, const C3Box& cb, const int idx[3], const float off[3], const float mom[3],
-                 int spc) {
-    float w[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) c3_weights(cb.tsc[d], off[d], w[d]);
-    float q[3] = {0.0f, 0.0f, 0.0f};
-    if constexpr (MASS) {
-      q[0] = sp_k[spc];
-    } else {
-      float u[3] = {mom[0], mom[1], mom[2]};
-      if (SB) u[1] = float(double(mom[1]) + qO * (B.ax[0].lo + (double(idx[0]) + 0.5 + double(off[0])) * B.ax[0].d));
-      float v[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const float wt = w[0][a] * w[1][bb] * w[2][c];
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-              v[m] += wt * (aux_gas_residual<SB>(B, fl, m, idx[0] + a - 1, idx[1] + bb - 1, idx[2] + c - 1, qO) - u[m]);
-          }
-#pragma unroll
-      for (int m = 0; m < 3; ++m) q[m] = -sp_k[spc] * v[m];
-    }
-    const float iv = float(inv_volume(B, 0, 0, 0));
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const float wt = w[0][a] * w[1][bb] * w[2][c] * iv;
-          const int64_t id = stored_index(B, idx[0] + a - 1, idx[1] + bb - 1, idx[2] + c - 1);
-#pragma unroll
-          for (int m = 0; m < NC; ++m) unsafeAtomicAdd(&outs[m][id], wt * q[m]);
-        }
-  };
-  auto load_far = [&](int64_t i) {
-    const int32_t cid = p.cell[i];
-    if (cid < 0) return;
-    const int b = find_box(boxes, nbox, cid);
-    const Box& B = boxes[b];
-    if (cid >= B.cell_base + B.ncell) {
-      flag(dg, DUST_FLAG_BAD_CELL);
-      return;
-    }
-    const C3Box cb = c3_box(B, 0.0f);
-    int idx[3];
-    c3_unravel(cid - cb.cell_base, cb.n[0], cb.n[1], B.ax[0].inv_n, B.ax[1].inv_n, idx);
-    float off[3], mom[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      off[d] = p.off[d][i];
-      mom[d] = MASS ? 0.0f : p.mom[d][i];
-    }
-    int spc = p.species ? p.species[i] : 0;
-    if (spc >= sp->n) spc = 0;
-    far(B, cb, idx, off, mom, spc);
-  };
-
-  if ((int)blockIdx.x >= ntiles) {
-    // slots after the binned ones (normally particles without a cell)
-    const int64_t first = bin_start[nbins];
-    for (int64_t i = first + (int64_t)(blockIdx.x - ntiles) * FUSED_THREADS + threadIdx.x; i < p.n;
-         i += (int64_t)(gridDim.x - ntiles) * FUSED_THREADS)
-      load_far(i);
-    return;
-  }
 
   const TileDesc td = tiles[blockIdx.x];
   const Box& B = boxes[td.box];
@@ -178,26 +202,29 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 #pragma unroll
     for (int m = 0; m < NC; ++m) acc[o][m] = 0.0f;
 
+  // particles loaded one level ahead of their use (a lane without a
+  // particle at a level loads the wave's first one, whose value it ignores)
   uint32_t lvl = wl.base;
   const int nlev = __builtin_amdgcn_readfirstlane(wl.nlev);
+  uint32_t slot = level_slot(wl, 0, lvl);
+  C3Raw nxt;
+  if (nlev > 0) c3_load<false>(p, wl.cnt > 0 ? slot : wl.base, nxt);
   for (int j = 0; j < nlev; ++j) {
-    const uint32_t i = level_slot(wl, j, lvl);
+    const uint32_t i = slot;
     const bool has = wl.cnt > j;
-    const uint32_t li = has ? i : wl.base;
-    const int32_t cid = at32(p.cell, li);
+    const C3Raw cur = nxt;
+    slot = level_slot(wl, j + 1, lvl);
+    if (j + 1 < nlev) c3_load<false>(p, wl.cnt > j + 1 ? slot : wl.base, nxt);
+    const int32_t cid = cur.cell;
     float off[3], mom[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      off[d] = at32(p.off[d], li);
-      mom[d] = MASS ? 0.0f : at32(p.mom[d], li);
+      off[d] = cur.off[d];
+      mom[d] = MASS ? 0.0f : cur.mom[d];
     }
-    int spc = p.species ? (int)at32(p.species, li) : 0;
+    int spc = p.species ? cur.species : 0;
     if (spc >= sp->n) spc = 0;
     bool live = has && cid >= cb.cell_base && cid < cb.cell_base + cb.ncell;
-    if (has && cid >= 0 && !live) {
-      // another box, or bad: the global path decides
-      load_far(i);
-    }
     int idx[3] = {mycell[0], mycell[1], mycell[2]};
     if (live && cid != mycid) c3_unravel(cid - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx);
     int la = lx + H, lb = ly + H, lcz = lz + H;
@@ -207,7 +234,20 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       lb = win_coord(idx[1], oy, n1, RY, cb.per[1]);
       lcz = win_coord(idx[2], oz, n2, RZ, cb.per[2]);
       inwin = la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 && lcz >= 1 && lcz <= RZ - 2;
-      if (!inwin) far(B, cb, idx, off, mom, spc);
+    }
+    {
+      // a particle of another box, or whose stencil leaves the window: to
+      // the list of k_c3_aux_far (one atomic per wave)
+      const bool away = (has && cid >= 0 && !live) || (live && !inwin);
+      const uint64_t am = __ballot(away);
+      if (am) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)am) - 1;
+        uint32_t fb = 0;
+        if (lane == leader) fb = atomicAdd(far_count, (uint32_t)__popcll(am));
+        fb = __shfl(fb, leader, 64);
+        if (away) far_list[fb + lanes_below(am)] = i;
+      }
     }
     const bool use = live && inwin;
     if (!use) {
@@ -319,8 +359,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   }
 }
 
-// extra workgroups of k_c3_aux for the slots after the binned ones
-static constexpr int AUX_TAIL_BLOCKS = 64;
+// Workgroups of k_c3_aux_far.
+static constexpr int AUX_FAR_BLOCKS = 256;
 
 template <int TX, int TY, int TZ>
 void launch_c3_aux_shape(const FusedPlan& plan, const PView<float>& p, const Box* boxes_d, int nbox,
@@ -328,23 +368,25 @@ void launch_c3_aux_shape(const FusedPlan& plan, const PView<float>& p, const Box
                          const Species* sp, double dt, const int64_t* bin_start, int64_t nbins, DiagDev* dg,
                          hipStream_t st) {
   constexpr int RC = (TX + 2 * FUSED_HALO) * (TY + 2 * FUSED_HALO) * (TZ + 2 * FUSED_HALO);
-  const dim3 grid(plan.ntiles + AUX_TAIL_BLOCKS);
   const float inv_dt = float(1.0 / dt);
-  if (mass) {
-    hipLaunchKernelGGL((k_c3_aux<TX, TY, TZ, false, true>), grid, dim3(FUSED_THREADS), RC * sizeof(double), st,
-                       plan.tiles_d, plan.ntiles, plan.tile_map, p, boxes_d, nbox, fl, out[0], out[1], out[2], f,
-                       sp, inv_dt, bin_start, nbins, dg);
-    return;
-  }
-  const size_t lds = RC * (3 * sizeof(double) + sizeof(float4));
-  if (f.kind == FORCE_SHEARBOX)
-    hipLaunchKernelGGL((k_c3_aux<TX, TY, TZ, true, false>), grid, dim3(FUSED_THREADS), lds, st, plan.tiles_d,
-                       plan.ntiles, plan.tile_map, p, boxes_d, nbox, fl, out[0], out[1], out[2], f, sp, inv_dt,
-                       bin_start, nbins, dg);
-  else
-    hipLaunchKernelGGL((k_c3_aux<TX, TY, TZ, false, false>), grid, dim3(FUSED_THREADS), lds, st, plan.tiles_d,
-                       plan.ntiles, plan.tile_map, p, boxes_d, nbox, fl, out[0], out[1], out[2], f, sp, inv_dt,
-                       bin_start, nbins, dg);
+  uint32_t* list = plan.defer_list;
+  uint32_t* count = plan.defer_count;
+  uint32_t* done = plan.defer_count + 1;   // second word of the count block
+  const size_t lds = mass ? RC * sizeof(double) : RC * (3 * sizeof(double) + sizeof(float4));
+#define DUST_AUX(SBV, MV)                                                                                  \
+  do {                                                                                                    \
+    if (plan.ntiles > 0)                                                                                  \
+      hipLaunchKernelGGL((k_c3_aux<TX, TY, TZ, SBV, MV>), dim3(plan.ntiles), dim3(FUSED_THREADS), lds, st, \
+                         plan.tiles_d, plan.tile_map, p, boxes_d, fl, out[0], out[1], out[2], f, sp, inv_dt, \
+                         bin_start, list, count, dg);                                                     \
+    hipLaunchKernelGGL((k_c3_aux_far<SBV, MV>), dim3(AUX_FAR_BLOCKS), dim3(256), 0, st, p, boxes_d, nbox,  \
+                       fl, out[0], out[1], out[2], f, sp, inv_dt, (const uint32_t*)list, count, bin_start,  \
+                       nbins, done, dg);                                                                  \
+  } while (0)
+  if (mass) DUST_AUX(false, true);
+  else if (f.kind == FORCE_SHEARBOX) DUST_AUX(true, false);
+  else DUST_AUX(false, false);
+#undef DUST_AUX
 }
 
 #define DUST_C3_AUX_SHAPE_DECL(PREFIX, TX, TY, TZ)                                                          \

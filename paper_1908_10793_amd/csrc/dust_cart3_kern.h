@@ -141,11 +141,16 @@ __device__ __forceinline__ WaveLevels c3_layout(const TileDesc& td, int lc,
   return wl;
 }
 
-// Element i (a slot number) of a particle array, with 64-bit index arithmetic.
+// Element i (a slot number) of a particle array through a 32-bit byte
+// offset from the (workgroup-uniform) base: the global instructions' scalar
+// base + vector offset form, with no 64-bit address arithmetic per access.
+// The path takes fewer than 2^30 particles, so 4 i < 2^32.
 template <typename T> __device__ __forceinline__ const T& at32(const T* base, uint32_t i) {
-  return base[(uint64_t)i];
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
 }
-template <typename T> __device__ __forceinline__ T& at32(T* base, uint32_t i) { return base[(uint64_t)i]; }
+template <typename T> __device__ __forceinline__ T& at32(T* base, uint32_t i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T));
+}
 
 // Stored state of a particle and its species (masses and stopping times
 // come from the species table on this path).
