@@ -219,7 +219,7 @@ dust_status_t dust_ctx_set_tile(void *ctx, int32_t tx, int32_t ty, int32_t tz, i
 
 /* Autotuner of the fused step (batching and tuning row of the hot path):
  * runs `steps` fused steps (after one warm-up step) for every compiled tile
- * shape and rebinning interval 1, 2, 3, 4, 6, 8, 12 or 16 (timed over whole intervals of at
+ * shape and rebinning interval 1, 2, 3, 4, 6, 8, 12, 16, 24 or 32 (timed over whole intervals of at
  * least `steps` steps) on device copies of p and f (the
  * caller's arrays and the context's diagnostics are left unchanged), times
  * them with HIP events on `stream`, and keeps the fastest tile shape and

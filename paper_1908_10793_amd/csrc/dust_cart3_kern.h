@@ -52,11 +52,28 @@ __device__ __forceinline__ int c3_move(int i, float& off, float v, float hinv) {
   return i;
 }
 
-// Cell coordinates of a local cell id (FP64 reciprocal with one correction).
+// floor(a / n) for 0 <= a <= 2^24, n >= 1, through an FP32 reciprocal: a is
+// exact in FP32 and the product is within one of the quotient, so one
+// correction step makes it exact.
+__device__ __forceinline__ int c3_div24(int a, int n, float inv) {
+  int q = (int)(float(a) * inv);
+  const int r = a - q * n;
+  q += r >= n ? 1 : (r < 0 ? -1 : 0);
+  return q;
+}
+
+// Cell coordinates of a local cell id: FP32 reciprocals for boxes of at
+// most 2^24 cells, else FP64 (one correction each).
 __device__ __forceinline__ void c3_unravel(int l, int n0, int n1, double inv0, double inv1, int idx[3]) {
-  const int r = div_small(l, n0, inv0);
+  int r, k;
+  if (l <= (1 << 24)) {
+    r = c3_div24(l, n0, float(inv0));
+    k = c3_div24(r, n1, float(inv1));
+  } else {
+    r = div_small(l, n0, inv0);
+    k = div_small(r, n1, inv1);
+  }
   idx[0] = l - r * n0;
-  const int k = div_small(r, n1, inv1);
   idx[1] = r - k * n1;
   idx[2] = k;
 }
