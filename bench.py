@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--tune-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU step")
+    ap.add_argument("--no-curvilinear", action="store_true",
+                    help="skip the cylindrical and spherical disks (FP64 vs FP32 arithmetic)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the side measurements (drag source, dust density, config 2)")
     ap.add_argument("--no-check", action="store_true", help="skip the parity check against the oracle")
@@ -474,6 +476,33 @@ def _clone(d):
     return {k: ([x.clone() for x in v] if isinstance(v, list) else v.clone()) for k, v in d.items()}
 
 
+def curvilinear(args, W):
+    """The cylindrical (256x512x64, 2^25 particles) and spherical
+    (256x128x512, 2^26) disks with the default FP64 per-particle arithmetic
+    and with the FP32 one (FP32 storage both): time per step and one step's
+    parity against the oracle on a particle sample, so that the cost of the
+    FP64 default is on record.  Fixed tile shape and rebinning interval (the
+    autotuner's picks at full size), 10 timed steps."""
+    import copy
+    res = {}
+    for cfg, tile, rebin in ((3, "4,16,4,0", 3), (4, "4,16,4,0", 2)):
+        a2 = copy.copy(args)
+        a2.no_tune, a2.tile, a2.rebin_every, a2.reps, a2.eager = True, tile, rebin, 3, True
+        row = {}
+        for arith in ("f64", "f32"):
+            r, w = run_config(cfg, a2, extra=True, K=10, W=W, arith_override=arith)
+            row[arith + "_arith"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                     "roofline_frac": r["roofline"]["frac"] if r["roofline"] else None,
+                                     "parity_worst": r["parity"]["worst"] if r["parity"] else None,
+                                     "parity_pass": r["parity"]["pass"] if r["parity"] else None}
+            del w
+        row["workload"] = WORKLOAD_NAMES[cfg]
+        row["tile"], row["rebin_every"] = tile, rebin
+        row["fp64_over_fp32_time"] = round(row["f64_arith"]["ms_per_step"] / row["f32_arith"]["ms_per_step"], 3)
+        res[WORKLOAD_NAMES[cfg]] = row
+    return res
+
+
 def timed_kernel(ctx, fn, K, stream):
     """Average time of K calls of fn() (HIP events on the launch stream)."""
     import torch
@@ -488,7 +517,7 @@ def timed_kernel(ctx, fn, K, stream):
     return e0.elapsed_time(e1) * 1e-3 / K
 
 
-def run_config(cfg: int, args, extra: bool, K: int, W: int):
+def run_config(cfg: int, args, extra: bool, K: int, W: int, arith_override=None):
     import numpy as np
     import torch
     from paper_1908_10793_amd import dust
@@ -500,7 +529,7 @@ def run_config(cfg: int, args, extra: bool, K: int, W: int):
     N = w.n
     C = sum(int(np.prod(b["n"][:b["ndim"]])) for b in w.boxes)
     ctx = dust.context_for(w)
-    arith = args.arith or ("f32" if w.boxes[0]["geom"] == "cart" else "f64")
+    arith = arith_override or args.arith or ("f32" if w.boxes[0]["geom"] == "cart" else "f64")
     if dtype == "f32":
         ctx.set_arith(arith)
     tx, ty, tz, slack = (int(v) for v in args.tile.split(","))
@@ -770,6 +799,8 @@ def main():
                           "rebin_every": r2["config"]["rebin_every"], "roofline": r2["roofline"],
                           "parity": r2["parity"], "diag": r2["diag"],
                           "drag_source": r2.get("drag_source"), "mass_density": r2.get("mass_density")}
+    if args.config == 5 and not args.no_extra and not args.no_curvilinear:
+        out["curvilinear"] = curvilinear(args, W)
     if args.calib_copy_mb > 0:
         nel = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
