@@ -89,6 +89,11 @@ struct Ctx {
   int64_t lay_n = 0;
   const void* lay_cell = nullptr;
   FusedPlan plan{};
+  // deterministic mode: the unfused step with the sorted (pull) deposit and
+  // fixed-order diagnostic sums; det_part holds the kick's block partials
+  bool det = false;
+  double* det_part = nullptr;
+  size_t det_part_words = 0;
   // fused-kernel timing
   std::vector<hipEvent_t> prof_ev;  // 2 per launch
   int prof_max = 0;
@@ -430,6 +435,21 @@ dust_status_t ensure_bin_start(Ctx* c) {
   return DUST_OK;
 }
 
+// Workspace of the deterministic mode for n particles: the sort's and the
+// kick's block partials.
+dust_status_t ensure_det(Ctx* c, int64_t n) {
+  dust_status_t s;
+  if ((s = ensure_bin(c, n)) || (s = ensure_bin_start(c))) return s;
+  size_t need = (size_t)kick_partial_words(n);
+  if (need <= c->det_part_words) return DUST_OK;
+  if (c->det_part) HIP_TRY(hipFree(c->det_part));
+  c->det_part = nullptr;
+  c->det_part_words = 0;
+  if (hipMalloc((void**)&c->det_part, need * 8) != hipSuccess) return fail(DUST_ENOMEM, "kick partials");
+  c->det_part_words = need;
+  return DUST_OK;
+}
+
 // Apply perm (sorted slot -> input index) to every particle array, staging
 // each through tmp (8 bytes per particle).
 dust_status_t apply_perm(Ctx* c, dust_particles_t* p, const uint32_t* perm, void* tmp, hipStream_t st) {
@@ -513,6 +533,19 @@ bool scratch_work(void* base, int64_t n, BinWork& w) {
 
 // ------------------------------------------------------------------ typed drivers
 
+// Deterministic deposit: a stable sort of the particles by cell (into the
+// binning workspace and bin starts, which no longer describe a fused
+// layout), then every box's cells sum their particles' contributions.
+template <typename TS, typename A, typename TW>
+void deposit_det(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const TW* const imp[4], hipStream_t st) {
+  c->bin_cur = launch_bin(pv.cell, pv.n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_CELL, c->tile, c->bin,
+                          nullptr, c->bin_start, false, st);
+  c->lay_valid = false;
+  for (auto& B : c->boxes)
+    launch_deposit_pull<TS, A, TW>(pv, B, c->geom, c->ndim, c->unif, fv, imp, c->bin.val[c->bin_cur],
+                                   c->bin_start, st);
+}
+
 template <typename TS, typename A>
 void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phases,
               const TS* const vg[3], TS* const imp[4], DiagDev* dg, hipStream_t st) {
@@ -520,7 +553,7 @@ void run_push(Ctx* c, const PView<TS>& pv, const Forces& F, double dt, int phase
     launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dg, st);
   if (phases & DUST_PHASE_KICK)
     launch_kick<TS, A, TS>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt,
-                           nullptr, vg, imp, dg, st);
+                           nullptr, vg, imp, dg, c->det ? c->det_part : nullptr, st);
   if (phases & DUST_PHASE_DRIFT2)
     launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dg, st);
 }
@@ -547,9 +580,12 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
                           (flags & DUST_STEP_NO_FILL) ? nullptr : c->xg, rho_p, vg, dflags, st);
   const A* cvg[3] = {vg[0], vg[1], vg[2]};
   launch_kick<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, c->species_d, c->drag_mode, dt, rho_p,
-                        cvg, imp, dg ? dg : dflags, st);
+                        cvg, imp, dg ? dg : dflags, c->det ? c->det_part : nullptr, st);
   const A* cimp[4] = {imp[0], imp[1], imp[2], imp[3]};
-  launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, cimp, dflags, st);
+  if (c->det)
+    deposit_det<TS, A, A>(c, pv, fv, cimp, st);
+  else
+    launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, cimp, dflags, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
   if (dg)
     for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, c->grid_part, st);
@@ -830,6 +866,7 @@ dust_status_t dust_ctx_destroy(void* ctx) {
   if (c->bin_mem) hipFree(c->bin_mem);
   if (c->shadow_mem) hipFree(c->shadow_mem);
   if (c->bin_start) hipFree(c->bin_start);
+  if (c->det_part) hipFree(c->det_part);
   fused_plan_free(c->plan);
   delete c;
   return DUST_OK;
@@ -839,6 +876,15 @@ dust_status_t dust_ctx_set_arith(void* ctx, int32_t arith) {
   if (check_ctx(ctx)) return DUST_EINVAL;
   if (arith != DUST_ARITH_F64 && arith != DUST_ARITH_F32) return fail(DUST_EINVAL, "unknown arith %d", arith);
   ((Ctx*)ctx)->arith = arith;
+  return DUST_OK;
+}
+
+dust_status_t dust_ctx_set_deterministic(void* ctx, int32_t on) {
+  if (check_ctx(ctx)) return DUST_EINVAL;
+  if (on != 0 && on != 1) return fail(DUST_EINVAL, "deterministic: 0 or 1, not %d", on);
+  Ctx* c = (Ctx*)ctx;
+  c->det = on != 0;
+  drop_graph(c);
   return DUST_OK;
 }
 
@@ -1075,6 +1121,7 @@ dust_status_t dust_push_expmid(void* ctx, dust_particles_t* p, const void* const
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(c->device));
   c->last_stream = st;
+  if (c->det && (phases & DUST_PHASE_KICK) && (s = ensure_det(c, p->n))) return s;
   launch_set_time(c->tdev, frc->t, st);
   Forces F = forces_of(frc);
   return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
@@ -1106,12 +1153,17 @@ dust_status_t dust_deposit(void* ctx, const dust_particles_t* p, const void* con
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(c->device));
   c->last_stream = st;
+  if (c->det && (s = ensure_det(c, p->n))) return s;
   return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
     using TS = decltype(ts);
     using A = decltype(ta);
     const TS* imp[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k <= nc; ++k) imp[k] = (const TS*)impulse[k];
-    launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), imp, c->diag, st);
+    if (c->det)
+      deposit_det<TS, A, TS>(c, pview<TS>(p), fview<TS>(f), imp, st);
+    else
+      launch_deposit<TS, A, TS>(pview<TS>(p), c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fview<TS>(f), imp,
+                                c->diag, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -1218,6 +1270,11 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(c->device));
   c->last_stream = st;
+  // the deterministic mode runs the unfused chain
+  if (c->det) {
+    flags &= ~DUST_STEP_FUSED;
+    if ((s = ensure_det(c, p->n))) return s;
+  }
   if (!(flags & DUST_STEP_FUSED) && (s = ensure_ws(c, p->n))) return s;
   if (flags & DUST_STEP_FUSED) {
     if (frc->integrator != DUST_INTEGRATOR_EXPMID)
@@ -1270,6 +1327,8 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   put(&c->bin_start, sizeof(c->bin_start));
   put(&c->ws, sizeof(c->ws));
   put(&c->prof_max, sizeof(c->prof_max));
+  put(&c->det, sizeof(c->det));
+  put(&c->det_part, sizeof(c->det_part));
   if (!(c->graph_exec && key == c->graph_key)) {
     if (c->graph_exec) {
       hipGraphExecDestroy(c->graph_exec);

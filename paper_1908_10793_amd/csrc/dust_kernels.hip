@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
                                               const Species* sp, int drag_mode, A dt, const TW* rho_p,
                                               const TW* vg0,
                                               const TW* vg1, const TW* vg2, TW* imp0, TW* imp1,
-                                              TW* imp2, TW* imp3, DiagDev* dg) {
+                                              TW* imp2, TW* imp3, DiagDev* dg, double* part) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   double sums[5] = {0, 0, 0, 0, 0};
@@ -125,13 +125,50 @@ __global__ void __launch_bounds__(256) k_kick(PView<TS> p, const Box* boxes, int
 #pragma unroll
     for (int k = 0; k < 5; ++k) sums[k] = wave_sum(sums[k]);
     cells = wave_max(cells);
+    if (part) {
+      // deterministic: the block's sums in a fixed order into its slot of
+      // part (added up by k_reduce_kick_partials)
+      __shared__ double red[4][5];
+      if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 5; ++k) red[threadIdx.x >> 6][k] = sums[k];
+      __syncthreads();
+      if (threadIdx.x < 5)
+        part[(size_t)blockIdx.x * 5 + threadIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    }
     if ((threadIdx.x & 63) == 0) {
-      for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&dg->p_part[k], sums[k]);
-      unsafeAtomicAdd(&dg->e_part, sums[3]);
-      unsafeAtomicAdd(&dg->sum_abs_j, sums[4]);
+      if (!part) {
+        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&dg->p_part[k], sums[k]);
+        unsafeAtomicAdd(&dg->e_part, sums[3]);
+        unsafeAtomicAdd(&dg->sum_abs_j, sums[4]);
+      }
       atomic_max_nonneg(&dg->max_cells_bits, cells);
       if (cells > 1.8) atomicOr(&dg->flags, (unsigned)DUST_FLAG_CFL);
     }
+  }
+}
+
+// Sum of the kick's per-block partials (5 per block) in a fixed order, added
+// to the diagnostics.
+__global__ void __launch_bounds__(256)
+    k_reduce_kick_partials(const double* __restrict__ part, int64_t nblocks, DiagDev* dg) {
+  __shared__ double red[256][5];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[k] += part[(size_t)b * 5 + k];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) red[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 5; ++k) red[threadIdx.x][k] += red[threadIdx.x + h][k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) dg->p_part[k] += red[0][k];
+    dg->e_part += red[0][3];
+    dg->sum_abs_j += red[0][4];
   }
 }
 
@@ -166,6 +203,61 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
         for (int k = 0; k <= nc; ++k) unsafeAtomicAdd(&fl.dep[k][id], TS(-w * q[k]));
       }
     }
+}
+
+// Deposit of Eq. dust_feedback_final without float atomics, for the
+// deterministic mode: one thread per stored cell (active or ghost) of box B
+// sums W J / dV over the particles whose stencil covers the cell -- those
+// of the 3^d active cells around it, the offsets in a fixed order and each
+// cell's particles in the order of a stable sort by cell (perm, bin_start
+// over the global cell ids) -- in FP64, and subtracts the sums from its
+// deposit words.  Every word has one writer and a fixed summation order,
+// so the result is the same bits on every run.
+template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
+__global__ void __launch_bounds__(256)
+    k_deposit_pull(PView<TS> p, Box B, FView<TS> fl, const TW* imp0, const TW* imp1, const TW* imp2,
+                   const TW* imp3, const uint32_t* __restrict__ perm, const int64_t* __restrict__ bin_start) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B.nstore) return;
+  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
+  const int i = (int)(t % B.g0) - 1;
+  const int j = (int)((t / B.g0) % B.g1) - 1;
+  const int k = (int)(t / ((int64_t)B.g0 * B.g1)) - B.k_off;
+  const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = NDIM > 2 ? B.ax[2].n : 1;
+  const TW* imp[4] = {imp0, imp1, imp2, imp3};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // this cell is the particle's host cell shifted by (a, bb, c)
+  for (int c = -c2; c <= c2; ++c) {
+    const int sk = k - c;
+    if (sk < 0 || sk >= n2) continue;
+    for (int bb = -1; bb <= 1; ++bb) {
+      const int sj = j - bb;
+      if (sj < 0 || sj >= n1) continue;
+      for (int a = -1; a <= 1; ++a) {
+        const int si = i - a;
+        if (si < 0 || si >= n0) continue;
+        int src[3] = {si, sj, sk};
+        const int64_t cid = B.cell_base + ravel(B, src);
+        const int64_t e = bin_start[cid + 1];
+        for (int64_t s = bin_start[cid]; s < e; ++s) {
+          const int64_t ip = perm[s];
+          A off[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) off[d] = d < NDIM ? A(p.off[d][ip]) : A(0);
+          Stencil<A> sw;
+          stencil_weights<A, GEOM, NDIM, U>(B, src, off, sw);
+          const double w = double(sw.w[0][a + 1] * sw.w[1][bb + 1] * sw.w[2][c + 1]);
+#pragma unroll
+          for (int m = 0; m <= nc; ++m) acc[m] += w * double(imp[m][ip]);
+        }
+      }
+    }
+  }
+  const double iv = inv_volume(B, i, j, k);
+  const int64_t id = B.store_base + t;
+#pragma unroll
+  for (int m = 0; m <= nc; ++m) fl.dep[m][id] = TS(double(fl.dep[m][id]) - acc[m] * iv);
 }
 
 // Drag source of the gas predictor (Sec. 3.1, Eq. Delta_vp and f_D): at the
@@ -885,13 +977,19 @@ void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int
 template <typename TS, typename A, typename TW>
 void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                  const Forces& f, const Species* sp, int drag_mode, double dt, const TW* rho_p,
-                 const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st) {
+                 const TW* const vg[3], TW* const imp[4], DiagDev* dg, double* part, hipStream_t st) {
   if (p.n == 0) return;
+  if (!dg) part = nullptr;
   DUST_GEOM_SWITCH(geom, ndim, unif,
                    hipLaunchKernelGGL((k_kick<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
                                       0, st, p, boxes, nbox, f, sp, drag_mode, A(dt), rho_p, vg[0], vg[1],
-                                      vg[2], imp[0], imp[1], imp[2], imp[3], dg));
+                                      vg[2], imp[0], imp[1], imp[2], imp[3], dg, part));
+  if (part)
+    hipLaunchKernelGGL(k_reduce_kick_partials, dim3(1), dim3(256), 0, st, (const double*)part,
+                       (int64_t)blocks_for(p.n), dg);
 }
+
+int64_t kick_partial_words(int64_t n) { return 5 * (int64_t)blocks_for(std::max<int64_t>(n, 1)); }
 
 template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
@@ -900,6 +998,16 @@ void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, in
   DUST_GEOM_SWITCH(geom, ndim, unif,
                    hipLaunchKernelGGL((k_deposit<TS, A, TW, G_, D_, U_>), dim3(blocks_for(p.n)), dim3(256),
                                       0, st, p, boxes, nbox, fl, imp[0], imp[1], imp[2], imp[3], dg));
+}
+
+template <typename TS, typename A, typename TW>
+void launch_deposit_pull(const PView<TS>& p, const Box& B, int geom, int ndim, int unif, const FView<TS>& fl,
+                         const TW* const imp[4], const uint32_t* perm, const int64_t* bin_start, hipStream_t st) {
+  if (B.nstore == 0) return;
+  DUST_GEOM_SWITCH(geom, ndim, unif,
+                   hipLaunchKernelGGL((k_deposit_pull<TS, A, TW, G_, D_, U_>), dim3(blocks_for(B.nstore)),
+                                      dim3(256), 0, st, p, B, fl, imp[0], imp[1], imp[2], imp[3], perm,
+                                      bin_start));
 }
 
 template <typename TS, typename A>
@@ -1020,10 +1128,13 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
                                          hipStream_t);                                            \
   template void launch_kick<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int, const Forces&, \
                                        const Species*, int, double, const TW*, const TW* const[3], \
-                                       TW* const[4], DiagDev*, hipStream_t);                      \
+                                       TW* const[4], DiagDev*, double*, hipStream_t);             \
   template void launch_deposit<TS, A, TW>(const PView<TS>&, const Box*, int, int, int, int,            \
                                           const FView<TS>&, const TW* const[4], DiagDev*,         \
-                                          hipStream_t);
+                                          hipStream_t);                                           \
+  template void launch_deposit_pull<TS, A, TW>(const PView<TS>&, const Box&, int, int, int, const FView<TS>&, \
+                                               const TW* const[4], const uint32_t*, const int64_t*,    \
+                                               hipStream_t);
 
 #define DUST_INST_DRIFT(TS, A)                                                                    \
   template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, int, int, int, const Forces&,   \

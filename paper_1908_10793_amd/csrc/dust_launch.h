@@ -38,12 +38,22 @@ void launch_gather(const PView<TS>& p, const Box* boxes, int nbox, int geom, int
                    hipStream_t st);
 template <typename TS, typename A, typename TW>
 // rho_p: the gathered gas density (Epstein drag; else unused, may be null).
+// part: null (diagnostic sums by atomics), or kick_partial_words(n) doubles
+// of scratch for per-block partials added up in a fixed order
+// (deterministic sums).
 void launch_kick(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                  const Forces& f, const Species* sp, int drag_mode, double dt, const TW* rho_p,
-                 const TW* const vg[3], TW* const imp[4], DiagDev* dg, hipStream_t st);
+                 const TW* const vg[3], TW* const imp[4], DiagDev* dg, double* part, hipStream_t st);
+int64_t kick_partial_words(int64_t n);
 template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                     const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st);
+// The deposit of one box without float atomics (same bits on every run):
+// perm and bin_start from a stable sort of the particles by global cell id
+// (launch_bin, DUST_BIN_CELL).  B: the host copy of the box.
+template <typename TS, typename A, typename TW>
+void launch_deposit_pull(const PView<TS>& p, const Box& B, int geom, int ndim, int unif, const FView<TS>& fl,
+                         const TW* const imp[4], const uint32_t* perm, const int64_t* bin_start, hipStream_t st);
 
 // Drag source of the gas predictor (Eq. f_D, tau <- max(tau, dt)) at the
 // particles' current positions, accumulated into the momentum channels of fl.

@@ -75,7 +75,8 @@ class dust_diag_t(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("steps", ctypes.c_int32)]
 
 
-EXPORTS = ["dust_ctx_create", "dust_ctx_destroy", "dust_ctx_set_arith", "dust_ctx_set_tile",
+EXPORTS = ["dust_ctx_create", "dust_ctx_destroy", "dust_ctx_set_arith", "dust_ctx_set_deterministic",
+           "dust_ctx_set_tile",
            "dust_ctx_grid_size", "dust_ctx_status", "dust_last_error", "dust_bin", "dust_bin_noalloc",
            "dust_fill_ghosts", "dust_gather", "dust_push_expmid", "dust_deposit",
            "dust_fold_ghosts", "dust_apply_feedback", "dust_step", "dust_ctx_set_profile",
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.c_int, i32, i32, _dp, _dp, ctypes.c_int]
     L.dust_ctx_destroy.argtypes = [_vp]
     L.dust_ctx_set_arith.argtypes = [_vp, i32]
+    L.dust_ctx_set_deterministic.argtypes = [_vp, i32]
     L.dust_ctx_set_tile.argtypes = [_vp, i32, i32, i32, i32]
     L.dust_ctx_grid_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -256,6 +258,11 @@ class Context:
         if arith not in ("f32", "f64"):
             raise ValueError(f"arith must be 'f32' or 'f64', not {arith!r}")
         _check(load_library().dust_ctx_set_arith(self.handle, ARITH_F32 if arith == "f32" else ARITH_F64))
+
+    def set_deterministic(self, on: bool = True):
+        """Deterministic mode: the same bits on every run (unfused step,
+        sorted deposit without float atomics, fixed-order sums)."""
+        _check(load_library().dust_ctx_set_deterministic(self.handle, 1 if on else 0))
 
     def set_tile(self, tx=0, ty=0, tz=0, slack=0):
         _check(load_library().dust_ctx_set_tile(self.handle, tx, ty, tz, slack))
