@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time the eager loop, not the graph")
     ap.add_argument("--arith", choices=("f64", "f32"), default=None,
                     help="per-particle arithmetic of the FP32-storage path (default: the "
-                         "context's, FP32 for Cartesian boxes)")
+                         "context's, FP32)")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="particles the oracle steps for the CPU baseline (configs 2-4)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -478,11 +478,11 @@ def _clone(d):
 
 def curvilinear(args, W):
     """The cylindrical (256x512x64, 2^25 particles) and spherical
-    (256x128x512, 2^26) disks with the default FP64 per-particle arithmetic
-    and with the FP32 one (FP32 storage both): time per step and one step's
-    parity against the oracle on a particle sample, so that the cost of the
-    FP64 default is on record.  Fixed tile shape and rebinning interval (the
-    autotuner's picks at full size), 10 timed steps."""
+    (256x128x512, 2^26) disks with FP64 per-particle arithmetic and with the
+    default FP32 one (FP32 storage both): time per step and one step's
+    parity against the oracle on a particle sample.  Fixed tile shape and
+    rebinning interval (the autotuner's picks at full size), 10 timed
+    steps."""
     import copy
     res = {}
     for cfg, tile, rebin in ((3, "4,16,4,0", 3), (4, "4,16,4,0", 2)):
@@ -529,7 +529,7 @@ def run_config(cfg: int, args, extra: bool, K: int, W: int, arith_override=None)
     N = w.n
     C = sum(int(np.prod(b["n"][:b["ndim"]])) for b in w.boxes)
     ctx = dust.context_for(w)
-    arith = arith_override or args.arith or ("f32" if w.boxes[0]["geom"] == "cart" else "f64")
+    arith = arith_override or args.arith or "f32"
     if dtype == "f32":
         ctx.set_arith(arith)
     tx, ty, tz, slack = (int(v) for v in args.tile.split(","))

@@ -198,17 +198,21 @@ dust_status_t dust_ctx_create(void **ctx, int device, const dust_box_t *boxes, i
 dust_status_t dust_ctx_destroy(void *ctx);
 
 /* Per-particle arithmetic of an F32 context in the fused step and in the
- * stage calls (dust_gather, dust_push_expmid, dust_deposit).
- * DUST_ARITH_F32 (default for Cartesian boxes): FP32 registers; the fused
- * kernel forms the slip p_g - p as a weighted sum of differences, which keeps
- * its relative accuracy where the velocities are much larger than the slip.
- * DUST_ARITH_F64 (default for cylindrical and spherical boxes): FP64
- * registers, the stored state staying FP32; needed where a particle close to
- * co-rotation has a slip far below the FP32 resolution of its angular
- * momentum.
- * The unfused chain of dust_step always computes in FP64 (its gathered
- * velocities and impulses pass through memory).  Ignored for F64 contexts.
- * Returns DUST_EINVAL for another value. */
+ * stage calls (dust_gather, dust_push_expmid, dust_deposit, dust_drag_source,
+ * dust_deposit_mass).
+ * DUST_ARITH_F32: FP32 registers.  The fused kernel forms the slip p_g - p
+ * (Eq. Delta_vp) as a weighted sum of differences, which keeps its relative
+ * accuracy where the velocities are much larger than the slip; in
+ * cylindrical and spherical boxes the scale factors (R, R sin theta; App. B.2)
+ * are FP64 values at the particle carried as two FP32 words, and the
+ * azimuthal component's gather sums in FP64 with FP64 radial weights, so
+ * that the slip of a particle close to co-rotation keeps its accuracy.
+ * DUST_ARITH_F64: FP64 registers, the stored state staying FP32.
+ * Defaults: FP32 for the fused step in every geometry; for the stage calls
+ * FP32 in Cartesian boxes and FP64 in cylindrical and spherical ones (they
+ * form the slip from a gathered velocity passed through memory).  This call
+ * sets both.  The unfused chain of dust_step always computes in FP64.
+ * Ignored for F64 contexts.  Returns DUST_EINVAL for another value. */
 dust_status_t dust_ctx_set_arith(void *ctx, int32_t arith);
 
 /* Deterministic mode (on = 1; 0, the default, turns it off): every result

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "dust_fused.h"
@@ -46,7 +47,8 @@ struct GraphKey {
 struct Ctx {
   int device = 0;
   int prec = DUST_F32;
-  int arith = DUST_ARITH_F32;
+  int arith = DUST_ARITH_F32;        // per-particle arithmetic of the step
+  int stage_arith = DUST_ARITH_F32;  // of the stage calls (gather, push, deposit, sources)
   int drag_mode = DUST_DRAG_TAU;
   Species species{};
   Species* species_d = nullptr;
@@ -725,11 +727,18 @@ dust_status_t run_steps(Ctx* c, dust_particles_t* p, dust_fields_t* f, double dt
   return DUST_OK;
 }
 
+// Typed dispatch on the storage precision and an arithmetic (DUST_ARITH_*).
+template <typename F>
+dust_status_t dispatch_arith(Ctx* c, int arith, F&& fn) {
+  if (c->prec == DUST_F64) return fn((double)0, (double)0);
+  if (arith == DUST_ARITH_F32) return fn((float)0, (float)0);
+  return fn((float)0, (double)0);
+}
+
+// The stage calls' dispatch.
 template <typename F>
 dust_status_t dispatch(Ctx* c, F&& fn) {
-  if (c->prec == DUST_F64) return fn((double)0, (double)0);
-  if (c->arith == DUST_ARITH_F32) return fn((float)0, (float)0);
-  return fn((float)0, (double)0);
+  return dispatch_arith(c, c->stage_arith, std::forward<F>(fn));
 }
 
 }  // namespace
@@ -810,12 +819,15 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
       dust_ctx_destroy(c);
       return fail(DUST_EUNSUPPORTED, "all boxes of a context must share geometry and ndim");
     }
-  // FP32 push arithmetic where the slip form keeps the slip accurate
-  // (Cartesian boxes, where large velocities come from a smooth background
-  // flow that the weights reproduce); FP64 in curvilinear boxes, where a
-  // particle close to co-rotation has a slip far below the FP32 resolution
-  // of its angular momentum
-  c->arith = c->geom == GEOM_CART ? DUST_ARITH_F32 : DUST_ARITH_F64;
+  // FP32 push arithmetic in the step: its slip form keeps the slip accurate
+  // (in Cartesian boxes the large velocities come from a smooth background
+  // flow that the weights reproduce; in curvilinear boxes the scale factors
+  // are two-word FP64 values at the particle and the azimuthal gather sums
+  // in FP64).  The stage calls form the slip from a gathered velocity passed
+  // through memory, which in curvilinear boxes loses the slip of a particle
+  // close to co-rotation in FP32: FP64 there.
+  c->arith = DUST_ARITH_F32;
+  c->stage_arith = c->geom == GEOM_CART ? DUST_ARITH_F32 : DUST_ARITH_F64;
   c->unif = c->geom == GEOM_CART ? 1 : 0;
   for (int b = 0; b < nbox; ++b)
     for (int d = 0; d < c->ndim; ++d)
@@ -876,6 +888,7 @@ dust_status_t dust_ctx_set_arith(void* ctx, int32_t arith) {
   if (check_ctx(ctx)) return DUST_EINVAL;
   if (arith != DUST_ARITH_F64 && arith != DUST_ARITH_F32) return fail(DUST_EINVAL, "unknown arith %d", arith);
   ((Ctx*)ctx)->arith = arith;
+  ((Ctx*)ctx)->stage_arith = arith;
   return DUST_OK;
 }
 
@@ -1292,7 +1305,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   launch_set_time(c->tdev, frc->t, st);
   auto body = [&]() -> dust_status_t {
     c->prof_used = 0;
-    return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
+    return dispatch_arith(c, c->arith, [&](auto ts, auto ta) -> dust_status_t {
       using TS = decltype(ts);
       using A = decltype(ta);
       return run_steps<TS, A>(c, p, f, dt, F, nsteps, flags, st);
@@ -1318,6 +1331,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
   put(&flags, sizeof(flags));
   put(&st, sizeof(st));
   put(&c->arith, sizeof(c->arith));
+  put(&c->stage_arith, sizeof(c->stage_arith));
   put(&c->tile, sizeof(c->tile));
   put(&c->rebin_default, sizeof(c->rebin_default));
   put(&c->plan.tiles_d, sizeof(c->plan.tiles_d));

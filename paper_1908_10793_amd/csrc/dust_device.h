@@ -423,8 +423,8 @@ __device__ __forceinline__ void where(const Box& b, const int idx[3], const A of
 // of u and sc.  In FP32 a particle close to co-rotation has a slip a
 // thousand times below u, where one FP32 word for u or sc (6e-8 relative)
 // would leave 6e-5 in the slip; so in FP32 both are carried as unevaluated
-// pairs hi + lo: sc from its FP64 cell-centre value (split in two words)
-// plus the offset term, and u = l / sc with its remainder formed by an FMA.
+// pairs hi + lo: sc evaluated in FP64 at the particle and split in two
+// words, and u = l / sc with its remainder formed by an FMA.
 // up: the hi part of u, which the gather subtracts from every v_i (those
 // differences are exact for close values); ulo, shi, slo: what
 // slip_canonical needs.  In FP64, and for Cartesian or radial components,
@@ -444,29 +444,30 @@ __device__ __forceinline__ void slip_scale(const Box& b, const int idx[3], const
     q.slo[m] = A(0);
   }
   if constexpr (GEOM != GEOM_CART && sizeof(A) == 4) {
-    // radius: FP64 cell centre split in two words, plus the offset term
-    const double rc = cell_centre<double, U>(b.ax[0], idx[0]);
-    const float rh = float(rc);
-    const float rl = float(rc - double(rh)) + off[0] * cell_width<float, U>(b.ax[0], idx[0]);
+    // the particle's radius in FP64 (cell centre plus offset), split in two
+    // words: an FP32 offset term would be off by up to half an ulp of half a
+    // cell width, which the slip of a particle close to co-rotation does not
+    // tolerate
+    const double R = fma(double(off[0]), cell_width<double, U>(b.ax[0], idx[0]),
+                         cell_centre<double, U>(b.ax[0], idx[0]));
+    const float rh = float(R);
     q.shi[1] = rh;
-    q.slo[1] = rl;
+    q.slo[1] = float(R - double(rh));
     if constexpr (GEOM == GEOM_SPH) {
       // sin(theta_c + d) = S + (S (cos d - 1) + C sin d), S and C from the
-      // FP64 table of cell centres, d = offset * width below a cell width
+      // FP64 table of cell centres, with series in d, |d| below half a cell
+      // (truncated at d^7 / 5040: below 1e-12 for cells up to 0.1 rad), and
+      // R sin(theta) in FP64
       const double* tg = b.ax[1].trig + 2 * (idx[1] + 1);
       const double S = tg[0], C = tg[1];
-      const float d = off[1] * cell_width<float, U>(b.ax[1], idx[1]);
-      const float d2 = d * d;
-      const float sd = d * (1.0f - d2 * (1.0f / 6.0f));
-      const float cm1 = -0.5f * d2 * (1.0f - d2 * (1.0f / 12.0f));
-      const float sh = float(S);
-      const float sl = float(S - double(sh)) + (sh * cm1 + float(C) * sd);
-      // (rh + rl)(sh + sl): the product of the high words and its exact
-      // rounding error, plus the other three products (the low words are
-      // up to a few percent of the high ones: none is negligible)
-      const float p = rh * sh;
-      q.shi[2] = p;
-      q.slo[2] = fmaf(rh, sh, -p) + (rh * sl + rl * (sh + sl));
+      const double d = double(off[1]) * cell_width<double, U>(b.ax[1], idx[1]);
+      const double d2 = d * d;
+      const double sd = d * (1.0 - d2 * (1.0 / 6.0) * (1.0 - d2 * (1.0 / 20.0)));
+      const double cm1 = -0.5 * d2 * (1.0 - d2 * (1.0 / 12.0) * (1.0 - d2 * (1.0 / 30.0)));
+      const double pr = R * (S + (S * cm1 + C * sd));
+      const float ph = float(pr);
+      q.shi[2] = ph;
+      q.slo[2] = float(pr - double(ph));
     }
 #pragma unroll
     for (int m = 1; m < 3; ++m) {

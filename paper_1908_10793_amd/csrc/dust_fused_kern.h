@@ -354,6 +354,10 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // weights at x^{n+1/2}
     Stencil<A> s;
     stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
+    constexpr bool AZ = az_gather<A, GEOM>();
+    constexpr int PHI = az_comp<GEOM>();
+    double wr[3] = {0.0, 0.0, 0.0};
+    if constexpr (AZ) radial_weights64<A, GEOM, U>(B, idx[0], off[0], s, wr);
     // cell of the particle relative to this thread's cell
     const int sx = la - (lx + H), sy = lb - (ly + H), sz = c2 ? lc - (lz + HZ) : 0;
     const bool near = sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1 && sz >= -1 && sz <= 1;
@@ -369,6 +373,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     slip_scale<A, GEOM, NDIM, U>(B, idx, off, mom, wh, ss);
     const A* up = ss.up;
     A v[3] = {A(0), A(0), A(0)};
+    double vaz = 0.0;   // azimuthal component in FP64 (AZ)
     // (always true here; kept as a branch, which bounds how far the compiler
     // hoists the window reads and so the register use)
     if (la >= 1) {
@@ -379,6 +384,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         for (int bb = -1; bb <= 1; ++bb) {
           const int r0 = base + RX * (bb + RY * c);
           A u[3] = {A(0), A(0), A(0)};
+          double uaz = 0.0;
 #pragma unroll
           for (int a = -1; a <= 1; ++a) {
             const G4 g = gas[r0 + a];
@@ -386,12 +392,15 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 #pragma unroll
             for (int m = 0; m < nc; ++m) u[m] += s.w[0][a + 1] * (A(gv[m]) - up[m]);
             if (nc > 1) u[1] += s.w[0][a + 1] * A(g.w);   // low word (shear x ghosts only)
+            if constexpr (AZ) uaz += wr[a + 1] * (double(gv[PHI]) - double(up[PHI]));
           }
           const A wbc = s.w[1][bb + 1] * s.w[2][c + 1];
 #pragma unroll
           for (int m = 0; m < nc; ++m) v[m] += wbc * u[m];
+          if constexpr (AZ) vaz += (double(s.w[1][bb + 1]) * double(s.w[2][c + 1])) * uaz;
         }
     }
+    if constexpr (AZ) v[PHI] = A(vaz);   // (the FP32 sum of that component is dropped)
     // kick
     A sl[3];
 #pragma unroll
@@ -656,12 +665,17 @@ __global__ void __launch_bounds__(256)
     if (alive) {
       Stencil<A> s;
       stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
+      constexpr bool AZ = az_gather<A, GEOM>();
+      constexpr int PHI = az_comp<GEOM>();
+      double wr[3] = {0.0, 0.0, 0.0};
+      if constexpr (AZ) radial_weights64<A, GEOM, U>(B, idx[0], off[0], s, wr);
       Where<A> wh;
       where<A, GEOM, NDIM, U>(B, idx, off, wh);
       SlipScale<A> ss;
       slip_scale<A, GEOM, NDIM, U>(B, idx, off, mom, wh, ss);
       const A* up = ss.up;
       A v[3] = {A(0), A(0), A(0)};
+      double vaz = 0.0;   // azimuthal component in FP64 (AZ)
       // The stencil's field values are loaded unconditionally, so that the
       // loads issue together; x ghosts of a shear-periodic box then take the
       // FP64 ghost layer's value (a rare branch).
@@ -688,9 +702,16 @@ __global__ void __launch_bounds__(256)
           for (int a = -1; a <= 1; ++a) {
             const A w = s.w[0][a + 1] * s.w[1][bb + 1] * s.w[2][c + 1];
 #pragma unroll
-            for (int m = 0; m < nc; ++m) v[m] += w * A(g[a + 1][m] - double(up[m]));
+            for (int m = 0; m < nc; ++m) {
+              if (AZ && m == PHI) continue;
+              v[m] += w * A(g[a + 1][m] - double(up[m]));
+            }
+            if constexpr (AZ)
+              vaz += wr[a + 1] * (double(s.w[1][bb + 1]) * double(s.w[2][c + 1])) *
+                     (g[a + 1][PHI] - double(up[PHI]));
           }
         }
+      if constexpr (AZ) v[PHI] = A(vaz);
       A sl[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) sl[m] = m < nc ? slip_canonical<A, GEOM>(ss, m, v[m]) : A(0);

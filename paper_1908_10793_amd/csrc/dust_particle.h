@@ -120,6 +120,27 @@ __device__ __forceinline__ void stencil_weights(const Box& B, const int idx[3], 
 }
 
 
+// FP32 arithmetic in cylindrical and spherical boxes: the azimuthal gas
+// velocity spreads over a particle's stencil by about the radial cell width
+// over the radius (it varies mostly with radius), far above the slip of a
+// particle close to co-rotation, so FP32 radial weights (a few ulp) and an
+// FP32 sum would leave errors of that size in the slip.  That component's
+// gather therefore sums in FP64 with FP64 radial weights (the other axes'
+// weights, exact FP32 values, enter as doubles); every other component
+// keeps the FP32 gather.
+template <typename A, int GEOM> __host__ __device__ constexpr bool az_gather() {
+  return sizeof(A) == 4 && GEOM != GEOM_CART;
+}
+template <int GEOM> __host__ __device__ constexpr int az_comp() { return GEOM == GEOM_SPH ? 2 : 1; }
+
+// Radial weights in FP64 for that gather, also rounded into s.w[0].
+template <typename A, int GEOM, bool U>
+__device__ __forceinline__ void radial_weights64(const Box& B, int i, A off0, Stencil<A>& s, double wr[3]) {
+  axis_weights<double, axis_kind(GEOM, 0), U>(B.ax[0], i, double(off0), wr);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) s.w[0][q] = A(wr[q]);
+}
+
 // Tile-major key of active cell `local` of box B: tiles in x-fastest order,
 // cells x-fastest inside a tile (tiles clipped at the box edges), plus the
 // box's first cell id.
