@@ -575,7 +575,7 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
   DiagDev* dg = (flags & DUST_STEP_DIAG) ? c->diag : nullptr;
   DiagDev* dflags = c->diag;  // sticky flags always recorded
   if (!(flags & DUST_STEP_NO_FILL))
-    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
+    launch_fill<TS>(c->boxes.data(), c->nbox, c->boxes_d, F, c->tdev, 0.5 * dt, fv, c->xg, st);
   launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, 0.5 * dt, 1, dflags, st);
   launch_gather<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv,
@@ -590,10 +590,10 @@ void unfused_step(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const Forces
     launch_deposit<TS, A, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fv, cimp, dflags, st);
   launch_drift<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, F, 0.5 * dt, c->tdev, dt, 0, dflags, st);
   if (dg)
-    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, c->grid_part, st);
-  for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+    launch_grid_sums<TS>(c->boxes.data(), c->nbox, c->boxes_d, fv, dg, c->grid_part, st);
+  launch_fold<TS>(c->boxes.data(), c->nbox, c->boxes_d, F, c->tdev, 0.5 * dt, fv, st);
   if (flags & DUST_STEP_APPLY_FEEDBACK)
-    for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
+    launch_feedback<TS>(c->boxes.data(), c->nbox, c->boxes_d, fv, st);
 }
 
 // How a fused step moves the particles between the caller's arrays and the
@@ -657,7 +657,7 @@ dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const F
   }
   const PView<TS>& out = mv == STEP_IN_PLACE ? x : y;
   if (!(flags & DUST_STEP_NO_FILL))
-    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.5 * dt, fv, c->xg, st);
+    launch_fill<TS>(c->boxes.data(), c->nbox, c->boxes_d, F, c->tdev, 0.5 * dt, fv, c->xg, st);
   launch_clear_deposits<TS>(fv, nc + 1, c->n_stored, st);
   const bool prof = c->prof_used < c->prof_max;
   hipEvent_t ev0 = prof ? c->prof_ev[2 * c->prof_used] : nullptr;
@@ -676,10 +676,10 @@ dust_status_t fused_step(Ctx* c, const PView<TS>& x, const PView<TS>& y, const F
   HIP_TRY(hipGetLastError());
   if (prof) ++c->prof_used;
   if (dg)
-    for (auto& B : c->boxes) launch_grid_sums<TS>(B, fv, dg, c->grid_part, st);
-  for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.5 * dt, fv, st);
+    launch_grid_sums<TS>(c->boxes.data(), c->nbox, c->boxes_d, fv, dg, c->grid_part, st);
+  launch_fold<TS>(c->boxes.data(), c->nbox, c->boxes_d, F, c->tdev, 0.5 * dt, fv, st);
   if (flags & DUST_STEP_APPLY_FEEDBACK)
-    for (auto& B : c->boxes) launch_feedback<TS>(B, fv, st);
+    launch_feedback<TS>(c->boxes.data(), c->nbox, c->boxes_d, fv, st);
   return DUST_OK;
 }
 
@@ -842,7 +842,7 @@ dust_status_t dust_ctx_create(void** ctx, int device, const dust_box_t* boxes, i
       hipMemcpy(c->species_d, &c->species, sizeof(Species), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc((void**)&c->boxes_d, sizeof(Box) * nbox) != hipSuccess ||
       hipMalloc((void**)&c->diag, sizeof(DiagDev)) != hipSuccess ||
-      hipMalloc((void**)&c->grid_part, sizeof(double) * 4 * GRID_SUM_BLOCKS) != hipSuccess ||
+      hipMalloc((void**)&c->grid_part, sizeof(double) * 4 * GRID_SUM_PARTS) != hipSuccess ||
       (c->xg_words && hipMalloc((void**)&c->xg, sizeof(double) * c->xg_words) != hipSuccess) ||
       hipMalloc((void**)&c->tdev, 64) != hipSuccess) {
     dust_ctx_destroy(c);
@@ -1060,7 +1060,7 @@ dust_status_t dust_fill_ghosts(void* ctx, dust_fields_t* f, const dust_forces_t*
   return dispatch(c, [&](auto ts, auto) -> dust_status_t {
     using TS = decltype(ts);
     FView<TS> fv = fview<TS>(f);
-    for (auto& B : c->boxes) launch_fill<TS>(B, F, c->tdev, 0.0, fv, c->xg, st);
+    launch_fill<TS>(c->boxes.data(), c->nbox, c->boxes_d, F, c->tdev, 0.0, fv, c->xg, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -1080,7 +1080,7 @@ dust_status_t dust_fold_ghosts(void* ctx, dust_fields_t* f, const dust_forces_t*
   return dispatch(c, [&](auto ts, auto) -> dust_status_t {
     using TS = decltype(ts);
     FView<TS> fv = fview<TS>(f);
-    for (auto& B : c->boxes) launch_fold<TS>(B, F, c->tdev, 0.0, fv, st);
+    launch_fold<TS>(c->boxes.data(), c->nbox, c->boxes_d, F, c->tdev, 0.0, fv, st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });
@@ -1261,7 +1261,7 @@ dust_status_t dust_apply_feedback(void* ctx, dust_fields_t* f, void* stream) {
   c->last_stream = st;
   return dispatch(c, [&](auto ts, auto) -> dust_status_t {
     using TS = decltype(ts);
-    for (auto& B : c->boxes) launch_feedback<TS>(B, fview<TS>(f), st);
+    launch_feedback<TS>(c->boxes.data(), c->nbox, c->boxes_d, fview<TS>(f), st);
     HIP_TRY(hipGetLastError());
     return DUST_OK;
   });

@@ -64,9 +64,18 @@ __global__ void __launch_bounds__(256)
   int64_t ps;
   const WaveLevels wl = c3_layout(td, lc, bin_start, ps);
   uint32_t lvl = wl.base;
-  for (int j = 0; j < wl.nlev; ++j) {
-    const uint32_t to = level_slot(wl, j, lvl);
-    if (wl.cnt > j) lm[to] = perm[ps + j];
+  // four levels at a time: a lane's four sources share a cache line, and
+  // their loads issue together
+  for (int j0 = 0; j0 < wl.nlev; j0 += 4) {
+    uint32_t src[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) src[q] = wl.cnt > j0 + q ? perm[ps + j0 + q] : 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (j0 + q >= wl.nlev) break;   // (wave-uniform)
+      const uint32_t to = level_slot(wl, j0 + q, lvl);
+      if (wl.cnt > j0 + q) lm[to] = src[q];
+    }
   }
 }
 

@@ -680,14 +680,39 @@ template <typename TS> struct Arr4 {
   TS* a[4];
 };
 
+// One launch of a per-box kernel over several boxes: box[e] takes blocks
+// [blk0[e], blk0[e+1]) of the grid (up to MB_BOXES boxes per launch); a
+// block finds its entry by a scan of blk0 and reads its box descriptor from
+// the device table (a block-uniform address).
+static constexpr int MB_BOXES = 16;
+static_assert(GRID_SUM_PARTS >= GRID_SUM_BLOCKS + MB_BOXES, "grid-sum partials");
+struct BoxGrid {
+  int n;
+  int box[MB_BOXES];
+  uint32_t blk0[MB_BOXES + 1];
+};
+__device__ __forceinline__ int grid_entry(const BoxGrid& g) {
+  int e = 0;
+  while (e + 1 < g.n && blockIdx.x >= g.blk0[e + 1]) ++e;
+  return e;
+}
+// thread index within the box's range
+__device__ __forceinline__ int64_t grid_thread(const BoxGrid& g, int e) {
+  return (int64_t)(blockIdx.x - g.blk0[e]) * blockDim.x + threadIdx.x;
+}
+
 // x ghosts of one box: shear-periodic (interpolated in y) or periodic.
 template <typename TS>
-__global__ void k_fill_x(Box B, Arr4<TS> arrs, int vy_slot, double qOmega, const double* tdev,
-                         double toff, int shear) {
+__global__ void k_fill_x(const Box* boxes, BoxGrid bg, Arr4<TS> arrs, int boost, double qOmega,
+                         const double* tdev, double toff) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
+  const int shear = B.ax[0].bc_lo == BC_SHEAR;
+  const int vy_slot = B.geom == GEOM_CART && boost ? 2 : -1;
   TS* a = arrs.a[blockIdx.y];
   const int comp_vy = (int)blockIdx.y == vy_slot;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)n1 * n2) return;
   const Shift sh = make_shift(B, qOmega, *tdev + toff);
   int j = (int)(t % n1), k = (int)(t / n1);
@@ -718,13 +743,15 @@ __global__ void k_fill_x(Box B, Arr4<TS> arrs, int vy_slot, double qOmega, const
 // boosted ghost values keep their FP64 rounding, so that a particle next to
 // the shear boundary sees the gas at the accuracy of the interior values.
 template <typename TS>
-__global__ void k_fill_xghost(Box B, Arr4<TS> vel, double* xg, double qOmega, const double* tdev,
-                              double toff, int boost) {
+__global__ void k_fill_xghost(const Box* boxes, BoxGrid bg, Arr4<TS> vel, double* xg, double qOmega,
+                              const double* tdev, double toff, int boost) {
+  const int ge = grid_entry(bg);
+  const Box& B = boxes[bg.box[ge]];
   const int m = blockIdx.y, comp_vy = boost && m == 1;
   const TS* a = vel.a[m];
   const int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
   const int g1 = n1 + 2, g2 = n2 + 2;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = grid_thread(bg, ge);
   if (t >= (int64_t)g1 * g2) return;
   const Shift sh = make_shift(B, qOmega, *tdev + toff);
   const int jg = (int)(t % g1), kg = (int)(t / g1);
@@ -744,30 +771,36 @@ __global__ void k_fill_xghost(Box B, Arr4<TS> vel, double* xg, double qOmega, co
   xg[B.xg_base + (1 * 3 + m) * layer + t] = right;
 }
 
-template <typename TS> __global__ void k_fill_y(Box B, Arr4<TS> arrs) {
+template <typename TS> __global__ void k_fill_y(const Box* boxes, BoxGrid bg, Arr4<TS> arrs) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
   TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)(n0 + 2) * n2) return;
   int i = (int)(t % (n0 + 2)) - 1, k = (int)(t / (n0 + 2));
   a[stored_index(B, i, -1, k)] = a[stored_index(B, i, n1 - 1, k)];
   a[stored_index(B, i, n1, k)] = a[stored_index(B, i, 0, k)];
 }
 
-template <typename TS> __global__ void k_fill_z(Box B, Arr4<TS> arrs) {
+template <typename TS> __global__ void k_fill_z(const Box* boxes, BoxGrid bg, Arr4<TS> arrs) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
   TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)(n0 + 2) * (n1 + 2)) return;
   int i = (int)(t % (n0 + 2)) - 1, j = (int)(t / (n0 + 2)) - 1;
   a[stored_index(B, i, j, -1)] = a[stored_index(B, i, j, n2 - 1)];
   a[stored_index(B, i, j, n2)] = a[stored_index(B, i, j, 0)];
 }
 
-template <typename TS> __global__ void k_fold_z(Box B, Arr4<TS> arrs) {
+template <typename TS> __global__ void k_fold_z(const Box* boxes, BoxGrid bg, Arr4<TS> arrs) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
   TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ax[2].n;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)(n0 + 2) * (n1 + 2)) return;
   int i = (int)(t % (n0 + 2)) - 1, j = (int)(t / (n0 + 2)) - 1;
   int64_t gl = stored_index(B, i, j, -1), gh = stored_index(B, i, j, n2);
@@ -777,10 +810,12 @@ template <typename TS> __global__ void k_fold_z(Box B, Arr4<TS> arrs) {
   a[gh] = TS(0);
 }
 
-template <typename TS> __global__ void k_fold_y(Box B, Arr4<TS> arrs) {
+template <typename TS> __global__ void k_fold_y(const Box* boxes, BoxGrid bg, Arr4<TS> arrs) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
   TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)(n0 + 2) * n2) return;
   int i = (int)(t % (n0 + 2)) - 1, k = (int)(t / (n0 + 2));
   int64_t gl = stored_index(B, i, -1, k), gh = stored_index(B, i, n1, k);
@@ -793,12 +828,17 @@ template <typename TS> __global__ void k_fold_y(Box B, Arr4<TS> arrs) {
 // x fold, written as a gather over the ghost rows that feed each partner
 // cell (no atomics).  The energy channel (e != NULL) gains +/- u D_y.
 template <typename TS>
-__global__ void k_fold_x(Box B, Arr4<TS> arrs, const TS* dy, int energy_slot, double qOmega,
-                         const double* tdev, double toff, int shear) {
+__global__ void k_fold_x(const Box* boxes, BoxGrid bg, Arr4<TS> arrs, const TS* dy, int boost_energy,
+                         double qOmega, const double* tdev, double toff) {
+  const int ge = grid_entry(bg);
+  const Box& B = boxes[bg.box[ge]];
+  const int shear = B.ax[0].bc_lo == BC_SHEAR;
+  const int nch = B.geom == GEOM_CART ? B.ndim : 3;
+  const int energy_slot = shear && boost_energy ? nch : -1;
   TS* a = arrs.a[blockIdx.y];
   const int is_energy = (int)blockIdx.y == energy_slot;
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, ge);
   if (t >= (int64_t)n1 * n2) return;
   const Shift sh = make_shift(B, qOmega, *tdev + toff);
   int jt = (int)(t % n1), k = (int)(t / n1);
@@ -833,10 +873,12 @@ __global__ void k_fold_x(Box B, Arr4<TS> arrs, const TS* dy, int energy_slot, do
   a[stored_index(B, n0 - 1, jt, k)] += TS(addn);
 }
 
-template <typename TS> __global__ void k_clear_x_ghosts(Box B, Arr4<TS> arrs) {
+template <typename TS> __global__ void k_clear_x_ghosts(const Box* boxes, BoxGrid bg, Arr4<TS> arrs) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
   TS* a = arrs.a[blockIdx.y];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)n1 * n2) return;
   int j = (int)(t % n1), k = (int)(t / n1);
   a[stored_index(B, -1, j, k)] = TS(0);
@@ -867,10 +909,12 @@ template <typename TS> __global__ void k_fill_value(TS* a, int64_t n, TS v) {
   if (i < n) a[i] = v;
 }
 
-// v_c += D_c / (rho s_c) on active cells of one box.
-template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
+// v_c += D_c / (rho s_c) on the active cells of the boxes.
+template <typename TS> __global__ void k_feedback(const Box* boxes, BoxGrid bg, FView<TS> fl) {
+  const int e = grid_entry(bg);
+  const Box& B = boxes[bg.box[e]];
   int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = grid_thread(bg, e);
   if (t >= (int64_t)n0 * n1 * n2) return;
   int idx[3];
   unravel(B, t, idx);   // (active cell counts are below 2^31)
@@ -890,17 +934,21 @@ template <typename TS> __global__ void k_feedback(Box B, FView<TS> fl) {
   }
 }
 
-// FP64 sums of dV D over every stored cell of one box: a grid-stride loop,
-// a block reduction into the block's slot of `part`, then one workgroup adds
-// the slots in a fixed order (no contended atomics, deterministic).
+// FP64 sums of dV D over every stored cell of the boxes: a grid-stride loop
+// over each box's blocks, a block reduction into the block's slot of
+// `part`, then one workgroup adds the slots in a fixed order (no contended
+// atomics, deterministic).
 template <typename TS>
-__global__ void __launch_bounds__(256) k_grid_sums(Box B, FView<TS> fl, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_grid_sums(const Box* boxes, BoxGrid bg, FView<TS> fl,
+                                                   double* __restrict__ part) {
   __shared__ double red[4][4];
+  const int ge = grid_entry(bg);
+  const Box& B = boxes[bg.box[ge]];
   const int nc = B.geom == GEOM_CART ? B.ndim : 3;
   const double inv_g0 = 1.0 / B.g0, inv_g1 = 1.0 / B.g1;
   double s[4] = {0, 0, 0, 0};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < B.nstore; t += stride) {
+  const int64_t stride = (int64_t)(bg.blk0[ge + 1] - bg.blk0[ge]) * blockDim.x;
+  for (int64_t t = grid_thread(bg, ge); t < B.nstore; t += stride) {
     int i, j, k;
     if (B.nstore < 0x7fffffffLL) {
       int r = div_small((int)t, B.g0, inv_g0);
@@ -1038,75 +1086,138 @@ void launch_mass_density(const PView<TS>& p, const Box* boxes, int nbox, int geo
                                       dim3(256), 0, st, p, boxes, nbox, fl, sp, dg));
 }
 
+// Launches `launch(grid, blocks)` over the boxes b with want(b), each with
+// blocks(b) blocks, MB_BOXES boxes per launch.
+template <typename Want, typename Blocks, typename Launch>
+static void for_box_grids(const Box* hb, int nbox, Want want, Blocks blocks, Launch launch) {
+  BoxGrid g{};
+  uint32_t nb = 0;
+  auto flush = [&]() {
+    if (g.n) {
+      g.blk0[g.n] = nb;
+      launch(g, nb);
+    }
+    g = BoxGrid{};
+    nb = 0;
+  };
+  for (int b = 0; b < nbox; ++b) {
+    if (!want(hb[b])) continue;
+    const uint32_t k = blocks(hb[b]);
+    if (k == 0) continue;
+    g.box[g.n] = b;
+    g.blk0[g.n] = nb;
+    nb += k;
+    if (++g.n == MB_BOXES) flush();
+  }
+  flush();
+}
+
+static inline int box_nc(const Box& B) { return B.geom == GEOM_CART ? B.ndim : 3; }
+static inline int64_t box_n(const Box& B, int d) { return d < B.ndim ? B.ax[d].n : 1; }
+
 template <typename TS>
-void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
-                 double* xg, hipStream_t st) {
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+void launch_fill(const Box* hb, int nbox, const Box* boxes_d, const Forces& f, const double* tdev, double toff,
+                 const FView<TS>& fl, double* xg, hipStream_t st) {
+  if (nbox <= 0) return;
+  const int nc = box_nc(hb[0]);
   const Arr4<TS> arrs{{fl.rho, fl.vel[0], fl.vel[1], fl.vel[2]}};
   const Arr4<TS> vel{{fl.vel[0], fl.vel[1], fl.vel[2], nullptr}};
   const unsigned na = (unsigned)(nc + 1);
   const double qOmega = f.q * f.Omega;
   // the v_y ghosts across a shear face carry the boost -/+ q Omega L_x,
   // except for the residual velocities of orbital advection
-  const bool boost = f.kind == FORCE_SHEARBOX;
-  if (xg && B.xg_base >= 0)
-    hipLaunchKernelGGL((k_fill_xghost<TS>), dim3(blocks_for((int64_t)(n1 + 2) * (n2 + 2)), (unsigned)nc),
-                       dim3(256), 0, st, B, vel, xg, qOmega, tdev, toff, (int)boost);
-  if (B.ax[0].bc_lo != BC_OPEN)
-    hipLaunchKernelGGL((k_fill_x<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st, B, arrs,
-                       B.geom == GEOM_CART && boost ? 2 : -1, qOmega, tdev, toff,
-                       (int)(B.ax[0].bc_lo == BC_SHEAR));
-  if (B.ax[1].bc_lo == BC_PERIODIC)
-    hipLaunchKernelGGL((k_fill_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2), na), dim3(256), 0, st, B,
-                       arrs);
-  if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
-    hipLaunchKernelGGL((k_fill_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2)), na), dim3(256), 0,
-                       st, B, arrs);
+  const int boost = f.kind == FORCE_SHEARBOX;
+  if (xg)
+    for_box_grids(hb, nbox, [](const Box& B) { return B.xg_base >= 0; },
+                  [](const Box& B) { return blocks_for((box_n(B, 1) + 2) * (box_n(B, 2) + 2)); },
+                  [&](const BoxGrid& g, uint32_t nb) {
+                    hipLaunchKernelGGL((k_fill_xghost<TS>), dim3(nb, (unsigned)nc), dim3(256), 0, st, boxes_d, g,
+                                       vel, xg, qOmega, tdev, toff, boost);
+                  });
+  for_box_grids(hb, nbox, [](const Box& B) { return B.ax[0].bc_lo != BC_OPEN; },
+                [](const Box& B) { return blocks_for(box_n(B, 1) * box_n(B, 2)); },
+                [&](const BoxGrid& g, uint32_t nb) {
+                  hipLaunchKernelGGL((k_fill_x<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, arrs, boost,
+                                     qOmega, tdev, toff);
+                });
+  for_box_grids(hb, nbox, [](const Box& B) { return B.ax[1].bc_lo == BC_PERIODIC; },
+                [](const Box& B) { return blocks_for((box_n(B, 0) + 2) * box_n(B, 2)); },
+                [&](const BoxGrid& g, uint32_t nb) {
+                  hipLaunchKernelGGL((k_fill_y<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, arrs);
+                });
+  for_box_grids(hb, nbox, [](const Box& B) { return B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC; },
+                [](const Box& B) { return blocks_for((box_n(B, 0) + 2) * (box_n(B, 1) + 2)); },
+                [&](const BoxGrid& g, uint32_t nb) {
+                  hipLaunchKernelGGL((k_fill_z<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, arrs);
+                });
 }
 
 template <typename TS>
-void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
-                 hipStream_t st) {
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  int n0 = B.ax[0].n, n1 = B.ax[1].n, n2 = B.ndim > 2 ? B.ax[2].n : 1;
+void launch_fold(const Box* hb, int nbox, const Box* boxes_d, const Forces& f, const double* tdev, double toff,
+                 const FView<TS>& fl, hipStream_t st) {
+  if (nbox <= 0) return;
+  const int nc = box_nc(hb[0]);
   const double qOmega = f.q * f.Omega;
   const Arr4<TS> deps{{fl.dep[0], fl.dep[1], fl.dep[2], fl.dep[3]}};
   const unsigned na = (unsigned)(nc + 1);
-  if (B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC)
-    hipLaunchKernelGGL((k_fold_z<TS>), dim3(blocks_for((int64_t)(n0 + 2) * (n1 + 2)), na), dim3(256), 0,
-                       st, B, deps);
-  if (B.ax[1].bc_lo == BC_PERIODIC)
-    hipLaunchKernelGGL((k_fold_y<TS>), dim3(blocks_for((int64_t)(n0 + 2) * n2), na), dim3(256), 0, st, B,
-                       deps);
-  if (B.ax[0].bc_lo != BC_OPEN) {
-    int shear = B.ax[0].bc_lo == BC_SHEAR;
-    // the energy channel reads the D_y ghosts, which no thread of this
-    // launch writes (they are cleared by the next one)
-    // (the energy term of the boost: standard shearing box only)
-    hipLaunchKernelGGL((k_fold_x<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st, B, deps,
-                       (const TS*)fl.dep[B.ndim > 1 ? 1 : 0],
-                       shear && f.kind == FORCE_SHEARBOX ? nc : -1, qOmega, tdev, toff, shear);
-    hipLaunchKernelGGL((k_clear_x_ghosts<TS>), dim3(blocks_for((int64_t)n1 * n2), na), dim3(256), 0, st,
-                       B, deps);
+  for_box_grids(hb, nbox, [](const Box& B) { return B.ndim > 2 && B.ax[2].bc_lo == BC_PERIODIC; },
+                [](const Box& B) { return blocks_for((box_n(B, 0) + 2) * (box_n(B, 1) + 2)); },
+                [&](const BoxGrid& g, uint32_t nb) {
+                  hipLaunchKernelGGL((k_fold_z<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, deps);
+                });
+  for_box_grids(hb, nbox, [](const Box& B) { return B.ax[1].bc_lo == BC_PERIODIC; },
+                [](const Box& B) { return blocks_for((box_n(B, 0) + 2) * box_n(B, 2)); },
+                [&](const BoxGrid& g, uint32_t nb) {
+                  hipLaunchKernelGGL((k_fold_y<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, deps);
+                });
+  // the energy channel reads the D_y ghosts, which no thread of this launch
+  // writes (they are cleared by the next one); the energy term of the boost:
+  // standard shearing box only
+  const TS* dy = fl.dep[hb[0].ndim > 1 ? 1 : 0];
+  const int boost_energy = f.kind == FORCE_SHEARBOX;
+  auto xfold = [](const Box& B) { return B.ax[0].bc_lo != BC_OPEN; };
+  auto xblocks = [](const Box& B) { return blocks_for(box_n(B, 1) * box_n(B, 2)); };
+  for_box_grids(hb, nbox, xfold, xblocks, [&](const BoxGrid& g, uint32_t nb) {
+    hipLaunchKernelGGL((k_fold_x<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, deps, dy, boost_energy,
+                       qOmega, tdev, toff);
+  });
+  for_box_grids(hb, nbox, xfold, xblocks, [&](const BoxGrid& g, uint32_t nb) {
+    hipLaunchKernelGGL((k_clear_x_ghosts<TS>), dim3(nb, na), dim3(256), 0, st, boxes_d, g, deps);
+  });
+}
+
+template <typename TS>
+void launch_feedback(const Box* hb, int nbox, const Box* boxes_d, const FView<TS>& fl, hipStream_t st) {
+  for_box_grids(hb, nbox, [](const Box&) { return true; }, [](const Box& B) { return blocks_for(B.ncell); },
+                [&](const BoxGrid& g, uint32_t nb) {
+                  hipLaunchKernelGGL((k_feedback<TS>), dim3(nb), dim3(256), 0, st, boxes_d, g, fl);
+                });
+}
+
+template <typename TS>
+void launch_grid_sums(const Box* hb, int nbox, const Box* boxes_d, const FView<TS>& fl, DiagDev* dg, double* part,
+                      hipStream_t st) {
+  if (nbox <= 0) return;
+  const int nc = box_nc(hb[0]);
+  // blocks shared out in proportion to the stored cells of each launch's
+  // boxes (at most GRID_SUM_BLOCKS + MB_BOXES in all)
+  for (int b0 = 0; b0 < nbox; b0 += MB_BOXES) {
+    const int b1 = std::min(nbox, b0 + MB_BOXES);
+    int64_t tot = 0;
+    for (int b = b0; b < b1; ++b) tot += hb[b].nstore;
+    if (tot == 0) continue;
+    for_box_grids(hb + b0, b1 - b0, [](const Box& B) { return B.nstore > 0; },
+                  [&](const Box& B) {
+                    const int64_t share = (int64_t)GRID_SUM_BLOCKS * B.nstore / tot;
+                    return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(blocks_for(B.nstore), share));
+                  },
+                  [&](BoxGrid g, uint32_t nb) {
+                    for (int e = 0; e < g.n; ++e) g.box[e] += b0;
+                    hipLaunchKernelGGL((k_grid_sums<TS>), dim3(nb), dim3(256), 0, st, boxes_d, g, fl, part);
+                    hipLaunchKernelGGL(k_reduce_grid_partials, dim3(1), dim3(256), 0, st, (const double*)part,
+                                       (int)nb, nc, dg);
+                  });
   }
-}
-
-template <typename TS>
-void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st) {
-  int64_t n = B.ncell;
-  hipLaunchKernelGGL((k_feedback<TS>), dim3(blocks_for(n)), dim3(256), 0, st, B, fl);
-}
-
-template <typename TS>
-void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, double* part, hipStream_t st) {
-  unsigned nb = blocks_for(B.nstore);
-  if (nb > (unsigned)GRID_SUM_BLOCKS) nb = GRID_SUM_BLOCKS;
-  if (nb == 0) return;
-  hipLaunchKernelGGL((k_grid_sums<TS>), dim3(nb), dim3(256), 0, st, B, fl, part);
-  const int nc = B.geom == GEOM_CART ? B.ndim : 3;
-  hipLaunchKernelGGL(k_reduce_grid_partials, dim3(1), dim3(256), 0, st, (const double*)part, (int)nb,
-                     nc, dg);
 }
 
 template <typename TS> void launch_clear_deposits(const FView<TS>& fl, int nch, int64_t n, hipStream_t st) {
@@ -1154,13 +1265,13 @@ DUST_INST(float, float, float)
 DUST_INST(double, double, double)
 
 #define DUST_INST_GRID(TS)                                                                        \
-  template void launch_fill<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
-                                double*,                                                          \
-                                hipStream_t);                                                     \
-  template void launch_fold<TS>(const Box&, const Forces&, const double*, double, const FView<TS>&, \
-                                hipStream_t);                                                     \
-  template void launch_feedback<TS>(const Box&, const FView<TS>&, hipStream_t);                   \
-  template void launch_grid_sums<TS>(const Box&, const FView<TS>&, DiagDev*, double*, hipStream_t); \
+  template void launch_fill<TS>(const Box*, int, const Box*, const Forces&, const double*, double,   \
+                                const FView<TS>&, double*, hipStream_t);                          \
+  template void launch_fold<TS>(const Box*, int, const Box*, const Forces&, const double*, double,   \
+                                const FView<TS>&, hipStream_t);                                   \
+  template void launch_feedback<TS>(const Box*, int, const Box*, const FView<TS>&, hipStream_t);     \
+  template void launch_grid_sums<TS>(const Box*, int, const Box*, const FView<TS>&, DiagDev*, double*, \
+                                     hipStream_t);                                                \
   template void launch_fill_value<TS>(TS*, int64_t, TS, hipStream_t);                              \
   template void launch_clear_deposits<TS>(const FView<TS>&, int, int64_t, hipStream_t);
 

@@ -67,22 +67,29 @@ template <typename TS, typename A>
 void launch_mass_density(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                          TS* rho_d, const Species* sp, DiagDev* dg, hipStream_t st);
 
-// Ghost fill of the gas of one box at *tdev + toff; with xg (the context's
-// FP64 x-ghost buffer), also the FP64 x-ghost layer of a shear-periodic box.
+// The per-box grid operations below take the host copies of the boxes (hb,
+// nbox; geometry and ndim shared) and their device table, and launch each
+// kernel once for up to 16 boxes.
+// Ghost fill of the gas at *tdev + toff; with xg (the context's FP64 x-ghost
+// buffer), also the FP64 x-ghost layers of shear-periodic boxes.
 template <typename TS>
-void launch_fill(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
-                 double* xg, hipStream_t st);
+void launch_fill(const Box* hb, int nbox, const Box* boxes_d, const Forces& f, const double* tdev, double toff,
+                 const FView<TS>& fl, double* xg, hipStream_t st);
 template <typename TS>
-void launch_fold(const Box& B, const Forces& f, const double* tdev, double toff, const FView<TS>& fl,
-                 hipStream_t st);
+void launch_fold(const Box* hb, int nbox, const Box* boxes_d, const Forces& f, const double* tdev, double toff,
+                 const FView<TS>& fl, hipStream_t st);
 void launch_set_time(double* tdev, double v, hipStream_t st);
 // advance the step time by dt; count: the diagnostics whose step count goes up (or null)
 void launch_advance_time(double* tdev, double dt, DiagDev* count, hipStream_t st);
-template <typename TS> void launch_feedback(const Box& B, const FView<TS>& fl, hipStream_t st);
-// FP64 grid sums of one box; part: GRID_SUM_BLOCKS * 4 doubles of scratch.
-static constexpr int GRID_SUM_BLOCKS = 2048;
 template <typename TS>
-void launch_grid_sums(const Box& B, const FView<TS>& fl, DiagDev* dg, double* part, hipStream_t st);
+void launch_feedback(const Box* hb, int nbox, const Box* boxes_d, const FView<TS>& fl, hipStream_t st);
+// FP64 grid sums of the boxes, added to dg; part: GRID_SUM_PARTS * 4
+// doubles of scratch.
+static constexpr int GRID_SUM_BLOCKS = 2048;
+static constexpr int GRID_SUM_PARTS = GRID_SUM_BLOCKS + 16;
+template <typename TS>
+void launch_grid_sums(const Box* hb, int nbox, const Box* boxes_d, const FView<TS>& fl, DiagDev* dg, double* part,
+                      hipStream_t st);
 template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_t st);
 // Zero the first nch deposit channels over n stored cells (one launch).
 template <typename TS> void launch_clear_deposits(const FView<TS>& fl, int nch, int64_t n, hipStream_t st);
