@@ -414,7 +414,8 @@ def parity_errors(sub, run, st, full_box: bool, tol: float):
             if den > 0:
                 edep = max(edep, float(np.abs(st["dep"][c] - ref).max() / den))
         evel = 0.0
-        act_sl = (slice(1, -1),) * 3
+        # active cells (a missing axis of a 2-D box has extent 1 and no ghosts)
+        act_sl = tuple(slice(1, -1) if g > 1 else slice(None) for g in box.ghosted_shape)
         for c in range(nc):
             ref = fo.vel[c].reshape(box.ghosted_shape)[act_sl]
             got = st["vel"][c].reshape(box.ghosted_shape)[act_sl]
