@@ -227,9 +227,10 @@ dust_status_t dust_ctx_set_arith(void *ctx, int32_t arith);
  * deposit, DRIFT2, fold and feedback give what dust_step gives, bit for bit.
  * Costs a sort per deposit and 3^d weight evaluations per particle; the
  * binned layout of the last fused run is forgotten (dust_drag_source and
- * dust_deposit_mass then take their particle-parallel kernels).  Workspace
- * (sort, partials) grows on first use.  Returns DUST_EINVAL for another
- * value of on. */
+ * dust_deposit_mass then take their particle-parallel kernels), and
+ * dust_ctx_autotune, which times the fused step, returns DUST_EUNSUPPORTED
+ * while the mode is on.  Workspace (sort, partials) grows on first use.
+ * Returns DUST_EINVAL for another value of on. */
 dust_status_t dust_ctx_set_deterministic(void *ctx, int32_t on);
 
 /* Tile shape of the fused path, in cells per axis (0 keeps the current

@@ -1405,6 +1405,8 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
     return fail(DUST_EUNSUPPORTED, "the autotuner times the fused step (exponential midpoint kick)");
   if (c->drag_mode == DUST_DRAG_EPSTEIN)
     return fail(DUST_EUNSUPPORTED, "the autotuner times the fused step (no Epstein drag)");
+  if (c->det)
+    return fail(DUST_EUNSUPPORTED, "the autotuner times the fused step, which the deterministic mode does not run");
   if (flags & ~(DUST_STEP_APPLY_FEEDBACK | DUST_STEP_DIAG | DUST_STEP_NO_FILL))
     return fail(DUST_EINVAL, "autotune flags: only APPLY_FEEDBACK, DIAG, NO_FILL");
   hipStream_t st = (hipStream_t)stream;

@@ -190,3 +190,14 @@ def test_set_deterministic_rejects_other_values():
     L = dust.load_library()
     assert L.dust_ctx_set_deterministic(ctx.handle, 2) == -1   # DUST_EINVAL
     assert L.dust_ctx_set_deterministic(ctx.handle, 0) == 0
+
+
+def test_autotune_is_refused_in_deterministic_mode():
+    dust = _dust()
+    w = workload("shearing_box", "f32")
+    ctx = dust.context_for(w)
+    ctx.set_deterministic(True)
+    P, F = dust.upload(w, ctx)
+    with pytest.raises(dust.DustError) as e:
+        ctx.autotune(P, F, w.dt, dust.forces_for(w), steps=1)
+    assert e.value.code == -5   # DUST_EUNSUPPORTED
