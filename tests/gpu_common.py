@@ -202,6 +202,11 @@ def compare_step(w, st_in, st_out, run: OracleRun, dtype: str, fields_too=True, 
         pg = st_out["mom"][gi][a][:, :nc]
         po = p_o[a][:, :nc]
         p0 = st_in["mom"][sel][a][:, :nc]
+        # |p_g| bound: the largest gas speed over the gather stencil at
+        # x^{n+1/2}, whose cells lie within one cell of the half-step cell,
+        # itself within one cell of the final cell (a half step moves a
+        # particle less than a cell under the dust time step, Eq.
+        # particles_dt): the 5x5x5 cells around the final cell
         vmax = np.max([np.abs(v) for v in st_in["gas"][b]["vel"][:nc]], axis=0)
         vmax = maximum_filter(vmax, size=5, mode="nearest").reshape(box.ghosted_shape)
         ci = O.unravel(box, cl_o)
