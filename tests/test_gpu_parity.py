@@ -84,12 +84,15 @@ def _run(name, fused, nsteps=3, arith=None, tile=None, integrator=None):
 
 @pytest.mark.parametrize("name", WORKLOADS)
 def test_unfused_step_matches_oracle(name):
-    _run(name, fused=False)
+    """Ten steps, each against the oracle from the GPU state before it."""
+    _run(name, fused=False, nsteps=10)
 
 
 @pytest.mark.parametrize("name", WORKLOADS)
 def test_fused_step_matches_oracle(name):
-    _run(name, fused=True)
+    """Ten steps (rebinning every step), each against the oracle from the GPU
+    state before it."""
+    _run(name, fused=True, nsteps=10)
 
 
 def test_fused_with_other_tile_shapes():
