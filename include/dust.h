@@ -216,20 +216,22 @@ dust_status_t dust_ctx_destroy(void *ctx);
 dust_status_t dust_ctx_set_arith(void *ctx, int32_t arith);
 
 /* Deterministic mode (on = 1; 0, the default, turns it off): every result
- * of dust_step, dust_push_expmid and dust_deposit is the same bits on every
- * run with the same inputs.  The deposit of Eq. dust_feedback_final (Sec. 3.1)
- * then runs without float atomics: a stable sort of the particles by cell,
- * then one thread per stored cell sums, in FP64 and in a fixed order, the
- * contributions of the particles of the 3^d cells around it; the kick's
- * diagnostic sums go through per-block partials added in a fixed order.
+ * of dust_step, dust_push_expmid, dust_deposit, dust_drag_source and
+ * dust_deposit_mass is the same bits on every run with the same inputs.
+ * Their deposits (Eq. dust_feedback_final, Sec. 3.1; the predictor's source,
+ * Eq. f_D; the dust density) then run without float atomics: a stable sort
+ * of the particles by cell, then one thread per stored cell sums, in FP64
+ * and in a fixed order, the contributions of the particles of the 3^d cells
+ * around it; the kick's diagnostic sums go through per-block partials added
+ * in a fixed order.
  * dust_step then runs the unfused chain (DUST_STEP_FUSED and the rebinning
  * interval are ignored), so that the stage calls fill, DRIFT1, gather, KICK,
  * deposit, DRIFT2, fold and feedback give what dust_step gives, bit for bit.
  * Costs a sort per deposit and 3^d weight evaluations per particle; the
- * binned layout of the last fused run is forgotten (dust_drag_source and
- * dust_deposit_mass then take their particle-parallel kernels), and
- * dust_ctx_autotune, which times the fused step, returns DUST_EUNSUPPORTED
- * while the mode is on.  Workspace (sort, partials) grows on first use.
+ * binned layout of the last fused run is forgotten, and dust_ctx_autotune,
+ * which times the fused step, returns DUST_EUNSUPPORTED while the mode is
+ * on.  Workspace (sort, partials, per-particle coefficients) grows on first
+ * use.
  * Returns DUST_EINVAL for another value of on. */
 dust_status_t dust_ctx_set_deterministic(void *ctx, int32_t on);
 

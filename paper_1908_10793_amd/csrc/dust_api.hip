@@ -537,15 +537,34 @@ bool scratch_work(void* base, int64_t n, BinWork& w) {
 
 // Deterministic deposit: a stable sort of the particles by cell (into the
 // binning workspace and bin starts, which no longer describe a fused
-// layout), then every box's cells sum their particles' contributions.
+// layout), then every box's cells sum their particles' contributions:
+// out.dep[m] += sgn * sum W q[m] / dV for m < nch (the step's deposit: all
+// channels, sgn = -1).
 template <typename TS, typename A, typename TW>
-void deposit_det(Ctx* c, const PView<TS>& pv, const FView<TS>& fv, const TW* const imp[4], hipStream_t st) {
+void deposit_det(Ctx* c, const PView<TS>& pv, const FView<TS>& out, const TW* const q[4], hipStream_t st,
+                 int nch = -1, double sgn = -1.0) {
+  if (nch < 0) nch = ctx_nc(c) + 1;
   c->bin_cur = launch_bin(pv.cell, pv.n, c->boxes_d, c->nbox, c->n_active, DUST_BIN_CELL, c->tile, c->bin,
                           nullptr, c->bin_start, false, st);
   c->lay_valid = false;
   for (auto& B : c->boxes)
-    launch_deposit_pull<TS, A, TW>(pv, B, c->geom, c->ndim, c->unif, fv, imp, c->bin.val[c->bin_cur],
+    launch_deposit_pull<TS, A, TW>(pv, B, c->geom, c->ndim, c->unif, out, nch, sgn, q, c->bin.val[c->bin_cur],
                                    c->bin_start, st);
+}
+
+// The drag source (mass: the dust density into out.dep[0]) of the
+// deterministic mode: per-particle coefficients into the unfused workspace,
+// then the sorted deposit.
+template <typename TS, typename A>
+void source_det(Ctx* c, const PView<TS>& pv, const FView<TS>& fl, const FView<TS>& out, const Forces& F, double dt,
+                bool mass, hipStream_t st) {
+  const int64_t n = pv.n;
+  A* ws = (A*)c->ws;
+  A* q[3] = {ws, ws + n, ws + 2 * n};
+  launch_source_coeffs<TS, A>(pv, c->boxes_d, c->nbox, c->geom, c->ndim, c->unif, fl, F, c->species_d,
+                              c->drag_mode, dt, mass, q, c->diag, st);
+  const A* cq[4] = {q[0], q[1], q[2], nullptr};
+  deposit_det<TS, A, A>(c, pv, out, cq, st, mass ? 1 : ctx_nc(c), mass ? 1.0 : -1.0);
 }
 
 template <typename TS, typename A>
@@ -1196,9 +1215,15 @@ dust_status_t dust_drag_source(void* ctx, const dust_particles_t* p, dust_fields
   HIP_TRY(hipSetDevice(c->device));
   c->last_stream = st;
   Forces F = forces_of(frc);
+  if (c->det && ((s = ensure_det(c, p->n)) || (s = ensure_ws(c, p->n)))) return s;
   return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
     using TS = decltype(ts);
     using A = decltype(ta);
+    if (c->det) {
+      source_det<TS, A>(c, pview<TS>(p), fview<TS>(f), fview<TS>(f), F, dt, false, st);
+      HIP_TRY(hipGetLastError());
+      return DUST_OK;
+    }
     if constexpr (std::is_same<TS, float>::value && std::is_same<A, float>::value) {
       const PView<float> pv = pview<float>(p);
       if (on_layout(c, pv) && use_c3(c, true, F, pv)) {
@@ -1229,9 +1254,17 @@ dust_status_t dust_deposit_mass(void* ctx, const dust_particles_t* p, void* rho_
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(c->device));
   c->last_stream = st;
+  if (c->det && ((s = ensure_det(c, p->n)) || (s = ensure_ws(c, p->n)))) return s;
   return dispatch(c, [&](auto ts, auto ta) -> dust_status_t {
     using TS = decltype(ts);
     using A = decltype(ta);
+    if (c->det) {
+      FView<TS> out{};
+      out.dep[0] = (TS*)rho_d;
+      source_det<TS, A>(c, pview<TS>(p), FView<TS>{}, out, Forces{}, 1.0, true, st);
+      HIP_TRY(hipGetLastError());
+      return DUST_OK;
+    }
     if constexpr (std::is_same<TS, float>::value && std::is_same<A, float>::value) {
       const PView<float> pv = pview<float>(p);
       const Forces none{};

@@ -205,21 +205,22 @@ __global__ void __launch_bounds__(256) k_deposit(PView<TS> p, const Box* boxes, 
     }
 }
 
-// Deposit of Eq. dust_feedback_final without float atomics, for the
-// deterministic mode: one thread per stored cell (active or ghost) of box B
-// sums W J / dV over the particles whose stencil covers the cell -- those
-// of the 3^d active cells around it, the offsets in a fixed order and each
-// cell's particles in the order of a stable sort by cell (perm, bin_start
-// over the global cell ids) -- in FP64, and subtracts the sums from its
-// deposit words.  Every word has one writer and a fixed summation order,
-// so the result is the same bits on every run.
+// Deposit without float atomics, for the deterministic mode (the step's
+// Eq. dust_feedback_final, the predictor's drag source, the dust density):
+// one thread per stored cell (active or ghost) of box B sums W q / dV of
+// the particles whose stencil covers the cell -- those of the 3^d active
+// cells around it, the offsets in a fixed order and each cell's particles
+// in the order of a stable sort by cell (perm, bin_start over the global
+// cell ids) -- in FP64, for the nch channels q0.. (per particle), and adds
+// sgn times the sums to out.dep[0..nch).  Every word has one writer and a
+// fixed summation order, so the result is the same bits on every run.
 template <typename TS, typename A, typename TW, int GEOM, int NDIM, bool U>
 __global__ void __launch_bounds__(256)
-    k_deposit_pull(PView<TS> p, Box B, FView<TS> fl, const TW* imp0, const TW* imp1, const TW* imp2,
-                   const TW* imp3, const uint32_t* __restrict__ perm, const int64_t* __restrict__ bin_start) {
+    k_deposit_pull(PView<TS> p, Box B, FView<TS> fl, int nch, double sgn, const TW* imp0, const TW* imp1,
+                   const TW* imp2, const TW* imp3, const uint32_t* __restrict__ perm,
+                   const int64_t* __restrict__ bin_start) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= B.nstore) return;
-  constexpr int nc = GEOM == GEOM_CART ? NDIM : 3;
   constexpr int c2 = NDIM > 2 ? 1 : 0;
   const int i = (int)(t % B.g0) - 1;
   const int j = (int)((t / B.g0) % B.g1) - 1;
@@ -249,7 +250,8 @@ __global__ void __launch_bounds__(256)
           stencil_weights<A, GEOM, NDIM, U>(B, src, off, sw);
           const double w = double(sw.w[0][a + 1] * sw.w[1][bb + 1] * sw.w[2][c + 1]);
 #pragma unroll
-          for (int m = 0; m <= nc; ++m) acc[m] += w * double(imp[m][ip]);
+          for (int m = 0; m < 4; ++m)
+            if (m < nch) acc[m] += w * double(imp[m][ip]);
         }
       }
     }
@@ -257,7 +259,72 @@ __global__ void __launch_bounds__(256)
   const double iv = inv_volume(B, i, j, k);
   const int64_t id = B.store_base + t;
 #pragma unroll
-  for (int m = 0; m <= nc; ++m) fl.dep[m][id] = TS(double(fl.dep[m][id]) - acc[m] * iv);
+  for (int m = 0; m < 4; ++m)
+    if (m < nch) fl.dep[m][id] = TS(double(fl.dep[m][id]) + sgn * (acc[m] * iv));
+}
+
+// Per-particle coefficients for the deterministic drag source and dust
+// density (deposited by k_deposit_pull): q_m = m min(1/tau, 1/dt) times the
+// slip sum_i W_i (s_m v_i - p_m), as ds_particles forms them (Epstein: tau
+// from the gathered gas density), or the particle mass (MASS); zero for a
+// particle without a cell (which no bin holds).
+template <typename TS, typename A, int GEOM, int NDIM, bool U, bool MASS>
+__global__ void __launch_bounds__(256)
+    k_source_coeffs(PView<TS> p, const Box* boxes, int nbox, FView<TS> fl, Forces f, const Species* sp,
+                    int drag_mode, A inv_dt, A* q0, A* q1, A* q2, DiagDev* dg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  constexpr int nc = MASS ? 1 : (GEOM == GEOM_CART ? NDIM : 3);
+  constexpr int c2 = NDIM > 2 ? 1 : 0;
+  A* q[3] = {q0, q1, q2};
+  int idx[3];
+  A off[3], mom[3] = {A(0), A(0), A(0)};
+  const int b = MASS ? load_position<TS, A, NDIM>(p, boxes, nbox, i, idx, off, dg)
+                     : load_particle<TS, A, GEOM, NDIM>(p, boxes, nbox, i, idx, off, mom, dg);
+  A out[3] = {A(0), A(0), A(0)};
+  if (b >= 0) {
+    const Box& B = boxes[b];
+    int sidx = p.species ? p.species[i] : 0;
+    if (sidx >= sp->n) {
+      flag(dg, DUST_FLAG_BAD_CELL);
+      sidx = 0;
+    }
+    const A m = p.mass ? A(p.mass[i]) : A(sp->mass[sidx]);
+    if constexpr (MASS) {
+      out[0] = m;
+    } else {
+      Stencil<A> s;
+      stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
+      Where<A> w;
+      where<A, GEOM, NDIM, U>(B, idx, off, w);
+      A sl[3] = {A(0), A(0), A(0)};
+      A rg = A(0);
+#pragma unroll
+      for (int cc = -c2; cc <= c2; ++cc)
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb) {
+          const A wbc = s.w[1][bb + 1] * s.w[2][cc + 1];
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            const A wt = s.w[0][a + 1] * wbc;
+            if (drag_mode == DRAG_EPSTEIN)
+              rg += wt * A(fl.rho[stored_index(B, idx[0] + a, idx[1] + bb, idx[2] + cc)]);
+#pragma unroll
+            for (int mm = 0; mm < nc; ++mm)
+              sl[mm] += wt * (A(gas_comp(B, fl, nullptr, mm, idx[0] + a, idx[1] + bb, idx[2] + cc)) * w.sc[mm] -
+                              mom[mm]);
+          }
+        }
+      const A dval = drag_mode == DRAG_SPECIES ? A(1) : A(p.drag[i]);
+      const A it = drag_mode == DRAG_EPSTEIN ? rg / dval
+                                             : inverse_tau<A, GEOM>(f, drag_mode, dval, A(sp->inv_tau[sidx]), w);
+      const A k = m * (it < inv_dt ? it : inv_dt);
+#pragma unroll
+      for (int mm = 0; mm < nc; ++mm) out[mm] = k * sl[mm];
+    }
+  }
+#pragma unroll
+  for (int mm = 0; mm < nc; ++mm) q[mm][i] = out[mm];
 }
 
 // Drag source of the gas predictor (Sec. 3.1, Eq. Delta_vp and f_D): at the
@@ -1050,12 +1117,30 @@ void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, in
 
 template <typename TS, typename A, typename TW>
 void launch_deposit_pull(const PView<TS>& p, const Box& B, int geom, int ndim, int unif, const FView<TS>& fl,
-                         const TW* const imp[4], const uint32_t* perm, const int64_t* bin_start, hipStream_t st) {
+                         int nch, double sgn, const TW* const imp[4], const uint32_t* perm,
+                         const int64_t* bin_start, hipStream_t st) {
   if (B.nstore == 0) return;
   DUST_GEOM_SWITCH(geom, ndim, unif,
                    hipLaunchKernelGGL((k_deposit_pull<TS, A, TW, G_, D_, U_>), dim3(blocks_for(B.nstore)),
-                                      dim3(256), 0, st, p, B, fl, imp[0], imp[1], imp[2], imp[3], perm,
-                                      bin_start));
+                                      dim3(256), 0, st, p, B, fl, nch, sgn, imp[0], imp[1], imp[2], imp[3],
+                                      perm, bin_start));
+}
+
+template <typename TS, typename A>
+void launch_source_coeffs(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
+                          const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode, double dt,
+                          bool mass, A* const q[3], DiagDev* dg, hipStream_t st) {
+  if (p.n == 0) return;
+  if (mass)
+    DUST_GEOM_SWITCH(geom, ndim, unif,
+                     hipLaunchKernelGGL((k_source_coeffs<TS, A, G_, D_, U_, true>), dim3(blocks_for(p.n)),
+                                        dim3(256), 0, st, p, boxes, nbox, fl, f, sp, drag_mode, A(1.0 / dt),
+                                        q[0], q[1], q[2], dg));
+  else
+    DUST_GEOM_SWITCH(geom, ndim, unif,
+                     hipLaunchKernelGGL((k_source_coeffs<TS, A, G_, D_, U_, false>), dim3(blocks_for(p.n)),
+                                        dim3(256), 0, st, p, boxes, nbox, fl, f, sp, drag_mode, A(1.0 / dt),
+                                        q[0], q[1], q[2], dg));
 }
 
 template <typename TS, typename A>
@@ -1244,8 +1329,8 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
                                           const FView<TS>&, const TW* const[4], DiagDev*,         \
                                           hipStream_t);                                           \
   template void launch_deposit_pull<TS, A, TW>(const PView<TS>&, const Box&, int, int, int, const FView<TS>&, \
-                                               const TW* const[4], const uint32_t*, const int64_t*,    \
-                                               hipStream_t);
+                                               int, double, const TW* const[4], const uint32_t*,       \
+                                               const int64_t*, hipStream_t);
 
 #define DUST_INST_DRIFT(TS, A)                                                                    \
   template void launch_drift<TS, A>(const PView<TS>&, const Box*, int, int, int, int, const Forces&,   \
@@ -1254,7 +1339,10 @@ template <typename TS> void launch_fill_value(TS* a, int64_t n, TS v, hipStream_
                                           const FView<TS>&, const Forces&, const Species*, int,     \
                                           double, DiagDev*, hipStream_t);                          \
   template void launch_mass_density<TS, A>(const PView<TS>&, const Box*, int, int, int, int, TS*,  \
-                                           const Species*, DiagDev*, hipStream_t);
+                                           const Species*, DiagDev*, hipStream_t);                \
+  template void launch_source_coeffs<TS, A>(const PView<TS>&, const Box*, int, int, int, int,      \
+                                            const FView<TS>&, const Forces&, const Species*, int,  \
+                                            double, bool, A* const[3], DiagDev*, hipStream_t);
 
 DUST_INST_DRIFT(float, double)
 DUST_INST_DRIFT(float, float)

@@ -48,12 +48,21 @@ int64_t kick_partial_words(int64_t n);
 template <typename TS, typename A, typename TW>
 void launch_deposit(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
                     const FView<TS>& fl, const TW* const imp[4], DiagDev* dg, hipStream_t st);
-// The deposit of one box without float atomics (same bits on every run):
-// perm and bin_start from a stable sort of the particles by global cell id
-// (launch_bin, DUST_BIN_CELL).  B: the host copy of the box.
+// A deposit into one box without float atomics (same bits on every run):
+// fl.dep[m] += sgn * sum W imp[m] / dV for m < nch; perm and bin_start from
+// a stable sort of the particles by global cell id (launch_bin,
+// DUST_BIN_CELL).  B: the host copy of the box.
 template <typename TS, typename A, typename TW>
 void launch_deposit_pull(const PView<TS>& p, const Box& B, int geom, int ndim, int unif, const FView<TS>& fl,
-                         const TW* const imp[4], const uint32_t* perm, const int64_t* bin_start, hipStream_t st);
+                         int nch, double sgn, const TW* const imp[4], const uint32_t* perm,
+                         const int64_t* bin_start, hipStream_t st);
+// Per-particle drag source coefficients (Eq. f_D with tau <- max(tau, dt);
+// channels of the momentum) or masses (mass) into q[0..2], for
+// launch_deposit_pull.
+template <typename TS, typename A>
+void launch_source_coeffs(const PView<TS>& p, const Box* boxes, int nbox, int geom, int ndim, int unif,
+                          const FView<TS>& fl, const Forces& f, const Species* sp, int drag_mode, double dt,
+                          bool mass, A* const q[3], DiagDev* dg, hipStream_t st);
 
 // Drag source of the gas predictor (Eq. f_D, tau <- max(tau, dt)) at the
 // particles' current positions, accumulated into the momentum channels of fl.

@@ -2,14 +2,18 @@
 against the oracle at the FP64 bar, the same bits on every run (eager and
 graph), the stage calls equal to dust_step bit for bit, and a run resumed
 from a saved state equal to the uninterrupted one."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 from oracle.run import OracleRun
 from paper_1908_10793_amd import synth
 
+import test_gpu_drag_source as DS
+import test_gpu_mass as MD
 import test_gpu_parity
-from gpu_common import compare_step, download, workload_from_state
+from gpu_common import TOL, compare_step, download, workload_from_state
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -201,3 +205,49 @@ def test_autotune_is_refused_in_deterministic_mode():
     with pytest.raises(dust.DustError) as e:
         ctx.autotune(P, F, w.dt, dust.forces_for(w), steps=1)
     assert e.value.code == -5   # DUST_EUNSUPPORTED
+
+
+SOURCE_CASES = [("shearing_box", "f32"), ("shearing_box", "f64"), ("cylindrical_disk", "f64"),
+                ("spherical_disk", "f64"), ("batched", "f32"), ("cart2d", "f64")]
+
+
+@pytest.mark.parametrize("name,dtype", SOURCE_CASES)
+def test_deterministic_sources_repeat_and_match_oracle(name, dtype):
+    """dust_drag_source and dust_deposit_mass in the deterministic mode: the
+    same bits on a second run, and the oracle's source and density at the
+    bars of their own tests (particles in a shuffled order)."""
+    dust = _dust()
+    w = DS._workload(name, dtype)
+    perm = np.random.default_rng(12).permutation(w.n)
+    kw = dict(cell=w.cell[perm], off=w.off[perm], mom=w.mom[perm])
+    for k in ("drag", "mass", "species"):
+        if getattr(w, k) is not None:
+            kw[k] = getattr(w, k)[perm]
+    w = dataclasses.replace(w, **kw)
+    print(f"[det] sources {name} {dtype} n={w.n}", flush=True)
+    t, dt = 0.3, float(w.dt)
+    ctx = dust.context_for(w)
+    ctx.set_deterministic(True)
+    runs = []
+    for rep in range(2):
+        P, F = dust.upload(w, ctx)
+        fr = dust.forces_for(w, t)
+        ctx.fill_ghosts(F, fr, t)
+        for d in F["dep"]:
+            d.zero_()
+        ctx.drag_source(P, F, dt, fr)
+        rho = torch.zeros_like(F["dep"][0])
+        ctx.deposit_mass(P, rho)
+        torch.cuda.synchronize()
+        runs.append((P, F, rho))
+    (P0, F0, r0), (P1, F1, r1) = runs
+    for a, b in zip(F0["dep"], F1["dep"]):
+        assert torch.equal(a, b)
+    assert torch.equal(r0, r1)
+    st = download(ctx, P0, F0, w)
+    DS._compare(w, st, DS._oracle_source(w, st, t, dt), TOL[dtype], f"det source {name} {dtype}")
+    for d in F0["dep"]:
+        d.zero_()
+    F0["dep"][0].copy_(r0)
+    st = download(ctx, P0, F0, w)
+    MD._compare(w, st, TOL[dtype], f"det density {name} {dtype}")
