@@ -194,6 +194,44 @@ __device__ __forceinline__ void c3_load(const PView<float>& p, uint32_t i, C3Raw
                             p.species ? i : 0u);
 }
 
+// The stencil planes of a particle one cell off its thread's cell (shift
+// sx, sy, sz in -1..1, not all 0) that lie outside the thread's 27 cells, to
+// the FP64 deposit window: row sy, column sx (rows other than sy), layer sz
+// (the cells in neither).  base: window index of the particle's cell; w:
+// its weights; q: its 4 deposit channels.
+template <int RX, int RY, int RC>
+__device__ __forceinline__ void c3_spill_planes(double* dep, int base, int sx, int sy, int sz, const float w[3][3],
+                                                const float q[4]) {
+  auto lds_add = [&](int a, int bb, int cc, float wt) {
+    const int r0 = base + a + RX * (bb + RY * cc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) atomicAdd(&dep[k * RC + r0], double(wt * q[k]));
+  };
+  if (sy != 0) {
+    const float wy = sy > 0 ? w[1][2] : w[1][0];
+#pragma unroll
+    for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) lds_add(a, sy, cc, w[0][a + 1] * wy * w[2][cc + 1]);
+  }
+  if (sx != 0) {
+    const float wx = sx > 0 ? w[0][2] : w[0][0];
+#pragma unroll
+    for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+      for (int bb = -1; bb <= 1; ++bb)
+        if (sy == 0 || bb != sy) lds_add(sx, bb, cc, wx * w[1][bb + 1] * w[2][cc + 1]);
+  }
+  if (sz != 0) {
+    const float wz = sz > 0 ? w[2][2] : w[2][0];
+#pragma unroll
+    for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+      for (int a = -1; a <= 1; ++a)
+        if ((sy == 0 || bb != sy) && (sx == 0 || a != sx)) lds_add(a, bb, sz, w[0][a + 1] * w[1][bb + 1] * wz);
+  }
+}
+
 // The fused step.  SB: standard shearing-box forces (else none or a constant
 // acceleration).  REBIN: the step after a rebinning (particles read through
 // src_index, attributes copied, input checks); else COPY: stale bins written
@@ -215,6 +253,15 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   float4* gas = reinterpret_cast<float4*>(smem + 4 * RC);              // RC
   __shared__ float sp_c[DUST_MAX_SPECIES], sp_psi[DUST_MAX_SPECIES], sp_m[DUST_MAX_SPECIES];
   __shared__ float2 xres[RX];   // SB: q Omega x_c of the window's x columns, as hi + lo
+  // Each wave's queue of particles one cell off their thread's cell (their
+  // outer stencil planes go to the window): window index of the particle's
+  // cell, shift code, offsets at x^{n+1/2}, deposits.  Queued rather than
+  // deposited at once, because a handful of such lanes would otherwise hold
+  // the whole wave in the planes' LDS atomics on most iterations; the wave
+  // drains its queue with every lane busy.
+  constexpr int NW = FUSED_THREADS / 64;
+  __shared__ int spq_r[NW][64], spq_s[NW][64];
+  __shared__ float spq_o[NW][3][64], spq_q[NW][4][64];
   const TileDesc td = tiles[blockIdx.x];
   const Box& B = boxes[td.box];
   const C3Box cb = c3_box(B, dt);
@@ -344,6 +391,28 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
                  "v"(nxt.off[2]), "v"(nxt.mom[0]), "v"(nxt.mom[1]), "v"(nxt.mom[2]), "v"(si_b));
   }
   const int nlev = __builtin_amdgcn_readfirstlane(wl.nlev);   // the same in every lane
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int spq_n = 0;   // entries in this wave's queue (wave-uniform)
+  auto spill_drain = [&]() {
+    // the entries written by other lanes of this wave are visible: a wave's
+    // LDS operations complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < spq_n) {
+      const int code = spq_s[wv][lane];
+      float w2[3][3], q2[4];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) c3_weights(cb.tsc[d], spq_o[wv][d][lane], w2[d]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q2[k] = spq_q[wv][k][lane];
+      c3_spill_planes<RX, RY, RC>(dep, spq_r[wv][lane], code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1, w2, q2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    spq_n = 0;
+  };
   for (int j = 0; j < nlev; ++j) {
     const bool has = wl.cnt > j;
     const uint32_t i = slot;
@@ -549,34 +618,6 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int a = -1; a <= 1; ++a) lds_add(a, bb, cc, w[0][a + 1] * w[1][bb + 1] * w[2][cc + 1]);
       }
-      if (live && near && (sx | sy | sz)) {
-        // stencil planes outside the thread's 27 cells: row sy, column sx
-        // (rows other than sy), layer sz (the cells in neither)
-        if (sy != 0) {
-          const float wy = sy > 0 ? w[1][2] : w[1][0];
-#pragma unroll
-          for (int cc = -1; cc <= 1; ++cc)
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) lds_add(a, sy, cc, w[0][a + 1] * wy * w[2][cc + 1]);
-        }
-        if (sx != 0) {
-          const float wx = sx > 0 ? w[0][2] : w[0][0];
-#pragma unroll
-          for (int cc = -1; cc <= 1; ++cc)
-#pragma unroll
-            for (int bb = -1; bb <= 1; ++bb)
-              if (sy == 0 || bb != sy) lds_add(sx, bb, cc, wx * w[1][bb + 1] * w[2][cc + 1]);
-        }
-        if (sz != 0) {
-          const float wz = sz > 0 ? w[2][2] : w[2][0];
-#pragma unroll
-          for (int bb = -1; bb <= 1; ++bb)
-#pragma unroll
-            for (int a = -1; a <= 1; ++a)
-              if ((sy == 0 || bb != sy) && (sx == 0 || a != sx))
-                lds_add(a, bb, sz, w[0][a + 1] * w[1][bb + 1] * wz);
-        }
-      }
     }
     {
       // weights shifted to this thread's cell (zero where the stencil leaves
@@ -610,6 +651,26 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
             for (int k = 0; k < 4; ++k) acc[oo][k] = fmaf(wbc, wq[a][k], acc[oo][k]);
           }
         }
+    }
+    // a particle one cell off its thread's cell: its outer stencil planes via
+    // the wave's queue
+    {
+      const bool spill = live && near && (sx | sy | sz);
+      const uint64_t sm = __ballot(spill);
+      const int nnew = __popcll(sm);
+      if (nnew) {
+        if (spq_n + nnew > 64) spill_drain();
+        if (spill) {
+          const int e = spq_n + (int)lanes_below(sm);
+          spq_r[wv][e] = la + RX * (lb + RY * lcz);
+          spq_s[wv][e] = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
+#pragma unroll
+          for (int d = 0; d < 3; ++d) spq_o[wv][d][e] = off[d];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) spq_q[wv][k][e] = qd[k];
+        }
+        spq_n += nnew;
+      }
     }
     // second half drift to x^{n+1}
     if (live) {
@@ -645,6 +706,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     }
   }
   store_pending();
+  if (spq_n) spill_drain();
 
   // register sums of my cell's stencil -> deposit window
   if (own) {
