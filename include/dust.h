@@ -243,8 +243,9 @@ dust_status_t dust_ctx_set_tile(void *ctx, int32_t tx, int32_t ty, int32_t tz, i
 
 /* Autotuner of the fused step (batching and tuning row of the hot path):
  * runs `steps` fused steps (after one warm-up step) for every compiled tile
- * shape and rebinning interval 1, 2, 3, 4, 6, 8, 12, 16, 24 or 32 (timed over whole intervals of at
- * least `steps` steps) on device copies of p and f (the
+ * shape and rebinning interval 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48 or 64
+ * (timed over whole intervals of at least `steps` steps) on device copies of
+ * p and f (the
  * caller's arrays and the context's diagnostics are left unchanged), times
  * them with HIP events on `stream`, and keeps the fastest tile shape and
  * interval in the context (the interval is then used by dust_step when its

@@ -1420,7 +1420,7 @@ dust_status_t dust_step(void* ctx, dust_particles_t* p, dust_fields_t* f, double
 
 
 // Autotuner: times the fused step for every compiled tile shape and
-// rebinning intervals 1, 2, 3, 4, 6, 8, 12, 16, 24, 32 on copies of the caller's particles and fields,
+// rebinning intervals 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64 on copies of the caller's particles and fields,
 // then keeps the fastest shape and interval in the context.
 dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust_fields_t* f,
                                 double dt, const dust_forces_t* frc, int32_t flags, int32_t steps,
@@ -1507,8 +1507,8 @@ dust_status_t dust_ctx_autotune(void* ctx, const dust_particles_t* p, const dust
     drop_graph(c);
     if (fused_plan_init(c->plan, c->boxes.data(), c->nbox, c->tile, c->slack) != DUST_OK) continue;
     if (fused_lds_bytes(c->plan, ctx_nc(c), (int)rs) + FUSED_STATIC_LDS > 160 * 1024) continue;
-    static const int kIntervals[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
-    for (int ki = 0; ki < 10 && !s; ++ki) {
+    static const int kIntervals[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+    for (int ki = 0; ki < 12 && !s; ++ki) {
       const int k = kIntervals[ki];
       // whole intervals, so that every candidate pays its share of rebinning
       const int n = k * ((steps + k - 1) / k);
