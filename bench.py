@@ -44,6 +44,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+CU_COUNT = 256           # MI355X compute units
+CLOCK_HZ = 2.4e9         # peak engine clock
 METRIC = "particle-steps/s (gather+exp-midpoint push+deposit)"
 WORKLOAD_NAMES = {1: "cart2d_periodic", 2: "shearing_box", 3: "cylindrical_disk",
                   4: "spherical_disk", 5: "batched_boxes"}
@@ -133,6 +135,36 @@ def counter_traffic(kernel: str, name: str, kernel_hash: str, n_particles: int):
     if d.get("kernel_source_hash") != kernel_hash or d.get("n_particles") != str(n_particles):
         return None
     return float(d["hbm_bytes_per_launch"])
+
+
+def counter_valu(kernel: str, name: str, kernel_hash: str, tile, rebin: int):
+    """VALU wave-instructions per launch of the tile kernel (launch-weighted
+    over its variants) from the committed rocprofv3 SQ counter summary of
+    this workload, if it was taken on the current kernel source with the
+    same tile shape and rebinning interval."""
+    import re
+    path = os.path.join(HERE, "profiles", f"{kernel}_{name}_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    total = launches = 0.0
+    ok_hash = ok_cfg = False
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# kernel_source_hash:"):
+                ok_hash = line.split(":", 1)[1].strip() == kernel_hash
+            elif line.startswith("# command:"):
+                m = re.search(r"--tile (\d+),(\d+),(\d+)", line)
+                k = re.search(r"--rebin-every (\d+)", line)
+                ok_cfg = bool(m and k) and [int(m.group(i)) for i in (1, 2, 3)] == list(tile) and \
+                    int(k.group(1)) == rebin
+            elif "SQ_INSTS_VALU " in line and not line.startswith("#"):
+                m = re.search(r"SQ_INSTS_VALU\s+([0-9.e+-]+)\s+\(launches (\d+)\)", line)
+                if m:
+                    total += float(m.group(1)) * int(m.group(2))
+                    launches += int(m.group(2))
+    if not (ok_hash and ok_cfg and launches):
+        return None
+    return total / launches
 
 
 def _rocpd(run_dir: str) -> str:
@@ -652,6 +684,14 @@ def run_config(cfg: int, args, extra: bool, K: int, W: int, arith_override=None)
                 "bytes_per_particle_step": round(bytes_per_pstep, 3),
                 "algorithmic_bytes_per_launch": bytes_per_pstep * N, "kernel_source_hash": khash,
                 "step_frac": round(bytes_per_pstep * value / 1e9 / HBM_PEAK_GBS, 4)}
+        valu = counter_valu(kname, WORKLOAD_NAMES[cfg], khash, (tx, ty, tz), rebin)
+        if valu:
+            # non-packed FP32 VALU issue: one wave64 instruction per SIMD every
+            # 4 cycles, 4 SIMDs per CU
+            issue_s = valu * 4.0 / (CU_COUNT * 4 * CLOCK_HZ)
+            roof["valu_issue"] = {"wave_instructions_per_launch": valu, "issue_ms": round(issue_s * 1e3, 3),
+                                  "frac": round(issue_s / kavg, 4),
+                                  "note": "SQ_INSTS_VALU from the committed counter summary of this tiling"}
     res = float(np.max(np.abs(np.array(diag["p_part"]) + np.array(diag["p_grid"])))) / max(
         diag["sum_abs_j"], 1e-300)
     out.update({
