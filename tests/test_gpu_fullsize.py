@@ -1,5 +1,6 @@
 """Parity at full size, in the launch configuration that bench.py times
-(autotuned fused step), on sampled outputs.
+(the autotuned or the bench's fixed tiling of each workload), on sampled
+outputs.
 
 The GPU steps the whole workload.  The oracle then steps only the particles
 whose cells lie within `margin` cells of a set of sampled interior cells;
@@ -90,10 +91,12 @@ def check_fields(w, run, dep_g, vel_g, regions, label):
     return worst
 
 
-def sampled_parity(w, ncenters=24, margin=3, seed=11, tune=True, label=""):
+def sampled_parity(w, ncenters=24, margin=3, seed=11, tune=True, tile=None, label=""):
     from paper_1908_10793_amd import dust
     print(f"[fullsize] {label}: {w.n} particles, uploading", flush=True)
     ctx = dust.context_for(w)
+    if tile:
+        ctx.set_tile(*tile)
     P, F = dust.upload(w, ctx)
     flags = dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG
     fr = dust.forces_for(w, w.t0)
@@ -163,15 +166,19 @@ def test_full_size_cylindrical_disk():
     """Cylindrical (R, phi, z) 256x512x64 grid, log-spaced R in [0.4, 2.5],
     2^25 particles with surface density ~ 1/R and Stokes numbers
     log-uniform in [1e-3, 10], TSC with the curvilinear weights, FP32
-    storage: one autotuned fused step (App. B.2 cylindrical step)."""
-    sampled_parity(synth.cylindrical_disk(), ncenters=16, label="cylindrical 256x512x64")
+    storage and arithmetic: one fused step with the bench's tiling of this
+    workload (4x16x4; App. B.2 cylindrical step)."""
+    sampled_parity(synth.cylindrical_disk(), ncenters=16, tune=False, tile=(4, 16, 4, 0),
+                   label="cylindrical 256x512x64")
 
 
 def test_full_size_spherical_disk():
     """Spherical (r, theta, phi) 256x128x512 grid, r in [0.5, 5], theta in
     pi/2 +- 0.3, 2^26 particles, stopping times log-uniform in [1e-6, 1]:
-    one autotuned fused step (App. B.2 spherical step, App. C weights)."""
-    sampled_parity(synth.spherical_disk(), ncenters=16, label="spherical 256x128x512")
+    one fused step in FP32 arithmetic with the bench's tiling of this
+    workload (4x16x4; App. B.2 spherical step, App. C weights)."""
+    sampled_parity(synth.spherical_disk(), ncenters=16, tune=False, tile=(4, 16, 4, 0),
+                   label="spherical 256x128x512")
 
 
 def test_full_size_batched_boxes_100_step_graph():
@@ -179,7 +186,7 @@ def test_full_size_batched_boxes_100_step_graph():
     four species, U{1..32} per cell and species, 994,755,343 particles),
     stepped 100 times through captured graphs (99 steps, then the last one),
     with the tile shape and rebinning interval the bench's autotuner picks
-    (8x8x4, every 16 steps).  The last step is checked against the oracle
+    (16x4x4, every 32 steps).  The last step is checked against the oracle
     started from the GPU state before it, on the particles within `margin`
     cells of sampled cells of every box (selected on the GPU by cell), and
     the conservation residual is checked over all 100 steps."""
@@ -189,10 +196,10 @@ def test_full_size_batched_boxes_100_step_graph():
     label = "batched, all boxes"
     print(f"[fullsize] {label}: {w.n} particles, uploading", flush=True)
     ctx = dust.context_for(w)
-    ctx.set_tile(8, 8, 4, 0)
+    ctx.set_tile(16, 4, 4, 0)
     P, F = dust.upload(w, ctx, with_id=True)
     flags = (dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG | dust.STEP_FUSED | dust.STEP_GRAPH
-             | dust.STEP_REBIN_EVERY(16))
+             | dust.STEP_REBIN_EVERY(32))
     t = w.t0
     ctx.step(P, F, w.dt, dust.forces_for(w, t), 99, flags)
     t += 99 * w.dt
