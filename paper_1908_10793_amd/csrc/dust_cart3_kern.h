@@ -33,49 +33,50 @@ namespace dust {
 
 
 // Move by dxc cells along one axis of a uniform grid (offset renormalised into
-// [-1/2, 1/2)); returns the new cell index (not wrapped).
+// [-1/2, 1/2)); returns the new cell index (not wrapped).  Without branches
+// (a wave takes a branch whenever one of its lanes crosses a face): the
+// nearest integer k splits the new offset d exactly (d - k is exact in FP32
+// for |d| < 2^23), a tie at +1/2 goes to the next cell, and an offset that
+// stays in its cell is kept as it is.
 __device__ __forceinline__ int c3_move(int i, float& off, float v, float hinv) {
-  float dn = fmaf(v, hinv, off);
-  if (dn >= 0.5f || dn < -0.5f) {
-    const float k = floorf(dn + 0.5f);
-    dn -= k;
-    i += (int)k;
-    if (dn >= 0.5f) {
-      dn -= 1.0f;
-      ++i;
-    } else if (dn < -0.5f) {
-      dn += 1.0f;
-      --i;
-    }
-  }
-  off = dn;
-  return i;
+  const float dn = fmaf(v, hinv, off);
+  const float k = rintf(dn);
+  const float r0 = k == 0.0f ? dn : dn - k;
+  const bool up = r0 >= 0.5f;
+  off = up ? r0 - 1.0f : r0;
+  return i + (int)k + (up ? 1 : 0);
 }
 
-// floor(a / n) for 0 <= a <= 2^24, n >= 1, through an FP32 reciprocal: a is
-// exact in FP32 and the product is within one of the quotient, so one
-// correction step makes it exact.
-__device__ __forceinline__ int c3_div24(int a, int n, float inv) {
+// floor(a / n) and a - n floor(a / n) for 0 <= a < 2^24, 1 <= n < 2^24,
+// through an FP32 reciprocal: a is exact in FP32 and the product is within
+// one of the quotient, so one correction step makes it exact.  Both factors
+// of q n are below 2^24: the full-rate 24-bit multiply.
+__device__ __forceinline__ int c3_div24(int a, int n, float inv, int& rem) {
   int q = (int)(float(a) * inv);
-  const int r = a - q * n;
-  q += r >= n ? 1 : (r < 0 ? -1 : 0);
+  const int r = a - __umul24((unsigned)q, (unsigned)n);
+  const bool hi = r >= n, lo = r < 0;
+  q += hi ? 1 : (lo ? -1 : 0);
+  rem = hi ? r - n : (lo ? r + n : r);
   return q;
 }
 
-// Cell coordinates of a local cell id: FP32 reciprocals for boxes of at
-// most 2^24 cells, else FP64 (one correction each).
-__device__ __forceinline__ void c3_unravel(int l, int n0, int n1, double inv0, double inv1, int idx[3]) {
-  int r, k;
-  if (l <= (1 << 24)) {
-    r = c3_div24(l, n0, float(inv0));
-    k = c3_div24(r, n1, float(inv1));
+// Cell coordinates of a local cell id: FP32 reciprocals where small (ids and
+// box sides below 2^24), else FP64 (one correction each).
+__device__ __forceinline__ void c3_unravel(int l, int n0, int n1, double inv0, double inv1, int idx[3],
+                                           bool small) {
+  if (small) {
+    const int r = c3_div24(l, n0, float(inv0), idx[0]);
+    idx[2] = c3_div24(r, n1, float(inv1), idx[1]);
   } else {
-    r = div_small(l, n0, inv0);
-    k = div_small(r, n1, inv1);
+    const int r = div_small(l, n0, inv0);
+    const int k = div_small(r, n1, inv1);
+    idx[0] = l - r * n0;
+    idx[1] = r - k * n1;
+    idx[2] = k;
   }
-  idx[0] = l - r * n0;
-  idx[1] = r - k * n1;
-  idx[2] = k;
+}
+__device__ __forceinline__ void c3_unravel(int l, int n0, int n1, double inv0, double inv1, int idx[3]) {
+  c3_unravel(l, n0, n1, inv0, inv1, idx, l < (1 << 24) && n0 < (1 << 24) && n1 < (1 << 24));
 }
 
 // Uniform constants of the workgroup's box.
@@ -105,17 +106,24 @@ __device__ __forceinline__ C3Box c3_box(const Box& B, float dt) {
   return c;
 }
 
+// Cell id of cell (i, j, k) of the box: 24-bit products (full rate) when the
+// box has fewer than 2^24 cells, so that every factor and product fits.
+__device__ __forceinline__ int32_t c3_cell_id(const C3Box& cb, int i, int j, int k) {
+  if (cb.ncell < (1 << 24))
+    return cb.cell_base + i +
+           (int)__umul24((unsigned)cb.n[0], (unsigned)(j + (int)__umul24((unsigned)cb.n[1], (unsigned)k)));
+  return cb.cell_base + i + cb.n[0] * (j + cb.n[1] * k);
+}
+
 // Weights of cells i-1, i, i+1 of one axis (b-spline overlaps, Eq. b0 / b1),
 // middle weight 1 - w0 - w2.
 __device__ __forceinline__ void c3_weights(bool tsc, float d, float w[3]) {
-  if (tsc) {
-    const float m = 0.5f - d, p = 0.5f + d;
-    w[0] = 0.5f * m * m;
-    w[2] = 0.5f * p * p;
-  } else {
-    w[0] = d < 0.0f ? -d : 0.0f;
-    w[2] = d > 0.0f ? d : 0.0f;
-  }
+  // both forms, blended by t = 1 (TSC) or 0 (CIC): t a + (1 - t) b is a or b
+  // exactly, and no branch on the box's shape
+  const float t = tsc ? 1.0f : 0.0f, u = 1.0f - t;
+  const float m = 0.5f - d, p = 0.5f + d;
+  w[0] = fmaf(t, 0.5f * m * m, u * (d < 0.0f ? -d : 0.0f));
+  w[2] = fmaf(t, 0.5f * p * p, u * (d > 0.0f ? d : 0.0f));
   w[1] = 1.0f - w[0] - w[2];
 }
 
@@ -251,7 +259,10 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   extern __shared__ double smem[];
   double* dep = smem;                                                  // 4 * RC (FP64)
   float4* gas = reinterpret_cast<float4*>(smem + 4 * RC);              // RC
-  __shared__ float sp_c[DUST_MAX_SPECIES], sp_psi[DUST_MAX_SPECIES], sp_m[DUST_MAX_SPECIES];
+  // per species: mass, c, and the step factors h1 = dt (1 + psi) and dt psi of
+  // Eq. exp_midpoint; in the shearing box also W = Omega h1 and 1 / (1 + W^2)
+  __shared__ float4 sp_k[DUST_MAX_SPECIES];
+  __shared__ float2 sp_w[DUST_MAX_SPECIES];
   __shared__ float2 xres[RX];   // SB: q Omega x_c of the window's x columns, as hi + lo
   // Each wave's queue of particles one cell off their thread's cell (their
   // outer stencil planes go to the window): window index of the particle's
@@ -266,12 +277,20 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   const Box& B = boxes[td.box];
   const C3Box cb = c3_box(B, dt);
   const int ox = td.i0 - H, oy = td.j0 - H, oz = td.k0 - H;
+  // window index of window coordinates a, b >= 0, c >= 0 (24-bit products:
+  // full rate, where a 32-bit product by RX or RX RY would take four passes)
+  auto win = [](int a, int b, int c) {
+    return a + (int)__umul24((unsigned)RX, (unsigned)(b + (int)__umul24((unsigned)RY, (unsigned)c)));
+  };
   if (threadIdx.x < sp->n) {
     float c, psi;
     propagator<float>(dt * float(sp->inv_tau[threadIdx.x]), c, psi);
-    sp_c[threadIdx.x] = c;
-    sp_psi[threadIdx.x] = psi;
-    sp_m[threadIdx.x] = float(sp->mass[threadIdx.x]);
+    const float h1 = dt + dt * psi;
+    sp_k[threadIdx.x] = make_float4(float(sp->mass[threadIdx.x]), c, h1, dt * psi);
+    if (SB) {
+      const float W = float(f.Omega) * h1;
+      sp_w[threadIdx.x] = make_float2(W, 1.0f / (1.0f + W * W));
+    }
   }
   const double qO = SB ? f.q * f.Omega : 0.0;
   const double x_lo = B.ax[0].lo, dx0 = B.ax[0].d;
@@ -322,7 +341,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
             lz = own ? lc / (td.ex * td.ey) : 0;
   const int mycell[3] = {td.i0 + lx, td.j0 + ly, td.k0 + lz};
   const int mybase = (lx + H) + RX * ((ly + H) + RY * (lz + H));
-  const int32_t mycid = cb.cell_base + mycell[0] + n0 * (mycell[1] + n1 * mycell[2]);
+  const int32_t mycid = c3_cell_id(cb, mycell[0], mycell[1], mycell[2]);
 
   float acc[27][4];
 #pragma unroll
@@ -422,7 +441,10 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     slot = slot_b;
     nxt_si = si_b;
     slot_b = level_slot(wl, j + 2, lvl);
-    if (j + 1 < nlev) c3_load<COPY>(p, nxt_si, nxt);
+    // issued at the last level too (the wave's first slot then, in range;
+    // the values go unused): with no skipped load, the prefetch registers
+    // need no copy of their old values on every iteration
+    c3_load<COPY>(p, nxt_si, nxt);
     si_b = valid(j + 2, slot_b);
     if constexpr (REBIN) {
       if (j + 2 < nlev) si_b = at32(src_index, si_b);
@@ -452,20 +474,38 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
         }
       }
     }
-    float off[3] = {cur.off[0], cur.off[1], cur.off[2]}, mom[3] = {cur.mom[0], cur.mom[1], cur.mom[2]};
-    if (live) {
-      if (cid != mycid) c3_unravel(cid - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx);
+    // a lane without a live particle drifts a particle at rest in the centre
+    // of its thread's cell (no branch around the drift)
+    float off[3], mom[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      off[d] = live ? cur.off[d] : 0.0f;
+      mom[d] = live ? cur.mom[d] : 0.0f;
+    }
+    {
+      // after a rebinning every particle is in its thread's cell; on stale
+      // bins some lane of a wave nearly always is not: no branch then (a box
+      // of fewer than 2^24 cells takes the FP32 division, a uniform choice)
+      if constexpr (REBIN) {
+        if (live && cid != mycid)
+          c3_unravel(cid - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx, cb.ncell < (1 << 24));
+      } else {
+        c3_unravel((live ? cid : mycid) - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx,
+                   cb.ncell < (1 << 24));
+      }
       // half drift to x^{n+1/2} (periodic images, open faces remove, a
-      // shear-periodic x face defers)
+      // shear-periodic x face defers); one test for the three axes
       bool removed = false;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        idx[d] = c3_move(idx[d], off[d], mom[d], cb.hinv[d]);
-        if (idx[d] < 0 || idx[d] >= cb.n[d]) {
-          if (cb.per[d]) idx[d] = c3_wrap(idx[d], cb.n[d]);
-          else if (d == 0 && cb.shear) deferred = true;
-          else removed = true;
-        }
+      for (int d = 0; d < 3; ++d) idx[d] = c3_move(idx[d], off[d], mom[d], cb.hinv[d]);
+      if ((unsigned)idx[0] >= (unsigned)n0 || (unsigned)idx[1] >= (unsigned)n1 || (unsigned)idx[2] >= (unsigned)n2) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (idx[d] < 0 || idx[d] >= cb.n[d]) {
+            if (cb.per[d]) idx[d] = c3_wrap(idx[d], cb.n[d]);
+            else if (d == 0 && cb.shear) deferred = true;
+            else removed = true;
+          }
       }
       if (removed) {
         // left through an open face: no cell from now on (it keeps the
@@ -512,7 +552,10 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       // a dummy at the centre of this thread's cell, with zero deposits (a
       // divergent skip would keep two copies of the register sums)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) off[d] = 0.0f;
+      for (int d = 0; d < 3; ++d) {
+        off[d] = 0.0f;
+        idx[d] = mycell[d];
+      }
       la = lx + H;
       lb = ly + H;
       lcz = lz + H;
@@ -529,7 +572,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     // are issued together
     float v[3] = {0.0f, 0.0f, 0.0f};
     {
-      int r0 = la + RX * (lb - 1 + RY * (lcz - 1));
+      int r0 = win(la, lb - 1, lcz - 1);
 #pragma unroll 1
       for (int c = 0; c < 3; ++c, r0 += RX * RY) {
         const float wz = c == 0 ? w[2][0] : c == 1 ? w[2][1] : w[2][2];
@@ -555,9 +598,8 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       flag(dg, DUST_FLAG_BAD_CELL);
       spc = 0;
     }
-    const float m = sp_m[spc], c = sp_c[spc], psi = sp_psi[spc];
-    const float h1 = dt + dt * psi;
-    const float dtp = dt * psi;
+    const float4 kc = sp_k[spc];
+    const float m = kc.x, c = kc.y, h1 = kc.z, dtp = kc.w;
     float dp[3], jj[3];
     if constexpr (SB) {
       // y relative to the background shear: v_y + q Omega x at x^{n+1/2}
@@ -567,7 +609,8 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       const float gz = gz_c * (z_lo + (float(idx[2]) + 0.5f + off[2]) * dz);
       const float an0 = 2.0f * Om * uy, an1 = -2.0f * Om * mom[0];
       const float r0 = c * s0 + h1 * an0, r1 = c * s1 + h1 * an1;
-      const float W = Om * h1, den = 1.0f / (1.0f + W * W);
+      const float2 wk = sp_w[spc];
+      const float W = wk.x, den = wk.y;
       dp[0] = (r0 + W * r1) * den;
       dp[1] = (r1 - W * r0) * den;
       dp[2] = c * s2 + h1 * gz;
@@ -604,7 +647,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     // deposit (same weights and cells as the gather): register sums over the
     // 27 cells around the thread's cell, the rest through the FP64 window
     {
-      const int base = la + RX * (lb + RY * lcz);
+      const int base = win(la, lb, lcz);
       auto lds_add = [&](int a, int bb, int cc, float wt) {
         const int r0 = base + a + RX * (bb + RY * cc);
 #pragma unroll
@@ -662,7 +705,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
         if (spq_n + nnew > 64) spill_drain();
         if (spill) {
           const int e = spq_n + (int)lanes_below(sm);
-          spq_r[wv][e] = la + RX * (lb + RY * lcz);
+          spq_r[wv][e] = win(la, lb, lcz);
           spq_s[wv][e] = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
 #pragma unroll
           for (int d = 0; d < 3; ++d) spq_o[wv][d][e] = off[d];
@@ -672,26 +715,29 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
         spq_n += nnew;
       }
     }
-    // second half drift to x^{n+1}
-    if (live) {
+    // second half drift to x^{n+1} (a lane without a live particle: its
+    // dummy at rest, no branch around the drift)
+    {
       bool alive = true;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) idx[d] = c3_move(idx[d], off[d], mom[d], cb.hinv[d]);
-      if (cb.shear && (idx[0] < 0 || idx[0] >= n0)) shear_image<float, false>(B, f, t0 + double(dt), idx, off, mom);
+      for (int d = 0; d < 3; ++d) idx[d] = c3_move(idx[d], off[d], live ? mom[d] : 0.0f, cb.hinv[d]);
+      if ((unsigned)idx[0] >= (unsigned)n0 || (unsigned)idx[1] >= (unsigned)n1 || (unsigned)idx[2] >= (unsigned)n2) {
+        if (cb.shear && (idx[0] < 0 || idx[0] >= n0)) shear_image<float, false>(B, f, t0 + double(dt), idx, off, mom);
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (idx[d] < 0 || idx[d] >= cb.n[d]) {
-          if (cb.per[d] || (d == 0 && cb.shear)) idx[d] = c3_wrap(idx[d], cb.n[d]);
-          else alive = false;
-        }
-      pend = true;
-      pend_cell = alive ? cb.cell_base + idx[0] + n0 * (idx[1] + n1 * idx[2]) : -1;
+        for (int d = 0; d < 3; ++d)
+          if (idx[d] < 0 || idx[d] >= cb.n[d]) {
+            if (cb.per[d] || (d == 0 && cb.shear)) idx[d] = c3_wrap(idx[d], cb.n[d]);
+            else alive = false;
+          }
+      }
+      pend = live;
+      pend_cell = alive ? c3_cell_id(cb, idx[0], idx[1], idx[2]) : -1;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         pend_off[d] = off[d];
         pend_mom[d] = mom[d];
       }
-      if (!alive && dg) {
+      if (live && !alive && dg) {
         atomicAdd(&dg->n_removed, 1ull);
         atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
       }
