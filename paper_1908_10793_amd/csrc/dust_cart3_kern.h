@@ -273,6 +273,9 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   constexpr int NW = FUSED_THREADS / 64;
   __shared__ int spq_r[NW][64], spq_s[NW][64];
   __shared__ float spq_o[NW][3][64], spq_q[NW][4][64];
+  // where the particles are written: stale bins in place write the arrays
+  // they read (the same pointers, held once)
+  const PView<float>& out = COPY ? dst : p;
   const TileDesc td = tiles[blockIdx.x];
   const Box& B = boxes[td.box];
   const C3Box cb = c3_box(B, dt);
@@ -370,17 +373,17 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   float pend_off[3] = {0.0f, 0.0f, 0.0f}, pend_mom[3] = {0.0f, 0.0f, 0.0f};
   auto store_pending = [&]() {
     if (pend) {
-      at32(dst.cell, pend_i) = pend_cell;
+      at32(out.cell, pend_i) = pend_cell;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        at32(dst.off[d], pend_i) = pend_off[d];
-        at32(dst.mom[d], pend_i) = pend_mom[d];
+        at32(out.off[d], pend_i) = pend_off[d];
+        at32(out.mom[d], pend_i) = pend_mom[d];
       }
     }
     if constexpr (COPY) {
       if (pend_attr) {
-        if (p.species) at32(dst.species, pend_i) = (uint8_t)pend_sp;
-        if (p.id) at32(dst.id, pend_i) = pend_id;
+        if (p.species) at32(out.species, pend_i) = (uint8_t)pend_sp;
+        if (p.id) at32(out.id, pend_i) = pend_id;
       }
     }
     pend = false;
@@ -412,6 +415,9 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   const int nlev = __builtin_amdgcn_readfirstlane(wl.nlev);   // the same in every lane
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int spq_n = 0;   // entries in this wave's queue (wave-uniform)
+  // this thread's removals and flags, added to the diagnostics once at the
+  // end (no atomics, and no branch around them, in the loop)
+  uint32_t n_rem = 0, flags_acc = 0;
   auto spill_drain = [&]() {
     // the entries written by other lanes of this wave are visible: a wave's
     // LDS operations complete in order
@@ -457,20 +463,20 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     if constexpr (REBIN) {
       // inputs from the caller (every call starts with a rebinning): cell ids
       // and offsets are checked here; later steps write them in range
-      if (cid >= 0 && !live) flag(dg, DUST_FLAG_BAD_CELL);
+      if (cid >= 0 && !live) flags_acc |= DUST_FLAG_BAD_CELL;
       bool bad = false;
 #pragma unroll
       for (int d = 0; d < 3; ++d) bad |= live && !(cur.off[d] >= -0.5f && cur.off[d] < 0.5f);
-      if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+      if (bad) flags_acc |= DUST_FLAG_OFFSET_RANGE;
     }
     if constexpr (COPY) {
       if (has && !live) {
         // a particle without a cell is carried unchanged
-        at32(dst.cell, i) = cid;
+        at32(out.cell, i) = cid;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          at32(dst.off[d], i) = cur.off[d];
-          at32(dst.mom[d], i) = cur.mom[d];
+          at32(out.off[d], i) = cur.off[d];
+          at32(out.mom[d], i) = cur.mom[d];
         }
       }
     }
@@ -506,33 +512,28 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
             else if (d == 0 && cb.shear) deferred = true;
             else removed = true;
           }
-      }
-      if (removed) {
-        // left through an open face: no cell from now on (it keeps the
-        // offsets and momenta it had when it left)
-        at32(dst.cell, i) = -1;
-        if (COPY) {
+        if (removed) {
+          // left through an open face: no cell from now on (it keeps the
+          // offsets and momenta it had when it left)
+          at32(out.cell, i) = -1;
+          if (COPY) {
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            at32(dst.off[d], i) = off[d];
-            at32(dst.mom[d], i) = mom[d];
+            for (int d = 0; d < 3; ++d) {
+              at32(out.off[d], i) = off[d];
+              at32(out.mom[d], i) = mom[d];
+            }
           }
+          ++n_rem;
+          live = false;
         }
-        if (dg) {
-          atomicAdd(&dg->n_removed, 1ull);
-          atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
-        }
-        live = false;
       }
     }
-    int la = lx + H, lb = ly + H, lcz = lz + H;
-    if (live && !deferred) {
-      la = win_coord(idx[0], ox, n0, RX, cb.per[0]);
-      lb = win_coord(idx[1], oy, n1, RY, cb.per[1]);
-      lcz = win_coord(idx[2], oz, n2, RZ, cb.per[2]);
-      deferred = !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 && lcz >= 1 && lcz <= RZ - 2);
-    }
-    deferred = deferred && live;
+    // window coordinates (every lane: those without a live particle take
+    // their thread's cell below); a stencil that leaves the window defers
+    int la = win_coord(idx[0], ox, n0, RX, cb.per[0]);
+    int lb = win_coord(idx[1], oy, n1, RY, cb.per[1]);
+    int lcz = win_coord(idx[2], oz, n2, RZ, cb.per[2]);
+    deferred = live && (deferred || !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 && lcz >= 1 && lcz <= RZ - 2));
     {
       const uint64_t dm = __ballot(deferred);
       if (dm) {
@@ -566,16 +567,17 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     for (int d = 0; d < 3; ++d) c3_weights(cb.tsc[d], off[d], w[d]);
     const int sx = la - (lx + H), sy = lb - (ly + H), sz = lcz - (lz + H);
     const bool near = sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1 && sz >= -1 && sz <= 1;
-    // gather (Eq. Delta_vp), one z-plane of the stencil per iteration of a
-    // loop that is not unrolled (straight-line code would let the compiler
-    // issue all 27 LDS reads first, 81 registers); the nine reads of a plane
-    // are issued together
+    // gather (Eq. Delta_vp), one z-plane of the stencil at a time: the nine
+    // reads of a plane are issued together, and an empty asm with a memory
+    // clobber keeps the next plane's reads after this plane's sums
+    // (straight-line code would otherwise issue all 27 reads first, 81
+    // registers)
     float v[3] = {0.0f, 0.0f, 0.0f};
     {
-      int r0 = win(la, lb - 1, lcz - 1);
-#pragma unroll 1
-      for (int c = 0; c < 3; ++c, r0 += RX * RY) {
-        const float wz = c == 0 ? w[2][0] : c == 1 ? w[2][1] : w[2][2];
+      const int r00 = win(la, lb - 1, lcz - 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int r0 = r00 + c * RX * RY;
         float4 g[9];
 #pragma unroll
         for (int q9 = 0; q9 < 9; ++q9) g[q9] = gas[r0 + RX * (q9 / 3) + (q9 % 3) - 1];
@@ -585,19 +587,18 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
           const float ux = w[0][0] * g0.x + w[0][1] * g1.x + w[0][2] * g2.x;
           const float uy = w[0][0] * g0.y + w[0][1] * g1.y + w[0][2] * g2.y;
           const float uz = w[0][0] * g0.z + w[0][1] * g1.z + w[0][2] * g2.z;
-          const float wbc = w[1][bb] * wz;
+          const float wbc = w[1][bb] * w[2][c];
           v[0] += wbc * ux;
           v[1] += wbc * uy;
           v[2] += wbc * uz;
         }
+        if (c < 2) asm volatile("" ::: "memory");
       }
     }
     // kick (Eq. exp_midpoint; App. B.1 Eq. standard_SB_exp_midpoint)
     int spc = live && p.species ? cur.species : 0;
-    if (spc >= sp->n) {
-      flag(dg, DUST_FLAG_BAD_CELL);
-      spc = 0;
-    }
+    flags_acc |= spc >= sp->n ? (uint32_t)DUST_FLAG_BAD_CELL : 0u;
+    spc = spc >= sp->n ? 0 : spc;
     const float4 kc = sp_k[spc];
     const float m = kc.x, c = kc.y, h1 = kc.z, dtp = kc.w;
     float dp[3], jj[3];
@@ -737,10 +738,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
         pend_off[d] = off[d];
         pend_mom[d] = mom[d];
       }
-      if (live && !alive && dg) {
-        atomicAdd(&dg->n_removed, 1ull);
-        atomicOr(&dg->flags, (unsigned)DUST_FLAG_LEFT_OPEN);
-      }
+      n_rem += live && !alive ? 1u : 0u;
     }
     pend_i = i;
     if constexpr (COPY) {
@@ -753,6 +751,13 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   }
   store_pending();
   if (spq_n) spill_drain();
+  if (dg) {
+    if (n_rem) {
+      atomicAdd(&dg->n_removed, (unsigned long long)n_rem);
+      flags_acc |= DUST_FLAG_LEFT_OPEN;
+    }
+    if (flags_acc) atomicOr(&dg->flags, (unsigned)flags_acc);
+  }
 
   // register sums of my cell's stencil -> deposit window
   if (own) {
