@@ -106,10 +106,11 @@ __device__ __forceinline__ C3Box c3_box(const Box& B, float dt) {
   return c;
 }
 
-// Cell id of cell (i, j, k) of the box: 24-bit products (full rate) when the
-// box has fewer than 2^24 cells, so that every factor and product fits.
-__device__ __forceinline__ int32_t c3_cell_id(const C3Box& cb, int i, int j, int k) {
-  if (cb.ncell < (1 << 24))
+// Cell id of cell (i, j, k) of the box: 24-bit products (full rate) when
+// small (the box has fewer than 2^24 cells, so that every factor and product
+// fits).
+__device__ __forceinline__ int32_t c3_cell_id(const C3Box& cb, int i, int j, int k, bool small) {
+  if (small)
     return cb.cell_base + i +
            (int)__umul24((unsigned)cb.n[0], (unsigned)(j + (int)__umul24((unsigned)cb.n[1], (unsigned)k)));
   return cb.cell_base + i + cb.n[0] * (j + cb.n[1] * k);
@@ -241,11 +242,11 @@ __device__ __forceinline__ void c3_spill_planes(double* dep, int base, int sx, i
 }
 
 // The fused step.  SB: standard shearing-box forces (else none or a constant
-// acceleration).  REBIN: the step after a rebinning (particles read through
+// acceleration).  SMALL: every box of the launch has fewer than 2^24 cells.  REBIN: the step after a rebinning (particles read through
 // src_index, attributes copied, input checks); else COPY: stale bins written
 // to another buffer slot for slot (attributes copied), or in place.  Masses
 // and stopping times come from the species table.
-template <int TX, int TY, int TZ, bool SB, bool REBIN, bool COPY>
+template <int TX, int TY, int TZ, bool SB, bool REBIN, bool COPY, bool SMALL>
 __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     k_c3(const TileDesc* __restrict__ tiles, const uint8_t* __restrict__ tmap, PView<float> p,
          PView<float> dst, int copy_attrs, const Box* __restrict__ boxes, FView<float> fl, Forces f,
@@ -344,7 +345,10 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
             lz = own ? lc / (td.ex * td.ey) : 0;
   const int mycell[3] = {td.i0 + lx, td.j0 + ly, td.k0 + lz};
   const int mybase = (lx + H) + RX * ((ly + H) + RY * (lz + H));
-  const int32_t mycid = c3_cell_id(cb, mycell[0], mycell[1], mycell[2]);
+  // boxes of fewer than 2^24 cells: FP32 division and 24-bit products (known
+  // at compile time when every box of the launch is that small)
+  const bool small = SMALL || cb.ncell < (1 << 24);
+  const int32_t mycid = c3_cell_id(cb, mycell[0], mycell[1], mycell[2], small);
 
   float acc[27][4];
 #pragma unroll
@@ -494,10 +498,9 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       // of fewer than 2^24 cells takes the FP32 division, a uniform choice)
       if constexpr (REBIN) {
         if (live && cid != mycid)
-          c3_unravel(cid - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx, cb.ncell < (1 << 24));
+          c3_unravel(cid - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx, small);
       } else {
-        c3_unravel((live ? cid : mycid) - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx,
-                   cb.ncell < (1 << 24));
+        c3_unravel((live ? cid : mycid) - cb.cell_base, n0, n1, B.ax[0].inv_n, B.ax[1].inv_n, idx, small);
       }
       // half drift to x^{n+1/2} (periodic images, open faces remove, a
       // shear-periodic x face defers); one test for the three axes
@@ -533,7 +536,8 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
     int la = win_coord(idx[0], ox, n0, RX, cb.per[0]);
     int lb = win_coord(idx[1], oy, n1, RY, cb.per[1]);
     int lcz = win_coord(idx[2], oz, n2, RZ, cb.per[2]);
-    deferred = live && (deferred || !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 && lcz >= 1 && lcz <= RZ - 2));
+    deferred = live & (deferred | !((la >= 1) & (la <= RX - 2) & (lb >= 1) & (lb <= RY - 2) & (lcz >= 1) &
+                                     (lcz <= RZ - 2)));
     {
       const uint64_t dm = __ballot(deferred);
       if (dm) {
@@ -549,18 +553,17 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       }
     }
     if (deferred) live = false;
-    if (!live) {
-      // a dummy at the centre of this thread's cell, with zero deposits (a
-      // divergent skip would keep two copies of the register sums)
+    // a lane without a live particle: a dummy at the centre of this thread's
+    // cell, with zero deposits (selects: a divergent skip would keep two
+    // copies of the register sums, and a branch costs more than the selects)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        off[d] = 0.0f;
-        idx[d] = mycell[d];
-      }
-      la = lx + H;
-      lb = ly + H;
-      lcz = lz + H;
+    for (int d = 0; d < 3; ++d) {
+      off[d] = live ? off[d] : 0.0f;
+      idx[d] = live ? idx[d] : mycell[d];
     }
+    la = live ? la : lx + H;
+    lb = live ? lb : ly + H;
+    lcz = live ? lcz : lz + H;
     // weights at x^{n+1/2}
     float w[3][3];
 #pragma unroll
@@ -732,7 +735,8 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
           }
       }
       pend = live;
-      pend_cell = alive ? c3_cell_id(cb, idx[0], idx[1], idx[2]) : -1;
+      const int32_t ncid = c3_cell_id(cb, idx[0], idx[1], idx[2], small);
+      pend_cell = alive ? ncid : -1;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         pend_off[d] = off[d];
@@ -819,13 +823,13 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
   }
 }
 
-template <int TX, int TY, int TZ, bool SB, bool REBIN, bool COPY>
+template <int TX, int TY, int TZ, bool SB, bool REBIN, bool COPY, bool SMALL>
 void launch_c3_t(const FusedPlan& plan, const PView<float>& p, const PView<float>& q, const Box* boxes_d,
                  const FView<float>& fl, const Forces& f, const Species* sp, int drag_mode, double dt,
                  const double* tdev, const int64_t* bin_start, const double* xg, DiagDev* dg, bool sums,
                  const uint32_t* src_index, hipStream_t st) {
   const size_t lds = c3_lds_bytes(plan);
-  auto kern = k_c3<TX, TY, TZ, SB, REBIN, COPY>;
+  auto kern = k_c3<TX, TY, TZ, SB, REBIN, COPY, SMALL>;
   if (lds > 64 * 1024) {
     static bool raised = false;
     if (!raised) {
@@ -848,8 +852,14 @@ void launch_c3_shape(const FusedPlan& plan, const PView<float>& p, const PView<f
                      int drag_mode, double dt, const double* tdev, const int64_t* bin_start, const double* xg,
                      DiagDev* dg, bool sums, const uint32_t* src_index, hipStream_t st) {
 #define DUST_C3M(SBV, RB, CP)                                                                               \
-  launch_c3_t<TX, TY, TZ, SBV, RB, CP>(plan, p, q, boxes_d, fl, f, sp, drag_mode, dt, tdev, bin_start, xg,  \
-                                       dg, sums, src_index, st)
+  do {                                                                                                      \
+    if (plan.small)                                                                                         \
+      launch_c3_t<TX, TY, TZ, SBV, RB, CP, true>(plan, p, q, boxes_d, fl, f, sp, drag_mode, dt, tdev,       \
+                                                 bin_start, xg, dg, sums, src_index, st);                   \
+    else                                                                                                    \
+      launch_c3_t<TX, TY, TZ, SBV, RB, CP, false>(plan, p, q, boxes_d, fl, f, sp, drag_mode, dt, tdev,      \
+                                                  bin_start, xg, dg, sums, src_index, st);                  \
+  } while (0)
   const bool sb = f.kind == FORCE_SHEARBOX;
   if (src_index) {
     if (sb) DUST_C3M(true, true, true);

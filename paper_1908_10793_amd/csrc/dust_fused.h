@@ -21,6 +21,7 @@ struct FusedPlan {
   bool ok = false;
   TileShape tile{{8, 8, 4}};
   int shape = 0;          // index of the compiled tile shape
+  bool small = false;     // every box has fewer than 2^24 cells
   int halo = 2;           // LDS window beyond the tile: stencil + half drift
   int ntiles = 0;
   int rmax[3] = {0, 0, 0};  // largest region extents

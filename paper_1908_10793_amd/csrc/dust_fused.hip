@@ -36,8 +36,10 @@ dust_status_t fused_plan_init(FusedPlan& plan, const Box* boxes, int nbox, TileS
   plan.shape = shape_id(ndim, plan.tile);
   if (plan.shape < 0) return DUST_EUNSUPPORTED;
   std::vector<TileDesc> tiles;
+  plan.small = true;
   for (int b = 0; b < nbox; ++b) {
     const Box& B = boxes[b];
+    if (B.ncell >= (1 << 24)) plan.small = false;
     int n[3] = {B.ax[0].n, B.ax[1].n, B.ndim > 2 ? B.ax[2].n : 1};
     int t[3] = {plan.tile.t[0], plan.tile.t[1], B.ndim > 2 ? plan.tile.t[2] : 1};
     int nt[3];

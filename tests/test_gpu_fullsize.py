@@ -181,35 +181,29 @@ def test_full_size_spherical_disk():
                    label="spherical 256x128x512")
 
 
-def test_full_size_batched_boxes_100_step_graph():
-    """All eight boxes of the batched workload at full size (32^3 ... 192^3,
-    four species, U{1..32} per cell and species, 994,755,343 particles),
-    stepped 100 times through captured graphs (99 steps, then the last one),
-    with the tile shape and rebinning interval the bench's autotuner picks
-    (16x4x4, every 32 steps).  The last step is checked against the oracle
-    started from the GPU state before it, on the particles within `margin`
-    cells of sampled cells of every box (selected on the GPU by cell), and
-    the conservation residual is checked over all 100 steps."""
+def last_step_parity(w, tile, rebin_every, nsteps, ncenters, margin, seed, label):
+    """nsteps fused steps through captured graphs (nsteps-1, then the last
+    one) with the given tiling and rebinning interval; the last step against
+    the oracle started from the GPU state before it, on the particles within
+    `margin` cells of sampled cells of every box (selected on the GPU by
+    cell), and the conservation residual over all steps."""
     from paper_1908_10793_amd import dust
-    ncenters, margin = 6, 3
-    w = synth.batched_boxes()
-    label = "batched, all boxes"
     print(f"[fullsize] {label}: {w.n} particles, uploading", flush=True)
     ctx = dust.context_for(w)
-    ctx.set_tile(16, 4, 4, 0)
+    ctx.set_tile(*tile)
     P, F = dust.upload(w, ctx, with_id=True)
     flags = (dust.STEP_APPLY_FEEDBACK | dust.STEP_DIAG | dust.STEP_FUSED | dust.STEP_GRAPH
-             | dust.STEP_REBIN_EVERY(32))
+             | dust.STEP_REBIN_EVERY(rebin_every))
     t = w.t0
-    ctx.step(P, F, w.dt, dust.forces_for(w, t), 99, flags)
-    t += 99 * w.dt
+    ctx.step(P, F, w.dt, dust.forces_for(w, t), nsteps - 1, flags)
+    t += (nsteps - 1) * w.dt
     torch.cuda.synchronize()
-    diag99 = ctx.status()
-    print(f"[fullsize] {label}: 99 graph steps done", flush=True)
+    diag_a = ctx.status()
+    print(f"[fullsize] {label}: {nsteps - 1} graph steps done", flush=True)
 
     # the state before the last step: gas of every box, and the particles of
     # the sampled regions (chosen on the GPU by their cell)
-    regions = sample_regions(w, ncenters, margin, seed=13)
+    regions = sample_regions(w, ncenters, margin, seed=seed)
     bases, C = w.cell_bases()
     near_all = torch.from_numpy(np.concatenate([r[0].ravel() for r in regions])).cuda()
     cell = P["cell"]
@@ -251,10 +245,10 @@ def test_full_size_batched_boxes_100_step_graph():
     dep_g = [d.cpu().numpy().astype(np.float64) for d in F["dep"]]
     vel_g = [v.cpu().numpy().astype(np.float64) for v in F["vel"]]
 
-    for dg in (diag99, diag1):
+    for dg in (diag_a, diag1):
         res_m = np.abs(np.array(dg["p_part"]) + np.array(dg["p_grid"])).max() / dg["sum_abs_j"]
         assert res_m < 2e-6, res_m
-    assert diag99["steps"] == 99 and diag1["steps"] == 1 and not diag99["flag_names"]
+    assert diag_a["steps"] == nsteps - 1 and diag1["steps"] == 1 and not diag_a["flag_names"]
 
     sub = dataclasses.replace(w, cell=st_in["cell"].astype(np.int32), off=st_in["off"],
                               mom=st_in["mom"], species=st_in["species"], gas=gas, t0=t)
@@ -264,3 +258,24 @@ def test_full_size_batched_boxes_100_step_graph():
     rep = compare_step(sub, st_in, st_out, run, "f32", fields_too=False, label=label)
     rep["fields"] = check_fields(w, run, dep_g, vel_g, regions, label)
     print(f"[fullsize] {label}: {rep}", flush=True)
+
+
+def test_full_size_batched_boxes_100_step_graph():
+    """All eight boxes of the batched workload at full size (32^3 ... 192^3,
+    four species, U{1..32} per cell and species, 994,755,343 particles),
+    stepped 100 times through captured graphs (99 steps, then the last one),
+    with the tile shape and rebinning interval the bench's autotuner picks
+    (16x4x4, every 32 steps).  The last step is checked against the oracle
+    started from the GPU state before it, on the particles within `margin`
+    cells of sampled cells of every box (selected on the GPU by cell), and
+    the conservation residual is checked over all 100 steps."""
+    last_step_parity(synth.batched_boxes(), (16, 4, 4, 0), 32, 100, 6, 3, 13, "batched, all boxes")
+
+
+def test_full_size_box_of_2_24_cells_stale_bins():
+    """One periodic box of 256^3 = 2^24 cells (one species, one particle per
+    cell): the tile kernel's path for boxes of 2^24 cells or more (FP64 cell
+    division, 32-bit cell-id products), six steps rebinned every four, so
+    that the checked last step runs on stale bins."""
+    w = synth.batched_boxes(sizes=(256,), max_per_species=1, species_tau=(0.1,))
+    last_step_parity(w, (16, 4, 4, 0), 4, 6, 8, 3, 17, "box of 256^3 cells")
