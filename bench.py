@@ -115,15 +115,18 @@ def tile_kernel(cfg: int, dtype: str, arith: str) -> str:
     return "k_c3" if cfg in (2, 5) and dtype == "f32" and arith == "f32" else "k_fused"
 
 
-def counter_summary_path(kernel: str, name: str) -> str:
-    return os.path.join(HERE, "profiles", f"{kernel}_{name}_hbm_bytes.txt")
+def profile_path(kernel: str, name: str, what: str, tile, rebin: int) -> str:
+    """A committed rocprofv3 summary of this workload and tiling (the file
+    name carries the tile shape and the rebinning interval)."""
+    tag = f"{tile[0]}x{tile[1]}x{tile[2]}_every{rebin}"
+    return os.path.join(HERE, "profiles", f"{kernel}_{name}_{tag}_{what}.txt")
 
 
-def counter_traffic(kernel: str, name: str, kernel_hash: str, n_particles: int):
+def counter_traffic(kernel: str, name: str, kernel_hash: str, n_particles: int, tile, rebin: int):
     """HBM bytes per launch of the tile kernel from the committed rocprofv3
-    counter summary of this workload, if it was taken on the current kernel
-    source and the same particle count."""
-    path = counter_summary_path(kernel, name)
+    counter summary of this workload and tiling, if it was taken on the
+    current kernel source and the same particle count."""
+    path = profile_path(kernel, name, "hbm_bytes", tile, rebin)
     if not os.path.exists(path):
         return None
     d = {}
@@ -140,10 +143,10 @@ def counter_traffic(kernel: str, name: str, kernel_hash: str, n_particles: int):
 def counter_valu(kernel: str, name: str, kernel_hash: str, tile, rebin: int):
     """VALU wave-instructions per launch of the tile kernel (launch-weighted
     over its variants) from the committed rocprofv3 SQ counter summary of
-    this workload, if it was taken on the current kernel source with the
-    same tile shape and rebinning interval."""
+    this workload and tiling, if it was taken on the current kernel source
+    with the same tile shape and rebinning interval."""
     import re
-    path = os.path.join(HERE, "profiles", f"{kernel}_{name}_sq_counters.txt")
+    path = profile_path(kernel, name, "sq_counters", tile, rebin)
     if not os.path.exists(path):
         return None
     total = launches = 0.0
@@ -678,7 +681,7 @@ def run_config(cfg: int, args, extra: bool, K: int, W: int, arith_override=None)
         kname = tile_kernel(cfg, dtype, arith)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": counter_traffic(kname, WORKLOAD_NAMES[cfg], khash, N),
+                "traffic": counter_traffic(kname, WORKLOAD_NAMES[cfg], khash, N, (tx, ty, tz), rebin),
                 "kernel": kname, "kernel_avg_us": round(kavg * 1e6, 2),
                 "launches_timed": len(kern),
                 "bytes_per_particle_step": round(bytes_per_pstep, 3),
