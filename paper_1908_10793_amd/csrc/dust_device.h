@@ -31,6 +31,9 @@ template <> __device__ __forceinline__ float dexpm1<float>(float x) { return exp
 template <typename A> __device__ __forceinline__ A dfloor(A x);
 template <> __device__ __forceinline__ double dfloor<double>(double x) { return floor(x); }
 template <> __device__ __forceinline__ float dfloor<float>(float x) { return floorf(x); }
+template <typename A> __device__ __forceinline__ A drint(A x);
+template <> __device__ __forceinline__ double drint<double>(double x) { return rint(x); }
+template <> __device__ __forceinline__ float drint<float>(float x) { return rintf(x); }
 
 // h - sin h without cancellation (series for small h; reciprocal constants
 // instead of divisions).
@@ -253,16 +256,16 @@ template <typename A, bool U>
 __device__ __forceinline__ int move_axis(const Axis& ax, int i, A& delta, A dxi) {
   const A half = A(0.5);
   if (U || ax.uniform) {
-    A dn = delta + dxi * A(ax.inv_d);
-    if (dn >= half || dn < -half) {
-      A k = dfloor(dn + half);
-      dn -= k;
-      i += (int)k;
-      if (dn >= half) { dn -= A(1); ++i; }
-      else if (dn < -half) { dn += A(1); --i; }
-    }
-    delta = dn;
-    return i;
+    // without branches (a wave would take one whenever a lane crosses a
+    // face): the nearest integer k splits the new offset exactly (dn - k is
+    // exact for |dn| < 2^23 in FP32), a tie at +1/2 goes to the next cell,
+    // and an offset that stays in its cell is kept as it is
+    const A dn = delta + dxi * A(ax.inv_d);
+    const A k = drint(dn);
+    const A r = k == A(0) ? dn : dn - k;
+    const bool up = r >= half;
+    delta = up ? r - A(1) : r;
+    return i + (int)k + (up ? 1 : 0);
   }
   A dn = delta + dxi / cell_width<A, U>(ax, i);
   if (dn < half && dn >= -half) {
@@ -293,6 +296,22 @@ __device__ __forceinline__ bool wrap_plain(const Axis& ax, int& i) {
   if (i < 0 ? lo_open : hi_open) return false;
   i %= ax.n;
   if (i < 0) i += ax.n;
+  return true;
+}
+
+// The boundaries of the first ND axes, with one test for all of them (a
+// wave branches only when one of its lanes is outside the box).  Returns
+// false if removed.
+template <typename A, int ND>
+__device__ __forceinline__ bool wrap_all(const Box& b, int idx[3]) {
+  bool out = false;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) out |= (unsigned)idx[d] >= (unsigned)b.ax[d].n;
+  if (out) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
+  }
   return true;
 }
 
@@ -351,10 +370,7 @@ __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first,
       for (int d = 0; d < NDIM; ++d) idx[d] = move_axis<A, U>(b.ax[d], idx[d], off[d], dx[d]);
     }
     if (NDIM == 3 && b.ax[0].bc_lo == BC_SHEAR) shear_image<A, FG>(b, f, t_after, idx, off, mom);
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d)
-      if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
-    return true;
+    return wrap_all<A, NDIM>(b, idx);
   }
   if constexpr (GEOM == GEOM_CYL) {
     if (first) {
@@ -388,10 +404,7 @@ __device__ __forceinline__ bool drift(const Box& b, const Forces& f, bool first,
       idx[0] = move_axis<A, U>(b.ax[0], idx[0], off[0], h * mom[0]);
     }
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if (!wrap_plain<A>(b.ax[d], idx[d])) return false;
-  return true;
+  return wrap_all<A, 3>(b, idx);
 }
 
 // ---------------------------------------------------------------- kick

@@ -272,6 +272,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     load_raw<TS, NDIM, nc>(p, nxt_si, nxt, copy_attrs);
   }
   if (src_index && wl.cnt > 1) si_b = src_index[slot_b];
+  // this thread's flags, raised once after the loop (no atomics in it)
+  uint32_t flags_acc = 0;
   for (int j = 0; j < wl.nlev; ++j) {
     const bool has = wl.cnt > j;
     const uint32_t i = slot;       // slot written
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     const int32_t cid = has ? cur.cell : -1;
     bool live = cid >= 0 && cid >= B.cell_base && cid < B.cell_base + B.ncell;
     bool removed = false;
-    if (cid >= 0 && !live) flag(dg, DUST_FLAG_BAD_CELL);
+    flags_acc |= cid >= 0 && !live ? (uint32_t)DUST_FLAG_BAD_CELL : 0u;
     if (live) {
       if (cid != mycid) unravel(B, cid - B.cell_base, idx);
       bool bad = false;
@@ -303,7 +305,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
         mom[d] = A(cur.mom[d]);
         bad |= !(off[d] >= A(-0.5) && off[d] < A(0.5));
       }
-      if (bad) flag(dg, DUST_FLAG_OFFSET_RANGE);
+      flags_acc |= bad ? (uint32_t)DUST_FLAG_OFFSET_RANGE : 0u;
       // half drift to x^{n+1/2}
       if (!drift<A, GEOM, NDIM, U, FG>(B, f, true, h, t0 + double(h), idx, off, mom)) {
         store_particle<TS, A, GEOM, NDIM, FG>(dst, B, f, t0 + double(h), i, false, idx, off, mom, dg);
@@ -315,16 +317,12 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     // since the binning, or wrapped across a periodic face) is left to the
     // deferred kernel, which does its step against global memory; here it
     // continues as a dummy.
-    bool deferred = false;
-    // window coordinates (this thread's cell for a dummy)
-    int la = lx + H, lb = ly + H, lc = c2 ? lz + HZ : 0;
-    if (live) {
-      la = win_coord(idx[0], ox, n0, RX, per0);
-      lb = win_coord(idx[1], oy, n1, RY, per1);
-      lc = c2 ? win_coord(idx[2], oz, n2, RZ, per2) : 0;
-      deferred = !(la >= 1 && la <= RX - 2 && lb >= 1 && lb <= RY - 2 &&
-                   (c2 == 0 || (lc >= 1 && lc <= RZ - 2)));
-    }
+    // window coordinates (every lane; a dummy takes this thread's cell below)
+    int la = win_coord(idx[0], ox, n0, RX, per0);
+    int lb = win_coord(idx[1], oy, n1, RY, per1);
+    int lc = c2 ? win_coord(idx[2], oz, n2, RZ, per2) : 0;
+    const bool deferred = live & !((la >= 1) & (la <= RX - 2) & (lb >= 1) & (lb <= RY - 2) &
+                                   ((c2 == 0) | ((lc >= 1) & (lc <= RZ - 2))));
     {
       const uint64_t dm = __ballot(deferred);
       if (dm) {
@@ -340,17 +338,16 @@ __global__ void __launch_bounds__(FUSED_THREADS)
       }
     }
     if (deferred) live = false;
-    if (!live) {
+    // the dummy by selects (a branch around them costs more)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        idx[d] = mycell[d];
-        off[d] = A(0);
-        mom[d] = A(0);
-      }
-      la = lx + H;
-      lb = ly + H;
-      lc = c2 ? lz + HZ : 0;
+    for (int d = 0; d < 3; ++d) {
+      idx[d] = live ? idx[d] : mycell[d];
+      off[d] = live ? off[d] : A(0);
+      mom[d] = live ? mom[d] : A(0);
     }
+    la = live ? la : lx + H;
+    lb = live ? lb : ly + H;
+    lc = live ? lc : (c2 ? lz + HZ : 0);
     // weights at x^{n+1/2}
     Stencil<A> s;
     stencil_weights<A, GEOM, NDIM, U>(B, idx, off, s);
@@ -406,10 +403,8 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 #pragma unroll
     for (int m = 0; m < 3; ++m) sl[m] = m < nc ? slip_canonical<A, GEOM>(ss, m, v[m]) : A(0);
     int spc = live ? cur.species : 0;
-    if (spc >= sp->n) {
-      flag(dg, DUST_FLAG_BAD_CELL);
-      spc = 0;
-    }
+    flags_acc |= spc >= sp->n ? (uint32_t)DUST_FLAG_BAD_CELL : 0u;
+    spc = spc >= sp->n ? 0 : spc;
     A m = p.mass && live ? A(cur.mass) : sp_m[spc];
     A c, psi;
     if (drag_mode == DRAG_SPECIES) {
@@ -554,6 +549,7 @@ __global__ void __launch_bounds__(FUSED_THREADS)
     }
   }
 
+  if (dg && flags_acc) atomicOr(&dg->flags, (unsigned)flags_acc);
   // register sums of my cell's stencil -> deposit window
   if (own) {
 #pragma unroll
