@@ -294,24 +294,89 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
       q[1] = k * (v[1] - u1);
       q[2] = k * (v[2] - mom[2]);
     }
-    const bool mine = use && la == lx + H && lb == ly + H && lcz == lz + H;
-    if (use && !mine) {
+    bool dep_reg;   // the particle's register-sum share (with weights shifted to this thread's cell)
+    if constexpr (MASS) {
+      const bool mine = use && la == lx + H && lb == ly + H && lcz == lz + H;
+      if (use && !mine) {
+        const int base = la + RX * (lb + RY * lcz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const double wt = double(w[0][a] * w[1][bb] * w[2][c]);
+              const int r = base + (a - 1) + RX * ((bb - 1) + RY * (c - 1));
+#pragma unroll
+              for (int m = 0; m < NC; ++m) atomicAdd(&dep[m * RC + r], wt * double(q[m]));
+            }
+      }
+      dep_reg = mine;
+    } else {
+      // the particle's cell relative to this thread's cell: in it or (drag
+      // source) a neighbour, the part of its stencil inside the thread's 27
+      // cells goes to the register sums (weights shifted by the offset), the
+      // planes outside to the window; further away, the whole stencil to the
+      // window.  The one-channel density keeps the whole stencil for every
+      // particle outside the thread's cell (the shifted weights took it from 6
+      // to 5 waves per SIMD and cost more than the atomics they save).
+      const int sx = la - (lx + H), sy = lb - (ly + H), sz = lcz - (lz + H);
+      const bool near = (sx >= -1) & (sx <= 1) & (sy >= -1) & (sy <= 1) & (sz >= -1) & (sz <= 1);
       const int base = la + RX * (lb + RY * lcz);
+      auto lds_add = [&](int a, int bb, int cc, float wt) {
+        const int r = base + a + RX * (bb + RY * cc);
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int m = 0; m < NC; ++m) atomicAdd(&dep[m * RC + r], double(wt) * double(q[m]));
+      };
+      if (use && !near) {
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const double wt = double(w[0][a] * w[1][bb] * w[2][c]);
-            const int r = base + (a - 1) + RX * ((bb - 1) + RY * (c - 1));
+          for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-            for (int m = 0; m < NC; ++m) atomicAdd(&dep[m * RC + r], wt * double(q[m]));
-          }
+            for (int a = 0; a < 3; ++a) lds_add(a - 1, bb - 1, c - 1, w[0][a] * w[1][bb] * w[2][c]);
+      }
+      if (use && near && (sx | sy | sz)) {
+        // row sy, column sx (rows other than sy), layer sz (the cells in neither)
+        if (sy != 0) {
+          const float wy = sy > 0 ? w[1][2] : w[1][0];
+#pragma unroll
+          for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) lds_add(a, sy, cc, w[0][a + 1] * wy * w[2][cc + 1]);
+        }
+        if (sx != 0) {
+          const float wx = sx > 0 ? w[0][2] : w[0][0];
+#pragma unroll
+          for (int cc = -1; cc <= 1; ++cc)
+#pragma unroll
+            for (int bb = -1; bb <= 1; ++bb)
+              if (sy == 0 || bb != sy) lds_add(sx, bb, cc, wx * w[1][bb + 1] * w[2][cc + 1]);
+        }
+        if (sz != 0) {
+          const float wz = sz > 0 ? w[2][2] : w[2][0];
+#pragma unroll
+          for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a)
+              if ((sy == 0 || bb != sy) && (sx == 0 || a != sx)) lds_add(a, bb, sz, w[0][a + 1] * w[1][bb + 1] * wz);
+        }
+      }
+      {
+        const int sd[3] = {sx, sy, sz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float w0 = w[d][0], w1 = w[d][1], w2 = w[d][2];
+          w[d][0] = sd[d] == 0 ? w0 : sd[d] < 0 ? w1 : 0.0f;
+          w[d][1] = sd[d] == 0 ? w1 : sd[d] < 0 ? w2 : w0;
+          w[d][2] = sd[d] == 0 ? w2 : sd[d] < 0 ? 0.0f : w1;
+        }
+      }
+      dep_reg = use && near;
     }
     float qf[NC], wq[3][NC];
 #pragma unroll
-    for (int m = 0; m < NC; ++m) qf[m] = mine ? q[m] : 0.0f;
+    for (int m = 0; m < NC; ++m) qf[m] = dep_reg ? q[m] : 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
